@@ -1,0 +1,1257 @@
+// Plain FP64 CPU oracle for one IMEX step of relativistic radiation MHD under
+// the gray M1 closure, with PLM MinMod reconstruction and the Jacobian-free
+// PVM-int face flux (Lopez-Miralles, Marti & Perucho, CPC, arXiv 2212.00370).
+//
+// TEST INFRASTRUCTURE ONLY. This file is the slow, obviously-correct
+// reference that the GPU library is checked against. Only the test suite, the
+// smoke check and the CPU-baseline leg of the benchmark may load it; the
+// product path never calls it. It shares no source with the GPU library.
+//
+// Every function follows the paper's definitions directly (section or
+// equation named in its comment). Where the paper leaves a choice open (the
+// primitive-recovery algorithm, the RK2 coefficients, the iteration used for
+// the stiff source, floors), the reading taken is stated in the comment.
+//
+// Floating point: IEEE binary64, no contraction (build with
+// -ffp-contract=off), no fast-math. The operation order of every expression
+// is the one written below, left to right with the parentheses shown.
+//
+// Build modes:
+//   default            : `real` is double.
+//   -DORACLE_COUNT_OPS : `real` is a wrapper that counts + - * / and sqrt,
+//                        so the same source yields the algorithmic operation
+//                        count of the method (results are bitwise unchanged).
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifdef ORACLE_COUNT_OPS
+struct OpCounts { unsigned long long add, mul, div, sqrt; };
+static OpCounts g_ops = {0, 0, 0, 0};
+struct real {
+  double v;
+  real() : v(0.0) {}
+  real(double x) : v(x) {}
+};
+static inline real operator+(real a, real b) { g_ops.add++; return real(a.v + b.v); }
+static inline real operator-(real a, real b) { g_ops.add++; return real(a.v - b.v); }
+static inline real operator*(real a, real b) { g_ops.mul++; return real(a.v * b.v); }
+static inline real operator/(real a, real b) { g_ops.div++; return real(a.v / b.v); }
+static inline real operator-(real a) { return real(-a.v); }
+static inline bool operator<(real a, real b) { return a.v < b.v; }
+static inline bool operator>(real a, real b) { return a.v > b.v; }
+static inline bool operator<=(real a, real b) { return a.v <= b.v; }
+static inline bool operator>=(real a, real b) { return a.v >= b.v; }
+static inline bool operator==(real a, real b) { return a.v == b.v; }
+static inline bool operator!=(real a, real b) { return a.v != b.v; }
+static inline real rsqrt_(real a) { g_ops.sqrt++; return real(std::sqrt(a.v)); }
+static inline double dv(real a) { return a.v; }
+static inline bool rfinite(real a) { return std::isfinite(a.v); }
+#else
+typedef double real;
+static inline real rsqrt_(real a) { return std::sqrt(a); }
+static inline double dv(real a) { return a; }
+static inline bool rfinite(real a) { return std::isfinite(a); }
+#endif
+
+static inline real rabs(real a) { return (a < real(0.0)) ? -a : a; }
+static inline real rmax(real a, real b) { return (a > b) ? a : b; }
+static inline real rmin(real a, real b) { return (a < b) ? a : b; }
+
+// Variable order. Conserved U and primitive V share slots 5..11 (B, E_r, F_r
+// are both primitive and conserved; Section 2.1).
+enum { NV = 12 };
+// U: 0 D, 1..3 S^j, 4 tau_e, 5..7 B^j, 8 E_r, 9..11 F_r^j
+// V: 0 rho, 1..3 v^j, 4 p, 5..7 B^j, 8 E_r, 9..11 F_r^j
+
+extern "C" {
+// Parameters (a ctypes mirror lives in oracle.py; keep the order).
+struct OPar {
+  double gamma;      // ideal-gas adiabatic index (eq. eos)
+  double a_rad;      // radiation constant a_R, 4*pi*B = a_R T^4
+  double t_coeff;    // T = t_coeff * p / rho (code units, mu m_p / k_B folded in)
+  double pvm_eps;    // finite-difference step of the Jacobian-free PVM (1e-8)
+  double c2p_tol;    // relative Newton step tolerance of primitive recovery
+  double imp_tol;    // relative tolerance of the implicit radiation solve
+  double rho_floor;  // state used only when recovery fails (counted)
+  double p_floor;
+  int pvm_k;         // degree index k of the internal polynomial, deg = 2^k
+  int beta_mode;     // 0: beta scales all 12 components; 1: radiation rows only; 2: beta = 1
+  int recon;         // 0: Godunov (piecewise constant); 1: PLM MinMod
+  int rk_order;      // 2: SSP-RK2 analogue; 3: the paper's IMEX RK3
+  int c2p_maxit;
+  int imp_maxit;
+  int imp_picard_it; // Picard (lagged) iterations before Newton takes over
+  int imp_method;    // 0: Picard then Newton; 1: Newton only; 2: Picard only
+};
+
+struct OGrid {
+  int ndim;
+  int n[3];
+  double dx[3];
+  int bc_lo[3], bc_hi[3];        // 0 periodic, 1 outflow, 2 inflow (lo side of last axis)
+  long long var_stride;          // elements between variable planes of U
+  const double* inflow_U;        // [12][transverse cells] conserved inflow state
+  const unsigned char* inflow_mask;  // [transverse cells] 1 = inflow, 0 = outflow
+};
+
+struct OReport {
+  long long c2p_fail, pvm_fallback, imp_fail, nonfinite;
+  long long first_bad_cell;
+  int max_c2p_it, max_imp_it;
+};
+}
+
+// ---------------------------------------------------------------------------
+// Derived constants of the gamma-law EOS (eq. eos): rho*h = rho + g1*p.
+struct Consts {
+  double g1;    // gamma / (gamma - 1)
+  double gm1g;  // (gamma - 1) / gamma
+  double gm1;   // gamma - 1
+};
+static Consts consts_of(const OPar& P) {
+  Consts c;
+  c.g1 = P.gamma / (P.gamma - 1.0);
+  c.gm1g = (P.gamma - 1.0) / P.gamma;
+  c.gm1 = P.gamma - 1.0;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// Quantities derived from the primitives (Section 2.1, definitions after
+// eqs. eqU/eqF): W, b^0 = W (v.B), b^i = B^i/W + v^i b^0,
+// |b|^2 = B^2/W^2 + (v.B)^2, total enthalpy density rho h* = rho h + |b|^2
+// (the printed h* carries a typo gamma/rho for p/rho), p* = p + |b|^2/2.
+struct Aux {
+  real W, iW, l2;     // Lorentz factor, 1/W, 1/W^2 = 1 - v^2
+  real b0, b[3], bb;  // magnetic four-vector components and |b|^2
+  real wtot;          // rho h* W^2
+  real ps;            // total pressure p*
+  real D;             // rho W
+};
+
+static void prim_aux(const real V[NV], const Consts& K, Aux& a) {
+  const real vx = V[1], vy = V[2], vz = V[3];
+  const real v2 = (vx * vx + vy * vy) + vz * vz;
+  a.l2 = 1.0 - v2;
+  a.iW = rsqrt_(a.l2);
+  a.W = 1.0 / a.iW;
+  const real vB = (vx * V[5] + vy * V[6]) + vz * V[7];
+  a.b0 = a.W * vB;
+  for (int j = 0; j < 3; ++j) a.b[j] = V[5 + j] * a.iW + V[1 + j] * a.b0;
+  const real B2 = (V[5] * V[5] + V[6] * V[6]) + V[7] * V[7];
+  a.bb = B2 * a.l2 + vB * vB;
+  const real rhoh = V[0] + K.g1 * V[4];
+  a.wtot = (rhoh + a.bb) * (a.W * a.W);
+  a.ps = V[4] + 0.5 * a.bb;
+  a.D = V[0] * a.W;
+}
+
+// Primitive -> conserved map, eq. eqU.
+static void p2c(const real V[NV], const Aux& a, real U[NV]) {
+  U[0] = a.D;
+  for (int j = 0; j < 3; ++j) U[1 + j] = a.wtot * V[1 + j] - a.b0 * a.b[j];
+  U[4] = ((a.wtot - a.ps) - a.b0 * a.b0) - a.D;
+  for (int q = 5; q < NV; ++q) U[q] = V[q];
+}
+
+// M1 closure (Section 2.2, eq. xi): row d of P_r = D_r E_r with
+// D_r = (1-xi)/2 delta + (3 xi - 1)/2 n n, n = F/|F|, f = |F|/E,
+// xi = (3 + 4 f^2) / (5 + 2 sqrt(4 - 3 f^2)). n n is taken as 0 when F = 0.
+static void m1_row(real E, const real F[3], int d, real P[3]) {
+  const real FF = (F[0] * F[0] + F[1] * F[1]) + F[2] * F[2];
+  const real f2 = FF / (E * E);
+  real t = 4.0 - 3.0 * f2;
+  t = (t > real(0.0)) ? t : real(0.0);
+  const real s = rsqrt_(t);
+  const real xi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * s);
+  const real ca = 0.5 * (1.0 - xi);
+  const real cb = 0.5 * (3.0 * xi - 1.0);
+  if (FF > real(0.0)) {
+    const real iFF = 1.0 / FF;
+    for (int j = 0; j < 3; ++j) {
+      const real nn = (F[d] * F[j]) * iFF;
+      P[j] = (j == d) ? E * (ca + cb * nn) : E * (cb * nn);
+    }
+  } else {
+    for (int j = 0; j < 3; ++j) P[j] = (j == d) ? E * ca : real(0.0);
+  }
+}
+
+// Physical flux in direction d, eq. eqF.
+static void flux(const real V[NV], const Aux& a, int d, real F[NV]) {
+  const real vd = V[1 + d];
+  F[0] = a.D * vd;
+  const real wv = a.wtot * vd;
+  for (int j = 0; j < 3; ++j) {
+    if (j == d) F[1 + j] = (wv * V[1 + j] + a.ps) - a.b[d] * a.b[j];
+    else        F[1 + j] = wv * V[1 + j] - a.b[d] * a.b[j];
+  }
+  F[4] = (wv - a.b0 * a.b[d]) - a.D * vd;
+  for (int j = 0; j < 3; ++j) F[5 + j] = vd * V[5 + j] - V[5 + d] * V[1 + j];
+  F[8] = V[9 + d];
+  m1_row(V[8], &V[9], d, &F[9]);
+}
+
+// ---------------------------------------------------------------------------
+// Conserved -> primitive recovery of the magnetofluid (Section 3.2 step 2 and
+// the implicit step; the paper defers the algorithm to its RMHD code).
+// Reading taken: Newton-Raphson on Z = rho h W^2 with a maintained bracket,
+// using the closed relations implied by eq. eqU
+//   S = (Z + B^2) v - (v.B) B,   v.B = (S.B)/Z,
+//   v^2(Z) = [S^2 + (S.B/Z)^2 (2Z + B^2)] / (Z + B^2)^2,
+//   tau + D = Z + B^2 - p - B^2/(2 W^2) - (S.B)^2/(2 Z^2),
+//   p(Z) = (gamma-1)/gamma (Z/W^2 - D/W).
+// f(Z) = Z + B^2 - p - B^2/(2W^2) - (S.B)^2/(2Z^2) - (tau + D).
+// Bracket: [D, gamma (tau + D)]; states with v^2 >= 1 or p <= 0 lie below the
+// root and are treated as f < 0. A Newton iterate that leaves the bracket
+// (or a non-positive slope) is replaced by bisection.
+struct C2PIn {
+  real D, S[3], B[3], Et, B2, S2, SB;
+};
+
+struct C2PEval {
+  bool ok;
+  real l2, iW, rho, p, vB, iZb, f, df;
+};
+
+static C2PEval c2p_eval(real Z, const C2PIn& in, const Consts& K, bool want_df) {
+  C2PEval e;
+  const real Zb = Z + in.B2;
+  const real iZ = 1.0 / Z;
+  e.iZb = 1.0 / Zb;
+  e.vB = in.SB * iZ;
+  const real vB2 = e.vB * e.vB;
+  const real v2 = (in.S2 + vB2 * (Z + Zb)) * (e.iZb * e.iZb);
+  e.ok = false;
+  if (!(v2 < real(1.0))) return e;
+  e.l2 = 1.0 - v2;
+  e.iW = rsqrt_(e.l2);
+  e.rho = in.D * e.iW;
+  e.p = K.gm1g * (Z * e.l2 - e.rho);
+  if (!(e.p > real(0.0))) return e;
+  e.ok = true;
+  if (!want_df) return e;
+  e.f = (((Z + in.B2) - e.p) - 0.5 * (in.B2 * e.l2)) - (0.5 * vB2 + in.Et);
+  // d(v^2)/dZ = -2 [S^2 + (S.B/Z)^2 (3 Z (Z+B^2) + B^4)/Z] / (Z+B^2)^3
+  const real dv2 = -2.0 * (in.S2 + (vB2 * (3.0 * (Z * Zb) + in.B2 * in.B2)) * iZ) *
+                   ((e.iZb * e.iZb) * e.iZb);
+  const real W = 1.0 / e.iW;
+  const real dp = K.gm1g * (e.l2 + dv2 * (0.5 * (in.D * W) - Z));
+  e.df = ((1.0 - dp) + 0.5 * (in.B2 * dv2)) + vB2 * iZ;
+  return e;
+}
+
+// Returns 0 on success. Zguess > 0 warm-starts the iteration (used for the
+// intermediate states of the PVM chain and inside the implicit solve); the
+// cold start is the rest-frame estimate Z0 = gamma (E - B^2/2) - (gamma-1) D,
+// exact for a fluid at rest.
+static int c2p(const real U[NV], const OPar& P, const Consts& K, real Zguess,
+               real V[NV], real* Zout, int* nit) {
+  C2PIn in;
+  in.D = U[0];
+  for (int j = 0; j < 3; ++j) { in.S[j] = U[1 + j]; in.B[j] = U[5 + j]; }
+  in.Et = U[4] + U[0];
+  in.B2 = (in.B[0] * in.B[0] + in.B[1] * in.B[1]) + in.B[2] * in.B[2];
+  in.S2 = (in.S[0] * in.S[0] + in.S[1] * in.S[1]) + in.S[2] * in.S[2];
+  in.SB = (in.S[0] * in.B[0] + in.S[1] * in.B[1]) + in.S[2] * in.B[2];
+  for (int q = 5; q < NV; ++q) V[q] = U[q];
+  *nit = 0;
+  if (!(in.D > real(0.0)) || !rfinite(in.Et) || !rfinite(in.S2) || !rfinite(in.B2)) return 1;
+  real lo = in.D;
+  real hi = P.gamma * in.Et;
+  if (!(hi > lo)) return 1;
+  real Z;
+  if (Zguess > real(0.0) && Zguess > lo && Zguess < hi) {
+    Z = Zguess;
+  } else {
+    Z = P.gamma * (in.Et - 0.5 * in.B2) - K.gm1 * in.D;
+    if (!(Z > lo && Z < hi)) Z = 0.5 * (lo + hi);
+  }
+  bool conv = false;
+  int it = 0;
+  while (it < P.c2p_maxit) {
+    ++it;
+    const C2PEval e = c2p_eval(Z, in, K, true);
+    real Zn;
+    if (!e.ok) {
+      lo = Z;
+      Zn = 0.5 * (lo + hi);
+    } else {
+      if (e.f == real(0.0)) { conv = true; break; }
+      if (e.f > real(0.0)) hi = Z; else lo = Z;
+      Zn = Z - e.f / e.df;
+      if (!(e.df > real(0.0)) || !(Zn > lo && Zn < hi)) Zn = 0.5 * (lo + hi);
+    }
+    const real dZ = rabs(Zn - Z);
+    Z = Zn;
+    if (dZ <= P.c2p_tol * Z) { conv = true; break; }
+  }
+  *nit = it;
+  if (!conv) return 2;
+  const C2PEval e = c2p_eval(Z, in, K, false);
+  if (!e.ok) return 3;
+  V[0] = e.rho;
+  for (int j = 0; j < 3; ++j) V[1 + j] = (in.S[j] + e.vB * in.B[j]) * e.iZb;
+  V[4] = e.p;
+  *Zout = Z;
+  return 0;
+}
+
+// Recovery failure fallback: a finite state at rest (counted, never silent).
+static void c2p_fallback(const real U[NV], const OPar& P, real V[NV]) {
+  V[0] = (U[0] > real(0.0)) ? U[0] : real(P.rho_floor);
+  V[1] = 0.0; V[2] = 0.0; V[3] = 0.0;
+  V[4] = P.p_floor;
+  for (int q = 5; q < NV; ++q) V[q] = U[q];
+}
+
+// ---------------------------------------------------------------------------
+// Coefficients of the internal polynomial approximation of |x| (eq. iterat):
+// p_0 = 1, p_k = (2 p_{k-1} - p_{k-1}^2 + x^2)/2. p_k is a polynomial in x^2
+// of degree M = 2^(k-1); c[m] multiplies x^(2m). All coefficients are dyadic
+// rationals, so this expansion is exact in binary64 for k <= 4.
+static int internal_poly(int k, double c[17]) {
+  double p[17];
+  for (int m = 0; m < 17; ++m) p[m] = 0.0;
+  p[0] = 1.0;
+  int M = 0;  // degree in x^2
+  for (int s = 1; s <= k; ++s) {
+    double q[17];
+    for (int m = 0; m < 17; ++m) q[m] = 0.0;
+    // p^2 (degree 2M in x^2)
+    for (int a = 0; a <= M; ++a)
+      for (int b = 0; b <= M; ++b) q[a + b] -= p[a] * p[b];
+    for (int m = 0; m <= M; ++m) q[m] += 2.0 * p[m];
+    q[1] += 1.0;
+    for (int m = 0; m < 17; ++m) p[m] = 0.5 * q[m];
+    M = (M == 0) ? 1 : 2 * M;
+  }
+  for (int m = 0; m < 17; ++m) c[m] = p[m];
+  return M;
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian-free PVM-int face flux (Section 3.2, PVM algorithm and eq. beta).
+// Y(w) = [F(U_m + F(U_m + eps w) - F(U_m)) - F(U_m)] / eps approximates
+// A(U_m)^2 w; Horner's scheme over x^2 gives U_{M} ~ p_k(A) U_0 with
+// lambda_max = 1, and F^ = (F_L + F_R)/2 - beta U_M / 2,
+// beta = min(1/tau_L, 1/tau_R, 1). If any intermediate recovery fails the face
+// falls back to p_0 = 1 (Rusanov with lambda = 1), counted.
+struct FaceOut { int fallback; int c2p_it; };
+
+// Recovery of an intermediate state U near U_m, warm-started at Z_m. The
+// recovery is a function of the fluid part of U only, so when that part equals
+// U_m's bit for bit the known V_m is reused (this makes the chain exact for
+// U_0 = 0 and for perturbations that leave the fluid untouched).
+static bool recover_near(const real U[NV], const real Um[NV], const real Vm[NV], real Zm,
+                         const OPar& P, const Consts& K, real V[NV], int* nit) {
+  bool same = true;
+  for (int q = 0; q < 8; ++q) same = same && (U[q] == Um[q]);
+  if (same) {
+    for (int q = 0; q < 5; ++q) V[q] = Vm[q];
+    for (int q = 5; q < NV; ++q) V[q] = U[q];
+    *nit = 0;
+    return true;
+  }
+  real Z = 0.0;
+  return c2p(U, P, K, Zm, V, &Z, nit) == 0;
+}
+
+static void pvm_face(const real VL[NV], const real VR[NV], real tauL, real tauR, int d,
+                     const OPar& P, const Consts& K, const double* coef, int M,
+                     real Fh[NV], FaceOut& fo) {
+  Aux aL, aR;
+  prim_aux(VL, K, aL);
+  prim_aux(VR, K, aR);
+  real UL[NV], UR[NV], FL[NV], FR[NV];
+  p2c(VL, aL, UL); flux(VL, aL, d, FL);
+  p2c(VR, aR, UR); flux(VR, aR, d, FR);
+  real U0[NV], Um[NV];
+  for (int q = 0; q < NV; ++q) { U0[q] = UR[q] - UL[q]; Um[q] = 0.5 * (UL[q] + UR[q]); }
+  const real beta = 1.0 / rmax(rmax(tauL, tauR), real(1.0));
+  fo.fallback = 0;
+  fo.c2p_it = 0;
+  real Uk[NV];
+  bool ok = true;
+  if (M == 0) {
+    for (int q = 0; q < NV; ++q) Uk[q] = U0[q];
+  } else {
+    real Vm[NV], Zm = 0.0;
+    int it = 0;
+    if (c2p(Um, P, K, real(0.0), Vm, &Zm, &it) != 0) ok = false;
+    fo.c2p_it += it;
+    real Fm[NV];
+    if (ok) { Aux am; prim_aux(Vm, K, am); flux(Vm, am, d, Fm); }
+    const real ieps = 1.0 / P.pvm_eps;
+    real w[NV];
+    for (int q = 0; q < NV; ++q) w[q] = U0[q];
+    for (int l = 0; l < M && ok; ++l) {
+      // Y(w)
+      real Ue[NV], Ve[NV], Fe[NV], Ut[NV], Vt[NV], Ft[NV];
+      for (int q = 0; q < NV; ++q) Ue[q] = Um[q] + P.pvm_eps * w[q];
+      if (!recover_near(Ue, Um, Vm, Zm, P, K, Ve, &it)) { ok = false; fo.c2p_it += it; break; }
+      fo.c2p_it += it;
+      { Aux ae; prim_aux(Ve, K, ae); flux(Ve, ae, d, Fe); }
+      for (int q = 0; q < NV; ++q) Ut[q] = Um[q] + (Fe[q] - Fm[q]);
+      if (!recover_near(Ut, Um, Vm, Zm, P, K, Vt, &it)) { ok = false; fo.c2p_it += it; break; }
+      fo.c2p_it += it;
+      { Aux at; prim_aux(Vt, K, at); flux(Vt, at, d, Ft); }
+      const real cnext = coef[M - 1 - l];
+      if (l == 0) {
+        const real ctop = coef[M];
+        for (int q = 0; q < NV; ++q) w[q] = ctop * ((Ft[q] - Fm[q]) * ieps) + cnext * U0[q];
+      } else {
+        for (int q = 0; q < NV; ++q) w[q] = (Ft[q] - Fm[q]) * ieps + cnext * U0[q];
+      }
+    }
+    if (ok) {
+      for (int q = 0; q < NV; ++q) Uk[q] = w[q];
+    } else {
+      fo.fallback = 1;
+      for (int q = 0; q < NV; ++q) Uk[q] = U0[q];
+    }
+  }
+  for (int q = 0; q < NV; ++q) {
+    const real bq = (P.beta_mode == 2 || (P.beta_mode == 1 && q < 8)) ? real(1.0) : beta;
+    Fh[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * (bq * Uk[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PLM reconstruction (Section 3.2, reconstruction paragraph).
+// minmod(a, b) = a or b, whichever is smaller in magnitude, if they share a
+// sign, else 0. A cell whose reconstructed face values give |v|^2 >= 1 falls
+// back to zeroth order on both of its faces. After reconstruction the face
+// radiation flux is limited to |F_r| <= E_r by rescaling.
+static inline real minmod(real a, real b) {
+  if ((a > real(0.0) && b > real(0.0)) || (a < real(0.0) && b < real(0.0)))
+    return (rabs(a) < rabs(b)) ? a : b;
+  return real(0.0);
+}
+
+static void cell_slopes(const real Vm[NV], const real Vc[NV], const real Vp[NV], int recon,
+                        real s[NV]) {
+  for (int q = 0; q < NV; ++q) s[q] = (recon == 1) ? minmod(Vc[q] - Vm[q], Vp[q] - Vc[q]) : real(0.0);
+  if (recon == 1) {
+    real lo[3], hi[3];
+    for (int j = 0; j < 3; ++j) { lo[j] = Vc[1 + j] - 0.5 * s[1 + j]; hi[j] = Vc[1 + j] + 0.5 * s[1 + j]; }
+    const real v2lo = (lo[0] * lo[0] + lo[1] * lo[1]) + lo[2] * lo[2];
+    const real v2hi = (hi[0] * hi[0] + hi[1] * hi[1]) + hi[2] * hi[2];
+    if (!(v2lo < real(1.0)) || !(v2hi < real(1.0)))
+      for (int q = 0; q < NV; ++q) s[q] = 0.0;
+  }
+}
+
+static void limit_rad_flux(real V[NV]) {
+  const real FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
+  if (FF > V[8] * V[8]) {
+    const real r = V[8] / rsqrt_(FF);
+    for (int j = 0; j < 3; ++j) V[9 + j] = V[9 + j] * r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4x4 linear solve by Gaussian elimination with partial pivoting (the paper
+// names LU decomposition for the implicit system).
+static bool solve4(real A[4][4], real b[4], real x[4]) {
+  for (int k = 0; k < 4; ++k) {
+    int piv = k;
+    real amax = rabs(A[k][k]);
+    for (int i = k + 1; i < 4; ++i)
+      if (rabs(A[i][k]) > amax) { amax = rabs(A[i][k]); piv = i; }
+    if (!(amax > real(0.0))) return false;
+    if (piv != k) {
+      for (int j = 0; j < 4; ++j) std::swap(A[k][j], A[piv][j]);
+      std::swap(b[k], b[piv]);
+    }
+    for (int i = k + 1; i < 4; ++i) {
+      const real l = A[i][k] / A[k][k];
+      for (int j = k + 1; j < 4; ++j) A[i][j] = A[i][j] - l * A[k][j];
+      b[i] = b[i] - l * b[k];
+    }
+  }
+  for (int i = 3; i >= 0; --i) {
+    real s = b[i];
+    for (int j = i + 1; j < 4; ++j) s = s - A[i][j] * x[j];
+    x[i] = s / A[i][i];
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Implicit radiation-matter step (Section 3.3, eqs. timeadv, totale, totalm,
+// g0, gi). Unknown X = (E_r, F_r); the fluid follows from recovery of
+// (D, S_t - F_r, tau_t - E_r, B). With h the implicit step, the backward-Euler
+// system X = X* + h S_r(X), S_r = (-G^0, -G^i), is C(X) X = b(X) with
+//   C11 = 1 - h rho W [-kappa + sigma (W^2 - 1 + u.D.u)]
+//   C1j = -h rho u_j [kappa - sigma (2 W^2 - 1)]
+//   Ci1 = -h rho [(kappa + sigma) (D.u)_i + sigma u_i (W^2 + u.D.u)]
+//   Cij = delta_ij + h rho W [(kappa + sigma) delta_ij + 2 sigma u_i u_j]
+//   b   = (E* + h rho W kappa a_R T^4,  F*_i + h rho u_i kappa a_R T^4).
+// Cij carries a plus sign: expanding eq. gi gives +, while the printed matrix
+// shows a minus (which would anti-damp F_r in a static medium).
+struct ImpSys {
+  real C[4][4];
+  real b[4];
+  real Z;
+};
+
+static bool imp_build(const real X[4], const real Us[NV], real Et, const real St[3], real h,
+                      real kap, real sig, const OPar& P, const Consts& K, real Zg,
+                      ImpSys& sy, int* c2p_it) {
+  real Uf[NV], Vf[NV];
+  Uf[0] = Us[0];
+  for (int j = 0; j < 3; ++j) Uf[1 + j] = St[j] - X[1 + j];
+  Uf[4] = Et - X[0];
+  for (int j = 0; j < 3; ++j) Uf[5 + j] = Us[5 + j];
+  Uf[8] = X[0];
+  for (int j = 0; j < 3; ++j) Uf[9 + j] = X[1 + j];
+  int it = 0;
+  real Z = 0.0;
+  if (c2p(Uf, P, K, Zg, Vf, &Z, &it) != 0) { *c2p_it += it; return false; }
+  *c2p_it += it;
+  sy.Z = Z;
+  const real rho = Vf[0], p = Vf[4];
+  const real v2 = (Vf[1] * Vf[1] + Vf[2] * Vf[2]) + Vf[3] * Vf[3];
+  const real iW = rsqrt_(1.0 - v2);
+  const real W = 1.0 / iW;
+  real u[3];
+  for (int j = 0; j < 3; ++j) u[j] = W * Vf[1 + j];
+  const real T = (P.t_coeff * p) / rho;
+  const real T2 = T * T;
+  const real aT4 = P.a_rad * (T2 * T2);
+  // Eddington tensor at the current radiation iterate (eq. xi).
+  const real E = X[0];
+  const real F[3] = {X[1], X[2], X[3]};
+  const real FF = (F[0] * F[0] + F[1] * F[1]) + F[2] * F[2];
+  const real f2 = FF / (E * E);
+  real t = 4.0 - 3.0 * f2;
+  t = (t > real(0.0)) ? t : real(0.0);
+  const real xi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * rsqrt_(t));
+  const real ca = 0.5 * (1.0 - xi);
+  const real cb = 0.5 * (3.0 * xi - 1.0);
+  real Dm[3][3];
+  if (FF > real(0.0)) {
+    const real iFF = 1.0 / FF;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const real nn = (F[i] * F[j]) * iFF;
+        Dm[i][j] = (i == j) ? ca + cb * nn : cb * nn;
+      }
+  } else {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Dm[i][j] = (i == j) ? ca : real(0.0);
+  }
+  real Du[3];
+  for (int i = 0; i < 3; ++i) Du[i] = (Dm[i][0] * u[0] + Dm[i][1] * u[1]) + Dm[i][2] * u[2];
+  const real uDu = (u[0] * Du[0] + u[1] * Du[1]) + u[2] * Du[2];
+  const real W2 = W * W;
+  const real hr = h * rho;
+  const real hrW = hr * W;
+  const real ks = kap + sig;
+  sy.C[0][0] = 1.0 - hrW * (sig * ((W2 - 1.0) + uDu) - kap);
+  const real c1 = kap - sig * (2.0 * W2 - 1.0);
+  for (int j = 0; j < 3; ++j) sy.C[0][1 + j] = -((hr * u[j]) * c1);
+  const real c2 = sig * (W2 + uDu);
+  for (int i = 0; i < 3; ++i) sy.C[1 + i][0] = -(hr * (ks * Du[i] + c2 * u[i]));
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const real g = 2.0 * ((sig * u[i]) * u[j]);
+      sy.C[1 + i][1 + j] = (i == j) ? 1.0 + hrW * (ks + g) : hrW * g;
+    }
+  const real em = (hr * kap) * aT4;
+  sy.b[0] = Us[8] + W * em;
+  for (int i = 0; i < 3; ++i) sy.b[1 + i] = Us[9 + i] + u[i] * em;
+  return true;
+}
+
+static void imp_residual(const ImpSys& sy, const real X[4], real R[4]) {
+  for (int i = 0; i < 4; ++i)
+    R[i] = (((sy.C[i][0] * X[0] + sy.C[i][1] * X[1]) + sy.C[i][2] * X[2]) + sy.C[i][3] * X[3]) - sy.b[i];
+}
+
+static real xscale(const real X[4]) {
+  return rmax(rmax(rabs(X[0]), rabs(X[1])), rmax(rabs(X[2]), rabs(X[3])));
+}
+
+static real vmaxabs4(const real a[4]) {
+  return rmax(rmax(rabs(a[0]), rabs(a[1])), rmax(rabs(a[2]), rabs(a[3])));
+}
+
+// Returns 0 on success and writes the new state; on failure Un = Us.
+// Picard (the paper's lagged iteration): X^{m+1} = C(X^m)^{-1} b(X^m), started
+// at X^0 = X*, accepted when max|X^{m+1} - X^m| <= tol * max|X| and the
+// recovery at X^{m+1} succeeds. If it has not converged after imp_picard_it
+// iterations (it diverges where the radiation heat capacity exceeds the
+// gas's), Newton on R(X) = C(X) X - b(X) with a forward-difference Jacobian
+// and step halving finishes from the last admissible iterate. Both reach the
+// same root of the backward-Euler system.
+static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OPar& P,
+                         const Consts& K, real Un[NV], int* iters, int* c2p_it) {
+  const real Et = Us[4] + Us[8];
+  real St[3];
+  for (int j = 0; j < 3; ++j) St[j] = Us[1 + j] + Us[9 + j];
+  // The upper limit |F_r| <= E_r (Section 3.2) is applied to the explicit
+  // radiation state before the solve, keeping the totals tau + E_r and
+  // S + F_r: the solve starts from, and its right-hand side uses, the
+  // limited state. A non-positive E_r cannot be repaired and fails.
+  real Ul[NV];
+  for (int q = 0; q < NV; ++q) Ul[q] = Us[q];
+  if (!(Ul[8] > real(0.0))) {
+    for (int q = 0; q < NV; ++q) Un[q] = Us[q];
+    *iters = 0;
+    *c2p_it = 0;
+    return 1;
+  }
+  {
+    const real FF = (Ul[9] * Ul[9] + Ul[10] * Ul[10]) + Ul[11] * Ul[11];
+    if (FF > Ul[8] * Ul[8]) {
+      const real r = Ul[8] / rsqrt_(FF);
+      for (int j = 0; j < 3; ++j) Ul[9 + j] = Ul[9 + j] * r;
+    }
+  }
+  real X[4] = {Ul[8], Ul[9], Ul[10], Ul[11]};
+  ImpSys sy;
+  real Zg = 0.0;
+  int it = 0;
+  bool conv = false;
+  bool have = false;
+  *c2p_it = 0;
+  const int npic = (P.imp_method == 1) ? 0 : ((P.imp_method == 2) ? P.imp_maxit : P.imp_picard_it);
+  // Picard phase; it stops early once its update grows. The Newton phase
+  // restarts from the explicit state X* (Xg), which is admissible whenever
+  // the first recovery succeeds.
+  const real Xg[4] = {X[0], X[1], X[2], X[3]};
+  real dlast = 0.0, dprev = 0.0;
+  for (int m = 0; m <= npic; ++m) {
+    if (!imp_build(X, Ul, Et, St, h, kap, sig, P, K, Zg, sy, c2p_it)) break;
+    Zg = sy.Z;
+    if (m == 0) have = true;
+    if (m > 0 && dlast <= P.imp_tol * xscale(X)) { conv = true; break; }
+    if (m == npic) break;
+    if (m > 1 && P.imp_method == 0 && dlast > dprev) break;
+    real A[4][4], bb[4], Xn[4];
+    for (int i = 0; i < 4; ++i) { bb[i] = sy.b[i]; for (int j = 0; j < 4; ++j) A[i][j] = sy.C[i][j]; }
+    if (!solve4(A, bb, Xn)) break;
+    ++it;
+    if (!(Xn[0] > real(0.0)) || !rfinite(Xn[0]) || !rfinite(Xn[1]) || !rfinite(Xn[2]) || !rfinite(Xn[3])) break;
+    real dd[4];
+    for (int i = 0; i < 4; ++i) { dd[i] = Xn[i] - X[i]; X[i] = Xn[i]; }
+    dprev = dlast;
+    dlast = vmaxabs4(dd);
+  }
+  if (!conv && have && P.imp_method != 2) {
+    // Newton phase from X* (its system is rebuilt).
+    for (int i = 0; i < 4; ++i) X[i] = Xg[i];
+    Zg = 0.0;
+    real R[4];
+    if (imp_build(X, Ul, Et, St, h, kap, sig, P, K, Zg, sy, c2p_it)) {
+      Zg = sy.Z;
+      imp_residual(sy, X, R);
+      for (int n = 0; n < P.imp_maxit; ++n) {
+        ++it;
+        const real sc = xscale(X);
+        const real del = 1e-8 * sc;
+        real J[4][4];
+        bool okj = true;
+        for (int j = 0; j < 4; ++j) {
+          real Xp[4] = {X[0], X[1], X[2], X[3]};
+          Xp[j] = Xp[j] + del;
+          ImpSys sp;
+          if (!imp_build(Xp, Ul, Et, St, h, kap, sig, P, K, Zg, sp, c2p_it)) { okj = false; break; }
+          real Rp[4];
+          imp_residual(sp, Xp, Rp);
+          for (int i = 0; i < 4; ++i) J[i][j] = (Rp[i] - R[i]) / del;
+        }
+        if (!okj) break;
+        real nR[4] = {-R[0], -R[1], -R[2], -R[3]}, dX[4];
+        if (!solve4(J, nR, dX)) break;
+        const real rn = vmaxabs4(R);
+        const real dn = vmaxabs4(dX);
+        real lam = 1.0;
+        bool acc = false;
+        real Xt[4], Rt[4];
+        ImpSys st;
+        for (int ls = 0; ls < 12; ++ls) {
+          for (int i = 0; i < 4; ++i) Xt[i] = X[i] + lam * dX[i];
+          if (Xt[0] > real(0.0) && imp_build(Xt, Ul, Et, St, h, kap, sig, P, K, Zg, st, c2p_it)) {
+            imp_residual(st, Xt, Rt);
+            if (vmaxabs4(Rt) < rn || lam * dn <= 1e-10 * sc) { acc = true; break; }
+          }
+          lam = 0.5 * lam;
+        }
+        if (!acc) break;
+        real stp[4];
+        for (int i = 0; i < 4; ++i) { stp[i] = Xt[i] - X[i]; X[i] = Xt[i]; R[i] = Rt[i]; }
+        sy = st;
+        Zg = st.Z;
+        if (vmaxabs4(stp) <= P.imp_tol * xscale(X)) { conv = true; break; }
+      }
+    }
+  }
+  *iters = it;
+  if (!conv) {
+    for (int q = 0; q < NV; ++q) Un[q] = Us[q];
+    return 1;
+  }
+  // |F_r| <= E_r after the solve, by a rescale that keeps S + F_r fixed.
+  const real FF = (X[1] * X[1] + X[2] * X[2]) + X[3] * X[3];
+  if (FF > X[0] * X[0]) {
+    const real r = X[0] / rsqrt_(FF);
+    for (int j = 0; j < 3; ++j) X[1 + j] = X[1 + j] * r;
+  }
+  Un[0] = Us[0];
+  for (int j = 0; j < 3; ++j) Un[1 + j] = St[j] - X[1 + j];
+  Un[4] = Et - X[0];
+  for (int j = 0; j < 3; ++j) Un[5 + j] = Us[5 + j];
+  Un[8] = X[0];
+  for (int j = 0; j < 3; ++j) Un[9 + j] = X[1 + j];
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Signal speed bound of one cell in direction d (for the CFL condition).
+// Fluid: the relativistic fast-speed bound with a^2 = cs^2 + ca^2 - cs^2 ca^2,
+//   lambda = [v_d (1 - a^2) +- sqrt(a^2 (1 - v^2)(1 - v^2 a^2 - v_d^2 (1 - a^2)))]
+//            / (1 - v^2 a^2).
+// Radiation: the M1 eigenvalues lambda_r1, lambda_r3 (eqs. lam1, lam2, lam3)
+// with cos(theta) = F_d/|F| (0 when F = 0).
+static real cell_speed(const real V[NV], int d, const OPar& P, const Consts& K) {
+  Aux a;
+  prim_aux(V, K, a);
+  const real rho = V[0], p = V[4];
+  const real rhoh = rho + K.g1 * p;
+  const real cs2 = (P.gamma * p) / rhoh;
+  const real ca2 = a.bb / (rhoh + a.bb);
+  const real a2 = (cs2 + ca2) - cs2 * ca2;
+  const real v2 = 1.0 - a.l2;
+  const real vd = V[1 + d];
+  const real den = 1.0 - v2 * a2;
+  real disc = (a2 * a.l2) * (den - (vd * vd) * (1.0 - a2));
+  disc = (disc > real(0.0)) ? disc : real(0.0);
+  const real sq = rsqrt_(disc);
+  const real lp = (vd * (1.0 - a2) + sq) / den;
+  const real lm = (vd * (1.0 - a2) - sq) / den;
+  real s = rmax(rabs(lp), rabs(lm));
+  const real E = V[8];
+  const real FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
+  real f = 0.0, cth = 0.0;
+  if (FF > real(0.0)) {
+    const real Fn = rsqrt_(FF);
+    f = rmin(Fn / E, real(1.0));
+    cth = V[9 + d] / Fn;
+  }
+  const real f2 = f * f;
+  const real r43 = 4.0 - 3.0 * f2;
+  const real sr = rsqrt_(r43);
+  real zz = (2.0 / 3.0) * (r43 - sr) + (2.0 * (cth * cth)) * ((2.0 - f2) - sr);
+  zz = (zz > real(0.0)) ? zz : real(0.0);
+  const real zeta = rsqrt_(zz);
+  const real l1 = (f * cth - zeta) / sr;
+  const real l3 = (f * cth + zeta) / sr;
+  s = rmax(s, rmax(rabs(l1), rabs(l3)));
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Grid helpers. U holds interior cells only, cell (i, j, k) at
+// i + n0 (j + n1 k), variable q at offset q * var_stride. Cells outside the
+// domain are mapped: periodic wraps, outflow copies the nearest interior cell
+// (zero gradient), inflow (lo side of the last axis) takes the prescribed
+// state where the mask is set and copies elsewhere.
+struct Grid {
+  OGrid g;
+  long long ncell;
+  int n[3];
+};
+
+// Returns the interior cell index, or -(t + 1) for an inflow cell with
+// transverse index t.
+static long long map_cell(const Grid& G, int i, int j, int k, int dir) {
+  int c[3] = {i, j, k};
+  const int d = dir;
+  const int nd = G.n[d];
+  if (c[d] < 0) {
+    if (G.g.bc_lo[d] == 0) c[d] = ((c[d] % nd) + nd) % nd;
+    else if (G.g.bc_lo[d] == 2) {
+      const long long t = (d == 0) ? 0 : ((d == 1) ? c[0] : (long long)c[0] + (long long)G.n[0] * c[1]);
+      if (G.g.inflow_mask && G.g.inflow_mask[t]) return -(t + 1);
+      c[d] = 0;
+    } else c[d] = 0;
+  } else if (c[d] >= nd) {
+    if (G.g.bc_hi[d] == 0) c[d] = c[d] % nd;
+    else c[d] = nd - 1;
+  }
+  return (long long)c[0] + (long long)G.n[0] * ((long long)c[1] + (long long)G.n[1] * c[2]);
+}
+
+struct CellPrim {
+  std::vector<double> V;      // [12][ncell]
+  std::vector<double> taup;   // D (kappa + sigma), optical depth per unit length
+  std::vector<double> inV;    // inflow primitives [12][ntrans]
+  std::vector<double> intaup;
+};
+
+static void load_U(const double* U, long long vs, long long c, real out[NV]) {
+  for (int q = 0; q < NV; ++q) out[q] = U[q * vs + c];
+}
+
+static double opac_at(const double* arr, double uni, long long c) { return arr ? arr[c] : uni; }
+
+// Cell recovery for one stage. Returns the number of failures.
+static long long stage_prims(const Grid& G, const OPar& P, const Consts& K, const double* U,
+                             const double* kap, const double* sig, double kap0, double sig0,
+                             CellPrim& cp, long long* first_bad, int* max_it) {
+  const long long N = G.ncell;
+  const long long vs = G.g.var_stride;
+  cp.V.assign((size_t)NV * N, 0.0);
+  cp.taup.assign(N, 0.0);
+  long long nfail = 0;
+  long long fb = -1;
+  int mit = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nfail) reduction(max : mit)
+  for (long long c = 0; c < N; ++c) {
+    real Uc[NV], Vc[NV], Z;
+    int it = 0;
+    load_U(U, vs, c, Uc);
+    if (c2p(Uc, P, K, real(0.0), Vc, &Z, &it) != 0) {
+      c2p_fallback(Uc, P, Vc);
+      nfail += 1;
+#pragma omp critical
+      { if (fb < 0 || c < fb) fb = c; }
+    }
+    mit = std::max(mit, it);
+    for (int q = 0; q < NV; ++q) cp.V[q * N + c] = dv(Vc[q]);
+    cp.taup[c] = dv(Uc[0] * (real(opac_at(kap, kap0, c)) + real(opac_at(sig, sig0, c))));
+  }
+  // Inflow cells (lo side of the last axis).
+  const int dl = G.g.ndim - 1;
+  cp.inV.clear();
+  cp.intaup.clear();
+  if (G.g.bc_lo[dl] == 2 && G.g.inflow_U) {
+    long long nt = 1;
+    for (int e = 0; e < G.g.ndim; ++e) if (e != dl) nt *= G.n[e];
+    cp.inV.assign((size_t)NV * nt, 0.0);
+    cp.intaup.assign(nt, 0.0);
+    for (long long t = 0; t < nt; ++t) {
+      real Uc[NV], Vc[NV], Z;
+      int it = 0;
+      for (int q = 0; q < NV; ++q) Uc[q] = G.g.inflow_U[q * nt + t];
+      if (c2p(Uc, P, K, real(0.0), Vc, &Z, &it) != 0) c2p_fallback(Uc, P, Vc);
+      for (int q = 0; q < NV; ++q) cp.inV[q * nt + t] = dv(Vc[q]);
+      // Inflow ghosts take the opacity of the adjacent interior cell.
+      long long c = (dl == 0) ? 0 : t;
+      cp.intaup[t] = dv(Uc[0] * (real(opac_at(kap, kap0, c)) + real(opac_at(sig, sig0, c))));
+    }
+  }
+  if (first_bad && fb >= 0 && (*first_bad < 0 || fb < *first_bad)) *first_bad = fb;
+  if (max_it && mit > *max_it) *max_it = mit;
+  return nfail;
+}
+
+static void get_cell(const Grid& G, const CellPrim& cp, long long m, real V[NV], real* taup) {
+  if (m >= 0) {
+    for (int q = 0; q < NV; ++q) V[q] = cp.V[q * G.ncell + m];
+    *taup = cp.taup[m];
+  } else {
+    const long long t = -m - 1;
+    const long long nt = (long long)cp.intaup.size();
+    for (int q = 0; q < NV; ++q) V[q] = cp.inV[q * nt + t];
+    *taup = cp.intaup[t];
+  }
+}
+
+static long long face_count(const Grid& G, int d) {
+  long long nf = 1;
+  for (int e = 0; e < 3; ++e) nf *= (e == d) ? (G.n[e] + 1) : G.n[e];
+  return nf;
+}
+
+// Face fluxes of one direction. Face index: along d the face i sits between
+// cells i-1 and i (i = 0..n_d); faces are numbered with x fastest over the
+// face-grid extents.
+static long long stage_faces(const Grid& G, const OPar& P, const Consts& K, const CellPrim& cp,
+                             int d, double* Fh, const double* coef, int M) {
+  const long long nf = face_count(G, d);
+  int fn[3] = {G.n[0], G.n[1], G.n[2]};
+  fn[d] += 1;
+  long long nfb = 0;
+  const double dxd = G.g.dx[d];
+#pragma omp parallel for schedule(static) reduction(+ : nfb)
+  for (long long f = 0; f < nf; ++f) {
+    int c[3];
+    c[0] = (int)(f % fn[0]);
+    c[1] = (int)((f / fn[0]) % fn[1]);
+    c[2] = (int)(f / ((long long)fn[0] * fn[1]));
+    real Vs[4][NV];
+    real tp[4];
+    for (int s = 0; s < 4; ++s) {
+      int cc[3] = {c[0], c[1], c[2]};
+      cc[d] = c[d] - 2 + s;
+      const long long m = map_cell(G, cc[0], cc[1], cc[2], d);
+      get_cell(G, cp, m, Vs[s], &tp[s]);
+    }
+    real sa[NV], sb[NV];
+    cell_slopes(Vs[0], Vs[1], Vs[2], P.recon, sa);
+    cell_slopes(Vs[1], Vs[2], Vs[3], P.recon, sb);
+    real VL[NV], VR[NV];
+    for (int q = 0; q < NV; ++q) { VL[q] = Vs[1][q] + 0.5 * sa[q]; VR[q] = Vs[2][q] - 0.5 * sb[q]; }
+    limit_rad_flux(VL);
+    limit_rad_flux(VR);
+    const real tauL = tp[1] * dxd, tauR = tp[2] * dxd;
+    real Fq[NV];
+    FaceOut fo;
+    pvm_face(VL, VR, tauL, tauR, d, P, K, coef, M, Fq, fo);
+    nfb += fo.fallback;
+    for (int q = 0; q < NV; ++q) Fh[q * nf + f] = dv(Fq[q]);
+  }
+  return nfb;
+}
+
+struct StageCoef { double a0, a1, c; };
+
+static int rk_stages(int order, StageCoef s[3]) {
+  if (order == 3) {
+    // The paper's IMEX RK3 (Section 3.1, Shu-Osher form).
+    s[0] = {1.0, 0.0, 1.0};
+    s[1] = {0.75, 0.25, 0.25};
+    s[2] = {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0};
+    return 3;
+  }
+  // RK2 analogue of the same pattern (Heun / SSP-RK2), implicit steps dt, dt/2.
+  s[0] = {1.0, 0.0, 1.0};
+  s[1] = {0.5, 0.5, 0.5};
+  return 2;
+}
+
+// One IMEX step (eqs. explicit, impliciteq and the RK pattern of Section 3.1).
+// Each stage: U* = a0 U^(0) + a1 U^(s) + c dt L(U^(s)) with
+// L = -sum_d (F^_{d,+} - F^_{d,-}) / dx_d (unsplit sum over directions), then
+// U^(s+1) = implicit solve of U* with h = c dt.
+static int step_impl(const OGrid& og, const OPar& P, double* U, const double* kap, const double* sig,
+                     double kap0, double sig0, double dt, OReport* rep) {
+  Grid G;
+  G.g = og;
+  for (int e = 0; e < 3; ++e) G.n[e] = (e < og.ndim) ? og.n[e] : 1;
+  G.ncell = (long long)G.n[0] * G.n[1] * G.n[2];
+  const Consts K = consts_of(P);
+  const long long N = G.ncell, vs = og.var_stride;
+  double coef[17];
+  const int M = internal_poly(P.pvm_k, coef);
+  OReport R = {0, 0, 0, 0, -1, 0, 0};
+  std::vector<double> U0((size_t)NV * N), Us((size_t)NV * N);
+  for (int q = 0; q < NV; ++q)
+    for (long long c = 0; c < N; ++c) { U0[q * N + c] = U[q * vs + c]; Us[q * N + c] = U[q * vs + c]; }
+  StageCoef sc[3];
+  const int ns = rk_stages(P.rk_order, sc);
+  std::vector<std::vector<double>> Fh(og.ndim);
+  CellPrim cp;
+  Grid Gs = G;
+  Gs.g.var_stride = N;
+  double idx[3];
+  for (int d = 0; d < og.ndim; ++d) idx[d] = 1.0 / og.dx[d];
+  for (int s = 0; s < ns; ++s) {
+    R.c2p_fail += stage_prims(Gs, P, K, Us.data(), kap, sig, kap0, sig0, cp, &R.first_bad_cell, &R.max_c2p_it);
+    for (int d = 0; d < og.ndim; ++d) {
+      Fh[d].assign((size_t)NV * face_count(G, d), 0.0);
+      R.pvm_fallback += stage_faces(G, P, K, cp, d, Fh[d].data(), coef, M);
+    }
+    const real cdt = real(sc[s].c) * real(dt);
+    std::vector<double> Un((size_t)NV * N);
+    long long nimp = 0, nnf = 0, fb = -1;
+    int mit = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nimp, nnf) reduction(max : mit)
+    for (long long c = 0; c < N; ++c) {
+      const int ci[3] = {(int)(c % G.n[0]), (int)((c / G.n[0]) % G.n[1]), (int)(c / ((long long)G.n[0] * G.n[1]))};
+      real Ust[NV];
+      for (int q = 0; q < NV; ++q) {
+        real div = 0.0;
+        for (int d = 0; d < og.ndim; ++d) {
+          int fn[3] = {G.n[0], G.n[1], G.n[2]};
+          fn[d] += 1;
+          const long long fm = (long long)ci[0] + (long long)fn[0] * ((long long)ci[1] + (long long)fn[1] * ci[2]);
+          long long stride = 1;
+          if (d == 1) stride = fn[0];
+          if (d == 2) stride = (long long)fn[0] * fn[1];
+          const long long nf = face_count(G, d);
+          const real dF = real(Fh[d][q * nf + fm + stride]) - real(Fh[d][q * nf + fm]);
+          if (d == 0) div = dF * idx[0];
+          else div = div + dF * idx[d];
+        }
+        Ust[q] = (real(sc[s].a0) * real(U0[q * N + c]) + real(sc[s].a1) * real(Us[q * N + c])) - cdt * div;
+      }
+      real Unc[NV];
+      int iters = 0, cit = 0;
+      const int st = implicit_cell(Ust, cdt, real(opac_at(kap, kap0, c)), real(opac_at(sig, sig0, c)), P, K, Unc, &iters, &cit);
+      if (st != 0) nimp += 1;
+      mit = std::max(mit, iters);
+      bool fin = true;
+      for (int q = 0; q < NV; ++q) { Un[q * N + c] = dv(Unc[q]); if (!std::isfinite(dv(Unc[q]))) fin = false; }
+      if (!fin) nnf += 1;
+      if (st != 0 || !fin) {
+#pragma omp critical
+        { if (fb < 0 || c < fb) fb = c; }
+      }
+    }
+    R.imp_fail += nimp;
+    R.nonfinite += nnf;
+    if (fb >= 0 && (R.first_bad_cell < 0 || fb < R.first_bad_cell)) R.first_bad_cell = fb;
+    if (mit > R.max_imp_it) R.max_imp_it = mit;
+    Us.swap(Un);
+  }
+  for (int q = 0; q < NV; ++q)
+    for (long long c = 0; c < N; ++c) U[q * vs + c] = Us[q * N + c];
+  if (rep) *rep = R;
+  return (R.c2p_fail || R.imp_fail) ? 1 : ((R.nonfinite) ? 4 : 0);
+}
+
+// ===========================================================================
+// C entry points used by the tests (ctypes). Arrays are [12][n] with the given
+// stride between variable planes.
+extern "C" {
+
+int or_threads(int nt) {
+#ifdef _OPENMP
+  if (nt > 0) omp_set_num_threads(nt);
+  return omp_get_max_threads();
+#else
+  (void)nt;
+  return 1;
+#endif
+}
+
+void or_p2c(long long n, const double* V, long long sv, const OPar* P, double* U, long long su) {
+  const Consts K = consts_of(*P);
+  for (long long c = 0; c < n; ++c) {
+    real Vc[NV], Uc[NV];
+    for (int q = 0; q < NV; ++q) Vc[q] = V[q * sv + c];
+    Aux a;
+    prim_aux(Vc, K, a);
+    p2c(Vc, a, Uc);
+    for (int q = 0; q < NV; ++q) U[q * su + c] = dv(Uc[q]);
+  }
+}
+
+void or_flux(long long n, const double* V, long long sv, int d, const OPar* P, double* F, long long sf) {
+  const Consts K = consts_of(*P);
+  for (long long c = 0; c < n; ++c) {
+    real Vc[NV], Fc[NV];
+    for (int q = 0; q < NV; ++q) Vc[q] = V[q * sv + c];
+    Aux a;
+    prim_aux(Vc, K, a);
+    flux(Vc, a, d, Fc);
+    for (int q = 0; q < NV; ++q) F[q * sf + c] = dv(Fc[q]);
+  }
+}
+
+// Z_in: optional warm-start values (NULL or <= 0: cold). status[c]: 0 ok.
+void or_c2p(long long n, const double* U, long long su, const OPar* P, const double* Z_in,
+            double* V, long long sv, double* Z_out, int* status, int* iters) {
+  const Consts K = consts_of(*P);
+  for (long long c = 0; c < n; ++c) {
+    real Uc[NV], Vc[NV], Z = 0.0;
+    for (int q = 0; q < NV; ++q) Uc[q] = U[q * su + c];
+    int it = 0;
+    const real zg = Z_in ? real(Z_in[c]) : real(0.0);
+    int st = c2p(Uc, *P, K, zg, Vc, &Z, &it);
+    if (st != 0) c2p_fallback(Uc, *P, Vc);
+    for (int q = 0; q < NV; ++q) V[q * sv + c] = dv(Vc[q]);
+    if (Z_out) Z_out[c] = dv(Z);
+    if (status) status[c] = st;
+    if (iters) iters[c] = it;
+  }
+}
+
+// PVM face flux from given reconstructed states.
+void or_pvm_face(long long n, const double* VL, const double* VR, long long sv, const double* tauL,
+                 const double* tauR, int d, const OPar* P, double* Fh, long long sf, int* fallback,
+                 int* c2p_its) {
+  const Consts K = consts_of(*P);
+  double coef[17];
+  const int M = internal_poly(P->pvm_k, coef);
+  for (long long c = 0; c < n; ++c) {
+    real L[NV], Rr[NV], Fq[NV];
+    for (int q = 0; q < NV; ++q) { L[q] = VL[q * sv + c]; Rr[q] = VR[q * sv + c]; }
+    FaceOut fo;
+    pvm_face(L, Rr, real(tauL[c]), real(tauR[c]), d, *P, K, coef, M, Fq, fo);
+    for (int q = 0; q < NV; ++q) Fh[q * sf + c] = dv(Fq[q]);
+    if (fallback) fallback[c] = fo.fallback;
+    if (c2p_its) c2p_its[c] = fo.c2p_it;
+  }
+}
+
+int or_poly_coef(int k, double* c) {
+  double cc[17];
+  const int M = internal_poly(k, cc);
+  for (int m = 0; m <= M; ++m) c[m] = cc[m];
+  return M;
+}
+
+void or_implicit(long long n, const double* Us, long long su, const double* h, const double* kap,
+                 const double* sig, const OPar* P, double* Un, long long sn, int* status, int* iters) {
+  const Consts K = consts_of(*P);
+  for (long long c = 0; c < n; ++c) {
+    real Uc[NV], Uo[NV];
+    for (int q = 0; q < NV; ++q) Uc[q] = Us[q * su + c];
+    int it = 0, cit = 0;
+    int st = implicit_cell(Uc, real(h[c]), real(kap[c]), real(sig[c]), *P, K, Uo, &it, &cit);
+    for (int q = 0; q < NV; ++q) Un[q * sn + c] = dv(Uo[q]);
+    if (status) status[c] = st;
+    if (iters) iters[c] = it;
+  }
+}
+
+// Direct evaluation of the radiation four-force (eqs. g0, gi) from a full
+// primitive state: out = (G^0, G^1, G^2, G^3). Used by the tests to check the
+// implicit solution against the backward-Euler equations without the matrix.
+void or_four_force(long long n, const double* V, long long sv, const double* kap, const double* sig,
+                   const OPar* P, double* G, long long sg) {
+  for (long long c = 0; c < n; ++c) {
+    real Vc[NV];
+    for (int q = 0; q < NV; ++q) Vc[q] = V[q * sv + c];
+    const real rho = Vc[0], p = Vc[4];
+    const real v2 = (Vc[1] * Vc[1] + Vc[2] * Vc[2]) + Vc[3] * Vc[3];
+    const real W = 1.0 / rsqrt_(1.0 - v2);
+    real u[3];
+    for (int j = 0; j < 3; ++j) u[j] = W * Vc[1 + j];
+    const real T = (P->t_coeff * p) / rho;
+    const real fourpiB = P->a_rad * ((T * T) * (T * T));
+    const real E = Vc[8];
+    const real F[3] = {Vc[9], Vc[10], Vc[11]};
+    real Pr[3][3];
+    for (int i = 0; i < 3; ++i) m1_row(E, F, i, Pr[i]);
+    const real k = kap[c], s = sig[c];
+    real uF = 0.0, uPu = 0.0;
+    for (int i = 0; i < 3; ++i) uF = uF + u[i] * F[i];
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) uPu = uPu + u[i] * u[j] * Pr[i][j];
+    const real G0 = -rho * k * (fourpiB * W - W * E + uF)
+                    - rho * s * (W * (W * W - 1.0) * E + W * uPu - (2.0 * W * W - 1.0) * uF);
+    G[0 * sg + c] = dv(G0);
+    for (int i = 0; i < 3; ++i) {
+      real uP = 0.0;
+      for (int j = 0; j < 3; ++j) uP = uP + u[j] * Pr[i][j];
+      const real Gi = -fourpiB * rho * k * u[i] + rho * (k + s) * (W * F[i] - uP)
+                      - rho * s * u[i] * (W * W * E - 2.0 * W * uF + uPu);
+      G[(1 + i) * sg + c] = dv(Gi);
+    }
+  }
+}
+
+void or_cell_speed(long long n, const double* V, long long sv, int d, const OPar* P, double* s) {
+  const Consts K = consts_of(*P);
+  for (long long c = 0; c < n; ++c) {
+    real Vc[NV];
+    for (int q = 0; q < NV; ++q) Vc[q] = V[q * sv + c];
+    s[c] = dv(cell_speed(Vc, d, *P, K));
+  }
+}
+
+// Global maximum signal speed of U (capped at 1), as used by the CFL rule.
+double or_max_speed(const OGrid* og, const OPar* P, const double* U, long long* nfail) {
+  Grid G;
+  G.g = *og;
+  for (int e = 0; e < 3; ++e) G.n[e] = (e < og->ndim) ? og->n[e] : 1;
+  G.ncell = (long long)G.n[0] * G.n[1] * G.n[2];
+  const Consts K = consts_of(*P);
+  const long long vs = og->var_stride;
+  double smax = 0.0;
+  long long nf = 0;
+#pragma omp parallel for schedule(static) reduction(max : smax) reduction(+ : nf)
+  for (long long c = 0; c < G.ncell; ++c) {
+    real Uc[NV], Vc[NV], Z;
+    int it;
+    load_U(U, vs, c, Uc);
+    if (c2p(Uc, *P, K, real(0.0), Vc, &Z, &it) != 0) { c2p_fallback(Uc, *P, Vc); nf += 1; }
+    for (int d = 0; d < og->ndim; ++d) smax = std::max(smax, dv(cell_speed(Vc, d, *P, K)));
+  }
+  if (nfail) *nfail = nf;
+  return std::min(smax, 1.0);
+}
+
+int or_step(const OGrid* og, const OPar* P, double* U, const double* kap, const double* sig,
+            double kap0, double sig0, double dt, OReport* rep) {
+  return step_impl(*og, *P, U, kap, sig, kap0, sig0, dt, rep);
+}
+
+// Face fluxes of the first stage only (cell recovery + reconstruction + PVM),
+// for per-face comparisons. Fh_d: [12][faces_d] per direction, packed one
+// direction after another.
+long long or_face_fluxes(const OGrid* og, const OPar* P, const double* U, const double* kap,
+                         const double* sig, double kap0, double sig0, double* Fh) {
+  Grid G;
+  G.g = *og;
+  for (int e = 0; e < 3; ++e) G.n[e] = (e < og->ndim) ? og->n[e] : 1;
+  G.ncell = (long long)G.n[0] * G.n[1] * G.n[2];
+  const Consts K = consts_of(*P);
+  double coef[17];
+  const int M = internal_poly(P->pvm_k, coef);
+  CellPrim cp;
+  stage_prims(G, *P, K, U, kap, sig, kap0, sig0, cp, nullptr, nullptr);
+  long long off = 0, nfb = 0;
+  for (int d = 0; d < og->ndim; ++d) {
+    nfb += stage_faces(G, *P, K, cp, d, Fh + off, coef, M);
+    off += NV * face_count(G, d);
+  }
+  return nfb;
+}
+
+// Explicit part of one stage: Ustar = a0 U0 + a1 Us - c dt sum_d dF^/dx_d,
+// with the fluxes computed from Us (no implicit solve). For stage-level tests.
+long long or_explicit_stage(const OGrid* og, const OPar* P, const double* U0, const double* Us,
+                            const double* kap, const double* sig, double kap0, double sig0,
+                            double a0, double a1, double c, double dt, double* Ust) {
+  Grid G;
+  G.g = *og;
+  for (int e = 0; e < 3; ++e) G.n[e] = (e < og->ndim) ? og->n[e] : 1;
+  G.ncell = (long long)G.n[0] * G.n[1] * G.n[2];
+  const Consts K = consts_of(*P);
+  double coef[17];
+  const int M = internal_poly(P->pvm_k, coef);
+  CellPrim cp;
+  long long nbad = stage_prims(G, *P, K, Us, kap, sig, kap0, sig0, cp, nullptr, nullptr);
+  std::vector<std::vector<double>> Fh(og->ndim);
+  for (int d = 0; d < og->ndim; ++d) {
+    Fh[d].assign((size_t)NV * face_count(G, d), 0.0);
+    stage_faces(G, *P, K, cp, d, Fh[d].data(), coef, M);
+  }
+  double idx[3];
+  for (int d = 0; d < og->ndim; ++d) idx[d] = 1.0 / og->dx[d];
+  const real cdt = real(c) * real(dt);
+  const long long N = G.ncell, vs = og->var_stride;
+  for (long long cc = 0; cc < N; ++cc) {
+    const int ci[3] = {(int)(cc % G.n[0]), (int)((cc / G.n[0]) % G.n[1]), (int)(cc / ((long long)G.n[0] * G.n[1]))};
+    for (int q = 0; q < NV; ++q) {
+      real div = 0.0;
+      for (int d = 0; d < og->ndim; ++d) {
+        int fn[3] = {G.n[0], G.n[1], G.n[2]};
+        fn[d] += 1;
+        const long long fm = (long long)ci[0] + (long long)fn[0] * ((long long)ci[1] + (long long)fn[1] * ci[2]);
+        long long stride = 1;
+        if (d == 1) stride = fn[0];
+        if (d == 2) stride = (long long)fn[0] * fn[1];
+        const long long nf = face_count(G, d);
+        const real dF = real(Fh[d][q * nf + fm + stride]) - real(Fh[d][q * nf + fm]);
+        if (d == 0) div = dF * idx[0];
+        else div = div + dF * idx[d];
+      }
+      Ust[q * vs + cc] = dv((real(a0) * real(U0[q * vs + cc]) + real(a1) * real(Us[q * vs + cc])) - cdt * div);
+    }
+  }
+  return nbad;
+}
+
+#ifdef ORACLE_COUNT_OPS
+void or_opcount_reset(void) { g_ops = {0, 0, 0, 0}; }
+void or_opcount_get(unsigned long long* out) {
+  out[0] = g_ops.add; out[1] = g_ops.mul; out[2] = g_ops.div; out[3] = g_ops.sqrt;
+}
+#endif
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+"""Seeded synthetic inputs (primitive states, opacities, grid parameters).
+
+This module holds no arithmetic of the method: it only draws initial states
+with numpy's PCG64 generator and returns primitive arrays ``[12, ncell]``
+(rho, v_x, v_y, v_z, p, B_x, B_y, B_z, E_r, F_x, F_y, F_z; x fastest), per-cell
+opacities and the run parameters. Both the GPU path and the CPU oracle start
+from these arrays, each converting primitives to conserved variables with its
+own code.
+
+Workloads (shapes and value ranges of the paper's test problems, Section 4):
+  * ``riemann_1d``  -- seeded piecewise-constant RRMHD+M1 Riemann problems on
+    [0, 1] (400 cells by default), outflow boundaries, gamma = 5/3.
+  * ``blast_2d``    -- magnetised cylindrical blast (overpressure 1e3 inside
+    r < 0.1) on [-1/2, 1/2]^2, smooth 1 % density perturbation, oblique
+    B = 0.5, equilibrium radiation, opacity field spanning free streaming to
+    diffusion, periodic boundaries, gamma = 4/3.
+  * ``random_prims`` -- i.i.d. admissible states for unit-level checks.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+NV = 12
+PERIODIC, OUTFLOW, INFLOW = 0, 1, 2
+
+
+@dataclass
+class Problem:
+    name: str
+    shape: tuple            # interior cells per axis, x first
+    dx: tuple
+    x0: tuple
+    V: np.ndarray           # [12, ncell] primitives
+    kappa: np.ndarray       # [ncell]
+    sigma: np.ndarray       # [ncell]
+    gamma: float
+    a_rad: float
+    t_coeff: float = 1.0
+    bc_lo: tuple = (OUTFLOW, OUTFLOW, OUTFLOW)
+    bc_hi: tuple = (OUTFLOW, OUTFLOW, OUTFLOW)
+    cfl: float = 0.4
+    t_end: float | None = None
+    steps: int | None = None
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def ncell(self) -> int:
+        return int(np.prod(self.shape))
+
+    @property
+    def ndim(self) -> int:
+        return len(self.shape)
+
+
+def _log_uniform(rng, lo, hi, size=None):
+    return np.exp(rng.uniform(math.log(lo), math.log(hi), size))
+
+
+def _unit_vectors(rng, n):
+    v = rng.normal(size=(3, n))
+    v /= np.linalg.norm(v, axis=0, keepdims=True)
+    return v
+
+
+def random_prims(seed: int, n: int, *, rho=(0.1, 10.0), p=(0.01, 10.0), vmax=0.9, bmax=2.0,
+                 er=(1e-3, 10.0), fmax=1.0, zero_flux_frac=0.0) -> np.ndarray:
+    """I.i.d. admissible primitive states: log-uniform rho, p, E_r; |v| < vmax
+    in a uniform direction; |B| < bmax; F_r = f E_r m with f ~ U[0, fmax)."""
+    rng = np.random.default_rng(seed)
+    V = np.zeros((NV, n))
+    V[0] = _log_uniform(rng, *rho, n)
+    V[1:4] = _unit_vectors(rng, n) * rng.uniform(0.0, vmax, n)
+    V[4] = _log_uniform(rng, *p, n)
+    V[5:8] = _unit_vectors(rng, n) * rng.uniform(0.0, bmax, n)
+    V[8] = _log_uniform(rng, *er, n)
+    f = rng.uniform(0.0, fmax, n)
+    if zero_flux_frac > 0:
+        f[rng.uniform(size=n) < zero_flux_frac] = 0.0
+    V[9:12] = _unit_vectors(rng, n) * (f * V[8])
+    return V
+
+
+def riemann_states(seed: int) -> dict:
+    """Left/right states of one seeded 1D RRMHD+M1 Riemann problem."""
+    rng = np.random.default_rng(seed)
+    bx = rng.uniform(-1.0, 1.0)
+    sides = {}
+    for s in ("L", "R"):
+        rho = _log_uniform(rng, 0.1, 10.0)
+        p = _log_uniform(rng, 0.01, 10.0)
+        n = _unit_vectors(rng, 1)[:, 0]
+        v = n * rng.uniform(0.0, 0.9)
+        while True:
+            by, bz = rng.uniform(-1.7, 1.7, 2)
+            if bx * bx + by * by + bz * bz < 4.0:
+                break
+        er = _log_uniform(rng, 1e-3, 10.0)
+        m = _unit_vectors(rng, 1)[:, 0]
+        fr = m * rng.uniform(0.0, 1.0) * er
+        kap = _log_uniform(rng, 1e-2, 1e3)
+        sig = _log_uniform(rng, 1e-2, 1e3)
+        sides[s] = dict(rho=rho, v=v, p=p, B=np.array([bx, by, bz]), E=er, F=fr, kappa=kap, sigma=sig)
+    TL = sides["L"]["p"] / sides["L"]["rho"]
+    TR = sides["R"]["p"] / sides["R"]["rho"]
+    a_rad = math.sqrt(sides["L"]["E"] * sides["R"]["E"]) / (TL * TR) ** 2
+    return dict(sides=sides, a_rad=a_rad)
+
+
+def riemann_1d(seed: int, n: int = 400) -> Problem:
+    """Seeded 1D Riemann problem on [0, 1] with the jump at x = 1/2."""
+    st = riemann_states(seed)
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    V = np.zeros((NV, n))
+    kap = np.zeros(n)
+    sig = np.zeros(n)
+    for s, mask in (("L", x < 0.5), ("R", x >= 0.5)):
+        d = st["sides"][s]
+        V[0, mask] = d["rho"]
+        V[1:4, mask] = d["v"][:, None]
+        V[4, mask] = d["p"]
+        V[5:8, mask] = d["B"][:, None]
+        V[8, mask] = d["E"]
+        V[9:12, mask] = d["F"][:, None]
+        kap[mask] = d["kappa"]
+        sig[mask] = d["sigma"]
+    return Problem(name=f"riemann1d_s{seed}_n{n}", shape=(n,), dx=(dx,), x0=(0.0,), V=V, kappa=kap,
+                   sigma=sig, gamma=5.0 / 3.0, a_rad=st["a_rad"], bc_lo=(OUTFLOW,) * 3,
+                   bc_hi=(OUTFLOW,) * 3, cfl=0.4, t_end=0.4)
+
+
+def blast_2d(seed: int = 0, nx: int = 512, ny: int | None = None, steps: int = 200,
+             e_bg: float = 0.0) -> Problem:
+    """Magnetised cylindrical blast on [-1/2, 1/2]^2 (periodic).
+
+    Radiation starts in equilibrium with the gas, E_r = a_R T^4, plus an
+    optional uniform isotropic background ``e_bg``; F_r = 0."""
+    ny = nx if ny is None else ny
+    rng = np.random.default_rng(seed)
+    dx, dy = 1.0 / nx, 1.0 / ny
+    x = -0.5 + (np.arange(nx) + 0.5) * dx
+    y = -0.5 + (np.arange(ny) + 0.5) * dy
+    X, Y = np.meshgrid(x, y, indexing="xy")      # [ny, nx], x fastest when flattened
+    g = np.zeros_like(X)
+    for _ in range(8):
+        kx, ky = rng.integers(1, 5, 2)
+        sx, sy = rng.choice([-1, 1], 2)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        g += np.cos(2.0 * math.pi * (sx * kx * X + sy * ky * Y) + ph)
+    g /= np.max(np.abs(g))
+    rho = 1.0 + 0.01 * g
+    r = np.sqrt(X * X + Y * Y)
+    p = np.where(r < 0.1, 10.0, 0.01)
+    T = p / rho
+    a_rad = 10.0 / 10.0 ** 4          # p_in / T_in^4: radiation ~ gas pressure inside
+    V = np.zeros((NV, ny * nx))
+    V[0] = rho.reshape(-1)
+    V[4] = p.reshape(-1)
+    V[5] = 0.5 * math.cos(math.pi / 4)
+    V[6] = 0.5 * math.sin(math.pi / 4)
+    V[8] = (a_rad * T ** 4 + e_bg).reshape(-1)
+    kap = (10.0 ** (-0.5 + 2.5 * np.sin(2.0 * math.pi * X)) / dx).reshape(-1)
+    sig = (10.0 ** (-0.5 + 2.5 * np.sin(2.0 * math.pi * Y)) / 10.0 / dy).reshape(-1)
+    return Problem(name=f"blast2d_s{seed}_{nx}x{ny}", shape=(nx, ny), dx=(dx, dy), x0=(-0.5, -0.5),
+                   V=V, kappa=kap, sigma=sig, gamma=4.0 / 3.0, a_rad=a_rad,
+                   bc_lo=(PERIODIC,) * 3, bc_hi=(PERIODIC,) * 3, cfl=0.4, steps=steps)
