@@ -175,7 +175,7 @@ def test_consistency_exact(oracle):
 def test_k0_is_rusanov(oracle):
     """p_0 = 1: F^ = (F_L + F_R)/2 - beta (U_R - U_L)/2, i.e. Rusanov with
     lambda_max = 1 (eq. iterat with k = 0), bit for bit."""
-    par = oracle.params(pvm_k=0)
+    par = oracle.params(pvm_k=0, beta_mode=0)
     VL = I.random_prims(14, 2000); VR = I.random_prims(15, 2000)
     tl = np.random.default_rng(0).uniform(0, 5, 2000); tr = np.random.default_rng(1).uniform(0, 5, 2000)
     for d in range(3):
@@ -234,7 +234,7 @@ def test_free_streaming_face_is_upwind(oracle):
 
 def test_beta_limits(oracle):
     """eq. beta: beta = min(1/tau_L, 1/tau_R, 1) multiplies the viscous term."""
-    par0 = oracle.params(pvm_k=0)
+    par0 = oracle.params(pvm_k=0, beta_mode=0)
     VL = I.random_prims(17, 10); VR = I.random_prims(18, 10)
     UL, UR = oracle.p2c(VL, par0), oracle.p2c(VR, par0)
     FL, FR = oracle.flux(VL, 0, par0), oracle.flux(VR, 0, par0)
