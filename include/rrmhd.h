@@ -1,0 +1,171 @@
+/*
+ * rrmhd.h -- C ABI of the MI355X (gfx950) library for one IMEX step of
+ * relativistic radiation magnetohydrodynamics under the gray M1 closure with
+ * the Jacobian-free PVM-int Riemann solver (Lopez-Miralles, Marti & Perucho,
+ * "On the application of Jacobian-free Riemann solvers for relativistic
+ * radiation magnetohydrodynamics under M1 closure", CPC, arXiv 2212.00370).
+ *
+ * Conventions for every entry point:
+ *   - Array pointers marked "device" are HIP device pointers owned by the
+ *     caller; the library never allocates, frees or retains device memory
+ *     beyond the caller-provided workspace (see rrmhd_init).
+ *   - State arrays are structure-of-arrays float64: variable q of cell c is at
+ *     U[q * var_stride + c], cells numbered i + n0 * (j + n1 * k) (x fastest).
+ *     Conserved order (Section 2.1, vector U):
+ *       0 D, 1..3 S^j, 4 tau_e, 5..7 B^j, 8 E_r, 9..11 F_r^j
+ *     Primitive order (Section 2.1, vector V):
+ *       0 rho, 1..3 v^j, 4 p, 5..7 B^j, 8 E_r, 9..11 F_r^j
+ *     Units: c = 1, 1/sqrt(4 pi) absorbed in B.
+ *   - Work is enqueued on the stream given to rrmhd_init and the call returns
+ *     without waiting, except where a call says it synchronizes. Argument and
+ *     launch errors are returned directly; numerical failures (primitive
+ *     recovery, implicit solve, non-finite values) are counted on the device
+ *     and read with rrmhd_report_sync.
+ *   - A context is used by one host thread at a time. Error strings are
+ *     static.
+ */
+#ifndef RRMHD_H
+#define RRMHD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { RRMHD_NVAR = 12 };
+
+typedef enum {
+  RRMHD_OK = 0,
+  RRMHD_E_INVALID = -1,    /* bad argument (null pointer, size mismatch, bad option) */
+  RRMHD_E_C2P = -2,        /* primitive recovery failed in at least one cell (report) */
+  RRMHD_E_IMPLICIT = -3,   /* implicit source solve failed in at least one cell     */
+  RRMHD_E_NONFINITE = -4,  /* a non-finite value was produced                       */
+  RRMHD_E_DEVICE = -5,     /* a HIP call or kernel launch failed                    */
+  RRMHD_E_WORKSPACE = -6   /* workspace null, too small or misaligned               */
+} rrmhd_status;
+
+typedef enum { RRMHD_BC_PERIODIC = 0, RRMHD_BC_OUTFLOW = 1, RRMHD_BC_INFLOW = 2 } rrmhd_bc;
+enum { RRMHD_RECON_GODUNOV = 0, RRMHD_RECON_MINMOD = 1 };
+enum { RRMHD_BETA_ALL = 0, RRMHD_BETA_RAD_ONLY = 1, RRMHD_BETA_OFF = 2 };
+enum { RRMHD_IMP_PICARD_NEWTON = 0, RRMHD_IMP_NEWTON = 1, RRMHD_IMP_PICARD = 2 };
+enum { RRMHD_FP64 = 0 };
+
+/* Cartesian grid of interior cells (Section 3.1: finite volumes, cell
+ * averages). Cells outside the domain are not stored: periodic boundaries
+ * wrap, outflow copies the nearest interior cell (zero gradient), inflow
+ * (allowed only on the lo side of the last axis) takes inflow_U where
+ * inflow_mask is set and copies elsewhere. */
+typedef struct {
+  int ndim;                         /* 1, 2 or 3                                          */
+  int n[3];                         /* interior cells per axis; unused axes must be 1     */
+  double dx[3];                     /* cell sizes                                         */
+  int bc_lo[3], bc_hi[3];           /* rrmhd_bc per axis side                             */
+  long long var_stride;             /* elements between variable planes, >= n0*n1*n2     */
+  const double* inflow_U;           /* device [12][transverse cells], conserved; or NULL  */
+  const unsigned char* inflow_mask; /* device [transverse cells]; or NULL                 */
+} rrmhd_grid;
+
+/* Method parameters. rrmhd_default_params fills the values used by the
+ * paper's scheme (PVM-int-8, eps = 1e-8, PLM MinMod, IMEX RK2 analogue). */
+typedef struct {
+  double gamma;     /* ideal-gas index (eq. eos)                                       */
+  double a_rad;     /* radiation constant a_R; 4 pi B = a_R T^4                        */
+  double t_coeff;   /* T = t_coeff * p / rho                                           */
+  double pvm_eps;   /* finite-difference step of the Jacobian-free chain (1e-8)        */
+  double c2p_tol;   /* relative Newton tolerance of primitive recovery                 */
+  double imp_tol;   /* relative tolerance of the implicit radiation solve              */
+  double rho_floor; /* state substituted (and counted) where recovery fails            */
+  double p_floor;
+  int pvm_k;        /* internal polynomial p_k, degree 2^k, k = 0..4 (3: PVM-int-8)     */
+  int beta_mode;    /* RRMHD_BETA_*: which rows the opacity factor beta scales          */
+  int recon;        /* RRMHD_RECON_*                                                    */
+  int rk_order;     /* 2: SSP-RK2 analogue of the paper's scheme; 3: the paper's RK3    */
+  int c2p_maxit;
+  int imp_maxit;
+  int imp_picard_it;/* Picard iterations before Newton (eq. C^(m) iteration)            */
+  int imp_method;   /* RRMHD_IMP_*                                                      */
+  int precision;    /* RRMHD_FP64                                                       */
+} rrmhd_params;
+
+/* Gray comoving opacities per unit mass (eqs. g0, gi): device arrays [ncell]
+ * (x fastest, plain cell count stride) or NULL to use the uniform value. */
+typedef struct {
+  const double* kappa;
+  const double* sigma;
+  double kappa0, sigma0;
+} rrmhd_opacities;
+
+/* Failure counters accumulated on the device since init or the last
+ * rrmhd_report_sync. first_bad_cell is the smallest failing cell index or
+ * -1. max_*_it are the largest iteration counts seen. */
+typedef struct {
+  long long c2p_fail, pvm_fallback, imp_fail, nonfinite;
+  long long first_bad_cell;
+  int max_c2p_it, max_imp_it;
+} rrmhd_report;
+
+typedef struct rrmhd_ctx rrmhd_ctx;
+
+/* Fill *p with the default parameters. */
+void rrmhd_default_params(rrmhd_params* p);
+
+/* Bytes of device workspace rrmhd_init needs for this grid and these
+ * parameters (stage state, primitives, face fluxes, reduction scratch,
+ * counters). Returns 0 for an invalid grid. */
+size_t rrmhd_workspace_bytes(const rrmhd_grid* g, const rrmhd_params* p);
+
+/* Create a context. `workspace` is caller-owned device memory of at least
+ * rrmhd_workspace_bytes(g, p) bytes, 256-byte aligned, used exclusively by
+ * this context until rrmhd_destroy. `hip_stream` is a hipStream_t (NULL: the
+ * default stream). Allocates a small pinned host buffer; zeroes the counters
+ * (enqueued). Errors: RRMHD_E_INVALID, RRMHD_E_WORKSPACE, RRMHD_E_DEVICE. */
+rrmhd_status rrmhd_init(rrmhd_ctx** ctx, const rrmhd_grid* g, const rrmhd_params* p,
+                        void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Primitive -> conserved map of eq. eqU on every cell of the context's grid.
+ * V, U: device, [12][var_stride]. Enqueued. */
+rrmhd_status rrmhd_prim_to_cons(rrmhd_ctx* ctx, const double* V, double* U);
+
+/* Conserved -> primitive recovery (the inversion used in the PVM algorithm and
+ * the implicit step) on every cell. Failing cells get the floor state and are
+ * counted. U, V: device, [12][var_stride]. Enqueued. */
+rrmhd_status rrmhd_cons_to_prim(rrmhd_ctx* ctx, const double* U, double* V);
+
+/* One IMEX step of size dt (Section 3.1: explicit stage with the PVM-int
+ * face fluxes of Section 3.2, eq. explicit, then the implicit solve of
+ * Section 3.3, eq. impliciteq; stages of the SSP RK pattern). U: device
+ * [12][var_stride], updated in place. g must describe the context's grid
+ * (same ndim and n; dx and boundaries are taken from g). Enqueued; on a
+ * numerical failure the failing cells keep their explicit state and the
+ * counters say which. */
+rrmhd_status rrmhd_step(rrmhd_ctx* ctx, double* U, const rrmhd_grid* g, double dt,
+                        const rrmhd_opacities* opac);
+
+/* Largest signal speed over all cells and directions (fluid fast-speed bound
+ * and the M1 eigenvalues of eqs. lam1-lam3), capped at 1. Synchronizes the
+ * stream and writes the value to *smax_host. */
+rrmhd_status rrmhd_max_speed(rrmhd_ctx* ctx, const double* U, const rrmhd_grid* g,
+                             double* smax_host);
+
+/* Diagnostic: the face fluxes of the first stage for state U (recovery,
+ * reconstruction and PVM-int flux, Section 3.2). Fh: device, the directions
+ * one after another, each [12][faces_d] with faces_d = prod(n) with n_d + 1
+ * along d, face i along d between cells i-1 and i, x fastest. Enqueued. */
+rrmhd_status rrmhd_face_fluxes(rrmhd_ctx* ctx, const double* U, const rrmhd_opacities* opac,
+                               double* Fh);
+
+/* Read the failure counters (synchronizes the stream) and reset them. */
+rrmhd_status rrmhd_report_sync(rrmhd_ctx* ctx, rrmhd_report* out);
+
+/* Release the context (not the workspace, which the caller owns). */
+void rrmhd_destroy(rrmhd_ctx* ctx);
+
+/* Static description of a status code. */
+const char* rrmhd_strerror(rrmhd_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RRMHD_H */

@@ -1,0 +1,755 @@
+// Host driver, kernels and C ABI of the RRMHD + M1 hot path on gfx950.
+//
+// One IMEX step (Section 3.1 of Lopez-Miralles, Marti & Perucho, CPC,
+// arXiv 2212.00370) is, per Runge-Kutta stage:
+//   k_prims   : cell primitive recovery of the stage state -> V, D(kappa+sigma)
+//   k_faces<d>: per face, PLM MinMod + PVM-int flux (Section 3.2) -> F^_d
+//   k_update  : U* = a0 U^(0) + a1 U^(s) - c dt sum_d dF^_d/dx_d (eq. explicit)
+//               followed by the per-cell implicit source solve (Section 3.3)
+// All kernels read and write structure-of-arrays float64 planes in HBM; one
+// thread owns one face or one cell, so the step is race-free and needs no
+// floating-point atomics. The CFL speed uses a per-block maximum in LDS and a
+// second single-block pass (deterministic, no memset).
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "rrmhd.h"
+#include "rrmhd_device.hpp"
+
+using rr::NV;
+using rr::Phys;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+
+struct DevReport {
+  unsigned long long c2p_fail, pvm_fallback, imp_fail, nonfinite;
+  unsigned long long first_bad;
+  unsigned int max_c2p_it, max_imp_it;
+  unsigned int pad[2];
+};
+
+// Grid description used on the device.
+struct GridDev {
+  int ndim;
+  int n[3];
+  int bc_lo[3], bc_hi[3];
+  long long N;              // interior cells
+  long long nt;             // transverse cells of the inflow face (0 if none)
+  const unsigned char* mask;
+};
+
+struct Opac {
+  const double* kappa;
+  const double* sigma;
+  double kappa0, sigma0;
+};
+
+__device__ __forceinline__ double opac_at(const double* a, double uni, long long c) {
+  return a ? a[c] : uni;
+}
+
+__device__ __forceinline__ unsigned int wave_max_u32(unsigned int v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const unsigned int w = __shfl_xor(v, o, kWave);
+    v = (w > v) ? w : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    const unsigned long long w = __shfl_xor(v, o, kWave);
+    v = (w < v) ? w : v;
+  }
+  return v;
+}
+
+// Accumulate per-thread failure flags into the device report: one atomic per
+// wave and field, and only when the wave saw something.
+__device__ __forceinline__ void report_add(DevReport* rep, unsigned long long f_c2p,
+                                           unsigned long long f_pvm, unsigned long long f_imp,
+                                           unsigned long long f_nf, unsigned long long bad_cell,
+                                           unsigned int c2p_it, unsigned int imp_it) {
+  const unsigned long long s_c2p = wave_sum_u64(f_c2p);
+  const unsigned long long s_pvm = wave_sum_u64(f_pvm);
+  const unsigned long long s_imp = wave_sum_u64(f_imp);
+  const unsigned long long s_nf = wave_sum_u64(f_nf);
+  const unsigned long long s_bad = wave_min_u64(bad_cell);
+  const unsigned int m_c2p = wave_max_u32(c2p_it);
+  const unsigned int m_imp = wave_max_u32(imp_it);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (s_c2p) atomicAdd(&rep->c2p_fail, s_c2p);
+    if (s_pvm) atomicAdd(&rep->pvm_fallback, s_pvm);
+    if (s_imp) atomicAdd(&rep->imp_fail, s_imp);
+    if (s_nf) atomicAdd(&rep->nonfinite, s_nf);
+    if (s_bad != ULLONG_MAX) atomicMin(&rep->first_bad, s_bad);
+    if (m_c2p) atomicMax(&rep->max_c2p_it, m_c2p);
+    if (m_imp) atomicMax(&rep->max_imp_it, m_imp);
+  }
+}
+
+// Map cell coordinates (c[d] possibly outside [0, n_d)) to an index into the
+// stage primitives: interior cells 0..N-1, inflow cells N + t.
+__device__ __forceinline__ long long map_cell(const GridDev& G, int c0, int c1, int c2, int d) {
+  int c[3] = {c0, c1, c2};
+  const int nd = G.n[d];
+  int cd = c[d];
+  if (cd < 0) {
+    const int bc = G.bc_lo[d];
+    if (bc == RRMHD_BC_PERIODIC) {
+      cd = ((cd % nd) + nd) % nd;
+    } else if (bc == RRMHD_BC_INFLOW) {
+      const long long t = (d == 0) ? 0 : ((d == 1) ? (long long)c[0] : (long long)c[0] + (long long)G.n[0] * c[1]);
+      if (G.mask && G.mask[t]) return G.N + t;
+      cd = 0;
+    } else {
+      cd = 0;
+    }
+  } else if (cd >= nd) {
+    cd = (G.bc_hi[d] == RRMHD_BC_PERIODIC) ? (cd % nd) : (nd - 1);
+  }
+  c[d] = cd;
+  return (long long)c[0] + (long long)G.n[0] * ((long long)c[1] + (long long)G.n[1] * c[2]);
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_p2c(long long n, const double* __restrict__ V, long long sv,
+                                                double* __restrict__ U, long long su, Phys K) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double v[NV], u[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = V[q * sv + c];
+  rr::Aux a;
+  rr::prim_aux(v, K, a);
+  rr::p2c(v, a, u);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) U[q * su + c] = u[q];
+}
+
+__global__ void __launch_bounds__(kBlock) k_c2p(long long n, const double* __restrict__ U, long long su,
+                                                double* __restrict__ V, long long sv, Phys K, DevReport* rep) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long fail = 0, bad = ULLONG_MAX;
+  unsigned int its = 0;
+  if (c < n) {
+    double u[NV], v[NV], Z = 0.0;
+    int it = 0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) u[q] = U[q * su + c];
+    if (rr::c2p(u, K, 0.0, v, Z, it) != 0) {
+      rr::c2p_fallback(u, K, v);
+      fail = 1;
+      bad = (unsigned long long)c;
+    }
+    its = (unsigned int)it;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) V[q * sv + c] = v[q];
+  }
+  report_add(rep, fail, 0, 0, 0, bad, its, 0);
+}
+
+// Stage primitives: interior cells (c < N) from U, inflow cells from inflow_U.
+// Vp: [12][Np], taup: [Np] = D (kappa + sigma).
+__global__ void __launch_bounds__(kBlock) k_prims(GridDev G, const double* __restrict__ U, long long su,
+                                                  const double* __restrict__ inU, Opac op,
+                                                  double* __restrict__ Vp, double* __restrict__ taup,
+                                                  long long np, Phys K, DevReport* rep) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long fail = 0, bad = ULLONG_MAX;
+  unsigned int its = 0;
+  if (c < G.N + G.nt) {
+    double u[NV], v[NV], Z = 0.0;
+    int it = 0;
+    long long oc;  // cell whose opacity applies
+    if (c < G.N) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) u[q] = U[q * su + c];
+      oc = c;
+    } else {
+      const long long t = c - G.N;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) u[q] = inU[q * G.nt + t];
+      oc = (G.ndim == 1) ? 0 : t;
+    }
+    if (rr::c2p(u, K, 0.0, v, Z, it) != 0) {
+      rr::c2p_fallback(u, K, v);
+      if (c < G.N) { fail = 1; bad = (unsigned long long)c; }
+    }
+    if (c < G.N) its = (unsigned int)it;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Vp[q * np + c] = v[q];
+    taup[c] = u[0] * (opac_at(op.kappa, op.kappa0, oc) + opac_at(op.sigma, op.sigma0, oc));
+  }
+  report_add(rep, fail, 0, 0, 0, bad, its, 0);
+}
+
+template <int d>
+__global__ void __launch_bounds__(kBlock) k_faces(GridDev G, const double* __restrict__ Vp,
+                                                  const double* __restrict__ taup, long long np,
+                                                  double dxd, double* __restrict__ Fh, long long nf,
+                                                  Phys K, DevReport* rep) {
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long fb = 0;
+  unsigned int its = 0;
+  if (f < nf) {
+    int fn0 = G.n[0], fn1 = G.n[1];
+    if (d == 0) fn0 += 1;
+    if (d == 1) fn1 += 1;
+    int c[3];
+    c[0] = (int)(f % fn0);
+    c[1] = (int)((f / fn0) % fn1);
+    c[2] = (int)(f / ((long long)fn0 * fn1));
+    double Vs[4][NV];
+    double tp[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      int cc[3] = {c[0], c[1], c[2]};
+      cc[d] = c[d] - 2 + s;
+      const long long m = map_cell(G, cc[0], cc[1], cc[2], d);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) Vs[s][q] = Vp[q * np + m];
+      tp[s] = taup[m];
+    }
+    double sa[NV], sb[NV];
+    rr::cell_slopes(Vs[0], Vs[1], Vs[2], K.recon, sa);
+    rr::cell_slopes(Vs[1], Vs[2], Vs[3], K.recon, sb);
+    double VL[NV], VR[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) { VL[q] = Vs[1][q] + 0.5 * sa[q]; VR[q] = Vs[2][q] - 0.5 * sb[q]; }
+    rr::limit_rad_flux(VL);
+    rr::limit_rad_flux(VR);
+    const double tauL = tp[1] * dxd, tauR = tp[2] * dxd;
+    double Fq[NV];
+    int fallback = 0, cit = 0;
+    rr::pvm_face<d>(VL, VR, tauL, tauR, K, Fq, fallback, cit);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Fh[q * nf + f] = Fq[q];
+    fb = (unsigned long long)fallback;
+    its = (unsigned int)cit;
+  }
+  report_add(rep, 0, fb, 0, 0, ULLONG_MAX, its, 0);
+}
+
+struct StageArgs {
+  const double* U0;
+  long long s0;
+  const double* Us;
+  long long ss;
+  double* Uo;
+  long long so;
+  const double* Fh[3];
+  long long nf[3];
+  double idx[3];
+  double a0, a1, cdt;
+};
+
+__global__ void __launch_bounds__(kBlock) k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
+  unsigned int its = 0;
+  if (c < G.N) {
+    const int ci[3] = {(int)(c % G.n[0]), (int)((c / G.n[0]) % G.n[1]), (int)(c / ((long long)G.n[0] * G.n[1]))};
+    long long fm[3], fs[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int fn0 = G.n[0], fn1 = G.n[1];
+      if (d == 0) fn0 += 1;
+      if (d == 1) fn1 += 1;
+      fm[d] = (long long)ci[0] + (long long)fn0 * ((long long)ci[1] + (long long)fn1 * ci[2]);
+      fs[d] = (d == 0) ? 1 : ((d == 1) ? (long long)fn0 : (long long)fn0 * fn1);
+    }
+    double Ust[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double div = (A.Fh[0][q * A.nf[0] + fm[0] + fs[0]] - A.Fh[0][q * A.nf[0] + fm[0]]) * A.idx[0];
+      if (G.ndim > 1) div = div + (A.Fh[1][q * A.nf[1] + fm[1] + fs[1]] - A.Fh[1][q * A.nf[1] + fm[1]]) * A.idx[1];
+      if (G.ndim > 2) div = div + (A.Fh[2][q * A.nf[2] + fm[2] + fs[2]] - A.Fh[2][q * A.nf[2] + fm[2]]) * A.idx[2];
+      Ust[q] = (A.a0 * A.U0[q * A.s0 + c] + A.a1 * A.Us[q * A.ss + c]) - A.cdt * div;
+    }
+    double Un[NV];
+    int it = 0;
+    const int st = rr::implicit_cell(Ust, A.cdt, opac_at(op.kappa, op.kappa0, c),
+                                     opac_at(op.sigma, op.sigma0, c), K, Un, it);
+    bool fin = true;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      A.Uo[q * A.so + c] = Un[q];
+      fin = fin && isfinite(Un[q]);
+    }
+    if (st != 0) fimp = 1;
+    if (!fin) fnf = 1;
+    if (st != 0 || !fin) bad = (unsigned long long)c;
+    its = (unsigned int)it;
+  }
+  report_add(rep, 0, 0, fimp, fnf, bad, 0, its);
+}
+
+// Per-block maximum of the cell signal speeds -> partial[blockIdx.x].
+__global__ void __launch_bounds__(kBlock) k_speed(GridDev G, const double* __restrict__ U, long long su,
+                                                  Phys K, double* __restrict__ partial, DevReport* rep) {
+  __shared__ double red[kBlock / kWave];
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  unsigned long long fail = 0, bad = ULLONG_MAX;
+  if (c < G.N) {
+    double u[NV], v[NV], Z = 0.0;
+    int it = 0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) u[q] = U[q * su + c];
+    if (rr::c2p(u, K, 0.0, v, Z, it) != 0) {
+      rr::c2p_fallback(u, K, v);
+      fail = 1;
+      bad = (unsigned long long)c;
+    }
+    rr::Aux a;
+    rr::prim_aux(v, K, a);
+    s = rr::dmax(s, rr::cell_speed<0>(v, a, K));
+    if (G.ndim > 1) s = rr::dmax(s, rr::cell_speed<1>(v, a, K));
+    if (G.ndim > 2) s = rr::dmax(s, rr::cell_speed<2>(v, a, K));
+  }
+  report_add(rep, fail, 0, 0, 0, bad, 0, 0);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) s = rr::dmax(s, __shfl_xor(s, o, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / kWave; ++w) m = rr::dmax(m, red[w]);
+    partial[blockIdx.x] = m;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_reduce_max(const double* __restrict__ partial, long long n,
+                                                       double* __restrict__ out) {
+  __shared__ double red[kBlock / kWave];
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) s = rr::dmax(s, partial[i]);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) s = rr::dmax(s, __shfl_xor(s, o, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / kWave; ++w) m = rr::dmax(m, red[w]);
+    out[0] = rr::dmin(m, 1.0);
+  }
+}
+
+__global__ void k_report_reset(DevReport* rep) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    rep->c2p_fail = 0; rep->pvm_fallback = 0; rep->imp_fail = 0; rep->nonfinite = 0;
+    rep->first_bad = ULLONG_MAX;
+    rep->max_c2p_it = 0; rep->max_imp_it = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+long long grid_cells(const rrmhd_grid* g) {
+  return (long long)g->n[0] * g->n[1] * g->n[2];
+}
+
+long long transverse_cells(const rrmhd_grid* g) {
+  const int dl = g->ndim - 1;
+  long long nt = 1;
+  for (int e = 0; e < g->ndim; ++e)
+    if (e != dl) nt *= g->n[e];
+  return nt;
+}
+
+bool grid_valid(const rrmhd_grid* g) {
+  if (!g || g->ndim < 1 || g->ndim > 3) return false;
+  for (int e = 0; e < 3; ++e) {
+    if (g->n[e] < 1) return false;
+    if (e >= g->ndim && g->n[e] != 1) return false;
+    if (e < g->ndim) {
+      if (!(g->dx[e] > 0.0)) return false;
+      for (int bc : {g->bc_lo[e], g->bc_hi[e]})
+        if (bc < RRMHD_BC_PERIODIC || bc > RRMHD_BC_INFLOW) return false;
+      if (g->bc_hi[e] == RRMHD_BC_INFLOW) return false;
+      if (g->bc_lo[e] == RRMHD_BC_INFLOW && e != g->ndim - 1) return false;
+      if ((g->bc_lo[e] == RRMHD_BC_PERIODIC) != (g->bc_hi[e] == RRMHD_BC_PERIODIC)) return false;
+    }
+  }
+  const long long N = grid_cells(g);
+  if (N > (1LL << 40)) return false;
+  if (g->var_stride < N) return false;
+  if (g->bc_lo[g->ndim - 1] == RRMHD_BC_INFLOW && (!g->inflow_U || !g->inflow_mask)) return false;
+  return true;
+}
+
+bool params_valid(const rrmhd_params* p) {
+  if (!p) return false;
+  if (!(p->gamma > 1.0 && p->gamma <= 2.0)) return false;
+  if (!(p->a_rad >= 0.0) || !(p->t_coeff > 0.0)) return false;
+  if (!(p->pvm_eps > 0.0)) return false;
+  if (p->pvm_k < 0 || p->pvm_k > 4) return false;
+  if (p->beta_mode < 0 || p->beta_mode > 2) return false;
+  if (p->recon < 0 || p->recon > 1) return false;
+  if (p->rk_order != 2 && p->rk_order != 3) return false;
+  if (p->c2p_maxit < 1 || p->imp_maxit < 1 || p->imp_picard_it < 0) return false;
+  if (p->imp_method < 0 || p->imp_method > 2) return false;
+  if (!(p->c2p_tol > 0.0) || !(p->imp_tol > 0.0)) return false;
+  if (p->precision != RRMHD_FP64) return false;
+  return true;
+}
+
+// Coefficients of the internal polynomial approximation of |x| (eq. iterat):
+// q_0(y) = 1, q_k(y) = q_{k-1}(y) - q_{k-1}(y)^2 / 2 + y / 2 with y = x^2.
+// Dyadic rationals: exact in binary64 for k <= 4.
+int internal_coefficients(int k, double out[rr::MAXCOEF]) {
+  double q[rr::MAXCOEF] = {1.0};
+  for (int m = 1; m < rr::MAXCOEF; ++m) q[m] = 0.0;
+  int deg = 0;
+  for (int step = 0; step < k; ++step) {
+    double sq[rr::MAXCOEF];
+    for (int m = 0; m < rr::MAXCOEF; ++m) sq[m] = 0.0;
+    for (int a = 0; a <= deg; ++a)
+      for (int b = 0; b <= deg; ++b) sq[a + b] += q[a] * q[b];
+    const int ndeg = (deg == 0) ? 1 : 2 * deg;
+    for (int m = 0; m <= ndeg; ++m) q[m] = q[m] - 0.5 * sq[m];
+    q[1] += 0.5;
+    deg = ndeg;
+  }
+  for (int m = 0; m < rr::MAXCOEF; ++m) out[m] = q[m];
+  return (k == 0) ? 0 : deg;
+}
+
+Phys make_phys(const rrmhd_params* p) {
+  Phys K;
+  std::memset(&K, 0, sizeof(K));
+  K.gamma = p->gamma;
+  K.g1 = p->gamma / (p->gamma - 1.0);
+  K.gm1g = (p->gamma - 1.0) / p->gamma;
+  K.gm1 = p->gamma - 1.0;
+  K.a_rad = p->a_rad;
+  K.t_coeff = p->t_coeff;
+  K.eps = p->pvm_eps;
+  K.ieps = 1.0 / p->pvm_eps;
+  K.c2p_tol = p->c2p_tol;
+  K.imp_tol = p->imp_tol;
+  K.rho_floor = p->rho_floor;
+  K.p_floor = p->p_floor;
+  K.c2p_maxit = p->c2p_maxit;
+  K.imp_maxit = p->imp_maxit;
+  K.imp_picard_it = p->imp_picard_it;
+  K.imp_method = p->imp_method;
+  K.beta_mode = p->beta_mode;
+  K.recon = p->recon;
+  K.M = internal_coefficients(p->pvm_k, K.coef);
+  return K;
+}
+
+struct Layout {
+  long long N, nt, Np, Ns;
+  long long nf[3];
+  long long npartial;
+  size_t off_Vp, off_taup, off_Us, off_Fh[3], off_partial, off_smax, off_rep, total;
+};
+
+Layout make_layout(const rrmhd_grid* g) {
+  Layout L;
+  std::memset(&L, 0, sizeof(L));
+  L.N = grid_cells(g);
+  L.nt = (g->bc_lo[g->ndim - 1] == RRMHD_BC_INFLOW) ? transverse_cells(g) : 0;
+  L.Np = (L.N + L.nt + 31) / 32 * 32;
+  L.Ns = (L.N + 31) / 32 * 32;
+  for (int d = 0; d < 3; ++d) {
+    if (d < g->ndim) {
+      long long nf = 1;
+      for (int e = 0; e < 3; ++e) nf *= (e == d) ? (g->n[e] + 1) : g->n[e];
+      L.nf[d] = nf;
+    }
+  }
+  L.npartial = (L.N + kBlock - 1) / kBlock;
+  size_t o = 0;
+  L.off_Vp = o; o = align256(o + sizeof(double) * NV * L.Np);
+  L.off_taup = o; o = align256(o + sizeof(double) * L.Np);
+  L.off_Us = o; o = align256(o + sizeof(double) * NV * L.Ns);
+  for (int d = 0; d < 3; ++d) { L.off_Fh[d] = o; o = align256(o + sizeof(double) * NV * L.nf[d]); }
+  L.off_partial = o; o = align256(o + sizeof(double) * L.npartial);
+  L.off_smax = o; o = align256(o + sizeof(double));
+  L.off_rep = o; o = align256(o + sizeof(DevReport));
+  L.total = o;
+  return L;
+}
+
+GridDev make_griddev(const rrmhd_grid* g, const Layout& L) {
+  GridDev G;
+  G.ndim = g->ndim;
+  for (int e = 0; e < 3; ++e) { G.n[e] = g->n[e]; G.bc_lo[e] = g->bc_lo[e]; G.bc_hi[e] = g->bc_hi[e]; }
+  G.N = L.N;
+  G.nt = L.nt;
+  G.mask = g->inflow_mask;
+  return G;
+}
+
+unsigned int nblocks(long long n) { return (unsigned int)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+struct rrmhd_ctx {
+  rrmhd_grid grid;
+  rrmhd_params par;
+  Phys K;
+  Layout L;
+  char* ws;
+  double* Vp;
+  double* taup;
+  double* Us;
+  double* Fh[3];
+  double* partial;
+  double* smax;
+  DevReport* rep;
+  hipStream_t stream;
+  void* host;  // pinned: DevReport + one double
+};
+
+namespace {
+
+rrmhd_status launch_ok() {
+  return (hipGetLastError() == hipSuccess) ? RRMHD_OK : RRMHD_E_DEVICE;
+}
+
+bool same_shape(const rrmhd_ctx* c, const rrmhd_grid* g) {
+  if (!g) return false;
+  if (g->ndim != c->grid.ndim) return false;
+  for (int e = 0; e < 3; ++e) if (g->n[e] != c->grid.n[e]) return false;
+  return true;
+}
+
+Opac make_opac(const rrmhd_opacities* o) {
+  Opac op;
+  op.kappa = o ? o->kappa : nullptr;
+  op.sigma = o ? o->sigma : nullptr;
+  op.kappa0 = o ? o->kappa0 : 0.0;
+  op.sigma0 = o ? o->sigma0 : 0.0;
+  return op;
+}
+
+// Stage primitives and face fluxes of state Us (stride ss) into `out[d]`.
+rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, long long ss,
+                          const Opac& op, double* const out[3]) {
+  const Layout& L = c->L;
+  const GridDev G = make_griddev(g, L);
+  k_prims<<<nblocks(L.N + L.nt), kBlock, 0, c->stream>>>(G, Us, ss, g->inflow_U, op, c->Vp, c->taup,
+                                                           L.Np, c->K, c->rep);
+  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  for (int d = 0; d < g->ndim; ++d) {
+    const unsigned int nb = nblocks(L.nf[d]);
+    if (d == 0) k_faces<0><<<nb, kBlock, 0, c->stream>>>(G, c->Vp, c->taup, L.Np, g->dx[0], out[0], L.nf[0], c->K, c->rep);
+    if (d == 1) k_faces<1><<<nb, kBlock, 0, c->stream>>>(G, c->Vp, c->taup, L.Np, g->dx[1], out[1], L.nf[1], c->K, c->rep);
+    if (d == 2) k_faces<2><<<nb, kBlock, 0, c->stream>>>(G, c->Vp, c->taup, L.Np, g->dx[2], out[2], L.nf[2], c->K, c->rep);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  }
+  return RRMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rrmhd_default_params(rrmhd_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->gamma = 5.0 / 3.0;
+  p->a_rad = 1.0;
+  p->t_coeff = 1.0;
+  p->pvm_eps = 1e-8;
+  p->c2p_tol = 1e-12;
+  p->imp_tol = 1e-13;
+  p->rho_floor = 1e-12;
+  p->p_floor = 1e-12;
+  p->pvm_k = 3;
+  p->beta_mode = RRMHD_BETA_RAD_ONLY;
+  p->recon = RRMHD_RECON_MINMOD;
+  p->rk_order = 2;
+  p->c2p_maxit = 100;
+  p->imp_maxit = 50;
+  p->imp_picard_it = 8;
+  p->imp_method = RRMHD_IMP_PICARD_NEWTON;
+  p->precision = RRMHD_FP64;
+}
+
+size_t rrmhd_workspace_bytes(const rrmhd_grid* g, const rrmhd_params* p) {
+  if (!grid_valid(g) || !params_valid(p)) return 0;
+  return make_layout(g).total;
+}
+
+rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params* p, void* workspace,
+                        size_t ws_bytes, void* hip_stream) {
+  if (!out) return RRMHD_E_INVALID;
+  *out = nullptr;
+  if (!grid_valid(g) || !params_valid(p)) return RRMHD_E_INVALID;
+  const Layout L = make_layout(g);
+  if (!workspace || ws_bytes < L.total || ((uintptr_t)workspace & 255u) != 0) return RRMHD_E_WORKSPACE;
+  rrmhd_ctx* c = new (std::nothrow) rrmhd_ctx;
+  if (!c) return RRMHD_E_DEVICE;
+  c->grid = *g;
+  c->par = *p;
+  c->K = make_phys(p);
+  c->L = L;
+  c->ws = (char*)workspace;
+  c->Vp = (double*)(c->ws + L.off_Vp);
+  c->taup = (double*)(c->ws + L.off_taup);
+  c->Us = (double*)(c->ws + L.off_Us);
+  for (int d = 0; d < 3; ++d) c->Fh[d] = (double*)(c->ws + L.off_Fh[d]);
+  c->partial = (double*)(c->ws + L.off_partial);
+  c->smax = (double*)(c->ws + L.off_smax);
+  c->rep = (DevReport*)(c->ws + L.off_rep);
+  c->stream = (hipStream_t)hip_stream;
+  c->host = nullptr;
+  if (hipHostMalloc(&c->host, sizeof(DevReport) + sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return RRMHD_E_DEVICE;
+  }
+  k_report_reset<<<1, 64, 0, c->stream>>>(c->rep);
+  if (launch_ok() != RRMHD_OK) {
+    hipHostFree(c->host);
+    delete c;
+    return RRMHD_E_DEVICE;
+  }
+  *out = c;
+  return RRMHD_OK;
+}
+
+rrmhd_status rrmhd_prim_to_cons(rrmhd_ctx* c, const double* V, double* U) {
+  if (!c || !V || !U) return RRMHD_E_INVALID;
+  const long long N = c->L.N, s = c->grid.var_stride;
+  if (N == 0) return RRMHD_OK;
+  k_p2c<<<nblocks(N), kBlock, 0, c->stream>>>(N, V, s, U, s, c->K);
+  return launch_ok();
+}
+
+rrmhd_status rrmhd_cons_to_prim(rrmhd_ctx* c, const double* U, double* V) {
+  if (!c || !V || !U) return RRMHD_E_INVALID;
+  const long long N = c->L.N, s = c->grid.var_stride;
+  if (N == 0) return RRMHD_OK;
+  k_c2p<<<nblocks(N), kBlock, 0, c->stream>>>(N, U, s, V, s, c->K, c->rep);
+  return launch_ok();
+}
+
+rrmhd_status rrmhd_face_fluxes(rrmhd_ctx* c, const double* U, const rrmhd_opacities* opac, double* Fh) {
+  if (!c || !U || !Fh) return RRMHD_E_INVALID;
+  double* out[3] = {Fh, nullptr, nullptr};
+  for (int d = 1; d < c->grid.ndim; ++d) out[d] = out[d - 1] + NV * c->L.nf[d - 1];
+  return stage_fluxes(c, &c->grid, U, c->grid.var_stride, make_opac(opac), out);
+}
+
+rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt, const rrmhd_opacities* opac) {
+  if (!c || !U || !same_shape(c, g) || !grid_valid(g)) return RRMHD_E_INVALID;
+  if (!(dt >= 0.0) || !(dt < 1e300)) return RRMHD_E_INVALID;
+  const Layout& L = c->L;
+  const GridDev G = make_griddev(g, L);
+  const Opac op = make_opac(opac);
+  const long long vs = g->var_stride;
+  // Stage coefficients (a0, a1, c) of U* = a0 U^(0) + a1 U^(s) + c dt L(U^(s)).
+  double co[3][3];
+  int ns;
+  if (c->par.rk_order == 3) {
+    const double t[3][3] = {{1.0, 0.0, 1.0}, {0.75, 0.25, 0.25}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
+    std::memcpy(co, t, sizeof(t));
+    ns = 3;
+  } else {
+    const double t[3][3] = {{1.0, 0.0, 1.0}, {0.5, 0.5, 0.5}, {0.0, 0.0, 0.0}};
+    std::memcpy(co, t, sizeof(t));
+    ns = 2;
+  }
+  double* const fl[3] = {c->Fh[0], c->Fh[1], c->Fh[2]};
+  for (int s = 0; s < ns; ++s) {
+    const double* Us = (s == 0) ? U : c->Us;
+    const long long ss = (s == 0) ? vs : L.Ns;
+    const rrmhd_status st = stage_fluxes(c, g, Us, ss, op, fl);
+    if (st != RRMHD_OK) return st;
+    StageArgs A;
+    A.U0 = U; A.s0 = vs;
+    A.Us = Us; A.ss = ss;
+    const bool last = (s == ns - 1);
+    A.Uo = last ? U : c->Us;
+    A.so = last ? vs : L.Ns;
+    for (int d = 0; d < 3; ++d) {
+      A.Fh[d] = (d < g->ndim) ? c->Fh[d] : c->Fh[0];
+      A.nf[d] = (d < g->ndim) ? L.nf[d] : 0;
+      A.idx[d] = (d < g->ndim) ? 1.0 / g->dx[d] : 0.0;
+    }
+    A.a0 = co[s][0];
+    A.a1 = co[s][1];
+    A.cdt = co[s][2] * dt;
+    k_update<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  }
+  return RRMHD_OK;
+}
+
+rrmhd_status rrmhd_max_speed(rrmhd_ctx* c, const double* U, const rrmhd_grid* g, double* smax_host) {
+  if (!c || !U || !smax_host || !same_shape(c, g)) return RRMHD_E_INVALID;
+  const Layout& L = c->L;
+  const GridDev G = make_griddev(g, L);
+  k_speed<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, U, g->var_stride, c->K, c->partial, c->rep);
+  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  k_reduce_max<<<1, kBlock, 0, c->stream>>>(c->partial, L.npartial, c->smax);
+  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  double* h = (double*)((char*)c->host + sizeof(DevReport));
+  if (hipMemcpyAsync(h, c->smax, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return RRMHD_E_DEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return RRMHD_E_DEVICE;
+  *smax_host = *h;
+  return RRMHD_OK;
+}
+
+rrmhd_status rrmhd_report_sync(rrmhd_ctx* c, rrmhd_report* out) {
+  if (!c || !out) return RRMHD_E_INVALID;
+  DevReport* h = (DevReport*)c->host;
+  if (hipMemcpyAsync(h, c->rep, sizeof(DevReport), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return RRMHD_E_DEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return RRMHD_E_DEVICE;
+  out->c2p_fail = (long long)h->c2p_fail;
+  out->pvm_fallback = (long long)h->pvm_fallback;
+  out->imp_fail = (long long)h->imp_fail;
+  out->nonfinite = (long long)h->nonfinite;
+  out->first_bad_cell = (h->first_bad == ULLONG_MAX) ? -1 : (long long)h->first_bad;
+  out->max_c2p_it = (int)h->max_c2p_it;
+  out->max_imp_it = (int)h->max_imp_it;
+  k_report_reset<<<1, 64, 0, c->stream>>>(c->rep);
+  return launch_ok();
+}
+
+void rrmhd_destroy(rrmhd_ctx* c) {
+  if (!c) return;
+  hipStreamSynchronize(c->stream);
+  if (c->host) hipHostFree(c->host);
+  delete c;
+}
+
+const char* rrmhd_strerror(rrmhd_status s) {
+  switch (s) {
+    case RRMHD_OK: return "ok";
+    case RRMHD_E_INVALID: return "invalid argument";
+    case RRMHD_E_C2P: return "primitive recovery failed";
+    case RRMHD_E_IMPLICIT: return "implicit source solve failed";
+    case RRMHD_E_NONFINITE: return "non-finite value";
+    case RRMHD_E_DEVICE: return "HIP device error";
+    case RRMHD_E_WORKSPACE: return "workspace missing, too small or misaligned";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

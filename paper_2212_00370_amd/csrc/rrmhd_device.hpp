@@ -1,0 +1,705 @@
+// Device physics of the RRMHD + M1 hot path for gfx950 (HIP).
+//
+// Per-cell and per-face functions of the scheme of Lopez-Miralles, Marti &
+// Perucho (CPC, arXiv 2212.00370): primitive/conserved maps (eq. eqU),
+// fluxes (eq. eqF), the M1 closure (eq. xi), primitive recovery, PLM MinMod
+// reconstruction, the Jacobian-free PVM-int face flux with the opacity factor
+// beta (Section 3.2, eq. beta) and the implicit radiation-matter solve
+// (Section 3.3, eqs. g0, gi).
+//
+// Floating point: every expression is evaluated in the order written (the
+// library is compiled with -ffp-contract=off, no fast-math). The same fixed
+// evaluation order is used by the CPU reference the tests compare against, so
+// that the eps = 1e-8 finite-difference chain of the PVM flux, which
+// amplifies rounding by 1/eps, yields identical results. Division and sqrt
+// are the correctly rounded IEEE operations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace rr {
+
+constexpr int NV = 12;
+constexpr int MAXCOEF = 17;
+
+// Per-run constants, passed by value to every kernel.
+struct Phys {
+  double gamma, g1, gm1g, gm1;  // gamma, gamma/(gamma-1), (gamma-1)/gamma, gamma-1
+  double a_rad, t_coeff;
+  double eps, ieps;             // PVM finite-difference step and its reciprocal
+  double c2p_tol, imp_tol;
+  double rho_floor, p_floor;
+  int c2p_maxit, imp_maxit, imp_picard_it, imp_method;
+  int beta_mode, recon, M;      // M = 2^(k-1) Horner steps (0 for k = 0)
+  double coef[MAXCOEF];         // p_k coefficients of x^(2m)
+};
+
+__device__ __forceinline__ double dabs(double a) { return (a < 0.0) ? -a : a; }
+__device__ __forceinline__ double dmax(double a, double b) { return (a > b) ? a : b; }
+__device__ __forceinline__ double dmin(double a, double b) { return (a < b) ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Quantities derived from primitives (definitions after eqs. eqU/eqF):
+// W, b^0 = W v.B, b^i = B^i/W + v^i b^0, |b|^2 = B^2/W^2 + (v.B)^2,
+// rho h* W^2 with rho h* = rho + gamma/(gamma-1) p + |b|^2, p* = p + |b|^2/2.
+struct Aux {
+  double W, iW, l2, b0, b[3], bb, wtot, ps, D;
+};
+
+__device__ __forceinline__ void prim_aux(const double V[NV], const Phys& K, Aux& a) {
+  const double vx = V[1], vy = V[2], vz = V[3];
+  const double v2 = (vx * vx + vy * vy) + vz * vz;
+  a.l2 = 1.0 - v2;
+  a.iW = sqrt(a.l2);
+  a.W = 1.0 / a.iW;
+  const double vB = (vx * V[5] + vy * V[6]) + vz * V[7];
+  a.b0 = a.W * vB;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) a.b[j] = V[5 + j] * a.iW + V[1 + j] * a.b0;
+  const double B2 = (V[5] * V[5] + V[6] * V[6]) + V[7] * V[7];
+  a.bb = B2 * a.l2 + vB * vB;
+  const double rhoh = V[0] + K.g1 * V[4];
+  a.wtot = (rhoh + a.bb) * (a.W * a.W);
+  a.ps = V[4] + 0.5 * a.bb;
+  a.D = V[0] * a.W;
+}
+
+// eq. eqU
+__device__ __forceinline__ void p2c(const double V[NV], const Aux& a, double U[NV]) {
+  U[0] = a.D;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) U[1 + j] = a.wtot * V[1 + j] - a.b0 * a.b[j];
+  U[4] = ((a.wtot - a.ps) - a.b0 * a.b0) - a.D;
+#pragma unroll
+  for (int q = 5; q < NV; ++q) U[q] = V[q];
+}
+
+// Row d of the M1 radiation pressure P = D_r E_r (eq. xi); n n := 0 when F = 0.
+template <int d>
+__device__ __forceinline__ void m1_row(double E, const double F[3], double P[3]) {
+  const double FF = (F[0] * F[0] + F[1] * F[1]) + F[2] * F[2];
+  const double f2 = FF / (E * E);
+  double t = 4.0 - 3.0 * f2;
+  t = (t > 0.0) ? t : 0.0;
+  const double s = sqrt(t);
+  const double xi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * s);
+  const double ca = 0.5 * (1.0 - xi);
+  const double cb = 0.5 * (3.0 * xi - 1.0);
+  if (FF > 0.0) {
+    const double iFF = 1.0 / FF;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double nn = (F[d] * F[j]) * iFF;
+      P[j] = (j == d) ? E * (ca + cb * nn) : E * (cb * nn);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) P[j] = (j == d) ? E * ca : 0.0;
+  }
+}
+
+// eq. eqF in direction d.
+template <int d>
+__device__ __forceinline__ void flux(const double V[NV], const Aux& a, double F[NV]) {
+  const double vd = V[1 + d];
+  F[0] = a.D * vd;
+  const double wv = a.wtot * vd;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if (j == d) F[1 + j] = (wv * V[1 + j] + a.ps) - a.b[d] * a.b[j];
+    else        F[1 + j] = wv * V[1 + j] - a.b[d] * a.b[j];
+  }
+  F[4] = (wv - a.b0 * a.b[d]) - a.D * vd;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) F[5 + j] = vd * V[5 + j] - V[5 + d] * V[1 + j];
+  F[8] = V[9 + d];
+  m1_row<d>(V[8], &V[9], &F[9]);
+}
+
+// ---------------------------------------------------------------------------
+// Primitive recovery: bracketed Newton on Z = rho h W^2 (closed relations of
+// eq. eqU): v^2(Z) = [S^2 + (S.B/Z)^2 (2Z + B^2)]/(Z + B^2)^2,
+// p = (gamma-1)/gamma (Z/W^2 - D/W),
+// f(Z) = Z + B^2 - p - B^2/(2W^2) - (S.B)^2/(2Z^2) - (tau + D).
+// Bracket [D, gamma (tau + D)]; v^2 >= 1 or p <= 0 counts as f < 0; a Newton
+// iterate outside the bracket (or a non-positive slope) is replaced by
+// bisection. Converged when |dZ| <= tol Z.
+struct C2PIn {
+  double D, S[3], B[3], Et, B2, S2, SB;
+};
+
+struct C2PEval {
+  bool ok;
+  double l2, iW, rho, p, vB, iZb, f, df;
+};
+
+template <bool WANT_DF>
+__device__ __forceinline__ C2PEval c2p_eval(double Z, const C2PIn& in, const Phys& K) {
+  C2PEval e;
+  const double Zb = Z + in.B2;
+  const double iZ = 1.0 / Z;
+  e.iZb = 1.0 / Zb;
+  e.vB = in.SB * iZ;
+  const double vB2 = e.vB * e.vB;
+  const double v2 = (in.S2 + vB2 * (Z + Zb)) * (e.iZb * e.iZb);
+  e.ok = false;
+  e.l2 = 0.0; e.iW = 0.0; e.rho = 0.0; e.p = 0.0; e.f = 0.0; e.df = 0.0;
+  if (!(v2 < 1.0)) return e;
+  e.l2 = 1.0 - v2;
+  e.iW = sqrt(e.l2);
+  e.rho = in.D * e.iW;
+  e.p = K.gm1g * (Z * e.l2 - e.rho);
+  if (!(e.p > 0.0)) return e;
+  e.ok = true;
+  if (!WANT_DF) return e;
+  e.f = (((Z + in.B2) - e.p) - 0.5 * (in.B2 * e.l2)) - (0.5 * vB2 + in.Et);
+  const double dv2 = -2.0 * (in.S2 + (vB2 * (3.0 * (Z * Zb) + in.B2 * in.B2)) * iZ) *
+                     ((e.iZb * e.iZb) * e.iZb);
+  const double W = 1.0 / e.iW;
+  const double dp = K.gm1g * (e.l2 + dv2 * (0.5 * (in.D * W) - Z));
+  e.df = ((1.0 - dp) + 0.5 * (in.B2 * dv2)) + vB2 * iZ;
+  return e;
+}
+
+// Returns 0 on success. Zguess > 0 warm-starts; otherwise the rest-frame
+// estimate gamma (E - B^2/2) - (gamma - 1) D is used.
+__device__ __forceinline__ int c2p(const double U[NV], const Phys& K, double Zguess, double V[NV],
+                                   double& Zout, int& nit) {
+  C2PIn in;
+  in.D = U[0];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) { in.S[j] = U[1 + j]; in.B[j] = U[5 + j]; }
+  in.Et = U[4] + U[0];
+  in.B2 = (in.B[0] * in.B[0] + in.B[1] * in.B[1]) + in.B[2] * in.B[2];
+  in.S2 = (in.S[0] * in.S[0] + in.S[1] * in.S[1]) + in.S[2] * in.S[2];
+  in.SB = (in.S[0] * in.B[0] + in.S[1] * in.B[1]) + in.S[2] * in.B[2];
+#pragma unroll
+  for (int q = 5; q < NV; ++q) V[q] = U[q];
+  nit = 0;
+  if (!(in.D > 0.0) || !isfinite(in.Et) || !isfinite(in.S2) || !isfinite(in.B2)) return 1;
+  double lo = in.D;
+  double hi = K.gamma * in.Et;
+  if (!(hi > lo)) return 1;
+  double Z;
+  if (Zguess > 0.0 && Zguess > lo && Zguess < hi) {
+    Z = Zguess;
+  } else {
+    Z = K.gamma * (in.Et - 0.5 * in.B2) - K.gm1 * in.D;
+    if (!(Z > lo && Z < hi)) Z = 0.5 * (lo + hi);
+  }
+  bool conv = false;
+  int it = 0;
+  while (it < K.c2p_maxit) {
+    ++it;
+    const C2PEval e = c2p_eval<true>(Z, in, K);
+    double Zn;
+    if (!e.ok) {
+      lo = Z;
+      Zn = 0.5 * (lo + hi);
+    } else {
+      if (e.f == 0.0) { conv = true; break; }
+      if (e.f > 0.0) hi = Z; else lo = Z;
+      Zn = Z - e.f / e.df;
+      if (!(e.df > 0.0) || !(Zn > lo && Zn < hi)) Zn = 0.5 * (lo + hi);
+    }
+    const double dZ = dabs(Zn - Z);
+    Z = Zn;
+    if (dZ <= K.c2p_tol * Z) { conv = true; break; }
+  }
+  nit = it;
+  if (!conv) return 2;
+  const C2PEval e = c2p_eval<false>(Z, in, K);
+  if (!e.ok) return 3;
+  V[0] = e.rho;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) V[1 + j] = (in.S[j] + e.vB * in.B[j]) * e.iZb;
+  V[4] = e.p;
+  Zout = Z;
+  return 0;
+}
+
+__device__ __forceinline__ void c2p_fallback(const double U[NV], const Phys& K, double V[NV]) {
+  V[0] = (U[0] > 0.0) ? U[0] : K.rho_floor;
+  V[1] = 0.0; V[2] = 0.0; V[3] = 0.0;
+  V[4] = K.p_floor;
+#pragma unroll
+  for (int q = 5; q < NV; ++q) V[q] = U[q];
+}
+
+// Recovery of an intermediate PVM state: reuse V_m when the fluid part of U
+// equals U_m's bit for bit (recovery depends on it only), else warm-start.
+__device__ __forceinline__ bool recover_near(const double U[NV], const double Um[NV],
+                                             const double Vm[NV], double Zm, const Phys& K,
+                                             double V[NV], int& nit) {
+  bool same = true;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) same = same && (U[q] == Um[q]);
+  if (same) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) V[q] = Vm[q];
+#pragma unroll
+    for (int q = 5; q < NV; ++q) V[q] = U[q];
+    nit = 0;
+    return true;
+  }
+  double Z = 0.0;
+  return c2p(U, K, Zm, V, Z, nit) == 0;
+}
+
+// ---------------------------------------------------------------------------
+// PLM MinMod with the Godunov fallback for |v|^2 >= 1 and the |F_r| <= E_r
+// limit (Section 3.2, reconstruction).
+__device__ __forceinline__ double minmod(double a, double b) {
+  if ((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0)) return (dabs(a) < dabs(b)) ? a : b;
+  return 0.0;
+}
+
+__device__ __forceinline__ void cell_slopes(const double Vm[NV], const double Vc[NV],
+                                            const double Vp[NV], int recon, double s[NV]) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) s[q] = (recon == 1) ? minmod(Vc[q] - Vm[q], Vp[q] - Vc[q]) : 0.0;
+  if (recon == 1) {
+    double lo[3], hi[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) { lo[j] = Vc[1 + j] - 0.5 * s[1 + j]; hi[j] = Vc[1 + j] + 0.5 * s[1 + j]; }
+    const double v2lo = (lo[0] * lo[0] + lo[1] * lo[1]) + lo[2] * lo[2];
+    const double v2hi = (hi[0] * hi[0] + hi[1] * hi[1]) + hi[2] * hi[2];
+    if (!(v2lo < 1.0) || !(v2hi < 1.0)) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) s[q] = 0.0;
+    }
+  }
+}
+
+__device__ __forceinline__ void limit_rad_flux(double V[NV]) {
+  const double FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
+  if (FF > V[8] * V[8]) {
+    const double r = V[8] / sqrt(FF);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[9 + j] = V[9 + j] * r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian-free PVM-int face flux (Section 3.2, PVM algorithm; eq. beta).
+// Y(w) = [F(U_m + F(U_m + eps w) - F(U_m)) - F(U_m)] / eps ~ A(U_m)^2 w;
+// Horner over x^2 gives U_M ~ p_k(A) U_0; F^ = (F_L + F_R)/2 - beta U_M / 2.
+// A failed intermediate recovery drops the face to p_0 = 1 (Rusanov).
+template <int d>
+__device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV], double tauL,
+                                         double tauR, const Phys& K, double Fh[NV],
+                                         int& fallback, int& c2p_its) {
+  double UL[NV], UR[NV], FL[NV], FR[NV];
+  {
+    Aux aL;
+    prim_aux(VL, K, aL);
+    p2c(VL, aL, UL);
+    flux<d>(VL, aL, FL);
+  }
+  {
+    Aux aR;
+    prim_aux(VR, K, aR);
+    p2c(VR, aR, UR);
+    flux<d>(VR, aR, FR);
+  }
+  double U0[NV], Um[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) { U0[q] = UR[q] - UL[q]; Um[q] = 0.5 * (UL[q] + UR[q]); }
+  const double beta = 1.0 / dmax(dmax(tauL, tauR), 1.0);
+  fallback = 0;
+  c2p_its = 0;
+  double w[NV];
+  bool ok = true;
+  if (K.M == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) w[q] = U0[q];
+  } else {
+    double Vm[NV], Zm = 0.0;
+    int it = 0;
+    if (c2p(Um, K, 0.0, Vm, Zm, it) != 0) ok = false;
+    c2p_its += it;
+    double Fm[NV];
+    if (ok) {
+      Aux am;
+      prim_aux(Vm, K, am);
+      flux<d>(Vm, am, Fm);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) Fm[q] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) w[q] = U0[q];
+    for (int l = 0; l < K.M && ok; ++l) {
+      double Ue[NV], Ve[NV], Fe[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) Ue[q] = Um[q] + K.eps * w[q];
+      if (!recover_near(Ue, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
+      c2p_its += it;
+      {
+        Aux ae;
+        prim_aux(Ve, K, ae);
+        flux<d>(Ve, ae, Fe);
+      }
+      double Ut[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) Ut[q] = Um[q] + (Fe[q] - Fm[q]);
+      if (!recover_near(Ut, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
+      c2p_its += it;
+      {
+        Aux at;
+        prim_aux(Ve, K, at);
+        flux<d>(Ve, at, Fe);
+      }
+      const double cnext = K.coef[K.M - 1 - l];
+      if (l == 0) {
+        const double ctop = K.coef[K.M];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) w[q] = ctop * ((Fe[q] - Fm[q]) * K.ieps) + cnext * U0[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) w[q] = (Fe[q] - Fm[q]) * K.ieps + cnext * U0[q];
+      }
+    }
+    if (!ok) {
+      fallback = 1;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) w[q] = U0[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double bq = (K.beta_mode == 2 || (K.beta_mode == 1 && q < 8)) ? 1.0 : beta;
+    Fh[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * (bq * w[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4x4 Gaussian elimination with partial pivoting (first maximum wins), all
+// indices static so the matrix stays in registers.
+__device__ __forceinline__ bool solve4(double A[4][4], double b[4], double x[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int piv = k;
+    double amax = dabs(A[k][k]);
+#pragma unroll
+    for (int i = k + 1; i < 4; ++i)
+      if (dabs(A[i][k]) > amax) { amax = dabs(A[i][k]); piv = i; }
+    if (!(amax > 0.0)) return false;
+#pragma unroll
+    for (int i = k + 1; i < 4; ++i) {
+      if (piv == i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { const double t = A[k][j]; A[k][j] = A[i][j]; A[i][j] = t; }
+        const double t = b[k]; b[k] = b[i]; b[i] = t;
+      }
+    }
+#pragma unroll
+    for (int i = k + 1; i < 4; ++i) {
+      const double l = A[i][k] / A[k][k];
+#pragma unroll
+      for (int j = k + 1; j < 4; ++j) A[i][j] = A[i][j] - l * A[k][j];
+      b[i] = b[i] - l * b[k];
+    }
+  }
+#pragma unroll
+  for (int i = 3; i >= 0; --i) {
+    double s = b[i];
+#pragma unroll
+    for (int j = i + 1; j < 4; ++j) s = s - A[i][j] * x[j];
+    x[i] = s / A[i][i];
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Implicit radiation-matter step (Section 3.3). X = (E_r, F_r); the fluid
+// follows from recovery of (D, S_t - F_r, tau_t - E_r, B). The backward-Euler
+// system from eqs. g0/gi reads C(X) X = b(X) with
+//   C11 = 1 - h rho W [-kappa + sigma (W^2 - 1 + u.D.u)]
+//   C1j = -h rho u_j [kappa - sigma (2W^2 - 1)]
+//   Ci1 = -h rho [(kappa + sigma)(D.u)_i + sigma u_i (W^2 + u.D.u)]
+//   Cij = delta_ij + h rho W [(kappa + sigma) delta_ij + 2 sigma u_i u_j]
+//   b   = (E* + h rho W kappa a T^4, F*_i + h rho u_i kappa a T^4)
+// (Cij with the sign that follows from eq. gi).
+struct ImpSys {
+  double C[4][4];
+  double b[4];
+  double Z;
+};
+
+__device__ __forceinline__ bool imp_build(const double X[4], const double Ul[NV], double Et,
+                                          const double St[3], double h, double kap, double sig,
+                                          const Phys& K, double Zg, ImpSys& sy, int& c2p_it) {
+  double Uf[NV], Vf[NV];
+  Uf[0] = Ul[0];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Uf[1 + j] = St[j] - X[1 + j];
+  Uf[4] = Et - X[0];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Uf[5 + j] = Ul[5 + j];
+  Uf[8] = X[0];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Uf[9 + j] = X[1 + j];
+  int it = 0;
+  double Z = 0.0;
+  if (c2p(Uf, K, Zg, Vf, Z, it) != 0) { c2p_it += it; return false; }
+  c2p_it += it;
+  sy.Z = Z;
+  const double rho = Vf[0], p = Vf[4];
+  const double v2 = (Vf[1] * Vf[1] + Vf[2] * Vf[2]) + Vf[3] * Vf[3];
+  const double iW = sqrt(1.0 - v2);
+  const double W = 1.0 / iW;
+  double u[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) u[j] = W * Vf[1 + j];
+  const double T = (K.t_coeff * p) / rho;
+  const double T2 = T * T;
+  const double aT4 = K.a_rad * (T2 * T2);
+  const double E = X[0];
+  const double F[3] = {X[1], X[2], X[3]};
+  const double FF = (F[0] * F[0] + F[1] * F[1]) + F[2] * F[2];
+  const double f2 = FF / (E * E);
+  double t = 4.0 - 3.0 * f2;
+  t = (t > 0.0) ? t : 0.0;
+  const double xi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * sqrt(t));
+  const double ca = 0.5 * (1.0 - xi);
+  const double cb = 0.5 * (3.0 * xi - 1.0);
+  double Dm[3][3];
+  if (FF > 0.0) {
+    const double iFF = 1.0 / FF;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double nn = (F[i] * F[j]) * iFF;
+        Dm[i][j] = (i == j) ? ca + cb * nn : cb * nn;
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Dm[i][j] = (i == j) ? ca : 0.0;
+  }
+  double Du[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Du[i] = (Dm[i][0] * u[0] + Dm[i][1] * u[1]) + Dm[i][2] * u[2];
+  const double uDu = (u[0] * Du[0] + u[1] * Du[1]) + u[2] * Du[2];
+  const double W2 = W * W;
+  const double hr = h * rho;
+  const double hrW = hr * W;
+  const double ks = kap + sig;
+  sy.C[0][0] = 1.0 - hrW * (sig * ((W2 - 1.0) + uDu) - kap);
+  const double c1 = kap - sig * (2.0 * W2 - 1.0);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) sy.C[0][1 + j] = -((hr * u[j]) * c1);
+  const double c2 = sig * (W2 + uDu);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) sy.C[1 + i][0] = -(hr * (ks * Du[i] + c2 * u[i]));
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double g = 2.0 * ((sig * u[i]) * u[j]);
+      sy.C[1 + i][1 + j] = (i == j) ? 1.0 + hrW * (ks + g) : hrW * g;
+    }
+  const double em = (hr * kap) * aT4;
+  sy.b[0] = Ul[8] + W * em;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) sy.b[1 + i] = Ul[9 + i] + u[i] * em;
+  return true;
+}
+
+__device__ __forceinline__ void imp_residual(const ImpSys& sy, const double X[4], double R[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    R[i] = (((sy.C[i][0] * X[0] + sy.C[i][1] * X[1]) + sy.C[i][2] * X[2]) + sy.C[i][3] * X[3]) - sy.b[i];
+}
+
+__device__ __forceinline__ double vmaxabs4(const double a[4]) {
+  return dmax(dmax(dabs(a[0]), dabs(a[1])), dmax(dabs(a[2]), dabs(a[3])));
+}
+
+// Returns 0 on success; on failure Un = Us. The paper's Picard iteration
+// X^{m+1} = C(X^m)^{-1} b(X^m) from the explicit state X*, stopped once its
+// update grows; Newton on C(X) X - b(X) (forward-difference Jacobian, step
+// halving) from X* finishes where Picard did not converge. The |F_r| <= E_r
+// limit is applied to the explicit radiation state first (keeping S + F_r),
+// and to the result.
+__device__ __forceinline__ int implicit_cell(const double Us[NV], double h, double kap, double sig,
+                                             const Phys& K, double Un[NV], int& iters) {
+  const double Et = Us[4] + Us[8];
+  double St[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) St[j] = Us[1 + j] + Us[9 + j];
+  double Ul[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) Ul[q] = Us[q];
+  iters = 0;
+  if (!(Ul[8] > 0.0)) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Un[q] = Us[q];
+    return 1;
+  }
+  {
+    const double FF = (Ul[9] * Ul[9] + Ul[10] * Ul[10]) + Ul[11] * Ul[11];
+    if (FF > Ul[8] * Ul[8]) {
+      const double r = Ul[8] / sqrt(FF);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Ul[9 + j] = Ul[9 + j] * r;
+    }
+  }
+  double X[4] = {Ul[8], Ul[9], Ul[10], Ul[11]};
+  ImpSys sy;
+  double Zg = 0.0;
+  int it = 0;
+  int c2p_it = 0;
+  bool conv = false;
+  bool have = false;
+  const int npic = (K.imp_method == 1) ? 0 : ((K.imp_method == 2) ? K.imp_maxit : K.imp_picard_it);
+  const double Xg[4] = {X[0], X[1], X[2], X[3]};
+  double dlast = 0.0, dprev = 0.0;
+  for (int m = 0; m <= npic; ++m) {
+    if (!imp_build(X, Ul, Et, St, h, kap, sig, K, Zg, sy, c2p_it)) break;
+    Zg = sy.Z;
+    if (m == 0) have = true;
+    if (m > 0 && dlast <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
+    if (m == npic) break;
+    if (m > 1 && K.imp_method == 0 && dlast > dprev) break;
+    double A[4][4], bb[4], Xn[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bb[i] = sy.b[i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) A[i][j] = sy.C[i][j];
+    }
+    if (!solve4(A, bb, Xn)) break;
+    ++it;
+    if (!(Xn[0] > 0.0) || !isfinite(Xn[0]) || !isfinite(Xn[1]) || !isfinite(Xn[2]) || !isfinite(Xn[3])) break;
+    double dd[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { dd[i] = Xn[i] - X[i]; X[i] = Xn[i]; }
+    dprev = dlast;
+    dlast = vmaxabs4(dd);
+  }
+  if (!conv && have && K.imp_method != 2) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) X[i] = Xg[i];
+    Zg = 0.0;
+    double R[4];
+    if (imp_build(X, Ul, Et, St, h, kap, sig, K, Zg, sy, c2p_it)) {
+      Zg = sy.Z;
+      imp_residual(sy, X, R);
+      for (int n = 0; n < K.imp_maxit; ++n) {
+        ++it;
+        const double sc = vmaxabs4(X);
+        const double del = 1e-8 * sc;
+        double J[4][4];
+        bool okj = true;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (okj) {
+            double Xp[4] = {X[0], X[1], X[2], X[3]};
+            Xp[j] = Xp[j] + del;
+            ImpSys sp;
+            if (!imp_build(Xp, Ul, Et, St, h, kap, sig, K, Zg, sp, c2p_it)) {
+              okj = false;
+            } else {
+              double Rp[4];
+              imp_residual(sp, Xp, Rp);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) J[i][j] = (Rp[i] - R[i]) / del;
+            }
+          }
+        }
+        if (!okj) break;
+        double nR[4] = {-R[0], -R[1], -R[2], -R[3]}, dX[4];
+        if (!solve4(J, nR, dX)) break;
+        const double rn = vmaxabs4(R);
+        const double dn = vmaxabs4(dX);
+        double lam = 1.0;
+        bool acc = false;
+        double Xt[4], Rt[4];
+        ImpSys st;
+        for (int ls = 0; ls < 12; ++ls) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Xt[i] = X[i] + lam * dX[i];
+          if (Xt[0] > 0.0 && imp_build(Xt, Ul, Et, St, h, kap, sig, K, Zg, st, c2p_it)) {
+            imp_residual(st, Xt, Rt);
+            if (vmaxabs4(Rt) < rn || lam * dn <= 1e-10 * sc) { acc = true; break; }
+          }
+          lam = 0.5 * lam;
+        }
+        if (!acc) break;
+        double stp[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { stp[i] = Xt[i] - X[i]; X[i] = Xt[i]; R[i] = Rt[i]; }
+        Zg = st.Z;
+        if (vmaxabs4(stp) <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
+      }
+    }
+  }
+  iters = it;
+  if (!conv) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Un[q] = Us[q];
+    return 1;
+  }
+  const double FF = (X[1] * X[1] + X[2] * X[2]) + X[3] * X[3];
+  if (FF > X[0] * X[0]) {
+    const double r = X[0] / sqrt(FF);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) X[1 + j] = X[1 + j] * r;
+  }
+  Un[0] = Us[0];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Un[1 + j] = St[j] - X[1 + j];
+  Un[4] = Et - X[0];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Un[5 + j] = Us[5 + j];
+  Un[8] = X[0];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Un[9 + j] = X[1 + j];
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Signal speed bound of a cell in direction d: relativistic fast-speed bound
+// with a^2 = cs^2 + ca^2 - cs^2 ca^2 for the fluid, M1 eigenvalues
+// lambda_r1, lambda_r3 (eqs. lam1-lam3) for the radiation.
+template <int d>
+__device__ __forceinline__ double cell_speed(const double V[NV], const Aux& a, const Phys& K) {
+  const double rho = V[0], p = V[4];
+  const double rhoh = rho + K.g1 * p;
+  const double cs2 = (K.gamma * p) / rhoh;
+  const double ca2 = a.bb / (rhoh + a.bb);
+  const double a2 = (cs2 + ca2) - cs2 * ca2;
+  const double v2 = 1.0 - a.l2;
+  const double vd = V[1 + d];
+  const double den = 1.0 - v2 * a2;
+  double disc = (a2 * a.l2) * (den - (vd * vd) * (1.0 - a2));
+  disc = (disc > 0.0) ? disc : 0.0;
+  const double sq = sqrt(disc);
+  const double lp = (vd * (1.0 - a2) + sq) / den;
+  const double lm = (vd * (1.0 - a2) - sq) / den;
+  double s = dmax(dabs(lp), dabs(lm));
+  const double E = V[8];
+  const double FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
+  double f = 0.0, cth = 0.0;
+  if (FF > 0.0) {
+    const double Fn = sqrt(FF);
+    f = dmin(Fn / E, 1.0);
+    cth = V[9 + d] / Fn;
+  }
+  const double f2 = f * f;
+  const double r43 = 4.0 - 3.0 * f2;
+  const double sr = sqrt(r43);
+  double zz = (2.0 / 3.0) * (r43 - sr) + (2.0 * (cth * cth)) * ((2.0 - f2) - sr);
+  zz = (zz > 0.0) ? zz : 0.0;
+  const double zeta = sqrt(zz);
+  const double l1 = (f * cth - zeta) / sr;
+  const double l3 = (f * cth + zeta) / sr;
+  s = dmax(s, dmax(dabs(l1), dabs(l3)));
+  return s;
+}
+
+}  // namespace rr

@@ -1,0 +1,250 @@
+"""Thin ctypes binding of ``librrmhd.so`` (the C ABI declared in
+``include/rrmhd.h``). Argument marshalling only: every step of the method runs
+in the library's HIP kernels. PyTorch provides device memory and streams.
+
+There is no CPU fallback: importing this module raises if the library has not
+been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librrmhd.so")
+
+NVAR = 12
+RRMHD_OK, RRMHD_E_INVALID, RRMHD_E_C2P, RRMHD_E_IMPLICIT = 0, -1, -2, -3
+RRMHD_E_NONFINITE, RRMHD_E_DEVICE, RRMHD_E_WORKSPACE = -4, -5, -6
+BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
+RECON_GODUNOV, RECON_MINMOD = 0, 1
+BETA_ALL, BETA_RAD_ONLY, BETA_OFF = 0, 1, 2
+IMP_PICARD_NEWTON, IMP_NEWTON, IMP_PICARD = 0, 1, 2
+FP64 = 0
+
+
+class rrmhd_grid(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int), ("n", C.c_int * 3), ("dx", C.c_double * 3),
+        ("bc_lo", C.c_int * 3), ("bc_hi", C.c_int * 3), ("var_stride", C.c_longlong),
+        ("inflow_U", C.c_void_p), ("inflow_mask", C.c_void_p),
+    ]
+
+
+class rrmhd_params(C.Structure):
+    _fields_ = [
+        ("gamma", C.c_double), ("a_rad", C.c_double), ("t_coeff", C.c_double),
+        ("pvm_eps", C.c_double), ("c2p_tol", C.c_double), ("imp_tol", C.c_double),
+        ("rho_floor", C.c_double), ("p_floor", C.c_double),
+        ("pvm_k", C.c_int), ("beta_mode", C.c_int), ("recon", C.c_int), ("rk_order", C.c_int),
+        ("c2p_maxit", C.c_int), ("imp_maxit", C.c_int), ("imp_picard_it", C.c_int),
+        ("imp_method", C.c_int), ("precision", C.c_int),
+    ]
+
+
+class rrmhd_opacities(C.Structure):
+    _fields_ = [("kappa", C.c_void_p), ("sigma", C.c_void_p), ("kappa0", C.c_double), ("sigma0", C.c_double)]
+
+
+class rrmhd_report(C.Structure):
+    _fields_ = [
+        ("c2p_fail", C.c_longlong), ("pvm_fallback", C.c_longlong), ("imp_fail", C.c_longlong),
+        ("nonfinite", C.c_longlong), ("first_bad_cell", C.c_longlong),
+        ("max_c2p_it", C.c_int), ("max_imp_it", C.c_int),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# Exported symbols and their signatures (kept in the order of rrmhd.h).
+_vp, _ll, _d = C.c_void_p, C.c_longlong, C.c_double
+SIGNATURES = {
+    "rrmhd_default_params": ([_vp], None),
+    "rrmhd_workspace_bytes": ([_vp, _vp], C.c_size_t),
+    "rrmhd_init": ([_vp, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "rrmhd_prim_to_cons": ([_vp, _vp, _vp], C.c_int),
+    "rrmhd_cons_to_prim": ([_vp, _vp, _vp], C.c_int),
+    "rrmhd_step": ([_vp, _vp, _vp, _d, _vp], C.c_int),
+    "rrmhd_max_speed": ([_vp, _vp, _vp, _vp], C.c_int),
+    "rrmhd_face_fluxes": ([_vp, _vp, _vp, _vp], C.c_int),
+    "rrmhd_report_sync": ([_vp, _vp], C.c_int),
+    "rrmhd_destroy": ([_vp], None),
+    "rrmhd_strerror": ([C.c_int], C.c_char_p),
+}
+
+
+def load(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not built: run paper_2212_00370_amd.build.build() "
+                          "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    lib = C.CDLL(path)
+    for name, (args, res) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = load()
+
+
+class RRMHDError(RuntimeError):
+    pass
+
+
+def _check(st: int, what: str) -> None:
+    if st != RRMHD_OK:
+        raise RRMHDError(f"{what}: {_lib.rrmhd_strerror(st).decode()} ({st})")
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+# ---- entry points, same names as the C ABI --------------------------------------
+def rrmhd_default_params(**overrides) -> rrmhd_params:
+    p = rrmhd_params()
+    _lib.rrmhd_default_params(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def rrmhd_workspace_bytes(grid: rrmhd_grid, params: rrmhd_params) -> int:
+    return int(_lib.rrmhd_workspace_bytes(C.byref(grid), C.byref(params)))
+
+
+def rrmhd_init(grid: rrmhd_grid, params: rrmhd_params, workspace, stream=None):
+    """workspace: a CUDA (HIP) uint8 tensor of at least rrmhd_workspace_bytes."""
+    ctx = C.c_void_p()
+    st = _lib.rrmhd_init(C.byref(ctx), C.byref(grid), C.byref(params), _ptr(workspace),
+                         workspace.numel() * workspace.element_size(),
+                         None if stream is None else C.c_void_p(stream.cuda_stream))
+    _check(st, "rrmhd_init")
+    return ctx
+
+
+def rrmhd_prim_to_cons(ctx, V, U) -> None:
+    _check(_lib.rrmhd_prim_to_cons(ctx, _ptr(V), _ptr(U)), "rrmhd_prim_to_cons")
+
+
+def rrmhd_cons_to_prim(ctx, U, V) -> None:
+    _check(_lib.rrmhd_cons_to_prim(ctx, _ptr(U), _ptr(V)), "rrmhd_cons_to_prim")
+
+
+def rrmhd_step(ctx, U, grid: rrmhd_grid, dt: float, opac: rrmhd_opacities) -> None:
+    _check(_lib.rrmhd_step(ctx, _ptr(U), C.byref(grid), float(dt), C.byref(opac)), "rrmhd_step")
+
+
+def rrmhd_max_speed(ctx, U, grid: rrmhd_grid) -> float:
+    out = C.c_double(0.0)
+    _check(_lib.rrmhd_max_speed(ctx, _ptr(U), C.byref(grid), C.byref(out)), "rrmhd_max_speed")
+    return out.value
+
+
+def rrmhd_face_fluxes(ctx, U, opac: rrmhd_opacities, Fh) -> None:
+    _check(_lib.rrmhd_face_fluxes(ctx, _ptr(U), C.byref(opac), _ptr(Fh)), "rrmhd_face_fluxes")
+
+
+def rrmhd_report_sync(ctx) -> dict:
+    r = rrmhd_report()
+    _check(_lib.rrmhd_report_sync(ctx, C.byref(r)), "rrmhd_report_sync")
+    return r.as_dict()
+
+
+def rrmhd_destroy(ctx) -> None:
+    _lib.rrmhd_destroy(ctx)
+
+
+def rrmhd_strerror(st: int) -> str:
+    return _lib.rrmhd_strerror(st).decode()
+
+
+# ---- helpers for building the C structs -------------------------------------------
+def make_grid(shape, dx, bc_lo=(BC_OUTFLOW,) * 3, bc_hi=(BC_OUTFLOW,) * 3, var_stride=None,
+              inflow_U=None, inflow_mask=None) -> rrmhd_grid:
+    g = rrmhd_grid()
+    g.ndim = len(shape)
+    n = list(shape) + [1] * (3 - len(shape))
+    dxs = list(dx) + [1.0] * (3 - len(dx))
+    for e in range(3):
+        g.n[e] = int(n[e]); g.dx[e] = float(dxs[e])
+        g.bc_lo[e] = int(bc_lo[e]); g.bc_hi[e] = int(bc_hi[e])
+    ncell = int(n[0] * n[1] * n[2])
+    g.var_stride = ncell if var_stride is None else int(var_stride)
+    g.inflow_U = _ptr(inflow_U)
+    g.inflow_mask = _ptr(inflow_mask)
+    g._keep = (inflow_U, inflow_mask)
+    return g
+
+
+def make_opacities(kappa=None, sigma=None, kappa0=0.0, sigma0=0.0) -> rrmhd_opacities:
+    o = rrmhd_opacities()
+    o.kappa = _ptr(kappa); o.sigma = _ptr(sigma)
+    o.kappa0 = float(kappa0); o.sigma0 = float(sigma0)
+    o._keep = (kappa, sigma)
+    return o
+
+
+class Solver:
+    """Device-resident state of one problem: U, opacities and workspace as torch
+    tensors on ``device``; each method is one C-ABI call."""
+
+    def __init__(self, grid: rrmhd_grid, params: rrmhd_params, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.grid = grid
+        self.params = params
+        self.device = torch.device(device)
+        nbytes = rrmhd_workspace_bytes(grid, params)
+        if nbytes == 0:
+            raise RRMHDError("invalid grid or parameters")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off: off + nbytes]
+        self.stream = stream
+        self.ctx = rrmhd_init(grid, params, self.ws, stream)
+
+    def close(self):
+        if self.ctx is not None:
+            rrmhd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prim_to_cons(self, V):
+        U = self.torch.empty_like(V)
+        rrmhd_prim_to_cons(self.ctx, V, U)
+        return U
+
+    def cons_to_prim(self, U):
+        V = self.torch.empty_like(U)
+        rrmhd_cons_to_prim(self.ctx, U, V)
+        return V
+
+    def step(self, U, dt, opac):
+        rrmhd_step(self.ctx, U, self.grid, dt, opac)
+
+    def max_speed(self, U):
+        return rrmhd_max_speed(self.ctx, U, self.grid)
+
+    def face_fluxes(self, U, opac):
+        sizes = []
+        n = [self.grid.n[e] for e in range(3)]
+        for d in range(self.grid.ndim):
+            m = list(n); m[d] += 1
+            sizes.append(m[0] * m[1] * m[2])
+        out = self.torch.empty(NVAR * sum(sizes), dtype=self.torch.float64, device=self.device)
+        rrmhd_face_fluxes(self.ctx, U, opac, out)
+        res, off = [], 0
+        for s in sizes:
+            res.append(out[off: off + NVAR * s].view(NVAR, s)); off += NVAR * s
+        return res
+
+    def report(self):
+        return rrmhd_report_sync(self.ctx)
