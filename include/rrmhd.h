@@ -155,6 +155,22 @@ rrmhd_status rrmhd_max_speed(rrmhd_ctx* ctx, const double* U, const rrmhd_grid* 
 rrmhd_status rrmhd_face_fluxes(rrmhd_ctx* ctx, const double* U, const rrmhd_opacities* opac,
                                double* Fh);
 
+/* Diagnostic kernel timing. While enabled, each launch of the library's
+ * kernels is bracketed by HIP events recorded on the context's stream (up to
+ * 8192 launches; further launches are not timed). Kernel classes:
+ * RRMHD_K_PRIMS (cell recovery), RRMHD_K_FACES (reconstruction + PVM-int face
+ * flux), RRMHD_K_UPDATE (flux divergence + implicit solve), RRMHD_K_SPEED
+ * (signal speeds). Enabling clears earlier records. Allocates host-side event
+ * objects only. */
+enum { RRMHD_K_PRIMS = 0, RRMHD_K_FACES = 1, RRMHD_K_UPDATE = 2, RRMHD_K_SPEED = 3, RRMHD_K_COUNT = 4 };
+rrmhd_status rrmhd_profile_enable(rrmhd_ctx* ctx, int enable);
+
+/* Totals of the timed launches of kernel class k since enabling: summed
+ * event time in ms, number of launches and work units (cells or faces)
+ * those launches processed. Synchronizes on the last recorded event. */
+rrmhd_status rrmhd_profile_read(rrmhd_ctx* ctx, int k, double* total_ms, long long* launches,
+                                long long* units);
+
 /* Read the failure counters (synchronizes the stream) and reset them. */
 rrmhd_status rrmhd_report_sync(rrmhd_ctx* ctx, rrmhd_report* out);
 

@@ -16,6 +16,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "rrmhd.h"
 #include "rrmhd_device.hpp"
@@ -523,9 +524,31 @@ struct rrmhd_ctx {
   DevReport* rep;
   hipStream_t stream;
   void* host;  // pinned: DevReport + one double
+  // Diagnostic timing (rrmhd_profile_*).
+  bool prof;
+  std::vector<hipEvent_t> ev;   // pairs: start, stop
+  std::vector<int> ev_kind;
+  std::vector<long long> ev_units;
+  int ev_used;
 };
 
 namespace {
+
+constexpr int kMaxTimed = 8192;
+
+// Record the start event of a timed launch; returns the pair index or -1.
+int prof_begin(rrmhd_ctx* c, int kind, long long units) {
+  if (!c->prof || c->ev_used >= kMaxTimed) return -1;
+  const int i = c->ev_used++;
+  c->ev_kind[i] = kind;
+  c->ev_units[i] = units;
+  hipEventRecord(c->ev[2 * i], c->stream);
+  return i;
+}
+
+void prof_end(rrmhd_ctx* c, int i) {
+  if (i >= 0) hipEventRecord(c->ev[2 * i + 1], c->stream);
+}
 
 rrmhd_status launch_ok() {
   return (hipGetLastError() == hipSuccess) ? RRMHD_OK : RRMHD_E_DEVICE;
@@ -552,14 +575,18 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
                           const Opac& op, double* const out[3]) {
   const Layout& L = c->L;
   const GridDev G = make_griddev(g, L);
+  int pe = prof_begin(c, RRMHD_K_PRIMS, L.N + L.nt);
   k_prims<<<nblocks(L.N + L.nt), kBlock, 0, c->stream>>>(G, Us, ss, g->inflow_U, op, c->Vp, c->taup,
                                                            L.Np, c->K, c->rep);
+  prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   for (int d = 0; d < g->ndim; ++d) {
     const unsigned int nb = nblocks(L.nf[d]);
+    pe = prof_begin(c, RRMHD_K_FACES, L.nf[d]);
     if (d == 0) k_faces<0><<<nb, kBlock, 0, c->stream>>>(G, c->Vp, c->taup, L.Np, g->dx[0], out[0], L.nf[0], c->K, c->rep);
     if (d == 1) k_faces<1><<<nb, kBlock, 0, c->stream>>>(G, c->Vp, c->taup, L.Np, g->dx[1], out[1], L.nf[1], c->K, c->rep);
     if (d == 2) k_faces<2><<<nb, kBlock, 0, c->stream>>>(G, c->Vp, c->taup, L.Np, g->dx[2], out[2], L.nf[2], c->K, c->rep);
+    prof_end(c, pe);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   }
   return RRMHD_OK;
@@ -619,6 +646,8 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   c->rep = (DevReport*)(c->ws + L.off_rep);
   c->stream = (hipStream_t)hip_stream;
   c->host = nullptr;
+  c->prof = false;
+  c->ev_used = 0;
   if (hipHostMalloc(&c->host, sizeof(DevReport) + sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return RRMHD_E_DEVICE;
@@ -695,7 +724,9 @@ rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt,
     A.a0 = co[s][0];
     A.a1 = co[s][1];
     A.cdt = co[s][2] * dt;
+    const int pe = prof_begin(c, RRMHD_K_UPDATE, L.N);
     k_update<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep);
+    prof_end(c, pe);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   }
   return RRMHD_OK;
@@ -705,7 +736,9 @@ rrmhd_status rrmhd_max_speed(rrmhd_ctx* c, const double* U, const rrmhd_grid* g,
   if (!c || !U || !smax_host || !same_shape(c, g)) return RRMHD_E_INVALID;
   const Layout& L = c->L;
   const GridDev G = make_griddev(g, L);
+  const int pe = prof_begin(c, RRMHD_K_SPEED, L.N);
   k_speed<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, U, g->var_stride, c->K, c->partial, c->rep);
+  prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   k_reduce_max<<<1, kBlock, 0, c->stream>>>(c->partial, L.npartial, c->smax);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
@@ -732,9 +765,42 @@ rrmhd_status rrmhd_report_sync(rrmhd_ctx* c, rrmhd_report* out) {
   return launch_ok();
 }
 
+rrmhd_status rrmhd_profile_enable(rrmhd_ctx* c, int enable) {
+  if (!c) return RRMHD_E_INVALID;
+  if (enable && c->ev.empty()) {
+    c->ev.resize(2 * kMaxTimed);
+    c->ev_kind.resize(kMaxTimed);
+    c->ev_units.resize(kMaxTimed);
+    for (auto& e : c->ev)
+      if (hipEventCreate(&e) != hipSuccess) return RRMHD_E_DEVICE;
+  }
+  c->prof = enable != 0;
+  if (enable) c->ev_used = 0;
+  return RRMHD_OK;
+}
+
+rrmhd_status rrmhd_profile_read(rrmhd_ctx* c, int k, double* total_ms, long long* launches, long long* units) {
+  if (!c || !total_ms || !launches || !units || k < 0 || k >= RRMHD_K_COUNT) return RRMHD_E_INVALID;
+  *total_ms = 0.0;
+  *launches = 0;
+  *units = 0;
+  if (c->ev_used == 0) return RRMHD_OK;
+  if (hipEventSynchronize(c->ev[2 * (c->ev_used - 1) + 1]) != hipSuccess) return RRMHD_E_DEVICE;
+  for (int i = 0; i < c->ev_used; ++i) {
+    if (c->ev_kind[i] != k) continue;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) != hipSuccess) return RRMHD_E_DEVICE;
+    *total_ms += ms;
+    *launches += 1;
+    *units += c->ev_units[i];
+  }
+  return RRMHD_OK;
+}
+
 void rrmhd_destroy(rrmhd_ctx* c) {
   if (!c) return;
   hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev) hipEventDestroy(e);
   if (c->host) hipHostFree(c->host);
   delete c;
 }

@@ -21,6 +21,7 @@ RECON_GODUNOV, RECON_MINMOD = 0, 1
 BETA_ALL, BETA_RAD_ONLY, BETA_OFF = 0, 1, 2
 IMP_PICARD_NEWTON, IMP_NEWTON, IMP_PICARD = 0, 1, 2
 FP64 = 0
+K_PRIMS, K_FACES, K_UPDATE, K_SPEED = 0, 1, 2, 3
 
 
 class rrmhd_grid(C.Structure):
@@ -68,6 +69,8 @@ SIGNATURES = {
     "rrmhd_step": ([_vp, _vp, _vp, _d, _vp], C.c_int),
     "rrmhd_max_speed": ([_vp, _vp, _vp, _vp], C.c_int),
     "rrmhd_face_fluxes": ([_vp, _vp, _vp, _vp], C.c_int),
+    "rrmhd_profile_enable": ([_vp, C.c_int], C.c_int),
+    "rrmhd_profile_read": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
     "rrmhd_report_sync": ([_vp, _vp], C.c_int),
     "rrmhd_destroy": ([_vp], None),
     "rrmhd_strerror": ([C.c_int], C.c_char_p),
@@ -145,6 +148,17 @@ def rrmhd_max_speed(ctx, U, grid: rrmhd_grid) -> float:
 
 def rrmhd_face_fluxes(ctx, U, opac: rrmhd_opacities, Fh) -> None:
     _check(_lib.rrmhd_face_fluxes(ctx, _ptr(U), C.byref(opac), _ptr(Fh)), "rrmhd_face_fluxes")
+
+
+def rrmhd_profile_enable(ctx, enable: bool = True) -> None:
+    _check(_lib.rrmhd_profile_enable(ctx, int(bool(enable))), "rrmhd_profile_enable")
+
+
+def rrmhd_profile_read(ctx, k: int):
+    """(total_ms, launches, units) of the timed launches of kernel class k."""
+    ms, n, u = C.c_double(0.0), C.c_longlong(0), C.c_longlong(0)
+    _check(_lib.rrmhd_profile_read(ctx, int(k), C.byref(ms), C.byref(n), C.byref(u)), "rrmhd_profile_read")
+    return ms.value, n.value, u.value
 
 
 def rrmhd_report_sync(ctx) -> dict:
