@@ -80,12 +80,17 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
   return v;
 }
 
-// Accumulate per-thread failure flags into the device report: one atomic per
-// wave and field, and only when the wave saw something.
-__device__ __forceinline__ void report_add(DevReport* rep, unsigned long long f_c2p,
+// Accumulate per-thread failure flags into the device report. Failures are
+// rare: one atomic per wave and field, only when the wave saw one. Iteration
+// maxima are not updated atomically (a same-address atomic per wave
+// serializes thousands of waves): each block keeps a running maximum in its
+// own slot of `blkmax` (one writer per slot, launches ordered on the stream),
+// folded into the report by rrmhd_report_sync.
+__device__ __forceinline__ void report_add(DevReport* rep, unsigned int* blkmax, unsigned long long f_c2p,
                                            unsigned long long f_pvm, unsigned long long f_imp,
                                            unsigned long long f_nf, unsigned long long bad_cell,
                                            unsigned int c2p_it, unsigned int imp_it) {
+  __shared__ unsigned int red_it[2][kBlock / kWave];
   const unsigned long long s_c2p = wave_sum_u64(f_c2p);
   const unsigned long long s_pvm = wave_sum_u64(f_pvm);
   const unsigned long long s_imp = wave_sum_u64(f_imp);
@@ -93,14 +98,28 @@ __device__ __forceinline__ void report_add(DevReport* rep, unsigned long long f_
   const unsigned long long s_bad = wave_min_u64(bad_cell);
   const unsigned int m_c2p = wave_max_u32(c2p_it);
   const unsigned int m_imp = wave_max_u32(imp_it);
-  if ((threadIdx.x & (kWave - 1)) == 0) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  if (lane == 0) {
     if (s_c2p) atomicAdd(&rep->c2p_fail, s_c2p);
     if (s_pvm) atomicAdd(&rep->pvm_fallback, s_pvm);
     if (s_imp) atomicAdd(&rep->imp_fail, s_imp);
     if (s_nf) atomicAdd(&rep->nonfinite, s_nf);
     if (s_bad != ULLONG_MAX) atomicMin(&rep->first_bad, s_bad);
-    if (m_c2p) atomicMax(&rep->max_c2p_it, m_c2p);
-    if (m_imp) atomicMax(&rep->max_imp_it, m_imp);
+    red_it[0][wid] = m_c2p;
+    red_it[1][wid] = m_imp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int a = red_it[0][0], b = red_it[1][0];
+#pragma unroll
+    for (int w = 1; w < kBlock / kWave; ++w) {
+      a = (red_it[0][w] > a) ? red_it[0][w] : a;
+      b = (red_it[1][w] > b) ? red_it[1][w] : b;
+    }
+    unsigned int* slot = blkmax + 2 * (size_t)blockIdx.x;
+    if (a > slot[0]) slot[0] = a;
+    if (b > slot[1]) slot[1] = b;
   }
 }
 
@@ -144,7 +163,7 @@ __global__ void __launch_bounds__(kBlock) k_p2c(long long n, const double* __res
 }
 
 __global__ void __launch_bounds__(kBlock) k_c2p(long long n, const double* __restrict__ U, long long su,
-                                                double* __restrict__ V, long long sv, Phys K, DevReport* rep) {
+                                                double* __restrict__ V, long long sv, Phys K, DevReport* rep, unsigned int* blkmax) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long fail = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
@@ -162,7 +181,7 @@ __global__ void __launch_bounds__(kBlock) k_c2p(long long n, const double* __res
 #pragma unroll
     for (int q = 0; q < NV; ++q) V[q * sv + c] = v[q];
   }
-  report_add(rep, fail, 0, 0, 0, bad, its, 0);
+  report_add(rep, blkmax, fail, 0, 0, 0, bad, its, 0);
 }
 
 // Stage primitives: interior cells (c < N) from U, inflow cells from inflow_U.
@@ -170,7 +189,7 @@ __global__ void __launch_bounds__(kBlock) k_c2p(long long n, const double* __res
 __global__ void __launch_bounds__(kBlock) k_prims(GridDev G, const double* __restrict__ U, long long su,
                                                   const double* __restrict__ inU, Opac op,
                                                   double* __restrict__ Vp, double* __restrict__ taup,
-                                                  long long np, Phys K, DevReport* rep) {
+                                                  long long np, Phys K, DevReport* rep, unsigned int* blkmax) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long fail = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
@@ -197,54 +216,84 @@ __global__ void __launch_bounds__(kBlock) k_prims(GridDev G, const double* __res
     for (int q = 0; q < NV; ++q) Vp[q * np + c] = v[q];
     taup[c] = u[0] * (opac_at(op.kappa, op.kappa0, oc) + opac_at(op.sigma, op.sigma0, oc));
   }
-  report_add(rep, fail, 0, 0, 0, bad, its, 0);
+  report_add(rep, blkmax, fail, 0, 0, 0, bad, its, 0);
 }
 
+struct FaceArgs {
+  const double* Vp;
+  const double* taup;
+  long long np;
+  double* Fh[3];
+  long long nf[3];
+  long long nb[3];   // blocks per direction
+  double dx[3];
+};
+
+// One face of direction d: PLM MinMod on the 4-cell stencil, |F_r| <= E_r,
+// then the PVM-int flux with beta from the two adjacent cells.
 template <int d>
-__global__ void __launch_bounds__(kBlock) k_faces(GridDev G, const double* __restrict__ Vp,
-                                                  const double* __restrict__ taup, long long np,
-                                                  double dxd, double* __restrict__ Fh, long long nf,
-                                                  Phys K, DevReport* rep) {
-  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, long long f, const Phys& K,
+                                          unsigned long long& fb, unsigned int& its) {
+  int fn0 = G.n[0], fn1 = G.n[1];
+  if (d == 0) fn0 += 1;
+  if (d == 1) fn1 += 1;
+  int c[3];
+  c[0] = (int)(f % fn0);
+  c[1] = (int)((f / fn0) % fn1);
+  c[2] = (int)(f / ((long long)fn0 * fn1));
+  double Vs[4][NV];
+  double tp[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[d] = c[d] - 2 + s;
+    const long long m = map_cell(G, cc[0], cc[1], cc[2], d);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Vs[s][q] = A.Vp[q * A.np + m];
+    tp[s] = A.taup[m];
+  }
+  double sa[NV], sb[NV];
+  rr::cell_slopes(Vs[0], Vs[1], Vs[2], K.recon, sa);
+  rr::cell_slopes(Vs[1], Vs[2], Vs[3], K.recon, sb);
+  double VL[NV], VR[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) { VL[q] = Vs[1][q] + 0.5 * sa[q]; VR[q] = Vs[2][q] - 0.5 * sb[q]; }
+  rr::limit_rad_flux(VL);
+  rr::limit_rad_flux(VR);
+  const double tauL = tp[1] * A.dx[d], tauR = tp[2] * A.dx[d];
+  double Fq[NV];
+  int fallback = 0, cit = 0;
+  rr::pvm_face<d>(VL, VR, tauL, tauR, K, Fq, fallback, cit);
+  double* out = A.Fh[d];
+  const long long nf = A.nf[d];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) out[q * nf + f] = Fq[q];
+  fb = (unsigned long long)fallback;
+  its = (unsigned int)cit;
+}
+
+// Face fluxes of all directions in one launch: blocks [0, nb0) take x faces,
+// the next nb1 blocks y faces, then z. The direction is uniform per block.
+// Two waves per SIMD (at the price of a few spilled registers) hide more of
+// the FP64 and transcendental latency than one wave with no spills.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep,
+                                                  unsigned int* blkmax) {
+  long long b = blockIdx.x;
+  int d = 0;
+  if (b >= A.nb[0]) {
+    b -= A.nb[0];
+    d = 1;
+    if (b >= A.nb[1]) { b -= A.nb[1]; d = 2; }
+  }
+  const long long f = b * blockDim.x + threadIdx.x;
   unsigned long long fb = 0;
   unsigned int its = 0;
-  if (f < nf) {
-    int fn0 = G.n[0], fn1 = G.n[1];
-    if (d == 0) fn0 += 1;
-    if (d == 1) fn1 += 1;
-    int c[3];
-    c[0] = (int)(f % fn0);
-    c[1] = (int)((f / fn0) % fn1);
-    c[2] = (int)(f / ((long long)fn0 * fn1));
-    double Vs[4][NV];
-    double tp[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      int cc[3] = {c[0], c[1], c[2]};
-      cc[d] = c[d] - 2 + s;
-      const long long m = map_cell(G, cc[0], cc[1], cc[2], d);
-#pragma unroll
-      for (int q = 0; q < NV; ++q) Vs[s][q] = Vp[q * np + m];
-      tp[s] = taup[m];
-    }
-    double sa[NV], sb[NV];
-    rr::cell_slopes(Vs[0], Vs[1], Vs[2], K.recon, sa);
-    rr::cell_slopes(Vs[1], Vs[2], Vs[3], K.recon, sb);
-    double VL[NV], VR[NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) { VL[q] = Vs[1][q] + 0.5 * sa[q]; VR[q] = Vs[2][q] - 0.5 * sb[q]; }
-    rr::limit_rad_flux(VL);
-    rr::limit_rad_flux(VR);
-    const double tauL = tp[1] * dxd, tauR = tp[2] * dxd;
-    double Fq[NV];
-    int fallback = 0, cit = 0;
-    rr::pvm_face<d>(VL, VR, tauL, tauR, K, Fq, fallback, cit);
-#pragma unroll
-    for (int q = 0; q < NV; ++q) Fh[q * nf + f] = Fq[q];
-    fb = (unsigned long long)fallback;
-    its = (unsigned int)cit;
+  if (f < A.nf[d]) {
+    if (d == 0) face_body<0>(G, A, f, K, fb, its);
+    else if (d == 1) face_body<1>(G, A, f, K, fb, its);
+    else face_body<2>(G, A, f, K, fb, its);
   }
-  report_add(rep, 0, fb, 0, 0, ULLONG_MAX, its, 0);
+  report_add(rep, blkmax, 0, fb, 0, 0, ULLONG_MAX, its, 0);
 }
 
 struct StageArgs {
@@ -260,7 +309,7 @@ struct StageArgs {
   double a0, a1, cdt;
 };
 
-__global__ void __launch_bounds__(kBlock) k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
@@ -298,12 +347,13 @@ __global__ void __launch_bounds__(kBlock) k_update(GridDev G, StageArgs A, Opac 
     if (st != 0 || !fin) bad = (unsigned long long)c;
     its = (unsigned int)it;
   }
-  report_add(rep, 0, 0, fimp, fnf, bad, 0, its);
+  report_add(rep, blkmax, 0, 0, fimp, fnf, bad, 0, its);
 }
 
 // Per-block maximum of the cell signal speeds -> partial[blockIdx.x].
 __global__ void __launch_bounds__(kBlock) k_speed(GridDev G, const double* __restrict__ U, long long su,
-                                                  Phys K, double* __restrict__ partial, DevReport* rep) {
+                                                  Phys K, double* __restrict__ partial, DevReport* rep,
+                                                  unsigned int* blkmax) {
   __shared__ double red[kBlock / kWave];
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double s = 0.0;
@@ -324,7 +374,7 @@ __global__ void __launch_bounds__(kBlock) k_speed(GridDev G, const double* __res
     if (G.ndim > 1) s = rr::dmax(s, rr::cell_speed<1>(v, a, K));
     if (G.ndim > 2) s = rr::dmax(s, rr::cell_speed<2>(v, a, K));
   }
-  report_add(rep, fail, 0, 0, 0, bad, 0, 0);
+  report_add(rep, blkmax, fail, 0, 0, 0, bad, 0, 0);
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) s = rr::dmax(s, __shfl_xor(s, o, kWave));
   if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
@@ -354,11 +404,38 @@ __global__ void __launch_bounds__(kBlock) k_reduce_max(const double* __restrict_
   }
 }
 
-__global__ void k_report_reset(DevReport* rep) {
+// Clear the counters and the per-block iteration maxima.
+__global__ void __launch_bounds__(kBlock) k_report_reset(DevReport* rep, unsigned int* blkmax, long long nslots) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     rep->c2p_fail = 0; rep->pvm_fallback = 0; rep->imp_fail = 0; rep->nonfinite = 0;
     rep->first_bad = ULLONG_MAX;
     rep->max_c2p_it = 0; rep->max_imp_it = 0;
+  }
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nslots; i += (long long)gridDim.x * blockDim.x)
+    blkmax[i] = 0;
+}
+
+// Fold the per-block iteration maxima into the report (single block).
+__global__ void __launch_bounds__(kBlock) k_report_fold(DevReport* rep, const unsigned int* blkmax, long long nblk) {
+  __shared__ unsigned int red[2][kBlock / kWave];
+  unsigned int a = 0, b = 0;
+  for (long long i = threadIdx.x; i < nblk; i += blockDim.x) {
+    a = (blkmax[2 * i] > a) ? blkmax[2 * i] : a;
+    b = (blkmax[2 * i + 1] > b) ? blkmax[2 * i + 1] : b;
+  }
+  a = wave_max_u32(a);
+  b = wave_max_u32(b);
+  if ((threadIdx.x & (kWave - 1)) == 0) { red[0][threadIdx.x / kWave] = a; red[1][threadIdx.x / kWave] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w) {
+      a = (red[0][w] > a) ? red[0][w] : a;
+      b = (red[1][w] > b) ? red[1][w] : b;
+    }
+    a = (red[0][0] > a) ? red[0][0] : a;
+    b = (red[1][0] > b) ? red[1][0] : b;
+    rep->max_c2p_it = (a > rep->max_c2p_it) ? a : rep->max_c2p_it;
+    rep->max_imp_it = (b > rep->max_imp_it) ? b : rep->max_imp_it;
   }
 }
 
@@ -465,7 +542,9 @@ struct Layout {
   long long N, nt, Np, Ns;
   long long nf[3];
   long long npartial;
-  size_t off_Vp, off_taup, off_Us, off_Fh[3], off_partial, off_smax, off_rep, total;
+  long long nb_faces[3];
+  long long nblkmax;  // block slots for the iteration maxima
+  size_t off_Vp, off_taup, off_Us, off_Fh[3], off_partial, off_smax, off_rep, off_blkmax, total;
 };
 
 Layout make_layout(const rrmhd_grid* g) {
@@ -483,6 +562,10 @@ Layout make_layout(const rrmhd_grid* g) {
     }
   }
   L.npartial = (L.N + kBlock - 1) / kBlock;
+  long long nbf = 0;
+  for (int d = 0; d < 3; ++d) { L.nb_faces[d] = (L.nf[d] + kBlock - 1) / kBlock; nbf += L.nb_faces[d]; }
+  const long long nbc = (L.N + L.nt + kBlock - 1) / kBlock;
+  L.nblkmax = (nbf > nbc) ? nbf : nbc;
   size_t o = 0;
   L.off_Vp = o; o = align256(o + sizeof(double) * NV * L.Np);
   L.off_taup = o; o = align256(o + sizeof(double) * L.Np);
@@ -491,6 +574,7 @@ Layout make_layout(const rrmhd_grid* g) {
   L.off_partial = o; o = align256(o + sizeof(double) * L.npartial);
   L.off_smax = o; o = align256(o + sizeof(double));
   L.off_rep = o; o = align256(o + sizeof(DevReport));
+  L.off_blkmax = o; o = align256(o + sizeof(unsigned int) * 2 * L.nblkmax);
   L.total = o;
   return L;
 }
@@ -522,6 +606,7 @@ struct rrmhd_ctx {
   double* partial;
   double* smax;
   DevReport* rep;
+  unsigned int* blkmax;
   hipStream_t stream;
   void* host;  // pinned: DevReport + one double
   // Diagnostic timing (rrmhd_profile_*).
@@ -577,18 +662,26 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   const GridDev G = make_griddev(g, L);
   int pe = prof_begin(c, RRMHD_K_PRIMS, L.N + L.nt);
   k_prims<<<nblocks(L.N + L.nt), kBlock, 0, c->stream>>>(G, Us, ss, g->inflow_U, op, c->Vp, c->taup,
-                                                           L.Np, c->K, c->rep);
+                                                           L.Np, c->K, c->rep, c->blkmax);
   prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-  for (int d = 0; d < g->ndim; ++d) {
-    const unsigned int nb = nblocks(L.nf[d]);
-    pe = prof_begin(c, RRMHD_K_FACES, L.nf[d]);
-    if (d == 0) k_faces<0><<<nb, kBlock, 0, c->stream>>>(G, c->Vp, c->taup, L.Np, g->dx[0], out[0], L.nf[0], c->K, c->rep);
-    if (d == 1) k_faces<1><<<nb, kBlock, 0, c->stream>>>(G, c->Vp, c->taup, L.Np, g->dx[1], out[1], L.nf[1], c->K, c->rep);
-    if (d == 2) k_faces<2><<<nb, kBlock, 0, c->stream>>>(G, c->Vp, c->taup, L.Np, g->dx[2], out[2], L.nf[2], c->K, c->rep);
-    prof_end(c, pe);
-    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  FaceArgs A;
+  A.Vp = c->Vp;
+  A.taup = c->taup;
+  A.np = L.Np;
+  long long nbt = 0;
+  for (int d = 0; d < 3; ++d) {
+    const bool on = d < g->ndim;
+    A.Fh[d] = on ? out[d] : nullptr;
+    A.nf[d] = on ? L.nf[d] : 0;
+    A.nb[d] = on ? L.nb_faces[d] : 0;
+    A.dx[d] = on ? g->dx[d] : 1.0;
+    nbt += A.nb[d];
   }
+  pe = prof_begin(c, RRMHD_K_FACES, A.nf[0] + A.nf[1] + A.nf[2]);
+  k_faces<<<(unsigned int)nbt, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax);
+  prof_end(c, pe);
+  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   return RRMHD_OK;
 }
 
@@ -644,6 +737,7 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   c->partial = (double*)(c->ws + L.off_partial);
   c->smax = (double*)(c->ws + L.off_smax);
   c->rep = (DevReport*)(c->ws + L.off_rep);
+  c->blkmax = (unsigned int*)(c->ws + L.off_blkmax);
   c->stream = (hipStream_t)hip_stream;
   c->host = nullptr;
   c->prof = false;
@@ -652,7 +746,7 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
     delete c;
     return RRMHD_E_DEVICE;
   }
-  k_report_reset<<<1, 64, 0, c->stream>>>(c->rep);
+  k_report_reset<<<64, kBlock, 0, c->stream>>>(c->rep, c->blkmax, 2 * L.nblkmax);
   if (launch_ok() != RRMHD_OK) {
     hipHostFree(c->host);
     delete c;
@@ -674,7 +768,7 @@ rrmhd_status rrmhd_cons_to_prim(rrmhd_ctx* c, const double* U, double* V) {
   if (!c || !V || !U) return RRMHD_E_INVALID;
   const long long N = c->L.N, s = c->grid.var_stride;
   if (N == 0) return RRMHD_OK;
-  k_c2p<<<nblocks(N), kBlock, 0, c->stream>>>(N, U, s, V, s, c->K, c->rep);
+  k_c2p<<<nblocks(N), kBlock, 0, c->stream>>>(N, U, s, V, s, c->K, c->rep, c->blkmax);
   return launch_ok();
 }
 
@@ -725,7 +819,7 @@ rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt,
     A.a1 = co[s][1];
     A.cdt = co[s][2] * dt;
     const int pe = prof_begin(c, RRMHD_K_UPDATE, L.N);
-    k_update<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep);
+    k_update<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax);
     prof_end(c, pe);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   }
@@ -737,7 +831,7 @@ rrmhd_status rrmhd_max_speed(rrmhd_ctx* c, const double* U, const rrmhd_grid* g,
   const Layout& L = c->L;
   const GridDev G = make_griddev(g, L);
   const int pe = prof_begin(c, RRMHD_K_SPEED, L.N);
-  k_speed<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, U, g->var_stride, c->K, c->partial, c->rep);
+  k_speed<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, U, g->var_stride, c->K, c->partial, c->rep, c->blkmax);
   prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   k_reduce_max<<<1, kBlock, 0, c->stream>>>(c->partial, L.npartial, c->smax);
@@ -752,6 +846,8 @@ rrmhd_status rrmhd_max_speed(rrmhd_ctx* c, const double* U, const rrmhd_grid* g,
 rrmhd_status rrmhd_report_sync(rrmhd_ctx* c, rrmhd_report* out) {
   if (!c || !out) return RRMHD_E_INVALID;
   DevReport* h = (DevReport*)c->host;
+  k_report_fold<<<1, kBlock, 0, c->stream>>>(c->rep, c->blkmax, c->L.nblkmax);
+  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   if (hipMemcpyAsync(h, c->rep, sizeof(DevReport), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return RRMHD_E_DEVICE;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return RRMHD_E_DEVICE;
   out->c2p_fail = (long long)h->c2p_fail;
@@ -761,7 +857,7 @@ rrmhd_status rrmhd_report_sync(rrmhd_ctx* c, rrmhd_report* out) {
   out->first_bad_cell = (h->first_bad == ULLONG_MAX) ? -1 : (long long)h->first_bad;
   out->max_c2p_it = (int)h->max_c2p_it;
   out->max_imp_it = (int)h->max_imp_it;
-  k_report_reset<<<1, 64, 0, c->stream>>>(c->rep);
+  k_report_reset<<<64, kBlock, 0, c->stream>>>(c->rep, c->blkmax, 2 * c->L.nblkmax);
   return launch_ok();
 }
 

@@ -289,22 +289,29 @@ template <int d>
 __device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV], double tauL,
                                          double tauR, const Phys& K, double Fh[NV],
                                          int& fallback, int& c2p_its) {
-  double UL[NV], UR[NV], FL[NV], FR[NV];
+  // Only (F_L + F_R)/2, U_0 and U_m are needed past this point.
+  double Fa[NV], U0[NV], Um[NV];
   {
-    Aux aL;
-    prim_aux(VL, K, aL);
-    p2c(VL, aL, UL);
-    flux<d>(VL, aL, FL);
-  }
-  {
-    Aux aR;
-    prim_aux(VR, K, aR);
-    p2c(VR, aR, UR);
-    flux<d>(VR, aR, FR);
-  }
-  double U0[NV], Um[NV];
+    double UL[NV], UR[NV], FL[NV], FR[NV];
+    {
+      Aux aL;
+      prim_aux(VL, K, aL);
+      p2c(VL, aL, UL);
+      flux<d>(VL, aL, FL);
+    }
+    {
+      Aux aR;
+      prim_aux(VR, K, aR);
+      p2c(VR, aR, UR);
+      flux<d>(VR, aR, FR);
+    }
 #pragma unroll
-  for (int q = 0; q < NV; ++q) { U0[q] = UR[q] - UL[q]; Um[q] = 0.5 * (UL[q] + UR[q]); }
+    for (int q = 0; q < NV; ++q) {
+      U0[q] = UR[q] - UL[q];
+      Um[q] = 0.5 * (UL[q] + UR[q]);
+      Fa[q] = 0.5 * (FL[q] + FR[q]);
+    }
+  }
   const double beta = 1.0 / dmax(dmax(tauL, tauR), 1.0);
   fallback = 0;
   c2p_its = 0;
@@ -369,7 +376,7 @@ __device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     const double bq = (K.beta_mode == 2 || (K.beta_mode == 1 && q < 8)) ? 1.0 : beta;
-    Fh[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * (bq * w[q]);
+    Fh[q] = Fa[q] - 0.5 * (bq * w[q]);
   }
 }
 
