@@ -114,7 +114,8 @@ def main():
     elapsed = t1 - t0
     rep = solver.report()
     prof = {name: R.rrmhd_profile_read(solver.ctx, k) for name, k in
-            (("prims", R.K_PRIMS), ("faces", R.K_FACES), ("update", R.K_UPDATE), ("speed", R.K_SPEED))}
+            (("prims", R.K_PRIMS), ("faces", R.K_FACES), ("update", R.K_UPDATE), ("newton", R.K_NEWTON),
+             ("speed", R.K_SPEED))}
     R.rrmhd_profile_enable(solver.ctx, False)
 
     value = P.ncell * args.steps / elapsed

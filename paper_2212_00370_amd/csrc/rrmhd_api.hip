@@ -189,8 +189,10 @@ __global__ void __launch_bounds__(kBlock) k_c2p(long long n, const double* __res
 __global__ void __launch_bounds__(kBlock) k_prims(GridDev G, const double* __restrict__ U, long long su,
                                                   const double* __restrict__ inU, Opac op,
                                                   double* __restrict__ Vp, double* __restrict__ taup,
-                                                  long long np, Phys K, DevReport* rep, unsigned int* blkmax) {
+                                                  long long np, Phys K, DevReport* rep, unsigned int* blkmax,
+                                                  unsigned long long* wcount) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) *wcount = 0;  // work list of this stage's implicit Newton phase
   unsigned long long fail = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
   if (c < G.N + G.nt) {
@@ -309,10 +311,16 @@ struct StageArgs {
   double a0, a1, cdt;
 };
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax) {
+// Flux divergence and stage combination, then phase 1 of the implicit solve
+// (Picard). Cells that need the Newton phase get their explicit state U*
+// written to the output and are appended to `worklist` (one atomic per wave).
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
+         long long* worklist, unsigned long long* wcount) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
+  bool newton = false;
   if (c < G.N) {
     const int ci[3] = {(int)(c % G.n[0]), (int)((c / G.n[0]) % G.n[1]), (int)(c / ((long long)G.n[0] * G.n[1]))};
     long long fm[3], fs[3];
@@ -334,18 +342,68 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     }
     double Un[NV];
     int it = 0;
-    const int st = rr::implicit_cell(Ust, A.cdt, opac_at(op.kappa, op.kappa0, c),
-                                     opac_at(op.sigma, op.sigma0, c), K, Un, it);
+    const int st = rr::implicit_picard(Ust, A.cdt, opac_at(op.kappa, op.kappa0, c),
+                                       opac_at(op.sigma, op.sigma0, c), K, Un, it);
+    its = (unsigned int)it;
+    if (st == rr::IMP_NEED_NEWTON) {
+      newton = true;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) A.Uo[q * A.so + c] = Ust[q];
+    } else {
+      bool fin = true;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        A.Uo[q * A.so + c] = Un[q];
+        fin = fin && isfinite(Un[q]);
+      }
+      if (st != rr::IMP_DONE) fimp = 1;
+      if (!fin) fnf = 1;
+      if (st != rr::IMP_DONE || !fin) bad = (unsigned long long)c;
+    }
+  }
+  // Append the cells that need phase 2.
+  const unsigned long long mask = __ballot(newton);
+  if (mask) {
+    const int lane = threadIdx.x & (kWave - 1);
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(wcount, (unsigned long long)__popcll(mask));
+    base = __shfl(base, 0, kWave);
+    if (newton) {
+      const unsigned int below = __builtin_amdgcn_mbcnt_hi((unsigned int)(mask >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((unsigned int)mask, 0u));
+      worklist[base + below] = c;
+    }
+  }
+  report_add(rep, blkmax, 0, 0, fimp, fnf, bad, 0, its);
+}
+
+// Phase 2 of the implicit solve (Newton) for the cells in `worklist`; the
+// explicit state U* was left in the output by k_update. Grid-stride.
+__global__ void __launch_bounds__(kBlock)
+k_newton(StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
+         const long long* __restrict__ worklist, const unsigned long long* wcount) {
+  const unsigned long long n = *wcount;
+  unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
+  unsigned int its = 0;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    const long long c = worklist[i];
+    double Ust[NV], Un[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Ust[q] = A.Uo[q * A.so + c];
+    int it = 0;
+    const int st = rr::implicit_newton(Ust, A.cdt, opac_at(op.kappa, op.kappa0, c),
+                                       opac_at(op.sigma, op.sigma0, c), K, Un, it);
     bool fin = true;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       A.Uo[q * A.so + c] = Un[q];
       fin = fin && isfinite(Un[q]);
     }
-    if (st != 0) fimp = 1;
-    if (!fin) fnf = 1;
-    if (st != 0 || !fin) bad = (unsigned long long)c;
-    its = (unsigned int)it;
+    if (st != rr::IMP_DONE) fimp += 1;
+    if (!fin) fnf += 1;
+    if ((st != rr::IMP_DONE || !fin) && (unsigned long long)c < bad) bad = (unsigned long long)c;
+    its = ((unsigned int)it > its) ? (unsigned int)it : its;
   }
   report_add(rep, blkmax, 0, 0, fimp, fnf, bad, 0, its);
 }
@@ -544,7 +602,7 @@ struct Layout {
   long long npartial;
   long long nb_faces[3];
   long long nblkmax;  // block slots for the iteration maxima
-  size_t off_Vp, off_taup, off_Us, off_Fh[3], off_partial, off_smax, off_rep, off_blkmax, total;
+  size_t off_Vp, off_taup, off_Us, off_Fh[3], off_partial, off_smax, off_rep, off_blkmax, off_work, off_wcount, total;
 };
 
 Layout make_layout(const rrmhd_grid* g) {
@@ -575,6 +633,8 @@ Layout make_layout(const rrmhd_grid* g) {
   L.off_smax = o; o = align256(o + sizeof(double));
   L.off_rep = o; o = align256(o + sizeof(DevReport));
   L.off_blkmax = o; o = align256(o + sizeof(unsigned int) * 2 * L.nblkmax);
+  L.off_work = o; o = align256(o + sizeof(long long) * L.N);
+  L.off_wcount = o; o = align256(o + sizeof(unsigned long long));
   L.total = o;
   return L;
 }
@@ -607,7 +667,10 @@ struct rrmhd_ctx {
   double* smax;
   DevReport* rep;
   unsigned int* blkmax;
+  long long* work;              // cells left to the Newton phase of the implicit solve
+  unsigned long long* wcount;
   hipStream_t stream;
+  unsigned int newton_blocks;
   void* host;  // pinned: DevReport + one double
   // Diagnostic timing (rrmhd_profile_*).
   bool prof;
@@ -662,7 +725,7 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   const GridDev G = make_griddev(g, L);
   int pe = prof_begin(c, RRMHD_K_PRIMS, L.N + L.nt);
   k_prims<<<nblocks(L.N + L.nt), kBlock, 0, c->stream>>>(G, Us, ss, g->inflow_U, op, c->Vp, c->taup,
-                                                           L.Np, c->K, c->rep, c->blkmax);
+                                                           L.Np, c->K, c->rep, c->blkmax, c->wcount);
   prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   FaceArgs A;
@@ -738,10 +801,17 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   c->smax = (double*)(c->ws + L.off_smax);
   c->rep = (DevReport*)(c->ws + L.off_rep);
   c->blkmax = (unsigned int*)(c->ws + L.off_blkmax);
+  c->work = (long long*)(c->ws + L.off_work);
+  c->wcount = (unsigned long long*)(c->ws + L.off_wcount);
   c->stream = (hipStream_t)hip_stream;
   c->host = nullptr;
   c->prof = false;
   c->ev_used = 0;
+  {
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    c->newton_blocks = (unsigned int)(2 * ncu);  // 2 blocks of 4 waves per CU = 2 waves per SIMD
+  }
   if (hipHostMalloc(&c->host, sizeof(DevReport) + sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return RRMHD_E_DEVICE;
@@ -818,8 +888,14 @@ rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt,
     A.a0 = co[s][0];
     A.a1 = co[s][1];
     A.cdt = co[s][2] * dt;
-    const int pe = prof_begin(c, RRMHD_K_UPDATE, L.N);
-    k_update<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax);
+    int pe = prof_begin(c, RRMHD_K_UPDATE, L.N);
+    k_update<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
+    prof_end(c, pe);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    // Grid-stride over the work list; a few blocks per CU.
+    const unsigned int nbn = (unsigned int)((nblocks(L.N) < c->newton_blocks) ? nblocks(L.N) : c->newton_blocks);
+    pe = prof_begin(c, RRMHD_K_NEWTON, L.N);
+    k_newton<<<nbn, kBlock, 0, c->stream>>>(A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
     prof_end(c, pe);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   }

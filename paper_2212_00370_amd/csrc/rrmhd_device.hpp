@@ -526,47 +526,73 @@ __device__ __forceinline__ double vmaxabs4(const double a[4]) {
   return dmax(dmax(dabs(a[0]), dabs(a[1])), dmax(dabs(a[2]), dabs(a[3])));
 }
 
-// Returns 0 on success; on failure Un = Us. The paper's Picard iteration
-// X^{m+1} = C(X^m)^{-1} b(X^m) from the explicit state X*, stopped once its
-// update grows; Newton on C(X) X - b(X) (forward-difference Jacobian, step
-// halving) from X* finishes where Picard did not converge. The |F_r| <= E_r
-// limit is applied to the explicit radiation state first (keeping S + F_r),
-// and to the result.
-__device__ __forceinline__ int implicit_cell(const double Us[NV], double h, double kap, double sig,
-                                             const Phys& K, double Un[NV], int& iters) {
-  const double Et = Us[4] + Us[8];
-  double St[3];
+// The implicit solve runs in two phases that together give one cell's result.
+// Phase 1 is the paper's Picard iteration X^{m+1} = C(X^m)^{-1} b(X^m) from
+// the explicit state X*, stopped once its update grows; phase 2 is Newton on
+// C(X) X - b(X) (forward-difference Jacobian, step halving) from X*, for the
+// cells phase 1 did not converge. The |F_r| <= E_r limit is applied to the
+// explicit radiation state first (keeping S + F_r), and to the result.
+struct ImpIn {
+  double Ul[NV];  // explicit state with the radiation flux limited
+  double Et, St[3];
+};
+
+__device__ __forceinline__ bool imp_prepare(const double Us[NV], ImpIn& in) {
+  in.Et = Us[4] + Us[8];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) St[j] = Us[1 + j] + Us[9 + j];
-  double Ul[NV];
+  for (int j = 0; j < 3; ++j) in.St[j] = Us[1 + j] + Us[9 + j];
 #pragma unroll
-  for (int q = 0; q < NV; ++q) Ul[q] = Us[q];
+  for (int q = 0; q < NV; ++q) in.Ul[q] = Us[q];
+  if (!(in.Ul[8] > 0.0)) return false;
+  const double FF = (in.Ul[9] * in.Ul[9] + in.Ul[10] * in.Ul[10]) + in.Ul[11] * in.Ul[11];
+  if (FF > in.Ul[8] * in.Ul[8]) {
+    const double r = in.Ul[8] / sqrt(FF);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) in.Ul[9 + j] = in.Ul[9 + j] * r;
+  }
+  return true;
+}
+
+__device__ __forceinline__ void imp_finish(double X[4], const double Us[NV], const ImpIn& in, double Un[NV]) {
+  const double FF = (X[1] * X[1] + X[2] * X[2]) + X[3] * X[3];
+  if (FF > X[0] * X[0]) {
+    const double r = X[0] / sqrt(FF);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) X[1 + j] = X[1 + j] * r;
+  }
+  Un[0] = Us[0];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Un[1 + j] = in.St[j] - X[1 + j];
+  Un[4] = in.Et - X[0];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Un[5 + j] = Us[5 + j];
+  Un[8] = X[0];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Un[9 + j] = X[1 + j];
+}
+
+enum { IMP_DONE = 0, IMP_FAILED = 1, IMP_NEED_NEWTON = 2 };
+
+// Phase 1. IMP_DONE: Un holds the result; IMP_FAILED: Un = Us;
+// IMP_NEED_NEWTON: phase 2 must finish the cell (Un untouched).
+__device__ __forceinline__ int implicit_picard(const double Us[NV], double h, double kap, double sig,
+                                               const Phys& K, double Un[NV], int& iters) {
+  ImpIn in;
   iters = 0;
-  if (!(Ul[8] > 0.0)) {
+  if (!imp_prepare(Us, in)) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) Un[q] = Us[q];
-    return 1;
+    return IMP_FAILED;
   }
-  {
-    const double FF = (Ul[9] * Ul[9] + Ul[10] * Ul[10]) + Ul[11] * Ul[11];
-    if (FF > Ul[8] * Ul[8]) {
-      const double r = Ul[8] / sqrt(FF);
-#pragma unroll
-      for (int j = 0; j < 3; ++j) Ul[9 + j] = Ul[9 + j] * r;
-    }
-  }
-  double X[4] = {Ul[8], Ul[9], Ul[10], Ul[11]};
+  double X[4] = {in.Ul[8], in.Ul[9], in.Ul[10], in.Ul[11]};
   ImpSys sy;
   double Zg = 0.0;
-  int it = 0;
-  int c2p_it = 0;
-  bool conv = false;
-  bool have = false;
+  int it = 0, c2p_it = 0;
+  bool conv = false, have = false;
   const int npic = (K.imp_method == 1) ? 0 : ((K.imp_method == 2) ? K.imp_maxit : K.imp_picard_it);
-  const double Xg[4] = {X[0], X[1], X[2], X[3]};
   double dlast = 0.0, dprev = 0.0;
   for (int m = 0; m <= npic; ++m) {
-    if (!imp_build(X, Ul, Et, St, h, kap, sig, K, Zg, sy, c2p_it)) break;
+    if (!imp_build(X, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sy, c2p_it)) break;
     Zg = sy.Z;
     if (m == 0) have = true;
     if (m > 0 && dlast <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
@@ -588,12 +614,30 @@ __device__ __forceinline__ int implicit_cell(const double Us[NV], double h, doub
     dprev = dlast;
     dlast = vmaxabs4(dd);
   }
-  if (!conv && have && K.imp_method != 2) {
+  iters = it;
+  if (conv) {
+    imp_finish(X, Us, in, Un);
+    return IMP_DONE;
+  }
+  if (have && K.imp_method != 2) return IMP_NEED_NEWTON;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) X[i] = Xg[i];
-    Zg = 0.0;
-    double R[4];
-    if (imp_build(X, Ul, Et, St, h, kap, sig, K, Zg, sy, c2p_it)) {
+  for (int q = 0; q < NV; ++q) Un[q] = Us[q];
+  return IMP_FAILED;
+}
+
+// Phase 2: Newton from X*. Returns IMP_DONE or IMP_FAILED (then Un = Us).
+__device__ __forceinline__ int implicit_newton(const double Us[NV], double h, double kap, double sig,
+                                               const Phys& K, double Un[NV], int& iters) {
+  ImpIn in;
+  iters = 0;
+  bool conv = false;
+  double X[4];
+  if (imp_prepare(Us, in)) {
+    X[0] = in.Ul[8]; X[1] = in.Ul[9]; X[2] = in.Ul[10]; X[3] = in.Ul[11];
+    ImpSys sy;
+    double Zg = 0.0, R[4];
+    int it = 0, c2p_it = 0;
+    if (imp_build(X, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sy, c2p_it)) {
       Zg = sy.Z;
       imp_residual(sy, X, R);
       for (int n = 0; n < K.imp_maxit; ++n) {
@@ -608,7 +652,7 @@ __device__ __forceinline__ int implicit_cell(const double Us[NV], double h, doub
             double Xp[4] = {X[0], X[1], X[2], X[3]};
             Xp[j] = Xp[j] + del;
             ImpSys sp;
-            if (!imp_build(Xp, Ul, Et, St, h, kap, sig, K, Zg, sp, c2p_it)) {
+            if (!imp_build(Xp, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sp, c2p_it)) {
               okj = false;
             } else {
               double Rp[4];
@@ -630,7 +674,7 @@ __device__ __forceinline__ int implicit_cell(const double Us[NV], double h, doub
         for (int ls = 0; ls < 12; ++ls) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) Xt[i] = X[i] + lam * dX[i];
-          if (Xt[0] > 0.0 && imp_build(Xt, Ul, Et, St, h, kap, sig, K, Zg, st, c2p_it)) {
+          if (Xt[0] > 0.0 && imp_build(Xt, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, st, c2p_it)) {
             imp_residual(st, Xt, Rt);
             if (vmaxabs4(Rt) < rn || lam * dn <= 1e-10 * sc) { acc = true; break; }
           }
@@ -644,29 +688,15 @@ __device__ __forceinline__ int implicit_cell(const double Us[NV], double h, doub
         if (vmaxabs4(stp) <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
       }
     }
+    iters = it;
   }
-  iters = it;
   if (!conv) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) Un[q] = Us[q];
-    return 1;
+    return IMP_FAILED;
   }
-  const double FF = (X[1] * X[1] + X[2] * X[2]) + X[3] * X[3];
-  if (FF > X[0] * X[0]) {
-    const double r = X[0] / sqrt(FF);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) X[1 + j] = X[1 + j] * r;
-  }
-  Un[0] = Us[0];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) Un[1 + j] = St[j] - X[1 + j];
-  Un[4] = Et - X[0];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) Un[5 + j] = Us[5 + j];
-  Un[8] = X[0];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) Un[9 + j] = X[1 + j];
-  return 0;
+  imp_finish(X, Us, in, Un);
+  return IMP_DONE;
 }
 
 // ---------------------------------------------------------------------------

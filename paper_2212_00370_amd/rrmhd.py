@@ -21,7 +21,7 @@ RECON_GODUNOV, RECON_MINMOD = 0, 1
 BETA_ALL, BETA_RAD_ONLY, BETA_OFF = 0, 1, 2
 IMP_PICARD_NEWTON, IMP_NEWTON, IMP_PICARD = 0, 1, 2
 FP64 = 0
-K_PRIMS, K_FACES, K_UPDATE, K_SPEED = 0, 1, 2, 3
+K_PRIMS, K_FACES, K_UPDATE, K_SPEED, K_NEWTON = 0, 1, 2, 3, 4
 
 
 class rrmhd_grid(C.Structure):
