@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -83,7 +84,8 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     P = I.blast_2d(args.seed, args.n, steps=args.steps)
-    params = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad)
+    mixed = args.precision == "mixed"
+    params = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=R.MIXED if mixed else R.FP64)
     grid = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
     solver = R.Solver(grid, params, device=dev)
     V = torch.from_numpy(P.V).to(dev)
@@ -125,7 +127,7 @@ def main():
     ops = load_json(os.path.join(ROOT, "oracle", f"opcount_blast2d_{args.n}.json"))
     fms, flaunch, ffaces = prof["faces"]
     roof = None
-    if ops and flaunch > 0:
+    if ops and flaunch > 0 and not mixed:
         per_face = ops["faces_ops_per_face"]
         mean_s = fms / 1e3 / flaunch
         flops_per_launch = per_face * ffaces / flaunch
@@ -151,11 +153,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": f"2D RRMHD+M1 magnetised blast {P.shape[0]}x{P.shape[1]} FP64, seed {args.seed}, "
+        "config": {"workload": f"2D RRMHD+M1 magnetised blast {P.shape[0]}x{P.shape[1]} "
+                               f"{'mixed FP32/FP64' if mixed else 'FP64'}, seed {args.seed}, "
                                f"PVM-int-8, PLM MinMod, IMEX RK2, CFL {P.cfl}, {args.steps} steps",
-                   "cells": P.ncell, "precision": "fp64", "beta_mode": "radiation rows"},
+                   "cells": P.ncell, "precision": args.precision, "beta_mode": "radiation rows"},
         "roofline": roof,
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
         "failures": {k: rep[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")},

@@ -49,7 +49,12 @@ typedef enum { RRMHD_BC_PERIODIC = 0, RRMHD_BC_OUTFLOW = 1, RRMHD_BC_INFLOW = 2 
 enum { RRMHD_RECON_GODUNOV = 0, RRMHD_RECON_MINMOD = 1 };
 enum { RRMHD_BETA_ALL = 0, RRMHD_BETA_RAD_ONLY = 1, RRMHD_BETA_OFF = 2 };
 enum { RRMHD_IMP_PICARD_NEWTON = 0, RRMHD_IMP_NEWTON = 1, RRMHD_IMP_PICARD = 2 };
-enum { RRMHD_FP64 = 0 };
+/* Precision of the explicit step. RRMHD_FP64: everything in binary64.
+ * RRMHD_MIXED: reconstruction, fluxes and the PVM Horner / finite-difference
+ * arithmetic in binary32 with a relative difference step pvm_eps_mixed; all
+ * primitive recoveries, the flux divergence and the implicit solve in
+ * binary64. */
+enum { RRMHD_FP64 = 0, RRMHD_MIXED = 1 };
 
 /* Cartesian grid of interior cells (Section 3.1: finite volumes, cell
  * averages). Cells outside the domain are not stored: periodic boundaries
@@ -85,7 +90,8 @@ typedef struct {
   int imp_maxit;
   int imp_picard_it;/* Picard iterations before Newton (eq. C^(m) iteration)            */
   int imp_method;   /* RRMHD_IMP_*                                                      */
-  int precision;    /* RRMHD_FP64                                                       */
+  int precision;    /* RRMHD_FP64 | RRMHD_MIXED                                         */
+  double pvm_eps_mixed; /* relative finite-difference step of the FP32 chain (2^-12)   */
 } rrmhd_params;
 
 /* Gray comoving opacities per unit mass (eqs. g0, gi): device arrays [ncell]

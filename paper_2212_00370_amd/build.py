@@ -15,6 +15,10 @@ HIPCC_FLAGS = [
     # Evaluation order is part of the numerics (see rrmhd_device.hpp): no
     # contraction into FMA, no fast-math.
     "-ffp-contract=off", "-fno-fast-math",
+    # FP32 division and sqrt (mixed-precision flux arithmetic only) use the
+    # hardware reciprocal / square-root instructions; binary64 operations are
+    # unaffected and stay IEEE correctly rounded.
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     # No packed FP32 instructions in any kernel.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fPIC", "-shared",

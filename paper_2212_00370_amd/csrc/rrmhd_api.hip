@@ -274,12 +274,57 @@ __device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, l
   its = (unsigned int)cit;
 }
 
+// Mixed precision: the same stencil in FP32 (FP64 recoveries inside), FP32
+// fluxes out.
+template <int d>
+__device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs& A, long long f, const Phys& K,
+                                                unsigned long long& fb, unsigned int& its) {
+  int fn0 = G.n[0], fn1 = G.n[1];
+  if (d == 0) fn0 += 1;
+  if (d == 1) fn1 += 1;
+  int c[3];
+  c[0] = (int)(f % fn0);
+  c[1] = (int)((f / fn0) % fn1);
+  c[2] = (int)(f / ((long long)fn0 * fn1));
+  float Vs[4][NV];
+  float tp[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    int cc[3] = {c[0], c[1], c[2]};
+    cc[d] = c[d] - 2 + s;
+    const long long m = map_cell(G, cc[0], cc[1], cc[2], d);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Vs[s][q] = (float)A.Vp[q * A.np + m];
+    tp[s] = (float)A.taup[m];
+  }
+  float sa[NV], sb[NV];
+  rr::cell_slopes<float>(Vs[0], Vs[1], Vs[2], K.recon, sa);
+  rr::cell_slopes<float>(Vs[1], Vs[2], Vs[3], K.recon, sb);
+  float VL[NV], VR[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) { VL[q] = Vs[1][q] + 0.5f * sa[q]; VR[q] = Vs[2][q] - 0.5f * sb[q]; }
+  rr::limit_rad_flux<float>(VL);
+  rr::limit_rad_flux<float>(VR);
+  const float dxd = (float)A.dx[d];
+  float Fq[NV];
+  int fallback = 0, cit = 0;
+  rr::pvm_face_mixed<d>(VL, VR, tp[1] * dxd, tp[2] * dxd, K, Fq, fallback, cit);
+  float* out = (float*)A.Fh[d];
+  const long long nf = A.nf[d];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) out[q * nf + f] = Fq[q];
+  fb = (unsigned long long)fallback;
+  its = (unsigned int)cit;
+}
+
 // Face fluxes of all directions in one launch: blocks [0, nb0) take x faces,
 // the next nb1 blocks y faces, then z. The direction is uniform per block.
 // Two waves per SIMD (at the price of a few spilled registers) hide more of
 // the FP64 and transcendental latency than one wave with no spills.
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep,
-                                                  unsigned int* blkmax) {
+// FT = double: FP64 path; FT = float: mixed-precision path.
+template <typename FT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax) {
   long long b = blockIdx.x;
   int d = 0;
   if (b >= A.nb[0]) {
@@ -291,9 +336,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
   unsigned long long fb = 0;
   unsigned int its = 0;
   if (f < A.nf[d]) {
-    if (d == 0) face_body<0>(G, A, f, K, fb, its);
-    else if (d == 1) face_body<1>(G, A, f, K, fb, its);
-    else face_body<2>(G, A, f, K, fb, its);
+    if constexpr (sizeof(FT) == sizeof(double)) {
+      if (d == 0) face_body<0>(G, A, f, K, fb, its);
+      else if (d == 1) face_body<1>(G, A, f, K, fb, its);
+      else face_body<2>(G, A, f, K, fb, its);
+    } else {
+      if (d == 0) face_body_mixed<0>(G, A, f, K, fb, its);
+      else if (d == 1) face_body_mixed<1>(G, A, f, K, fb, its);
+      else face_body_mixed<2>(G, A, f, K, fb, its);
+    }
   }
   report_add(rep, blkmax, 0, fb, 0, 0, ULLONG_MAX, its, 0);
 }
@@ -305,7 +356,7 @@ struct StageArgs {
   long long ss;
   double* Uo;
   long long so;
-  const double* Fh[3];
+  const void* Fh[3];   // double (FP64 path) or float (mixed path)
   long long nf[3];
   double idx[3];
   double a0, a1, cdt;
@@ -314,9 +365,15 @@ struct StageArgs {
 // Flux divergence and stage combination, then phase 1 of the implicit solve
 // (Picard). Cells that need the Newton phase get their explicit state U*
 // written to the output and are appended to `worklist` (one atomic per wave).
+// FT: storage type of the face fluxes; the divergence is accumulated in FP64
+// either way (differences of stored values are exact in FP64 for FP32 data).
+template <typename FT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
          long long* worklist, unsigned long long* wcount) {
+  const FT* F0 = (const FT*)A.Fh[0];
+  const FT* F1 = (const FT*)A.Fh[1];
+  const FT* F2 = (const FT*)A.Fh[2];
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
@@ -335,9 +392,9 @@ k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* 
     double Ust[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      double div = (A.Fh[0][q * A.nf[0] + fm[0] + fs[0]] - A.Fh[0][q * A.nf[0] + fm[0]]) * A.idx[0];
-      if (G.ndim > 1) div = div + (A.Fh[1][q * A.nf[1] + fm[1] + fs[1]] - A.Fh[1][q * A.nf[1] + fm[1]]) * A.idx[1];
-      if (G.ndim > 2) div = div + (A.Fh[2][q * A.nf[2] + fm[2] + fs[2]] - A.Fh[2][q * A.nf[2] + fm[2]]) * A.idx[2];
+      double div = ((double)F0[q * A.nf[0] + fm[0] + fs[0]] - (double)F0[q * A.nf[0] + fm[0]]) * A.idx[0];
+      if (G.ndim > 1) div = div + ((double)F1[q * A.nf[1] + fm[1] + fs[1]] - (double)F1[q * A.nf[1] + fm[1]]) * A.idx[1];
+      if (G.ndim > 2) div = div + ((double)F2[q * A.nf[2] + fm[2] + fs[2]] - (double)F2[q * A.nf[2] + fm[2]]) * A.idx[2];
       Ust[q] = (A.a0 * A.U0[q * A.s0 + c] + A.a1 * A.Us[q * A.ss + c]) - A.cdt * div;
     }
     double Un[NV];
@@ -546,7 +603,8 @@ bool params_valid(const rrmhd_params* p) {
   if (p->c2p_maxit < 1 || p->imp_maxit < 1 || p->imp_picard_it < 0) return false;
   if (p->imp_method < 0 || p->imp_method > 2) return false;
   if (!(p->c2p_tol > 0.0) || !(p->imp_tol > 0.0)) return false;
-  if (p->precision != RRMHD_FP64) return false;
+  if (p->precision != RRMHD_FP64 && p->precision != RRMHD_MIXED) return false;
+  if (!(p->pvm_eps_mixed > 0.0 && p->pvm_eps_mixed < 0.5)) return false;
   return true;
 }
 
@@ -582,6 +640,7 @@ Phys make_phys(const rrmhd_params* p) {
   K.t_coeff = p->t_coeff;
   K.eps = p->pvm_eps;
   K.ieps = 1.0 / p->pvm_eps;
+  K.eps32 = p->pvm_eps_mixed;
   K.c2p_tol = p->c2p_tol;
   K.imp_tol = p->imp_tol;
   K.rho_floor = p->rho_floor;
@@ -742,7 +801,10 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
     nbt += A.nb[d];
   }
   pe = prof_begin(c, RRMHD_K_FACES, A.nf[0] + A.nf[1] + A.nf[2]);
-  k_faces<<<(unsigned int)nbt, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax);
+  if (c->par.precision == RRMHD_MIXED)
+    k_faces<float><<<(unsigned int)nbt, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax);
+  else
+    k_faces<double><<<(unsigned int)nbt, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax);
   prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   return RRMHD_OK;
@@ -772,6 +834,7 @@ void rrmhd_default_params(rrmhd_params* p) {
   p->imp_picard_it = 8;
   p->imp_method = RRMHD_IMP_PICARD_NEWTON;
   p->precision = RRMHD_FP64;
+  p->pvm_eps_mixed = 1.0 / 4096.0;
 }
 
 size_t rrmhd_workspace_bytes(const rrmhd_grid* g, const rrmhd_params* p) {
@@ -889,7 +952,10 @@ rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt,
     A.a1 = co[s][1];
     A.cdt = co[s][2] * dt;
     int pe = prof_begin(c, RRMHD_K_UPDATE, L.N);
-    k_update<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
+    if (c->par.precision == RRMHD_MIXED)
+      k_update<float><<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
+    else
+      k_update<double><<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
     prof_end(c, pe);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
     // Grid-stride over the work list; a few blocks per CU.

@@ -27,6 +27,7 @@ struct Phys {
   double gamma, g1, gm1g, gm1;  // gamma, gamma/(gamma-1), (gamma-1)/gamma, gamma-1
   double a_rad, t_coeff;
   double eps, ieps;             // PVM finite-difference step and its reciprocal
+  double eps32;                 // relative step of the FP32 chain (mixed precision)
   double c2p_tol, imp_tol;
   double rho_floor, p_floor;
   int c2p_maxit, imp_maxit, imp_picard_it, imp_method;
@@ -42,30 +43,39 @@ __device__ __forceinline__ double dmin(double a, double b) { return (a < b) ? a 
 // Quantities derived from primitives (definitions after eqs. eqU/eqF):
 // W, b^0 = W v.B, b^i = B^i/W + v^i b^0, |b|^2 = B^2/W^2 + (v.B)^2,
 // rho h* W^2 with rho h* = rho + gamma/(gamma-1) p + |b|^2, p* = p + |b|^2/2.
-struct Aux {
-  double W, iW, l2, b0, b[3], bb, wtot, ps, D;
+// Templated on the arithmetic type: double for the FP64 path, float for the
+// FP32 flux arithmetic of the mixed-precision path. The double instantiation
+// performs exactly the operations written (constants are exact).
+template <typename R>
+struct AuxT {
+  R W, iW, l2, b0, b[3], bb, wtot, ps, D;
 };
+using Aux = AuxT<double>;
 
-__device__ __forceinline__ void prim_aux(const double V[NV], const Phys& K, Aux& a) {
-  const double vx = V[1], vy = V[2], vz = V[3];
-  const double v2 = (vx * vx + vy * vy) + vz * vz;
-  a.l2 = 1.0 - v2;
+template <typename R>
+__device__ __forceinline__ void prim_aux(const R V[NV], R g1, AuxT<R>& a) {
+  const R vx = V[1], vy = V[2], vz = V[3];
+  const R v2 = (vx * vx + vy * vy) + vz * vz;
+  a.l2 = R(1) - v2;
   a.iW = sqrt(a.l2);
-  a.W = 1.0 / a.iW;
-  const double vB = (vx * V[5] + vy * V[6]) + vz * V[7];
+  a.W = R(1) / a.iW;
+  const R vB = (vx * V[5] + vy * V[6]) + vz * V[7];
   a.b0 = a.W * vB;
 #pragma unroll
   for (int j = 0; j < 3; ++j) a.b[j] = V[5 + j] * a.iW + V[1 + j] * a.b0;
-  const double B2 = (V[5] * V[5] + V[6] * V[6]) + V[7] * V[7];
+  const R B2 = (V[5] * V[5] + V[6] * V[6]) + V[7] * V[7];
   a.bb = B2 * a.l2 + vB * vB;
-  const double rhoh = V[0] + K.g1 * V[4];
+  const R rhoh = V[0] + g1 * V[4];
   a.wtot = (rhoh + a.bb) * (a.W * a.W);
-  a.ps = V[4] + 0.5 * a.bb;
+  a.ps = V[4] + R(0.5) * a.bb;
   a.D = V[0] * a.W;
 }
 
+__device__ __forceinline__ void prim_aux(const double V[NV], const Phys& K, Aux& a) { prim_aux<double>(V, K.g1, a); }
+
 // eq. eqU
-__device__ __forceinline__ void p2c(const double V[NV], const Aux& a, double U[NV]) {
+template <typename R>
+__device__ __forceinline__ void p2c(const R V[NV], const AuxT<R>& a, R U[NV]) {
   U[0] = a.D;
 #pragma unroll
   for (int j = 0; j < 3; ++j) U[1 + j] = a.wtot * V[1 + j] - a.b0 * a.b[j];
@@ -75,35 +85,60 @@ __device__ __forceinline__ void p2c(const double V[NV], const Aux& a, double U[N
 }
 
 // Row d of the M1 radiation pressure P = D_r E_r (eq. xi); n n := 0 when F = 0.
-template <int d>
-__device__ __forceinline__ void m1_row(double E, const double F[3], double P[3]) {
-  const double FF = (F[0] * F[0] + F[1] * F[1]) + F[2] * F[2];
-  const double f2 = FF / (E * E);
-  double t = 4.0 - 3.0 * f2;
-  t = (t > 0.0) ? t : 0.0;
-  const double s = sqrt(t);
-  const double xi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * s);
-  const double ca = 0.5 * (1.0 - xi);
-  const double cb = 0.5 * (3.0 * xi - 1.0);
-  if (FF > 0.0) {
-    const double iFF = 1.0 / FF;
+// The FP32 instantiation works with the reduced flux f = F/E_r (|f| <~ 1):
+// products of raw F_r components underflow FP32 where E_r ~ 1e-11.
+template <int d, typename R>
+__device__ __forceinline__ void m1_row(R E, const R F[3], R P[3]) {
+  if constexpr (sizeof(R) == sizeof(float)) {
+    const R iE = R(1) / E;
+    const R g[3] = {F[0] * iE, F[1] * iE, F[2] * iE};
+    const R f2 = (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
+    R t = R(4) - R(3) * f2;
+    t = (t > R(0)) ? t : R(0);
+    const R s = sqrt(t);
+    const R xi = (R(3) + R(4) * f2) / (R(5) + R(2) * s);
+    const R ca = R(0.5) * (R(1) - xi);
+    const R cb = R(0.5) * (R(3) * xi - R(1));
+    if (f2 > R(1e-30)) {
+      const R if2 = R(1) / f2;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const double nn = (F[d] * F[j]) * iFF;
-      P[j] = (j == d) ? E * (ca + cb * nn) : E * (cb * nn);
+      for (int j = 0; j < 3; ++j) {
+        const R nn = (g[d] * g[j]) * if2;
+        P[j] = (j == d) ? E * (ca + cb * nn) : E * (cb * nn);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) P[j] = (j == d) ? E * ca : R(0);
     }
   } else {
+    const R FF = (F[0] * F[0] + F[1] * F[1]) + F[2] * F[2];
+    const R f2 = FF / (E * E);
+    R t = R(4) - R(3) * f2;
+    t = (t > R(0)) ? t : R(0);
+    const R s = sqrt(t);
+    const R xi = (R(3) + R(4) * f2) / (R(5) + R(2) * s);
+    const R ca = R(0.5) * (R(1) - xi);
+    const R cb = R(0.5) * (R(3) * xi - R(1));
+    if (FF > R(0)) {
+      const R iFF = R(1) / FF;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) P[j] = (j == d) ? E * ca : 0.0;
+      for (int j = 0; j < 3; ++j) {
+        const R nn = (F[d] * F[j]) * iFF;
+        P[j] = (j == d) ? E * (ca + cb * nn) : E * (cb * nn);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) P[j] = (j == d) ? E * ca : R(0);
+    }
   }
 }
 
 // eq. eqF in direction d.
-template <int d>
-__device__ __forceinline__ void flux(const double V[NV], const Aux& a, double F[NV]) {
-  const double vd = V[1 + d];
+template <int d, typename R>
+__device__ __forceinline__ void flux(const R V[NV], const AuxT<R>& a, R F[NV]) {
+  const R vd = V[1 + d];
   F[0] = a.D * vd;
-  const double wv = a.wtot * vd;
+  const R wv = a.wtot * vd;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     if (j == d) F[1 + j] = (wv * V[1 + j] + a.ps) - a.b[d] * a.b[j];
@@ -113,7 +148,7 @@ __device__ __forceinline__ void flux(const double V[NV], const Aux& a, double F[
 #pragma unroll
   for (int j = 0; j < 3; ++j) F[5 + j] = vd * V[5 + j] - V[5 + d] * V[1 + j];
   F[8] = V[9 + d];
-  m1_row<d>(V[8], &V[9], &F[9]);
+  m1_row<d, R>(V[8], &V[9], &F[9]);
 }
 
 // ---------------------------------------------------------------------------
@@ -249,34 +284,48 @@ __device__ __forceinline__ bool recover_near(const double U[NV], const double Um
 // ---------------------------------------------------------------------------
 // PLM MinMod with the Godunov fallback for |v|^2 >= 1 and the |F_r| <= E_r
 // limit (Section 3.2, reconstruction).
-__device__ __forceinline__ double minmod(double a, double b) {
-  if ((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0)) return (dabs(a) < dabs(b)) ? a : b;
-  return 0.0;
+template <typename R>
+__device__ __forceinline__ R minmod(R a, R b) {
+  if ((a > R(0) && b > R(0)) || (a < R(0) && b < R(0))) return ((a < R(0) ? -a : a) < (b < R(0) ? -b : b)) ? a : b;
+  return R(0);
 }
 
-__device__ __forceinline__ void cell_slopes(const double Vm[NV], const double Vc[NV],
-                                            const double Vp[NV], int recon, double s[NV]) {
+template <typename R>
+__device__ __forceinline__ void cell_slopes(const R Vm[NV], const R Vc[NV], const R Vp[NV], int recon, R s[NV]) {
 #pragma unroll
-  for (int q = 0; q < NV; ++q) s[q] = (recon == 1) ? minmod(Vc[q] - Vm[q], Vp[q] - Vc[q]) : 0.0;
+  for (int q = 0; q < NV; ++q) s[q] = (recon == 1) ? minmod<R>(Vc[q] - Vm[q], Vp[q] - Vc[q]) : R(0);
   if (recon == 1) {
-    double lo[3], hi[3];
+    R lo[3], hi[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) { lo[j] = Vc[1 + j] - 0.5 * s[1 + j]; hi[j] = Vc[1 + j] + 0.5 * s[1 + j]; }
-    const double v2lo = (lo[0] * lo[0] + lo[1] * lo[1]) + lo[2] * lo[2];
-    const double v2hi = (hi[0] * hi[0] + hi[1] * hi[1]) + hi[2] * hi[2];
-    if (!(v2lo < 1.0) || !(v2hi < 1.0)) {
+    for (int j = 0; j < 3; ++j) { lo[j] = Vc[1 + j] - R(0.5) * s[1 + j]; hi[j] = Vc[1 + j] + R(0.5) * s[1 + j]; }
+    const R v2lo = (lo[0] * lo[0] + lo[1] * lo[1]) + lo[2] * lo[2];
+    const R v2hi = (hi[0] * hi[0] + hi[1] * hi[1]) + hi[2] * hi[2];
+    if (!(v2lo < R(1)) || !(v2hi < R(1))) {
 #pragma unroll
-      for (int q = 0; q < NV; ++q) s[q] = 0.0;
+      for (int q = 0; q < NV; ++q) s[q] = R(0);
     }
   }
 }
 
-__device__ __forceinline__ void limit_rad_flux(double V[NV]) {
-  const double FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
-  if (FF > V[8] * V[8]) {
-    const double r = V[8] / sqrt(FF);
+template <typename R>
+__device__ __forceinline__ void limit_rad_flux(R V[NV]) {
+  if constexpr (sizeof(R) == sizeof(float)) {
+    // reduced flux, as in m1_row
+    const R iE = R(1) / V[8];
+    const R g[3] = {V[9] * iE, V[10] * iE, V[11] * iE};
+    const R f2 = (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
+    if (f2 > R(1)) {
+      const R r = R(1) / sqrt(f2);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) V[9 + j] = V[9 + j] * r;
+      for (int j = 0; j < 3; ++j) V[9 + j] = V[9 + j] * r;
+    }
+  } else {
+    const R FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
+    if (FF > V[8] * V[8]) {
+      const R r = V[8] / sqrt(FF);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) V[9 + j] = V[9 + j] * r;
+    }
   }
 }
 
@@ -377,6 +426,140 @@ __device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV
   for (int q = 0; q < NV; ++q) {
     const double bq = (K.beta_mode == 2 || (K.beta_mode == 1 && q < 8)) ? 1.0 : beta;
     Fh[q] = Fa[q] - 0.5 * (bq * w[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-precision PVM-int face flux: reconstruction, p2c, fluxes and the
+// Horner/finite-difference arithmetic in FP32; every primitive recovery
+// (U_m and the intermediate states) in FP64. eps = 1e-8 is below FP32
+// rounding (U_m + eps w == U_m), so the chain keeps the paper's form
+// U_m + eps w with eps = eps32 = 2^-12, about the square root of the FP32
+// unit roundoff, which balances truncation and rounding error.
+__device__ __forceinline__ bool recover_near_mixed(const float U[NV], const float Um[NV], const float Vm[NV],
+                                                   double Zm, const Phys& K, float V[NV], int& nit) {
+  bool same = true;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) same = same && (U[q] == Um[q]);
+  if (same) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) V[q] = Vm[q];
+#pragma unroll
+    for (int q = 5; q < NV; ++q) V[q] = U[q];
+    nit = 0;
+    return true;
+  }
+  double Ud[NV], Vd[NV], Z = 0.0;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) Ud[q] = (double)U[q];
+  if (c2p(Ud, K, Zm, Vd, Z, nit) != 0) return false;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) V[q] = (float)Vd[q];
+#pragma unroll
+  for (int q = 5; q < NV; ++q) V[q] = U[q];
+  return true;
+}
+
+template <int d>
+__device__ __forceinline__ void pvm_face_mixed(const float VL[NV], const float VR[NV], float tauL, float tauR,
+                                               const Phys& K, float Fh[NV], int& fallback, int& c2p_its) {
+  const float g1 = (float)K.g1;
+  float Fa[NV], U0[NV], Um[NV];
+  {
+    float UL[NV], UR[NV], FL[NV], FR[NV];
+    {
+      AuxT<float> aL;
+      prim_aux<float>(VL, g1, aL);
+      p2c<float>(VL, aL, UL);
+      flux<d, float>(VL, aL, FL);
+    }
+    {
+      AuxT<float> aR;
+      prim_aux<float>(VR, g1, aR);
+      p2c<float>(VR, aR, UR);
+      flux<d, float>(VR, aR, FR);
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      U0[q] = UR[q] - UL[q];
+      Um[q] = 0.5f * (UL[q] + UR[q]);
+      Fa[q] = 0.5f * (FL[q] + FR[q]);
+    }
+  }
+  const float beta = 1.0f / fmaxf(fmaxf(tauL, tauR), 1.0f);
+  fallback = 0;
+  c2p_its = 0;
+  float w[NV];
+  bool ok = true;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) w[q] = U0[q];
+  if (K.M > 0) {
+    float Vm[NV], Fm[NV];
+    double Zm = 0.0;
+    int it = 0;
+    {
+      double Ud[NV], Vd[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) Ud[q] = (double)Um[q];
+      if (c2p(Ud, K, 0.0, Vd, Zm, it) != 0) ok = false;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) Vm[q] = (float)Vd[q];
+#pragma unroll
+      for (int q = 5; q < NV; ++q) Vm[q] = Um[q];
+    }
+    c2p_its += it;
+    if (ok) {
+      AuxT<float> am;
+      prim_aux<float>(Vm, g1, am);
+      flux<d, float>(Vm, am, Fm);
+    }
+    const float h = (float)K.eps32;
+    const float ih = 1.0f / h;
+    for (int l = 0; l < K.M && ok; ++l) {
+      float Y[NV];
+      {
+        float Ue[NV], Ve[NV], Fe[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Ue[q] = Um[q] + h * w[q];
+        if (!recover_near_mixed(Ue, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
+        c2p_its += it;
+        {
+          AuxT<float> ae;
+          prim_aux<float>(Ve, g1, ae);
+          flux<d, float>(Ve, ae, Fe);
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Ue[q] = Um[q] + (Fe[q] - Fm[q]);
+        if (!recover_near_mixed(Ue, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
+        c2p_its += it;
+        {
+          AuxT<float> at;
+          prim_aux<float>(Ve, g1, at);
+          flux<d, float>(Ve, at, Fe);
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Y[q] = (Fe[q] - Fm[q]) * ih;
+      }
+      const float cnext = (float)K.coef[K.M - 1 - l];
+      if (l == 0) {
+        const float ctop = (float)K.coef[K.M];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) w[q] = ctop * Y[q] + cnext * U0[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) w[q] = Y[q] + cnext * U0[q];
+      }
+    }
+    if (!ok) {
+      fallback = 1;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) w[q] = U0[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const float bq = (K.beta_mode == 2 || (K.beta_mode == 1 && q < 8)) ? 1.0f : beta;
+    Fh[q] = Fa[q] - 0.5f * (bq * w[q]);
   }
 }
 

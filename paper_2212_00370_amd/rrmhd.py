@@ -20,7 +20,7 @@ BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 RECON_GODUNOV, RECON_MINMOD = 0, 1
 BETA_ALL, BETA_RAD_ONLY, BETA_OFF = 0, 1, 2
 IMP_PICARD_NEWTON, IMP_NEWTON, IMP_PICARD = 0, 1, 2
-FP64 = 0
+FP64, MIXED = 0, 1
 K_PRIMS, K_FACES, K_UPDATE, K_SPEED, K_NEWTON = 0, 1, 2, 3, 4
 
 
@@ -39,7 +39,7 @@ class rrmhd_params(C.Structure):
         ("rho_floor", C.c_double), ("p_floor", C.c_double),
         ("pvm_k", C.c_int), ("beta_mode", C.c_int), ("recon", C.c_int), ("rk_order", C.c_int),
         ("c2p_maxit", C.c_int), ("imp_maxit", C.c_int), ("imp_picard_it", C.c_int),
-        ("imp_method", C.c_int), ("precision", C.c_int),
+        ("imp_method", C.c_int), ("precision", C.c_int), ("pvm_eps_mixed", C.c_double),
     ]
 
 

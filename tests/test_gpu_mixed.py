@@ -1,0 +1,79 @@
+"""Mixed precision (FP32 reconstruction/flux/PVM arithmetic, FP64 recoveries,
+divergence and implicit solve) against the FP64 CPU oracle.
+
+The mixed path is not bitwise: its finite differences use a relative step of
+2^-12 (eps = 1e-8 is below FP32 rounding), so its truncation error is
+O(2^-12). The tests state the L1 bound and check conservation to FP64
+round-off (one stored flux per face, divergence accumulated in FP64).
+"""
+import numpy as np
+import pytest
+
+from paper_2212_00370_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2212_00370_amd import rrmhd
+    return rrmhd
+
+
+def l1rel(a, b):
+    return float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
+
+
+def run_pair(R, oracle, P, steps, check_at):
+    import torch
+    p = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=R.MIXED)
+    op = oracle.params(gamma=P.gamma, a_rad=P.a_rad, beta_mode=p.beta_mode)
+    g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
+    og = oracle.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
+    s = R.Solver(g, p)
+    U0 = oracle.p2c(P.V, op)
+    Ud = torch.from_numpy(U0).to("cuda:0")
+    opac = R.make_opacities(torch.from_numpy(P.kappa).to("cuda:0"), torch.from_numpy(P.sigma).to("cuda:0"))
+    Uo = U0.copy()
+    out = {}
+    for k in range(1, steps + 1):
+        sm, _ = oracle.max_speed(og, Uo, op)
+        dt = P.cfl * min(P.dx) / sm
+        Uo, st, rep = oracle.step(og, Uo, dt, P.kappa, P.sigma, op)
+        assert st == 0
+        s.step(Ud, dt, opac)
+        if k in check_at:
+            Ug = Ud.cpu().numpy()
+            Vg = s.cons_to_prim(Ud).cpu().numpy()
+            Vo, _, _, _ = oracle.c2p(Uo, op)
+            out[k] = dict(rho=l1rel(Vg[0], Vo[0]), Er=l1rel(Ug[8], Uo[8]))
+    rep = s.report()
+    s.close()
+    return out, rep, Ud.cpu().numpy(), U0
+
+
+def test_mixed_blast_l1_and_conservation(R, oracle):
+    oracle.threads(0)
+    P = I.blast_2d(0, 256)
+    out, rep, U, U0 = run_pair(R, oracle, P, 200, (1, 10, 50, 200))
+    print("mixed-precision L1 vs FP64 oracle (256^2 blast):", out)
+    assert rep["c2p_fail"] == 0 and rep["imp_fail"] == 0 and rep["nonfinite"] == 0
+    for k, e in out.items():
+        assert e["rho"] < 1e-3 and e["Er"] < 1e-2, (k, e)
+    # periodic grid: conservation to FP64 round-off despite FP32 fluxes
+    tot = lambda U: np.array([U[0].sum(), (U[4] + U[8]).sum(), *(U[1:4] + U[9:12]).sum(axis=1)])
+    scale = np.abs(U0[0]).sum() + np.abs(U0[4] + U0[8]).sum()
+    assert np.max(np.abs(tot(U) - tot(U0))) / scale < 1e-13
+
+
+@pytest.mark.parametrize("seed", [0, 2, 5])
+def test_mixed_riemann_1d(R, oracle, seed):
+    P = I.riemann_1d(seed)
+    out, rep, U, U0 = run_pair(R, oracle, P, 60, (1, 60))
+    print(f"seed {seed}:", out)
+    assert rep["c2p_fail"] == 0 and rep["imp_fail"] == 0
+    assert out[1]["rho"] < 1e-4
+    assert out[60]["rho"] < 1e-2
