@@ -59,6 +59,73 @@ def cpu_baseline(P, steps: int):
                        f"(CFL signal speed + IMEX step), {el:.1f} s")
 
 
+def serving_bench(args):
+    """Continuous batching of a Poisson stream of independent problems (1D
+    Riemann N ~ logU[256, 8192] to t = 0.05; 2D blasts N^2, N ~ logU[64, 512],
+    10-50 steps; FP64 / mixed 50/50). Capacity is measured first with every
+    request present at t = 0; the timed run uses Poisson arrivals at
+    `load` x capacity. The comparison runs the same requests one at a time in
+    FP64 through rrmhd_step."""
+    import numpy as np
+    import torch
+    from paper_2212_00370_amd import inputs as I
+    from paper_2212_00370_amd import rrmhd as R
+    from paper_2212_00370_amd import serving as S
+
+    mix = I.serving_mix(args.seed, args.requests)
+    def reqs(arrivals, force_fp64=False):
+        return [S.Request(rid=i, problem=m["problem"], precision=R.FP64 if (force_fp64 or not m["mixed"]) else R.MIXED,
+                          t_end=m["t_end"], steps=m["steps"], arrival=float(a)) for i, (m, a) in enumerate(zip(mix, arrivals))]
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.5 * free)
+    # capacity: all requests present at once
+    srv = S.Server(budget, max_sims=256)
+    t0 = time.perf_counter()
+    res0 = srv.run(reqs(np.zeros(len(mix))))
+    cap_s = time.perf_counter() - t0
+    srv.close()
+    zu = sum(r.zone_updates for r in res0)
+    mu = len(mix) / cap_s
+    rate = args.load * mu
+    arr = I.poisson_arrivals(args.seed + 1, len(mix), rate)
+    srv = S.Server(budget, max_sims=256)
+    t0 = time.perf_counter()
+    res = srv.run(reqs(arr))
+    wall = time.perf_counter() - t0
+    tts = [r.time_to_solution for r in res]
+    # one at a time, FP64, single-simulation entry points
+    t0 = time.perf_counter()
+    for m in mix:
+        P = m["problem"]
+        p = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad)
+        g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
+        s = R.Solver(g, p)
+        U = s.prim_to_cons(torch.from_numpy(P.V).cuda())
+        o = R.make_opacities(torch.from_numpy(P.kappa).cuda(), torch.from_numpy(P.sigma).cuda())
+        t, k = 0.0, 0
+        while (m["steps"] is not None and k < m["steps"]) or (m["t_end"] is not None and t < m["t_end"] * (1 - 1e-14)):
+            dt = P.cfl * min(P.dx) / s.max_speed(U)
+            if m["t_end"] is not None:
+                dt = min(dt, m["t_end"] - t)
+            s.step(U, dt, o)
+            t += dt; k += 1
+        torch.cuda.synchronize()
+        s.close()
+    seq_s = time.perf_counter() - t0
+    return {
+        "metric": METRIC, "value": zu / wall, "unit": "zone-updates/s", "n_gpus": 1,
+        "mode": "serving", "requests": len(mix), "higher_is_better": True, "data": "synthetic",
+        "dtype": "f64 and f32+f64 requests (50/50)",
+        "p50_time_to_solution_s": S.percentile(tts, 50), "p99_time_to_solution_s": S.percentile(tts, 99),
+        "arrival_rate_per_s": rate, "capacity_req_per_s": mu, "load": args.load,
+        "capacity_zone_updates_per_s": zu / cap_s, "sequential_fp64_zone_updates_per_s": zu / seq_s,
+        "wall_s": wall, "ticks": srv.ticks, "mean_batch": float(np.mean(srv.batch_sizes)),
+        "hbm_budget_bytes": budget, "peak_resident_bytes": srv.peak_in_use,
+        "config": {"workload": "Poisson stream: 1D Riemann N~logU[256,8192] to t=0.05, 2D blast N^2 with "
+                               "N~logU[64,512] for 10-50 steps, FP64/mixed 50/50"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -69,6 +136,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--mode", choices=("step", "serving"), default="step")
+    ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--load", type=float, default=0.8, help="arrival rate / measured capacity")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -83,6 +153,9 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.mode == "serving":
+        print(json.dumps(serving_bench(args)), flush=True)
+        return
     P = I.blast_2d(args.seed, args.n, steps=args.steps)
     mixed = args.precision == "mixed"
     params = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=R.MIXED if mixed else R.FP64)

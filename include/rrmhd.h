@@ -182,6 +182,40 @@ rrmhd_status rrmhd_profile_read(rrmhd_ctx* ctx, int k, double* total_ms, long lo
 /* Read the failure counters (synchronizes the stream) and reset them. */
 rrmhd_status rrmhd_report_sync(rrmhd_ctx* ctx, rrmhd_report* out);
 
+/* ---- Batched stepping of independent simulations (serving) ----------------
+ * A batch advances several contexts (each with its own grid, parameters,
+ * state and workspace) with one launch per kernel class and stage: every
+ * block looks its simulation up in a device descriptor table. Each
+ * simulation's arithmetic is exactly that of rrmhd_step / rrmhd_max_speed,
+ * so results do not depend on the batch composition. Work is enqueued on the
+ * batch's stream; the contexts must not be used on other streams meanwhile.
+ * All contexts of one call must use the same rk_order, and a context may
+ * appear only once per call. */
+typedef struct rrmhd_batch rrmhd_batch;
+
+/* Device workspace for a batch of up to max_sims simulations (descriptor
+ * table, block offsets, per-simulation maxima); 0 if max_sims is invalid. */
+size_t rrmhd_batch_workspace_bytes(int max_sims);
+
+/* Create a batch handle. workspace: caller-owned device memory, 256-byte
+ * aligned, >= rrmhd_batch_workspace_bytes(max_sims). Allocates pinned host
+ * staging buffers and two events. */
+rrmhd_status rrmhd_batch_init(rrmhd_batch** b, int max_sims, void* workspace, size_t ws_bytes,
+                              void* hip_stream);
+
+/* Signal speed of each simulation (as rrmhd_max_speed), all in one pass;
+ * one stream synchronization for the whole batch. smax_host: [nsim]. */
+rrmhd_status rrmhd_max_speed_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx,
+                                   const double* const* U, double* smax_host);
+
+/* One IMEX step of each simulation s with its own dt_host[s] (as
+ * rrmhd_step with the context's grid). opac: [nsim] (entries may be NULL for
+ * zero opacity). Enqueued. */
+rrmhd_status rrmhd_step_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, double* const* U,
+                              const double* dt_host, const rrmhd_opacities* const* opac);
+
+void rrmhd_batch_destroy(rrmhd_batch* b);
+
 /* Release the context (not the workspace, which the caller owns). */
 void rrmhd_destroy(rrmhd_ctx* ctx);
 

@@ -86,7 +86,8 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
 // serializes thousands of waves): each block keeps a running maximum in its
 // own slot of `blkmax` (one writer per slot, launches ordered on the stream),
 // folded into the report by rrmhd_report_sync.
-__device__ __forceinline__ void report_add(DevReport* rep, unsigned int* blkmax, unsigned long long f_c2p,
+__device__ __forceinline__ void report_add(DevReport* rep, unsigned int* blkmax, long long slot_block,
+                                           unsigned long long f_c2p,
                                            unsigned long long f_pvm, unsigned long long f_imp,
                                            unsigned long long f_nf, unsigned long long bad_cell,
                                            unsigned int c2p_it, unsigned int imp_it) {
@@ -117,7 +118,7 @@ __device__ __forceinline__ void report_add(DevReport* rep, unsigned int* blkmax,
       a = (red_it[0][w] > a) ? red_it[0][w] : a;
       b = (red_it[1][w] > b) ? red_it[1][w] : b;
     }
-    unsigned int* slot = blkmax + 2 * (size_t)blockIdx.x;
+    unsigned int* slot = blkmax + 2 * (size_t)slot_block;
     if (a > slot[0]) slot[0] = a;
     if (b > slot[1]) slot[1] = b;
   }
@@ -181,18 +182,19 @@ __global__ void __launch_bounds__(kBlock) k_c2p(long long n, const double* __res
 #pragma unroll
     for (int q = 0; q < NV; ++q) V[q * sv + c] = v[q];
   }
-  report_add(rep, blkmax, fail, 0, 0, 0, bad, its, 0);
+  report_add(rep, blkmax, blockIdx.x, fail, 0, 0, 0, bad, its, 0);
 }
 
 // Stage primitives: interior cells (c < N) from U, inflow cells from inflow_U.
-// Vp: [12][Np], taup: [Np] = D (kappa + sigma).
-__global__ void __launch_bounds__(kBlock) k_prims(GridDev G, const double* __restrict__ U, long long su,
-                                                  const double* __restrict__ inU, Opac op,
-                                                  double* __restrict__ Vp, double* __restrict__ taup,
-                                                  long long np, Phys K, DevReport* rep, unsigned int* blkmax,
-                                                  unsigned long long* wcount) {
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c == 0) *wcount = 0;  // work list of this stage's implicit Newton phase
+// Vp: [12][Np], taup: [Np] = D (kappa + sigma). lb: block index within the
+// simulation. Cell 0 also clears the stage's Newton work-list counter.
+__device__ __forceinline__ void prims_block(long long lb, const GridDev& G, const double* __restrict__ U,
+                                            long long su, const double* __restrict__ inU, const Opac& op,
+                                            double* __restrict__ Vp, double* __restrict__ taup, long long np,
+                                            const Phys& K, DevReport* rep, unsigned int* blkmax,
+                                            unsigned long long* wcount) {
+  const long long c = lb * kBlock + threadIdx.x;
+  if (c == 0) *wcount = 0;
   unsigned long long fail = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
   if (c < G.N + G.nt) {
@@ -218,7 +220,15 @@ __global__ void __launch_bounds__(kBlock) k_prims(GridDev G, const double* __res
     for (int q = 0; q < NV; ++q) Vp[q * np + c] = v[q];
     taup[c] = u[0] * (opac_at(op.kappa, op.kappa0, oc) + opac_at(op.sigma, op.sigma0, oc));
   }
-  report_add(rep, blkmax, fail, 0, 0, 0, bad, its, 0);
+  report_add(rep, blkmax, lb, fail, 0, 0, 0, bad, its, 0);
+}
+
+__global__ void __launch_bounds__(kBlock) k_prims(GridDev G, const double* __restrict__ U, long long su,
+                                                  const double* __restrict__ inU, Opac op,
+                                                  double* __restrict__ Vp, double* __restrict__ taup,
+                                                  long long np, Phys K, DevReport* rep, unsigned int* blkmax,
+                                                  unsigned long long* wcount) {
+  prims_block(blockIdx.x, G, U, su, inU, op, Vp, taup, np, K, rep, blkmax, wcount);
 }
 
 struct FaceArgs {
@@ -319,24 +329,22 @@ __device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs
 
 // Face fluxes of all directions in one launch: blocks [0, nb0) take x faces,
 // the next nb1 blocks y faces, then z. The direction is uniform per block.
-// Two waves per SIMD (at the price of a few spilled registers) hide more of
-// the FP64 and transcendental latency than one wave with no spills.
-// FT = double: FP64 path; FT = float: mixed-precision path.
-template <typename FT>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
-k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax) {
-  long long b = blockIdx.x;
+// MIXED selects the mixed-precision stencil (FP32 fluxes out).
+template <bool MIXED>
+__device__ __forceinline__ void faces_block(long long lb, const GridDev& G, const FaceArgs& A, const Phys& K,
+                                            DevReport* rep, unsigned int* blkmax) {
+  long long b = lb;
   int d = 0;
   if (b >= A.nb[0]) {
     b -= A.nb[0];
     d = 1;
     if (b >= A.nb[1]) { b -= A.nb[1]; d = 2; }
   }
-  const long long f = b * blockDim.x + threadIdx.x;
+  const long long f = b * kBlock + threadIdx.x;
   unsigned long long fb = 0;
   unsigned int its = 0;
   if (f < A.nf[d]) {
-    if constexpr (sizeof(FT) == sizeof(double)) {
+    if constexpr (!MIXED) {
       if (d == 0) face_body<0>(G, A, f, K, fb, its);
       else if (d == 1) face_body<1>(G, A, f, K, fb, its);
       else face_body<2>(G, A, f, K, fb, its);
@@ -346,7 +354,16 @@ k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax) {
       else face_body_mixed<2>(G, A, f, K, fb, its);
     }
   }
-  report_add(rep, blkmax, 0, fb, 0, 0, ULLONG_MAX, its, 0);
+  report_add(rep, blkmax, lb, 0, fb, 0, 0, ULLONG_MAX, its, 0);
+}
+
+// Two waves per SIMD (at the price of a few spilled registers) hide more of
+// the FP64 and transcendental latency than one wave with no spills.
+// FT = double: FP64 path; FT = float: mixed-precision path.
+template <typename FT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax) {
+  faces_block<sizeof(FT) == sizeof(float)>(blockIdx.x, G, A, K, rep, blkmax);
 }
 
 struct StageArgs {
@@ -368,13 +385,13 @@ struct StageArgs {
 // FT: storage type of the face fluxes; the divergence is accumulated in FP64
 // either way (differences of stored values are exact in FP64 for FP32 data).
 template <typename FT>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
-k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
-         long long* worklist, unsigned long long* wcount) {
+__device__ __forceinline__ void update_block(long long lb, const GridDev& G, const StageArgs& A, const Opac& op,
+                                             const Phys& K, DevReport* rep, unsigned int* blkmax,
+                                             long long* worklist, unsigned long long* wcount) {
   const FT* F0 = (const FT*)A.Fh[0];
   const FT* F1 = (const FT*)A.Fh[1];
   const FT* F2 = (const FT*)A.Fh[2];
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long c = lb * kBlock + threadIdx.x;
   unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
   bool newton = false;
@@ -431,19 +448,28 @@ k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* 
       worklist[base + below] = c;
     }
   }
-  report_add(rep, blkmax, 0, 0, fimp, fnf, bad, 0, its);
+  report_add(rep, blkmax, lb, 0, 0, fimp, fnf, bad, 0, its);
+}
+
+template <typename FT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
+         long long* worklist, unsigned long long* wcount) {
+  update_block<FT>(blockIdx.x, G, A, op, K, rep, blkmax, worklist, wcount);
 }
 
 // Phase 2 of the implicit solve (Newton) for the cells in `worklist`; the
-// explicit state U* was left in the output by k_update. Grid-stride.
-__global__ void __launch_bounds__(kBlock)
-k_newton(StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
-         const long long* __restrict__ worklist, const unsigned long long* wcount) {
+// explicit state U* was left in the output by the update pass. Grid-stride
+// over the list with blocks bi = 0..nb-1.
+__device__ __forceinline__ void newton_blocks(long long bi, long long nb, const StageArgs& A, const Opac& op,
+                                              const Phys& K, DevReport* rep, unsigned int* blkmax,
+                                              const long long* __restrict__ worklist,
+                                              const unsigned long long* wcount) {
   const unsigned long long n = *wcount;
   unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
-  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (unsigned long long)gridDim.x * blockDim.x) {
+  for (unsigned long long i = (unsigned long long)bi * kBlock + threadIdx.x; i < n;
+       i += (unsigned long long)nb * kBlock) {
     const long long c = worklist[i];
     double Ust[NV], Un[NV];
 #pragma unroll
@@ -462,15 +488,21 @@ k_newton(StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
     if ((st != rr::IMP_DONE || !fin) && (unsigned long long)c < bad) bad = (unsigned long long)c;
     its = ((unsigned int)it > its) ? (unsigned int)it : its;
   }
-  report_add(rep, blkmax, 0, 0, fimp, fnf, bad, 0, its);
+  report_add(rep, blkmax, bi, 0, 0, fimp, fnf, bad, 0, its);
 }
 
-// Per-block maximum of the cell signal speeds -> partial[blockIdx.x].
-__global__ void __launch_bounds__(kBlock) k_speed(GridDev G, const double* __restrict__ U, long long su,
-                                                  Phys K, double* __restrict__ partial, DevReport* rep,
-                                                  unsigned int* blkmax) {
+__global__ void __launch_bounds__(kBlock)
+k_newton(StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
+         const long long* __restrict__ worklist, const unsigned long long* wcount) {
+  newton_blocks(blockIdx.x, gridDim.x, A, op, K, rep, blkmax, worklist, wcount);
+}
+
+// Per-block maximum of the cell signal speeds -> partial[lb].
+__device__ __forceinline__ void speed_block(long long lb, const GridDev& G, const double* __restrict__ U,
+                                            long long su, const Phys& K, double* __restrict__ partial,
+                                            DevReport* rep, unsigned int* blkmax) {
   __shared__ double red[kBlock / kWave];
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long c = lb * kBlock + threadIdx.x;
   double s = 0.0;
   unsigned long long fail = 0, bad = ULLONG_MAX;
   if (c < G.N) {
@@ -489,7 +521,7 @@ __global__ void __launch_bounds__(kBlock) k_speed(GridDev G, const double* __res
     if (G.ndim > 1) s = rr::dmax(s, rr::cell_speed<1>(v, a, K));
     if (G.ndim > 2) s = rr::dmax(s, rr::cell_speed<2>(v, a, K));
   }
-  report_add(rep, blkmax, fail, 0, 0, 0, bad, 0, 0);
+  report_add(rep, blkmax, lb, fail, 0, 0, 0, bad, 0, 0);
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) s = rr::dmax(s, __shfl_xor(s, o, kWave));
   if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
@@ -498,15 +530,21 @@ __global__ void __launch_bounds__(kBlock) k_speed(GridDev G, const double* __res
     double m = red[0];
 #pragma unroll
     for (int w = 1; w < kBlock / kWave; ++w) m = rr::dmax(m, red[w]);
-    partial[blockIdx.x] = m;
+    partial[lb] = m;
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_reduce_max(const double* __restrict__ partial, long long n,
-                                                       double* __restrict__ out) {
+__global__ void __launch_bounds__(kBlock) k_speed(GridDev G, const double* __restrict__ U, long long su,
+                                                  Phys K, double* __restrict__ partial, DevReport* rep,
+                                                  unsigned int* blkmax) {
+  speed_block(blockIdx.x, G, U, su, K, partial, rep, blkmax);
+}
+
+__device__ __forceinline__ void reduce_max_block(const double* __restrict__ partial, long long n,
+                                                 double* __restrict__ out) {
   __shared__ double red[kBlock / kWave];
   double s = 0.0;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) s = rr::dmax(s, partial[i]);
+  for (long long i = threadIdx.x; i < n; i += kBlock) s = rr::dmax(s, partial[i]);
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) s = rr::dmax(s, __shfl_xor(s, o, kWave));
   if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
@@ -517,6 +555,122 @@ __global__ void __launch_bounds__(kBlock) k_reduce_max(const double* __restrict_
     for (int w = 1; w < kBlock / kWave; ++w) m = rr::dmax(m, red[w]);
     out[0] = rr::dmin(m, 1.0);
   }
+}
+
+__global__ void __launch_bounds__(kBlock) k_reduce_max(const double* __restrict__ partial, long long n,
+                                                       double* __restrict__ out) {
+  reduce_max_block(partial, n, out);
+}
+
+// ---------------------------------------------------------------------------
+// Batched kernels: one launch covers every simulation of a batch. Each block
+// finds its simulation by binary search in a block-offset table and works on
+// that simulation's data exactly as the single-simulation kernels do, so a
+// simulation's result does not depend on what else is in the batch.
+struct SimDesc {
+  GridDev G;
+  Phys K;
+  Opac op;
+  FaceArgs FA;
+  double* Vp;
+  double* taup;
+  double idx[3];
+  double* U;
+  long long vs;
+  double* Us;
+  long long ns;
+  const double* inflow_U;
+  long long* work;
+  unsigned long long* wcount;
+  DevReport* rep;
+  unsigned int* blkmax;
+  double* partial;
+  long long npartial;
+  double dt;
+  int mixed;
+};
+
+enum { OFF_PRIMS = 0, OFF_FACES = 1, OFF_CELLS = 2, OFF_NEWTON = 3, OFF_KINDS = 4 };
+
+__device__ __forceinline__ int find_sim(const long long* __restrict__ off, int nsim, long long b) {
+  int lo = 0, hi = nsim;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ StageArgs stage_args(const SimDesc& D, int stage, int last, double a0, double a1,
+                                                double c) {
+  StageArgs A;
+  A.U0 = D.U; A.s0 = D.vs;
+  A.Us = (stage == 0) ? D.U : D.Us;
+  A.ss = (stage == 0) ? D.vs : D.ns;
+  A.Uo = last ? D.U : D.Us;
+  A.so = last ? D.vs : D.ns;
+  for (int d = 0; d < 3; ++d) {
+    A.Fh[d] = (d < D.G.ndim) ? (const void*)D.FA.Fh[d] : (const void*)D.FA.Fh[0];
+    A.nf[d] = D.FA.nf[d];
+    A.idx[d] = D.idx[d];
+  }
+  A.a0 = a0;
+  A.a1 = a1;
+  A.cdt = c * D.dt;
+  return A;
+}
+
+__global__ void __launch_bounds__(kBlock) k_prims_b(const SimDesc* __restrict__ T, const long long* __restrict__ off,
+                                                    int nsim, int stage) {
+  const long long* o = off + OFF_PRIMS * (nsim + 1);
+  const int s = find_sim(o, nsim, blockIdx.x);
+  const SimDesc& D = T[s];
+  const double* Us = (stage == 0) ? D.U : D.Us;
+  const long long ss = (stage == 0) ? D.vs : D.ns;
+  prims_block(blockIdx.x - o[s], D.G, Us, ss, D.inflow_U, D.op, D.Vp, D.taup, D.FA.np, D.K, D.rep, D.blkmax,
+              D.wcount);
+}
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_faces_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, int nsim) {
+  const long long* o = off + OFF_FACES * (nsim + 1);
+  const int s = find_sim(o, nsim, blockIdx.x);
+  const SimDesc& D = T[s];
+  if (D.mixed) faces_block<true>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
+  else faces_block<false>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
+}
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_update_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, int nsim, int stage, int last,
+           double a0, double a1, double c) {
+  const long long* o = off + OFF_CELLS * (nsim + 1);
+  const int s = find_sim(o, nsim, blockIdx.x);
+  const SimDesc& D = T[s];
+  const StageArgs A = stage_args(D, stage, last, a0, a1, c);
+  if (D.mixed) update_block<float>(blockIdx.x - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
+  else update_block<double>(blockIdx.x - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
+}
+
+__global__ void __launch_bounds__(kBlock) k_newton_b(const SimDesc* __restrict__ T, const long long* __restrict__ off,
+                                                     int nsim, int stage, int last, double a0, double a1, double c) {
+  const long long* o = off + OFF_NEWTON * (nsim + 1);
+  const int s = find_sim(o, nsim, blockIdx.x);
+  const SimDesc& D = T[s];
+  const StageArgs A = stage_args(D, stage, last, a0, a1, c);
+  newton_blocks(blockIdx.x - o[s], o[s + 1] - o[s], A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
+}
+
+__global__ void __launch_bounds__(kBlock) k_speed_b(const SimDesc* __restrict__ T, const long long* __restrict__ off,
+                                                    int nsim) {
+  const long long* o = off + OFF_CELLS * (nsim + 1);
+  const int s = find_sim(o, nsim, blockIdx.x);
+  const SimDesc& D = T[s];
+  speed_block(blockIdx.x - o[s], D.G, D.U, D.vs, D.K, D.partial, D.rep, D.blkmax);
+}
+
+__global__ void __launch_bounds__(kBlock) k_reduce_max_b(const SimDesc* __restrict__ T, double* __restrict__ smax) {
+  const SimDesc& D = T[blockIdx.x];
+  reduce_max_block(D.partial, D.npartial, smax + blockIdx.x);
 }
 
 // Clear the counters and the per-block iteration maxima.
@@ -810,6 +964,113 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   return RRMHD_OK;
 }
 
+// Blocks of the Newton pass per simulation: about one per 16 cell blocks.
+long long newton_blocks_for(long long ncell_blocks, unsigned int cap) {
+  long long b = ncell_blocks / 16;
+  if (b < 1) b = 1;
+  if (b > (long long)cap) b = cap;
+  return b;
+}
+
+SimDesc make_desc(rrmhd_ctx* c, double* U, const rrmhd_opacities* opac, double dt) {
+  SimDesc D;
+  std::memset(&D, 0, sizeof(D));
+  const Layout& L = c->L;
+  const rrmhd_grid* g = &c->grid;
+  D.G = make_griddev(g, L);
+  D.K = c->K;
+  D.op = make_opac(opac);
+  D.Vp = c->Vp;
+  D.taup = c->taup;
+  D.FA.Vp = c->Vp;
+  D.FA.taup = c->taup;
+  D.FA.np = L.Np;
+  for (int d = 0; d < 3; ++d) {
+    const bool on = d < g->ndim;
+    D.FA.Fh[d] = on ? c->Fh[d] : nullptr;
+    D.FA.nf[d] = on ? L.nf[d] : 0;
+    D.FA.nb[d] = on ? L.nb_faces[d] : 0;
+    D.FA.dx[d] = on ? g->dx[d] : 1.0;
+    D.idx[d] = on ? 1.0 / g->dx[d] : 0.0;
+  }
+  D.U = U;
+  D.vs = g->var_stride;
+  D.Us = c->Us;
+  D.ns = L.Ns;
+  D.inflow_U = g->inflow_U;
+  D.work = c->work;
+  D.wcount = c->wcount;
+  D.rep = c->rep;
+  D.blkmax = c->blkmax;
+  D.partial = c->partial;
+  D.npartial = L.npartial;
+  D.dt = dt;
+  D.mixed = (c->par.precision == RRMHD_MIXED) ? 1 : 0;
+  return D;
+}
+
+}  // namespace
+
+struct rrmhd_batch {
+  int max_sims;
+  hipStream_t stream;
+  SimDesc* table;       // device
+  long long* off;       // device [OFF_KINDS][max_sims + 1]
+  double* smax;         // device [max_sims]
+  void* host[2];        // pinned staging: table + offsets
+  hipEvent_t ev[2];
+  int cur;
+  double* hsmax;        // pinned [max_sims]
+  unsigned int newton_cap;
+};
+
+namespace {
+
+size_t batch_table_bytes(int m) { return align256(sizeof(SimDesc) * (size_t)m); }
+size_t batch_off_bytes(int m) { return align256(sizeof(long long) * OFF_KINDS * (size_t)(m + 1)); }
+
+// Fill a staging buffer with the batch's descriptors and block offsets and
+// copy it to the device (enqueued). Returns total blocks per kind in tot[].
+rrmhd_status batch_upload(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, double* const* U,
+                          const double* dt, const rrmhd_opacities* const* opac, long long tot[OFF_KINDS]) {
+  const int k = b->cur;
+  b->cur ^= 1;
+  if (hipEventSynchronize(b->ev[k]) != hipSuccess) return RRMHD_E_DEVICE;
+  SimDesc* T = (SimDesc*)b->host[k];
+  long long* off = (long long*)((char*)b->host[k] + batch_table_bytes(b->max_sims));
+  for (int i = 0; i < OFF_KINDS; ++i) { off[i * (nsim + 1)] = 0; tot[i] = 0; }
+  for (int s = 0; s < nsim; ++s) {
+    rrmhd_ctx* c = ctx[s];
+    T[s] = make_desc(c, U[s], opac ? opac[s] : nullptr, dt ? dt[s] : 0.0);
+    const Layout& L = c->L;
+    const long long nbc = nblocks(L.N);
+    const long long nb[OFF_KINDS] = {(long long)nblocks(L.N + L.nt), L.nb_faces[0] + L.nb_faces[1] + L.nb_faces[2],
+                                     nbc, newton_blocks_for(nbc, b->newton_cap)};
+    for (int i = 0; i < OFF_KINDS; ++i) {
+      tot[i] += nb[i];
+      off[i * (nsim + 1) + s + 1] = tot[i];
+    }
+  }
+  if (hipMemcpyAsync(b->table, T, sizeof(SimDesc) * nsim, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+    return RRMHD_E_DEVICE;
+  if (hipMemcpyAsync(b->off, off, sizeof(long long) * OFF_KINDS * (nsim + 1), hipMemcpyHostToDevice, b->stream) !=
+      hipSuccess)
+    return RRMHD_E_DEVICE;
+  if (hipEventRecord(b->ev[k], b->stream) != hipSuccess) return RRMHD_E_DEVICE;
+  return RRMHD_OK;
+}
+
+rrmhd_status batch_check(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, const void* const* U) {
+  if (!b || nsim < 1 || nsim > b->max_sims || !ctx || !U) return RRMHD_E_INVALID;
+  for (int s = 0; s < nsim; ++s) {
+    if (!ctx[s] || !U[s]) return RRMHD_E_INVALID;
+    if (ctx[s]->par.rk_order != ctx[0]->par.rk_order) return RRMHD_E_INVALID;
+    for (int t = 0; t < s; ++t)
+      if (ctx[t] == ctx[s]) return RRMHD_E_INVALID;  // each context's workspace is used once per launch
+  }
+  return RRMHD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1041,6 +1302,111 @@ void rrmhd_destroy(rrmhd_ctx* c) {
   for (auto& e : c->ev) hipEventDestroy(e);
   if (c->host) hipHostFree(c->host);
   delete c;
+}
+
+size_t rrmhd_batch_workspace_bytes(int max_sims) {
+  if (max_sims < 1 || max_sims > 65536) return 0;
+  return batch_table_bytes(max_sims) + batch_off_bytes(max_sims) + align256(sizeof(double) * max_sims);
+}
+
+rrmhd_status rrmhd_batch_init(rrmhd_batch** out, int max_sims, void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!out) return RRMHD_E_INVALID;
+  *out = nullptr;
+  const size_t need = rrmhd_batch_workspace_bytes(max_sims);
+  if (need == 0) return RRMHD_E_INVALID;
+  if (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255u) != 0) return RRMHD_E_WORKSPACE;
+  rrmhd_batch* b = new (std::nothrow) rrmhd_batch;
+  if (!b) return RRMHD_E_DEVICE;
+  std::memset(b, 0, sizeof(*b));
+  b->max_sims = max_sims;
+  b->stream = (hipStream_t)hip_stream;
+  char* w = (char*)workspace;
+  b->table = (SimDesc*)w;
+  b->off = (long long*)(w + batch_table_bytes(max_sims));
+  b->smax = (double*)(w + batch_table_bytes(max_sims) + batch_off_bytes(max_sims));
+  const size_t hb = batch_table_bytes(max_sims) + batch_off_bytes(max_sims);
+  bool ok = true;
+  for (int k = 0; k < 2 && ok; ++k) {
+    ok = hipHostMalloc(&b->host[k], hb, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming) == hipSuccess;
+  }
+  ok = ok && hipHostMalloc((void**)&b->hsmax, sizeof(double) * max_sims, hipHostMallocDefault) == hipSuccess;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  b->newton_cap = (unsigned int)(2 * ncu);
+  if (!ok) {
+    rrmhd_batch_destroy(b);
+    return RRMHD_E_DEVICE;
+  }
+  *out = b;
+  return RRMHD_OK;
+}
+
+rrmhd_status rrmhd_max_speed_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, const double* const* U,
+                                   double* smax_host) {
+  rrmhd_status st = batch_check(b, nsim, ctx, (const void* const*)U);
+  if (st != RRMHD_OK) return st;
+  if (!smax_host) return RRMHD_E_INVALID;
+  long long tot[OFF_KINDS];
+  st = batch_upload(b, nsim, ctx, (double* const*)U, nullptr, nullptr, tot);
+  if (st != RRMHD_OK) return st;
+  k_speed_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, nsim);
+  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  k_reduce_max_b<<<(unsigned int)nsim, kBlock, 0, b->stream>>>(b->table, b->smax);
+  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  if (hipMemcpyAsync(b->hsmax, b->smax, sizeof(double) * nsim, hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+    return RRMHD_E_DEVICE;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return RRMHD_E_DEVICE;
+  std::memcpy(smax_host, b->hsmax, sizeof(double) * nsim);
+  return RRMHD_OK;
+}
+
+rrmhd_status rrmhd_step_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, double* const* U,
+                              const double* dt_host, const rrmhd_opacities* const* opac) {
+  rrmhd_status st = batch_check(b, nsim, ctx, (const void* const*)U);
+  if (st != RRMHD_OK) return st;
+  if (!dt_host) return RRMHD_E_INVALID;
+  for (int s = 0; s < nsim; ++s)
+    if (!(dt_host[s] >= 0.0) || !(dt_host[s] < 1e300)) return RRMHD_E_INVALID;
+  long long tot[OFF_KINDS];
+  st = batch_upload(b, nsim, ctx, U, dt_host, opac, tot);
+  if (st != RRMHD_OK) return st;
+  double co[3][3];
+  int ns;
+  if (ctx[0]->par.rk_order == 3) {
+    const double t[3][3] = {{1.0, 0.0, 1.0}, {0.75, 0.25, 0.25}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
+    std::memcpy(co, t, sizeof(t));
+    ns = 3;
+  } else {
+    const double t[3][3] = {{1.0, 0.0, 1.0}, {0.5, 0.5, 0.5}, {0.0, 0.0, 0.0}};
+    std::memcpy(co, t, sizeof(t));
+    ns = 2;
+  }
+  for (int s = 0; s < ns; ++s) {
+    const int last = (s == ns - 1) ? 1 : 0;
+    k_prims_b<<<(unsigned int)tot[OFF_PRIMS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    k_faces_b<<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off, nsim);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    k_update_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s, last, co[s][0],
+                                                                       co[s][1], co[s][2]);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    k_newton_b<<<(unsigned int)tot[OFF_NEWTON], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s, last, co[s][0],
+                                                                        co[s][1], co[s][2]);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  }
+  return RRMHD_OK;
+}
+
+void rrmhd_batch_destroy(rrmhd_batch* b) {
+  if (!b) return;
+  hipStreamSynchronize(b->stream);
+  for (int k = 0; k < 2; ++k) {
+    if (b->host[k]) hipHostFree(b->host[k]);
+    if (b->ev[k]) hipEventDestroy(b->ev[k]);
+  }
+  if (b->hsmax) hipHostFree(b->hsmax);
+  delete b;
 }
 
 const char* rrmhd_strerror(rrmhd_status s) {

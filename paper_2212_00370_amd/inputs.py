@@ -167,3 +167,30 @@ def blast_2d(seed: int = 0, nx: int = 512, ny: int | None = None, steps: int = 2
     return Problem(name=f"blast2d_s{seed}_{nx}x{ny}", shape=(nx, ny), dx=(dx, dy), x0=(-0.5, -0.5),
                    V=V, kappa=kap, sigma=sig, gamma=4.0 / 3.0, a_rad=a_rad,
                    bc_lo=(PERIODIC,) * 3, bc_hi=(PERIODIC,) * 3, cfl=0.4, steps=steps)
+
+
+def serving_mix(seed: int, n: int, *, n1d=(256, 8192), n2d=(64, 512), t_end_1d: float = 0.05,
+                steps_2d=(10, 50), mixed_frac: float = 0.5) -> list[dict]:
+    """Request mix for the serving loop: half 1D Riemann problems with
+    N ~ logU[256, 8192] run to t_end_1d, half 2D blasts with N^2 cells,
+    N ~ logU[64, 512], run for a number of steps; FP64 / mixed precision
+    50/50. Returns plain dicts (problem, precision flag, t_end or steps)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        mixed = bool(rng.uniform() < mixed_frac)
+        if rng.uniform() < 0.5:
+            N = int(round(_log_uniform(rng, *n1d)))
+            P = riemann_1d(int(rng.integers(0, 2**31 - 1)), n=N)
+            out.append(dict(problem=P, mixed=mixed, t_end=t_end_1d, steps=None))
+        else:
+            N = int(round(_log_uniform(rng, *n2d)))
+            P = blast_2d(int(rng.integers(0, 2**31 - 1)), N)
+            out.append(dict(problem=P, mixed=mixed, t_end=None, steps=int(rng.integers(steps_2d[0], steps_2d[1] + 1))))
+    return out
+
+
+def poisson_arrivals(seed: int, n: int, rate: float) -> np.ndarray:
+    """Arrival times (s) of a Poisson process with the given rate (1/s)."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, n))

@@ -72,6 +72,11 @@ SIGNATURES = {
     "rrmhd_profile_enable": ([_vp, C.c_int], C.c_int),
     "rrmhd_profile_read": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
     "rrmhd_report_sync": ([_vp, _vp], C.c_int),
+    "rrmhd_batch_workspace_bytes": ([C.c_int], C.c_size_t),
+    "rrmhd_batch_init": ([_vp, C.c_int, _vp, C.c_size_t, _vp], C.c_int),
+    "rrmhd_max_speed_batch": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
+    "rrmhd_step_batch": ([_vp, C.c_int, _vp, _vp, _vp, _vp], C.c_int),
+    "rrmhd_batch_destroy": ([_vp], None),
     "rrmhd_destroy": ([_vp], None),
     "rrmhd_strerror": ([C.c_int], C.c_char_p),
 }
@@ -167,6 +172,41 @@ def rrmhd_report_sync(ctx) -> dict:
     return r.as_dict()
 
 
+def rrmhd_batch_workspace_bytes(max_sims: int) -> int:
+    return int(_lib.rrmhd_batch_workspace_bytes(int(max_sims)))
+
+
+def rrmhd_batch_init(max_sims: int, workspace, stream=None):
+    bh = C.c_void_p()
+    st = _lib.rrmhd_batch_init(C.byref(bh), int(max_sims), _ptr(workspace),
+                               workspace.numel() * workspace.element_size(),
+                               None if stream is None else C.c_void_p(stream.cuda_stream))
+    _check(st, "rrmhd_batch_init")
+    return bh
+
+
+def rrmhd_max_speed_batch(batch, ctxs, Us):
+    n = len(ctxs)
+    cv = (C.c_void_p * n)(*[c.value for c in ctxs])
+    uv = (C.c_void_p * n)(*[u.data_ptr() for u in Us])
+    out = (C.c_double * n)()
+    _check(_lib.rrmhd_max_speed_batch(batch, n, cv, uv, out), "rrmhd_max_speed_batch")
+    return list(out)
+
+
+def rrmhd_step_batch(batch, ctxs, Us, dts, opacs) -> None:
+    n = len(ctxs)
+    cv = (C.c_void_p * n)(*[c.value for c in ctxs])
+    uv = (C.c_void_p * n)(*[u.data_ptr() for u in Us])
+    dv = (C.c_double * n)(*[float(x) for x in dts])
+    ov = (C.c_void_p * n)(*[C.addressof(o) for o in opacs])
+    _check(_lib.rrmhd_step_batch(batch, n, cv, uv, dv, ov), "rrmhd_step_batch")
+
+
+def rrmhd_batch_destroy(batch) -> None:
+    _lib.rrmhd_batch_destroy(batch)
+
+
 def rrmhd_destroy(ctx) -> None:
     _lib.rrmhd_destroy(ctx)
 
@@ -199,6 +239,39 @@ def make_opacities(kappa=None, sigma=None, kappa0=0.0, sigma0=0.0) -> rrmhd_opac
     o.kappa0 = float(kappa0); o.sigma0 = float(sigma0)
     o._keep = (kappa, sigma)
     return o
+
+
+class Batch:
+    """Device descriptor table for stepping many Solvers with one launch per
+    kernel class (rrmhd_step_batch)."""
+
+    def __init__(self, max_sims: int, device="cuda:0", stream=None):
+        import torch
+        nbytes = rrmhd_batch_workspace_bytes(max_sims)
+        if nbytes == 0:
+            raise RRMHDError("invalid max_sims")
+        self.max_sims = max_sims
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off: off + nbytes]
+        self.handle = rrmhd_batch_init(max_sims, self.ws, stream)
+
+    def max_speed(self, solvers, Us):
+        return rrmhd_max_speed_batch(self.handle, [s.ctx for s in solvers], Us)
+
+    def step(self, solvers, Us, dts, opacs):
+        rrmhd_step_batch(self.handle, [s.ctx for s in solvers], Us, dts, opacs)
+
+    def close(self):
+        if self.handle is not None:
+            rrmhd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Solver:

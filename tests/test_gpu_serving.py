@@ -1,0 +1,100 @@
+"""Batched stepping and the continuous-batching server: each simulation's
+result is bit-for-bit the same alone, in a batch, and through the
+single-simulation entry points; admission respects the HBM budget; a failing
+request does not disturb the others."""
+import numpy as np
+import pytest
+
+from paper_2212_00370_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2212_00370_amd import rrmhd as R
+    from paper_2212_00370_amd import serving as S
+    return torch, R, S
+
+
+def problems():
+    return [(I.riemann_1d(3, n=300), 0), (I.riemann_1d(7, n=517), 1), (I.blast_2d(1, 40, 24), 0),
+            (I.blast_2d(2, 33, 50), 1), (I.riemann_1d(5, n=64), 0)]
+
+
+def make(torch, R, P, prec):
+    p = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=prec)
+    g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
+    s = R.Solver(g, p)
+    U = s.prim_to_cons(torch.from_numpy(P.V).to("cuda:0"))
+    opac = R.make_opacities(torch.from_numpy(P.kappa).to("cuda:0"), torch.from_numpy(P.sigma).to("cuda:0"))
+    return s, U, opac
+
+
+def test_batch_equals_single(mods):
+    torch, R, S = mods
+    cases = problems()
+    single = [make(torch, R, P, prec) for P, prec in cases]
+    batched = [make(torch, R, P, prec) for P, prec in cases]
+    B = R.Batch(16)
+    for k in range(4):
+        sm_b = B.max_speed([c[0] for c in batched], [c[1] for c in batched])
+        dts = []
+        for (P, _), (s, U, o), smb in zip(cases, single, sm_b):
+            sm = s.max_speed(U)
+            assert sm == smb
+            dt = P.cfl * min(P.dx) / sm
+            dts.append(dt)
+            s.step(U, dt, o)
+        B.step([c[0] for c in batched], [c[1] for c in batched], dts, [c[2] for c in batched])
+        for (s1, U1, _), (s2, U2, _) in zip(single, batched):
+            assert torch.equal(U1, U2)
+    for c in single + batched:
+        rep = c[0].report()
+        assert rep["c2p_fail"] == 0 and rep["imp_fail"] == 0
+        c[0].close()
+    B.close()
+
+
+def test_server_alone_vs_mix_and_budget(mods):
+    torch, R, S = mods
+    mix = I.serving_mix(11, 10, n1d=(64, 400), n2d=(16, 48), t_end_1d=0.02, steps_2d=(3, 8))
+    reqs = [S.Request(rid=i, problem=m["problem"], precision=R.MIXED if m["mixed"] else R.FP64,
+                      t_end=m["t_end"], steps=m["steps"], arrival=0.002 * i) for i, m in enumerate(mix)]
+    fps = [S.footprint_bytes(r.problem, r.precision) for r in reqs]
+    budget = int(2.5 * max(fps))          # forces queueing: at most a few resident at once
+    srv = S.Server(budget, max_sims=8)
+    res = {r.rid: r for r in srv.run(reqs)}
+    assert srv.peak_in_use <= budget
+    assert max(srv.batch_sizes) > 1       # work really overlapped
+    srv.close()
+    assert sorted(res) == list(range(len(reqs)))
+    for r in reqs:
+        alone = S.Server(10 * max(fps), max_sims=1)
+        ra = alone.run([S.Request(rid=r.rid, problem=r.problem, precision=r.precision, t_end=r.t_end,
+                                  steps=r.steps, arrival=0.0)])[0]
+        alone.close()
+        assert ra.steps == res[r.rid].steps
+        assert np.array_equal(ra.U, res[r.rid].U), r.rid
+
+
+def test_failing_request_is_isolated(mods):
+    torch, R, S = mods
+    good = [I.riemann_1d(3, n=128), I.blast_2d(4, 24, 24)]
+    bad = I.riemann_1d(9, n=96)
+    bad.V[4, 40] = -1.0                   # negative pressure: recovery fails in that cell
+    reqs = [S.Request(rid=0, problem=good[0], steps=5), S.Request(rid=1, problem=bad, steps=5),
+            S.Request(rid=2, problem=good[1], steps=5)]
+    srv = S.Server(1 << 34, max_sims=4)
+    res = {r.rid: r for r in srv.run(reqs)}
+    srv.close()
+    assert res[1].report["c2p_fail"] > 0 or res[1].report["imp_fail"] > 0
+    for rid in (0, 2):
+        assert res[rid].report["c2p_fail"] == 0
+        alone = S.Server(1 << 34, max_sims=1)
+        ra = alone.run([reqs[rid]])[0]
+        alone.close()
+        assert np.array_equal(ra.U, res[rid].U)
