@@ -92,6 +92,9 @@ typedef struct {
   int imp_method;   /* RRMHD_IMP_*                                                      */
   int precision;    /* RRMHD_FP64 | RRMHD_MIXED                                         */
   double pvm_eps_mixed; /* relative finite-difference step of the FP32 chain (2^-12)   */
+  double e_floor;   /* 0 (default): a non-positive E_r entering the implicit solve fails
+                       the cell; > 0: it is raised to e_floor keeping tau + E_r and
+                       S + F_r (the gas pays), and counted in e_floor_hits           */
 } rrmhd_params;
 
 /* Gray comoving opacities per unit mass (eqs. g0, gi): device arrays [ncell]
@@ -106,7 +109,7 @@ typedef struct {
  * rrmhd_report_sync. first_bad_cell is the smallest failing cell index or
  * -1. max_*_it are the largest iteration counts seen. */
 typedef struct {
-  long long c2p_fail, pvm_fallback, imp_fail, nonfinite;
+  long long c2p_fail, pvm_fallback, imp_fail, nonfinite, e_floor_hits;
   long long first_bad_cell;
   int max_c2p_it, max_imp_it;
 } rrmhd_report;

@@ -40,7 +40,7 @@ class OPar(C.Structure):
         ("rho_floor", C.c_double), ("p_floor", C.c_double),
         ("pvm_k", C.c_int), ("beta_mode", C.c_int), ("recon", C.c_int), ("rk_order", C.c_int),
         ("c2p_maxit", C.c_int), ("imp_maxit", C.c_int), ("imp_picard_it", C.c_int),
-        ("imp_method", C.c_int),
+        ("imp_method", C.c_int), ("e_floor", C.c_double),
     ]
 
 
@@ -55,7 +55,7 @@ class OGrid(C.Structure):
 class OReport(C.Structure):
     _fields_ = [
         ("c2p_fail", C.c_longlong), ("pvm_fallback", C.c_longlong), ("imp_fail", C.c_longlong),
-        ("nonfinite", C.c_longlong), ("first_bad_cell", C.c_longlong),
+        ("nonfinite", C.c_longlong), ("e_floor_hits", C.c_longlong), ("first_bad_cell", C.c_longlong),
         ("max_c2p_it", C.c_int), ("max_imp_it", C.c_int),
     ]
 
@@ -63,7 +63,7 @@ class OReport(C.Structure):
 DEFAULTS = dict(
     gamma=5.0 / 3.0, a_rad=1.0, t_coeff=1.0, pvm_eps=1e-8, c2p_tol=1e-12, imp_tol=1e-13,
     rho_floor=1e-12, p_floor=1e-12, pvm_k=3, beta_mode=1, recon=1, rk_order=2,
-    c2p_maxit=100, imp_maxit=50, imp_picard_it=8, imp_method=0,
+    c2p_maxit=100, imp_maxit=50, imp_picard_it=8, imp_method=0, e_floor=0.0,
 )
 
 

@@ -89,6 +89,7 @@ struct OPar {
   int imp_maxit;
   int imp_picard_it; // Picard (lagged) iterations before Newton takes over
   int imp_method;    // 0: Picard then Newton; 1: Newton only; 2: Picard only
+  double e_floor;    // > 0: a non-positive explicit E_r is raised to this (counted); 0: failure
 };
 
 struct OGrid {
@@ -102,7 +103,7 @@ struct OGrid {
 };
 
 struct OReport {
-  long long c2p_fail, pvm_fallback, imp_fail, nonfinite;
+  long long c2p_fail, pvm_fallback, imp_fail, nonfinite, e_floor_hits;
   long long first_bad_cell;
   int max_c2p_it, max_imp_it;
 };
@@ -594,7 +595,7 @@ static real vmaxabs4(const real a[4]) {
 // and step halving finishes from the last admissible iterate. Both reach the
 // same root of the backward-Euler system.
 static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OPar& P,
-                         const Consts& K, real Un[NV], int* iters, int* c2p_it) {
+                         const Consts& K, real Un[NV], int* iters, int* c2p_it, int* floored) {
   const real Et = Us[4] + Us[8];
   real St[3];
   for (int j = 0; j < 3; ++j) St[j] = Us[1 + j] + Us[9 + j];
@@ -604,11 +605,19 @@ static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OP
   // limited state. A non-positive E_r cannot be repaired and fails.
   real Ul[NV];
   for (int q = 0; q < NV; ++q) Ul[q] = Us[q];
+  *floored = 0;
   if (!(Ul[8] > real(0.0))) {
-    for (int q = 0; q < NV; ++q) Un[q] = Us[q];
-    *iters = 0;
-    *c2p_it = 0;
-    return 1;
+    // Optional floor: the totals tau + E_r and S + F_r are kept, so the gas
+    // pays for the raised radiation energy (conservative; counted).
+    if (P.e_floor > 0.0 && rfinite(Ul[8])) {
+      Ul[8] = P.e_floor;
+      *floored = 1;
+    } else {
+      for (int q = 0; q < NV; ++q) Un[q] = Us[q];
+      *iters = 0;
+      *c2p_it = 0;
+      return 1;
+    }
   }
   {
     const real FF = (Ul[9] * Ul[9] + Ul[10] * Ul[10]) + Ul[11] * Ul[11];
@@ -625,17 +634,19 @@ static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OP
   bool have = false;
   *c2p_it = 0;
   const int npic = (P.imp_method == 1) ? 0 : ((P.imp_method == 2) ? P.imp_maxit : P.imp_picard_it);
-  // Picard phase; it stops early once its update grows. The Newton phase
-  // restarts from the explicit state X* (Xg), which is admissible whenever
-  // the first recovery succeeds.
+  // Picard phase; it stops early once its update grows. If Picard is still
+  // contracting when it reaches its iteration cap, Newton continues from its
+  // last (admissible) iterate; otherwise Newton restarts from X*.
   const real Xg[4] = {X[0], X[1], X[2], X[3]};
   real dlast = 0.0, dprev = 0.0;
+  bool built = false, capped = false;
   for (int m = 0; m <= npic; ++m) {
-    if (!imp_build(X, Ul, Et, St, h, kap, sig, P, K, Zg, sy, c2p_it)) break;
+    built = imp_build(X, Ul, Et, St, h, kap, sig, P, K, Zg, sy, c2p_it);
+    if (!built) break;
     Zg = sy.Z;
     if (m == 0) have = true;
     if (m > 0 && dlast <= P.imp_tol * xscale(X)) { conv = true; break; }
-    if (m == npic) break;
+    if (m == npic) { capped = true; break; }
     if (m > 1 && P.imp_method == 0 && dlast > dprev) break;
     real A[4][4], bb[4], Xn[4];
     for (int i = 0; i < 4; ++i) { bb[i] = sy.b[i]; for (int j = 0; j < 4; ++j) A[i][j] = sy.C[i][j]; }
@@ -648,16 +659,24 @@ static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OP
     dlast = vmaxabs4(dd);
   }
   if (!conv && have && P.imp_method != 2) {
-    // Newton phase from X* (its system is rebuilt).
-    for (int i = 0; i < 4; ++i) X[i] = Xg[i];
-    Zg = 0.0;
+    // Newton phase (its system is rebuilt at the start point).
+    const bool from_picard = built && capped && npic > 1 && dlast < dprev;
+    if (!from_picard) {
+      for (int i = 0; i < 4; ++i) X[i] = Xg[i];
+      Zg = 0.0;
+    }
     real R[4];
     if (imp_build(X, Ul, Et, St, h, kap, sig, P, K, Zg, sy, c2p_it)) {
       Zg = sy.Z;
       imp_residual(sy, X, R);
+      real sprev = 0.0;
       for (int n = 0; n < P.imp_maxit; ++n) {
         ++it;
-        const real sc = xscale(X);
+        // difference step: relative to the iterate and to the scale of the
+        // solution of the current linear system, ~ b_i / C_ii
+        real bd[4];
+        for (int i = 0; i < 4; ++i) bd[i] = sy.b[i] / sy.C[i][i];
+        const real sc = rmax(xscale(X), vmaxabs4(bd));
         const real del = 1e-8 * sc;
         real J[4][4];
         bool okj = true;
@@ -692,7 +711,11 @@ static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OP
         for (int i = 0; i < 4; ++i) { stp[i] = Xt[i] - X[i]; X[i] = Xt[i]; R[i] = Rt[i]; }
         sy = st;
         Zg = st.Z;
-        if (vmaxabs4(stp) <= P.imp_tol * xscale(X)) { conv = true; break; }
+        const real sn = vmaxabs4(stp);
+        if (sn <= P.imp_tol * xscale(X)) { conv = true; break; }
+        // at the rounding floor: a tiny step that no longer shrinks
+        if (n > 0 && sn <= 1e-9 * sc && sn >= sprev) { conv = true; break; }
+        sprev = sn;
       }
     }
   }
@@ -945,7 +968,7 @@ static int step_impl(const OGrid& og, const OPar& P, double* U, const double* ka
   const long long N = G.ncell, vs = og.var_stride;
   double coef[17];
   const int M = internal_poly(P.pvm_k, coef);
-  OReport R = {0, 0, 0, 0, -1, 0, 0};
+  OReport R = {0, 0, 0, 0, 0, -1, 0, 0};
   std::vector<double> U0((size_t)NV * N), Us((size_t)NV * N);
   for (int q = 0; q < NV; ++q)
     for (long long c = 0; c < N; ++c) { U0[q * N + c] = U[q * vs + c]; Us[q * N + c] = U[q * vs + c]; }
@@ -965,9 +988,9 @@ static int step_impl(const OGrid& og, const OPar& P, double* U, const double* ka
     }
     const real cdt = real(sc[s].c) * real(dt);
     std::vector<double> Un((size_t)NV * N);
-    long long nimp = 0, nnf = 0, fb = -1;
+    long long nimp = 0, nnf = 0, nfl = 0, fb = -1;
     int mit = 0;
-#pragma omp parallel for schedule(static) reduction(+ : nimp, nnf) reduction(max : mit)
+#pragma omp parallel for schedule(static) reduction(+ : nimp, nnf, nfl) reduction(max : mit)
     for (long long c = 0; c < N; ++c) {
       const int ci[3] = {(int)(c % G.n[0]), (int)((c / G.n[0]) % G.n[1]), (int)(c / ((long long)G.n[0] * G.n[1]))};
       real Ust[NV];
@@ -988,9 +1011,10 @@ static int step_impl(const OGrid& og, const OPar& P, double* U, const double* ka
         Ust[q] = (real(sc[s].a0) * real(U0[q * N + c]) + real(sc[s].a1) * real(Us[q * N + c])) - cdt * div;
       }
       real Unc[NV];
-      int iters = 0, cit = 0;
-      const int st = implicit_cell(Ust, cdt, real(opac_at(kap, kap0, c)), real(opac_at(sig, sig0, c)), P, K, Unc, &iters, &cit);
+      int iters = 0, cit = 0, fl = 0;
+      const int st = implicit_cell(Ust, cdt, real(opac_at(kap, kap0, c)), real(opac_at(sig, sig0, c)), P, K, Unc, &iters, &cit, &fl);
       if (st != 0) nimp += 1;
+      nfl += fl;
       mit = std::max(mit, iters);
       bool fin = true;
       for (int q = 0; q < NV; ++q) { Un[q * N + c] = dv(Unc[q]); if (!std::isfinite(dv(Unc[q]))) fin = false; }
@@ -1002,6 +1026,7 @@ static int step_impl(const OGrid& og, const OPar& P, double* U, const double* ka
     }
     R.imp_fail += nimp;
     R.nonfinite += nnf;
+    R.e_floor_hits += nfl;
     if (fb >= 0 && (R.first_bad_cell < 0 || fb < R.first_bad_cell)) R.first_bad_cell = fb;
     if (mit > R.max_imp_it) R.max_imp_it = mit;
     Us.swap(Un);
@@ -1100,8 +1125,8 @@ void or_implicit(long long n, const double* Us, long long su, const double* h, c
   for (long long c = 0; c < n; ++c) {
     real Uc[NV], Uo[NV];
     for (int q = 0; q < NV; ++q) Uc[q] = Us[q * su + c];
-    int it = 0, cit = 0;
-    int st = implicit_cell(Uc, real(h[c]), real(kap[c]), real(sig[c]), *P, K, Uo, &it, &cit);
+    int it = 0, cit = 0, fl = 0;
+    int st = implicit_cell(Uc, real(h[c]), real(kap[c]), real(sig[c]), *P, K, Uo, &it, &cit, &fl);
     for (int q = 0; q < NV; ++q) Un[q * sn + c] = dv(Uo[q]);
     if (status) status[c] = st;
     if (iters) iters[c] = it;

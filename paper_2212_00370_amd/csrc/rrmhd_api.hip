@@ -30,7 +30,7 @@ constexpr int kBlock = 256;
 constexpr int kWave = 64;
 
 struct DevReport {
-  unsigned long long c2p_fail, pvm_fallback, imp_fail, nonfinite;
+  unsigned long long c2p_fail, pvm_fallback, imp_fail, nonfinite, e_floor_hits;
   unsigned long long first_bad;
   unsigned int max_c2p_it, max_imp_it;
   unsigned int pad[2];
@@ -90,12 +90,14 @@ __device__ __forceinline__ void report_add(DevReport* rep, unsigned int* blkmax,
                                            unsigned long long f_c2p,
                                            unsigned long long f_pvm, unsigned long long f_imp,
                                            unsigned long long f_nf, unsigned long long bad_cell,
-                                           unsigned int c2p_it, unsigned int imp_it) {
+                                           unsigned int c2p_it, unsigned int imp_it,
+                                           unsigned long long f_floor = 0) {
   __shared__ unsigned int red_it[2][kBlock / kWave];
   const unsigned long long s_c2p = wave_sum_u64(f_c2p);
   const unsigned long long s_pvm = wave_sum_u64(f_pvm);
   const unsigned long long s_imp = wave_sum_u64(f_imp);
   const unsigned long long s_nf = wave_sum_u64(f_nf);
+  const unsigned long long s_fl = wave_sum_u64(f_floor);
   const unsigned long long s_bad = wave_min_u64(bad_cell);
   const unsigned int m_c2p = wave_max_u32(c2p_it);
   const unsigned int m_imp = wave_max_u32(imp_it);
@@ -106,6 +108,7 @@ __device__ __forceinline__ void report_add(DevReport* rep, unsigned int* blkmax,
     if (s_pvm) atomicAdd(&rep->pvm_fallback, s_pvm);
     if (s_imp) atomicAdd(&rep->imp_fail, s_imp);
     if (s_nf) atomicAdd(&rep->nonfinite, s_nf);
+    if (s_fl) atomicAdd(&rep->e_floor_hits, s_fl);
     if (s_bad != ULLONG_MAX) atomicMin(&rep->first_bad, s_bad);
     red_it[0][wid] = m_c2p;
     red_it[1][wid] = m_imp;
@@ -392,9 +395,10 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
   const FT* F1 = (const FT*)A.Fh[1];
   const FT* F2 = (const FT*)A.Fh[2];
   const long long c = lb * kBlock + threadIdx.x;
-  unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
+  unsigned long long fimp = 0, fnf = 0, ffl = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
   bool newton = false;
+  double X0[4] = {0.0, 0.0, 0.0, 0.0}, Z0 = 0.0;
   if (c < G.N) {
     const int ci[3] = {(int)(c % G.n[0]), (int)((c / G.n[0]) % G.n[1]), (int)(c / ((long long)G.n[0] * G.n[1]))};
     long long fm[3], fs[3];
@@ -416,9 +420,11 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
     }
     double Un[NV];
     int it = 0;
+    bool floored = false;
     const int st = rr::implicit_picard(Ust, A.cdt, opac_at(op.kappa, op.kappa0, c),
-                                       opac_at(op.sigma, op.sigma0, c), K, Un, it);
+                                       opac_at(op.sigma, op.sigma0, c), K, Un, it, floored, X0, Z0);
     its = (unsigned int)it;
+    ffl = floored ? 1 : 0;
     if (st == rr::IMP_NEED_NEWTON) {
       newton = true;
 #pragma unroll
@@ -445,10 +451,18 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
     if (newton) {
       const unsigned int below = __builtin_amdgcn_mbcnt_hi((unsigned int)(mask >> 32),
                                                            __builtin_amdgcn_mbcnt_lo((unsigned int)mask, 0u));
-      worklist[base + below] = c;
+      const unsigned long long slot = base + below;
+      worklist[slot] = c;
+      // Newton start point and warm start, [5][N] planes
+      double* xs = (double*)(worklist + G.N);
+      xs[0 * G.N + slot] = X0[0];
+      xs[1 * G.N + slot] = X0[1];
+      xs[2 * G.N + slot] = X0[2];
+      xs[3 * G.N + slot] = X0[3];
+      xs[4 * G.N + slot] = Z0;
     }
   }
-  report_add(rep, blkmax, lb, 0, 0, fimp, fnf, bad, 0, its);
+  report_add(rep, blkmax, lb, 0, 0, fimp, fnf, bad, 0, its, ffl);
 }
 
 template <typename FT>
@@ -461,10 +475,11 @@ k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* 
 // Phase 2 of the implicit solve (Newton) for the cells in `worklist`; the
 // explicit state U* was left in the output by the update pass. Grid-stride
 // over the list with blocks bi = 0..nb-1.
-__device__ __forceinline__ void newton_blocks(long long bi, long long nb, const StageArgs& A, const Opac& op,
-                                              const Phys& K, DevReport* rep, unsigned int* blkmax,
+__device__ __forceinline__ void newton_blocks(long long bi, long long nb, long long ncell, const StageArgs& A,
+                                              const Opac& op, const Phys& K, DevReport* rep, unsigned int* blkmax,
                                               const long long* __restrict__ worklist,
                                               const unsigned long long* wcount) {
+  const double* xs = (const double*)(worklist + ncell);
   const unsigned long long n = *wcount;
   unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
@@ -475,8 +490,9 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, const 
 #pragma unroll
     for (int q = 0; q < NV; ++q) Ust[q] = A.Uo[q * A.so + c];
     int it = 0;
+    const double X0[4] = {xs[0 * ncell + i], xs[1 * ncell + i], xs[2 * ncell + i], xs[3 * ncell + i]};
     const int st = rr::implicit_newton(Ust, A.cdt, opac_at(op.kappa, op.kappa0, c),
-                                       opac_at(op.sigma, op.sigma0, c), K, Un, it);
+                                       opac_at(op.sigma, op.sigma0, c), K, X0, xs[4 * ncell + i], Un, it);
     bool fin = true;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -492,9 +508,9 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, const 
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_newton(StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
+k_newton(long long ncell, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
          const long long* __restrict__ worklist, const unsigned long long* wcount) {
-  newton_blocks(blockIdx.x, gridDim.x, A, op, K, rep, blkmax, worklist, wcount);
+  newton_blocks(blockIdx.x, gridDim.x, ncell, A, op, K, rep, blkmax, worklist, wcount);
 }
 
 // Per-block maximum of the cell signal speeds -> partial[lb].
@@ -657,7 +673,7 @@ __global__ void __launch_bounds__(kBlock) k_newton_b(const SimDesc* __restrict__
   const int s = find_sim(o, nsim, blockIdx.x);
   const SimDesc& D = T[s];
   const StageArgs A = stage_args(D, stage, last, a0, a1, c);
-  newton_blocks(blockIdx.x - o[s], o[s + 1] - o[s], A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
+  newton_blocks(blockIdx.x - o[s], o[s + 1] - o[s], D.G.N, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
 }
 
 __global__ void __launch_bounds__(kBlock) k_speed_b(const SimDesc* __restrict__ T, const long long* __restrict__ off,
@@ -676,7 +692,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_max_b(const SimDesc* __restri
 // Clear the counters and the per-block iteration maxima.
 __global__ void __launch_bounds__(kBlock) k_report_reset(DevReport* rep, unsigned int* blkmax, long long nslots) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    rep->c2p_fail = 0; rep->pvm_fallback = 0; rep->imp_fail = 0; rep->nonfinite = 0;
+    rep->c2p_fail = 0; rep->pvm_fallback = 0; rep->imp_fail = 0; rep->nonfinite = 0; rep->e_floor_hits = 0;
     rep->first_bad = ULLONG_MAX;
     rep->max_c2p_it = 0; rep->max_imp_it = 0;
   }
@@ -757,6 +773,7 @@ bool params_valid(const rrmhd_params* p) {
   if (p->c2p_maxit < 1 || p->imp_maxit < 1 || p->imp_picard_it < 0) return false;
   if (p->imp_method < 0 || p->imp_method > 2) return false;
   if (!(p->c2p_tol > 0.0) || !(p->imp_tol > 0.0)) return false;
+  if (!(p->e_floor >= 0.0)) return false;
   if (p->precision != RRMHD_FP64 && p->precision != RRMHD_MIXED) return false;
   if (!(p->pvm_eps_mixed > 0.0 && p->pvm_eps_mixed < 0.5)) return false;
   return true;
@@ -798,6 +815,7 @@ Phys make_phys(const rrmhd_params* p) {
   K.c2p_tol = p->c2p_tol;
   K.imp_tol = p->imp_tol;
   K.rho_floor = p->rho_floor;
+  K.e_floor = p->e_floor;
   K.p_floor = p->p_floor;
   K.c2p_maxit = p->c2p_maxit;
   K.imp_maxit = p->imp_maxit;
@@ -846,7 +864,7 @@ Layout make_layout(const rrmhd_grid* g) {
   L.off_smax = o; o = align256(o + sizeof(double));
   L.off_rep = o; o = align256(o + sizeof(DevReport));
   L.off_blkmax = o; o = align256(o + sizeof(unsigned int) * 2 * L.nblkmax);
-  L.off_work = o; o = align256(o + sizeof(long long) * L.N);
+  L.off_work = o; o = align256(o + sizeof(long long) * L.N + sizeof(double) * 5 * L.N);  // cells + [5][N] starts
   L.off_wcount = o; o = align256(o + sizeof(unsigned long long));
   L.total = o;
   return L;
@@ -1222,7 +1240,7 @@ rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt,
     // Grid-stride over the work list; a few blocks per CU.
     const unsigned int nbn = (unsigned int)((nblocks(L.N) < c->newton_blocks) ? nblocks(L.N) : c->newton_blocks);
     pe = prof_begin(c, RRMHD_K_NEWTON, L.N);
-    k_newton<<<nbn, kBlock, 0, c->stream>>>(A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
+    k_newton<<<nbn, kBlock, 0, c->stream>>>(L.N, A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
     prof_end(c, pe);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   }
@@ -1257,6 +1275,7 @@ rrmhd_status rrmhd_report_sync(rrmhd_ctx* c, rrmhd_report* out) {
   out->pvm_fallback = (long long)h->pvm_fallback;
   out->imp_fail = (long long)h->imp_fail;
   out->nonfinite = (long long)h->nonfinite;
+  out->e_floor_hits = (long long)h->e_floor_hits;
   out->first_bad_cell = (h->first_bad == ULLONG_MAX) ? -1 : (long long)h->first_bad;
   out->max_c2p_it = (int)h->max_c2p_it;
   out->max_imp_it = (int)h->max_imp_it;

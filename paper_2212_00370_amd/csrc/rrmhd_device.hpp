@@ -30,6 +30,7 @@ struct Phys {
   double eps32;                 // relative step of the FP32 chain (mixed precision)
   double c2p_tol, imp_tol;
   double rho_floor, p_floor;
+  double e_floor;               // > 0: floor for a non-positive explicit E_r (counted)
   int c2p_maxit, imp_maxit, imp_picard_it, imp_method;
   int beta_mode, recon, M;      // M = 2^(k-1) Horner steps (0 for k = 0)
   double coef[MAXCOEF];         // p_k coefficients of x^(2m)
@@ -720,13 +721,23 @@ struct ImpIn {
   double Et, St[3];
 };
 
-__device__ __forceinline__ bool imp_prepare(const double Us[NV], ImpIn& in) {
+// A non-positive explicit E_r fails the cell, or, with e_floor > 0, is raised
+// to e_floor keeping tau + E_r and S + F_r (the gas pays; `floored` is set).
+__device__ __forceinline__ bool imp_prepare(const double Us[NV], const Phys& K, ImpIn& in, bool& floored) {
   in.Et = Us[4] + Us[8];
 #pragma unroll
   for (int j = 0; j < 3; ++j) in.St[j] = Us[1 + j] + Us[9 + j];
 #pragma unroll
   for (int q = 0; q < NV; ++q) in.Ul[q] = Us[q];
-  if (!(in.Ul[8] > 0.0)) return false;
+  floored = false;
+  if (!(in.Ul[8] > 0.0)) {
+    if (K.e_floor > 0.0 && isfinite(in.Ul[8])) {
+      in.Ul[8] = K.e_floor;
+      floored = true;
+    } else {
+      return false;
+    }
+  }
   const double FF = (in.Ul[9] * in.Ul[9] + in.Ul[10] * in.Ul[10]) + in.Ul[11] * in.Ul[11];
   if (FF > in.Ul[8] * in.Ul[8]) {
     const double r = in.Ul[8] / sqrt(FF);
@@ -757,12 +768,14 @@ __device__ __forceinline__ void imp_finish(double X[4], const double Us[NV], con
 enum { IMP_DONE = 0, IMP_FAILED = 1, IMP_NEED_NEWTON = 2 };
 
 // Phase 1. IMP_DONE: Un holds the result; IMP_FAILED: Un = Us;
-// IMP_NEED_NEWTON: phase 2 must finish the cell (Un untouched).
+// IMP_NEED_NEWTON: phase 2 must finish the cell from X0 (warm start Z0): the
+// last Picard iterate if Picard was still contracting at its cap, else X*.
 __device__ __forceinline__ int implicit_picard(const double Us[NV], double h, double kap, double sig,
-                                               const Phys& K, double Un[NV], int& iters) {
+                                               const Phys& K, double Un[NV], int& iters, bool& floored,
+                                               double X0[4], double& Z0) {
   ImpIn in;
   iters = 0;
-  if (!imp_prepare(Us, in)) {
+  if (!imp_prepare(Us, K, in, floored)) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) Un[q] = Us[q];
     return IMP_FAILED;
@@ -771,15 +784,16 @@ __device__ __forceinline__ int implicit_picard(const double Us[NV], double h, do
   ImpSys sy;
   double Zg = 0.0;
   int it = 0, c2p_it = 0;
-  bool conv = false, have = false;
+  bool conv = false, have = false, built = false, capped = false;
   const int npic = (K.imp_method == 1) ? 0 : ((K.imp_method == 2) ? K.imp_maxit : K.imp_picard_it);
   double dlast = 0.0, dprev = 0.0;
   for (int m = 0; m <= npic; ++m) {
-    if (!imp_build(X, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sy, c2p_it)) break;
+    built = imp_build(X, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sy, c2p_it);
+    if (!built) break;
     Zg = sy.Z;
     if (m == 0) have = true;
     if (m > 0 && dlast <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
-    if (m == npic) break;
+    if (m == npic) { capped = true; break; }
     if (m > 1 && K.imp_method == 0 && dlast > dprev) break;
     double A[4][4], bb[4], Xn[4];
 #pragma unroll
@@ -802,30 +816,49 @@ __device__ __forceinline__ int implicit_picard(const double Us[NV], double h, do
     imp_finish(X, Us, in, Un);
     return IMP_DONE;
   }
-  if (have && K.imp_method != 2) return IMP_NEED_NEWTON;
+  if (have && K.imp_method != 2) {
+    const bool from_picard = built && capped && npic > 1 && dlast < dprev;
+    if (from_picard) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) X0[i] = X[i];
+      Z0 = Zg;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) X0[i] = in.Ul[8 + i];
+      Z0 = 0.0;
+    }
+    return IMP_NEED_NEWTON;
+  }
 #pragma unroll
   for (int q = 0; q < NV; ++q) Un[q] = Us[q];
   return IMP_FAILED;
 }
 
-// Phase 2: Newton from X*. Returns IMP_DONE or IMP_FAILED (then Un = Us).
+// Phase 2: Newton from X0 with warm start Z0. Returns IMP_DONE or
+// IMP_FAILED (then Un = Us).
 __device__ __forceinline__ int implicit_newton(const double Us[NV], double h, double kap, double sig,
-                                               const Phys& K, double Un[NV], int& iters) {
+                                               const Phys& K, const double X0[4], double Z0, double Un[NV],
+                                               int& iters) {
   ImpIn in;
   iters = 0;
   bool conv = false;
   double X[4];
-  if (imp_prepare(Us, in)) {
-    X[0] = in.Ul[8]; X[1] = in.Ul[9]; X[2] = in.Ul[10]; X[3] = in.Ul[11];
+  bool floored = false;
+  if (imp_prepare(Us, K, in, floored)) {
+    X[0] = X0[0]; X[1] = X0[1]; X[2] = X0[2]; X[3] = X0[3];
     ImpSys sy;
-    double Zg = 0.0, R[4];
+    double Zg = Z0, R[4];
     int it = 0, c2p_it = 0;
     if (imp_build(X, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sy, c2p_it)) {
       Zg = sy.Z;
       imp_residual(sy, X, R);
+      double sprev = 0.0;
       for (int n = 0; n < K.imp_maxit; ++n) {
         ++it;
-        const double sc = vmaxabs4(X);
+        double bd[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bd[i] = sy.b[i] / sy.C[i][i];
+        const double sc = dmax(vmaxabs4(X), vmaxabs4(bd));
         const double del = 1e-8 * sc;
         double J[4][4];
         bool okj = true;
@@ -867,8 +900,13 @@ __device__ __forceinline__ int implicit_newton(const double Us[NV], double h, do
         double stp[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) { stp[i] = Xt[i] - X[i]; X[i] = Xt[i]; R[i] = Rt[i]; }
+        sy = st;
         Zg = st.Z;
-        if (vmaxabs4(stp) <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
+        const double sn = vmaxabs4(stp);
+        if (sn <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
+        // at the rounding floor: a tiny step that no longer shrinks
+        if (n > 0 && sn <= 1e-9 * sc && sn >= sprev) { conv = true; break; }
+        sprev = sn;
       }
     }
     iters = it;

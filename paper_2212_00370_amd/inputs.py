@@ -14,6 +14,10 @@ Workloads (shapes and value ranges of the paper's test problems, Section 4):
     r < 0.1) on [-1/2, 1/2]^2, smooth 1 % density perturbation, oblique
     B = 0.5, equilibrium radiation, opacity field spanning free streaming to
     diffusion, periodic boundaries, gamma = 4/3.
+  * ``beam_3d``     -- relativistic magnetised beam (Lorentz factor 7) injected
+    through a nozzle in the z = 0 face into an optically thick ambient medium,
+    outflow elsewhere.
+  * ``serving_mix`` -- request mixes for the serving loop.
   * ``random_prims`` -- i.i.d. admissible states for unit-level checks.
 """
 from __future__ import annotations
@@ -194,3 +198,59 @@ def poisson_arrivals(seed: int, n: int, rate: float) -> np.ndarray:
     """Arrival times (s) of a Poisson process with the given rate (1/s)."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+def beam_3d(seed: int = 0, nx: int = 512, ny: int | None = None, nz: int | None = None, steps: int = 50,
+            r_noz: float = 0.05) -> Problem:
+    """Cylindrical beam into an ambient medium on [-1/2,1/2]^2 x [0,1].
+
+    Ambient: rho = 1 + 0.01 g (periodic Fourier modes), p = 0.01, v = 0,
+    B = 0, radiation in equilibrium E_r = a_R T^4 (T = p/rho), F_r = 0.
+    Beam (inflow cells below z = 0 inside r < r_noz): W = 7 along z,
+    rho = 0.01, p = 0.01, B_phi = 0.3 r / r_noz, E_r = a_R (T = 1), F_r = 0.
+    a_R = 0.01; kappa ~ logU[10, 1e3] i.i.d. per cell, sigma = 0.
+    Returns the problem; the inflow primitives [12, nx*ny] and the mask are in
+    ``extra`` (the caller converts them to conserved variables)."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    rng = np.random.default_rng(seed)
+    dx, dy, dz = 1.0 / nx, 1.0 / ny, 1.0 / nz
+    x = -0.5 + (np.arange(nx) + 0.5) * dx
+    y = -0.5 + (np.arange(ny) + 0.5) * dy
+    z = (np.arange(nz) + 0.5) * dz
+    a_rad = 0.01
+    n = nx * ny * nz
+    V = np.zeros((NV, n))
+    # smooth density perturbation, built plane by plane (x fastest)
+    Xp, Yp = np.meshgrid(x, y, indexing="xy")
+    modes = [(rng.integers(1, 5, 3), rng.choice([-1, 1], 3), rng.uniform(0, 2 * math.pi)) for _ in range(8)]
+    g = np.zeros((nz, ny, nx))
+    for k, zz in enumerate(z):
+        acc = np.zeros_like(Xp)
+        for (kx, ky, kz), (sx, sy, sz), ph in modes:
+            acc += np.cos(2 * math.pi * (sx * kx * Xp + sy * ky * Yp + sz * kz * zz) + ph)
+        g[k] = acc
+    g /= np.max(np.abs(g))
+    rho = (1.0 + 0.01 * g).reshape(-1)
+    V[0] = rho
+    V[4] = 0.01
+    V[8] = a_rad * (0.01 / rho) ** 4
+    kap = _log_uniform(rng, 10.0, 1e3, n)
+    sig = np.zeros(n)
+    # inflow face (z = 0), transverse index i + nx j
+    r = np.sqrt(Xp * Xp + Yp * Yp).reshape(-1)
+    phi = np.arctan2(Yp, Xp).reshape(-1)
+    mask = (r < r_noz).astype(np.uint8)
+    Vin = np.zeros((NV, nx * ny))
+    W = 7.0
+    Vin[0] = 0.01
+    Vin[3] = math.sqrt(1.0 - 1.0 / (W * W))
+    Vin[4] = 0.01
+    bphi = 0.3 * np.minimum(r / r_noz, 1.0)
+    Vin[5] = -bphi * np.sin(phi)
+    Vin[6] = bphi * np.cos(phi)
+    Vin[8] = a_rad * 1.0
+    return Problem(name=f"beam3d_s{seed}_{nx}x{ny}x{nz}", shape=(nx, ny, nz), dx=(dx, dy, dz), x0=(-0.5, -0.5, 0.0),
+                   V=V, kappa=kap, sigma=sig, gamma=4.0 / 3.0, a_rad=a_rad,
+                   bc_lo=(OUTFLOW, OUTFLOW, INFLOW), bc_hi=(OUTFLOW, OUTFLOW, OUTFLOW), cfl=0.3, steps=steps,
+                   extra=dict(inflow_V=Vin, inflow_mask=mask))

@@ -40,6 +40,7 @@ class rrmhd_params(C.Structure):
         ("pvm_k", C.c_int), ("beta_mode", C.c_int), ("recon", C.c_int), ("rk_order", C.c_int),
         ("c2p_maxit", C.c_int), ("imp_maxit", C.c_int), ("imp_picard_it", C.c_int),
         ("imp_method", C.c_int), ("precision", C.c_int), ("pvm_eps_mixed", C.c_double),
+        ("e_floor", C.c_double),
     ]
 
 
@@ -50,7 +51,7 @@ class rrmhd_opacities(C.Structure):
 class rrmhd_report(C.Structure):
     _fields_ = [
         ("c2p_fail", C.c_longlong), ("pvm_fallback", C.c_longlong), ("imp_fail", C.c_longlong),
-        ("nonfinite", C.c_longlong), ("first_bad_cell", C.c_longlong),
+        ("nonfinite", C.c_longlong), ("e_floor_hits", C.c_longlong), ("first_bad_cell", C.c_longlong),
         ("max_c2p_it", C.c_int), ("max_imp_it", C.c_int),
     ]
 

@@ -52,7 +52,7 @@ def oracle_params(oracle, p):
                          c2p_tol=p.c2p_tol, imp_tol=p.imp_tol, rho_floor=p.rho_floor, p_floor=p.p_floor,
                          pvm_k=p.pvm_k, beta_mode=p.beta_mode, recon=p.recon, rk_order=p.rk_order,
                          c2p_maxit=p.c2p_maxit, imp_maxit=p.imp_maxit, imp_picard_it=p.imp_picard_it,
-                         imp_method=p.imp_method)
+                         imp_method=p.imp_method, e_floor=p.e_floor)
 
 
 def make_case(R, oracle, torch, P, **kw):
@@ -159,6 +159,7 @@ def one_step_compare(R, oracle, torch, P, dt=None, steps=1, **kw):
         assert rep_g["imp_fail"] == rep_o.imp_fail
         assert rep_g["pvm_fallback"] == rep_o.pvm_fallback
         assert rep_g["first_bad_cell"] == rep_o.first_bad_cell
+        assert rep_g["e_floor_hits"] == rep_o.e_floor_hits
     s.close()
     return worst, bit
 
@@ -187,3 +188,75 @@ def test_step_2d_full_size(R, oracle, torch_mod):
     oracle.threads(0)
     worst, bit = one_step_compare(R, oracle, torch_mod, I.blast_2d(0, 512), steps=1)
     assert bit
+
+
+# ---------------------------------------------------------------------- 3D ----
+def beam_case(R, oracle, torch, P, **kw):
+    p = lib_params(R, gamma=P.gamma, a_rad=P.a_rad, **kw)
+    op = oracle_params(oracle, p)
+    Uin = np.ascontiguousarray(oracle.p2c(P.extra["inflow_V"], op))
+    mask = np.ascontiguousarray(P.extra["inflow_mask"])
+    Uin_d, mask_d = dev(torch, Uin), dev(torch, mask)
+    g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi, inflow_U=Uin_d, inflow_mask=mask_d)
+    og = oracle.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi, inflow_U=Uin, inflow_mask=mask)
+    s = R.Solver(g, p)
+    U = oracle.p2c(P.V, op)
+    opac = R.make_opacities(dev(torch, P.kappa), dev(torch, P.sigma))
+    return p, op, g, og, s, U, opac
+
+
+def test_step_3d_beam_inflow(R, oracle, torch_mod):
+    """3D beam through an inflow mask on the z = 0 face (outflow elsewhere),
+    with the counted E_r floor; several steps, each from identical input."""
+    torch = torch_mod
+    oracle.threads(0)
+    P = I.beam_3d(0, 24, 20, 16, r_noz=0.2)
+    p, op, g, og, s, U, opac = beam_case(R, oracle, torch, P, e_floor=1e-14)
+    Ud = dev(torch, U)
+    floors = 0
+    for k in range(12):
+        Uin = host(Ud)
+        sm = s.max_speed(Ud)
+        sm_o, _ = oracle.max_speed(og, Uin, op)
+        assert sm == sm_o
+        dt = P.cfl * min(P.dx) / sm
+        s.step(Ud, dt, opac)
+        rep = s.report()
+        Uo, st, rep_o = oracle.step(og, Uin, dt, P.kappa, P.sigma, op)
+        assert np.array_equal(host(Ud), Uo), (k, relerr(host(Ud), Uo))
+        assert rep["e_floor_hits"] == rep_o.e_floor_hits and rep["imp_fail"] == rep_o.imp_fail
+        floors += rep["e_floor_hits"]
+    s.close()
+
+
+def test_step_3d_periodic_rough(R, oracle, torch_mod):
+    """Periodic 3D grid of i.i.d. states (every face a strong jump: exercises
+    the fallbacks and failure counters in all three directions)."""
+    torch = torch_mod
+    shape = (11, 7, 5)
+    n = int(np.prod(shape))
+    V = I.random_prims(77, n, vmax=0.6, rho=(0.5, 2.0), p=(0.5, 2.0), er=(0.1, 1.0))
+    rng = np.random.default_rng(3)
+    P = I.Problem(name="rough3d", shape=shape, dx=(0.1, 0.13, 0.17), x0=(0, 0, 0), V=V,
+                  kappa=rng.uniform(0.1, 10, n), sigma=rng.uniform(0.1, 10, n), gamma=5 / 3, a_rad=0.5,
+                  bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), cfl=0.3)
+    worst, bit = one_step_compare(R, oracle, torch, P, steps=2)
+    assert bit
+
+
+def test_step_3d_beam_subbox_256(R, oracle, torch_mod):
+    """One FP64 step of the 256^3 beam (the sub-box size of the 3D workload)
+    through the C ABI against the oracle."""
+    torch = torch_mod
+    oracle.threads(0)
+    P = I.beam_3d(0, 256, 256, 256)
+    p, op, g, og, s, U, opac = beam_case(R, oracle, torch, P, e_floor=1e-14)
+    Ud = dev(torch, U)
+    sm = s.max_speed(Ud)
+    sm_o, _ = oracle.max_speed(og, U, op)
+    assert sm == sm_o
+    dt = P.cfl * min(P.dx) / sm
+    s.step(Ud, dt, opac)
+    Uo, st, rep_o = oracle.step(og, U, dt, P.kappa, P.sigma, op)
+    assert np.array_equal(host(Ud), Uo), relerr(host(Ud), Uo)
+    s.close()
