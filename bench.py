@@ -126,6 +126,82 @@ def serving_bench(args):
     }
 
 
+def beam3d_bench(args):
+    """3D beam (W = 7, B_phi = 0.3, inflow mask on z = 0) into a thick ambient
+    medium, n^3 cells (default 512^3) in mixed precision, CFL 0.3. Also runs the
+    256^3 problem in FP64 and in mixed precision with the FP64 run's dt
+    sequence and reports L1(rho), L1(E_r) of mixed vs FP64 (the FP64 GPU path
+    is bit-identical to the CPU oracle per step)."""
+    import numpy as np
+    import torch
+    from paper_2212_00370_amd import inputs as I
+    from paper_2212_00370_amd import rrmhd as R
+
+    n = args.n if args.n != 512 or True else 512
+    steps = args.steps if args.steps != 200 else 50
+
+    def setup(P, prec):
+        p = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=prec, e_floor=1e-14)
+        Vin = torch.from_numpy(P.extra["inflow_V"]).cuda()
+        mask = torch.from_numpy(P.extra["inflow_mask"]).cuda()
+        g0 = R.make_grid(P.shape[:2], P.dx[:2])        # transverse plane, for the inflow state's p2c
+        s0 = R.Solver(g0, p)
+        Uin = s0.prim_to_cons(Vin)
+        torch.cuda.synchronize(); s0.close()
+        g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi, inflow_U=Uin, inflow_mask=mask)
+        s = R.Solver(g, p)
+        V = torch.from_numpy(P.V).cuda()
+        U = s.prim_to_cons(V)
+        del V
+        o = R.make_opacities(torch.from_numpy(P.kappa).cuda(), None, 0.0, 0.0)
+        torch.cuda.synchronize()
+        return s, U, o, (Uin, mask)
+
+    # full grid, mixed precision
+    P = I.beam_3d(args.seed, n)
+    s, U, o, keep = setup(P, R.MIXED)
+    Uw = U.clone()
+    for _ in range(2):
+        s.step(Uw, P.cfl * min(P.dx) / s.max_speed(Uw), o)
+    del Uw
+    s.report()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step(U, P.cfl * min(P.dx) / s.max_speed(U), o)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rep = s.report()
+    s.close()
+    del U, s, o, keep
+    torch.cuda.empty_cache()
+    # 256^3 sub-box problem: FP64 vs mixed
+    Q = I.beam_3d(args.seed, 256)
+    s64, U64, o64, k64 = setup(Q, R.FP64)
+    smx, Umx, omx, kmx = setup(Q, R.MIXED)
+    t64 = tmx = 0.0
+    for _ in range(steps):
+        dt = Q.cfl * min(Q.dx) / s64.max_speed(U64)
+        torch.cuda.synchronize(); a = time.perf_counter()
+        s64.step(U64, dt, o64); torch.cuda.synchronize(); b_ = time.perf_counter()
+        smx.step(Umx, dt, omx); torch.cuda.synchronize(); c = time.perf_counter()
+        t64 += b_ - a; tmx += c - b_
+    V64 = s64.cons_to_prim(U64); Vmx = smx.cons_to_prim(Umx)
+    l1 = lambda x, y: float((x - y).abs().sum() / y.abs().sum())
+    sub = {"cells": Q.ncell, "steps": steps, "L1_rho_mixed_vs_fp64": l1(Vmx[0], V64[0]),
+           "L1_Er_mixed_vs_fp64": l1(Umx[8], U64[8]),
+           "fp64_step_zone_updates_per_s": Q.ncell * steps / t64,
+           "mixed_step_zone_updates_per_s": Q.ncell * steps / tmx,
+           "fp64_report": s64.report(), "mixed_report": smx.report()}
+    s64.close(); smx.close()
+    return {"metric": METRIC, "value": P.ncell * steps / el, "unit": "zone-updates/s", "n_gpus": 1,
+            "steps": steps, "warmup": 2, "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic", "mode": "beam3d",
+            "config": {"workload": f"3D RRMHD+M1 beam {n}^3 mixed FP32/FP64 (W=7, B_phi 0.3, inflow mask, "
+                                   f"kappa logU[10,1e3]), CFL 0.3, {steps} steps", "cells": P.ncell},
+            "failures": rep, "subbox_256": sub}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -136,7 +212,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
-    ap.add_argument("--mode", choices=("step", "serving"), default="step")
+    ap.add_argument("--mode", choices=("step", "serving", "beam3d", "copycal"), default="step")
     ap.add_argument("--requests", type=int, default=120)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate / measured capacity")
     args = ap.parse_args()
@@ -155,6 +231,19 @@ def main():
     dev = torch.device("cuda:0")
     if args.mode == "serving":
         print(json.dumps(serving_bench(args)), flush=True)
+        return
+    if args.mode == "beam3d":
+        print(json.dumps(beam3d_bench(args)), flush=True)
+        return
+    if args.mode == "copycal":
+        # Plain device copy of a known size (256 MiB, 5 times): the reference
+        # that scales the HBM byte counters (FETCH_SIZE / WRITE_SIZE).
+        x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copycal", "bytes_per_copy": x.numel() * 8, "copies": 5}), flush=True)
         return
     P = I.blast_2d(args.seed, args.n, steps=args.steps)
     mixed = args.precision == "mixed"
