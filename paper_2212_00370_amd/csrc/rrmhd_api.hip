@@ -473,8 +473,9 @@ k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* 
 }
 
 // Phase 2 of the implicit solve (Newton) for the cells in `worklist`; the
-// explicit state U* was left in the output by the update pass. Grid-stride
-// over the list with blocks bi = 0..nb-1.
+// explicit state U* was left in the output by the update pass. Each cell is
+// handled by a quad of 4 lanes (see implicit_newton_quad); grid-stride over
+// the list with blocks bi = 0..nb-1 (64 cells per block).
 __device__ __forceinline__ void newton_blocks(long long bi, long long nb, long long ncell, const StageArgs& A,
                                               const Opac& op, const Phys& K, DevReport* rep, unsigned int* blkmax,
                                               const long long* __restrict__ worklist,
@@ -483,26 +484,32 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, long l
   const unsigned long long n = *wcount;
   unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
-  for (unsigned long long i = (unsigned long long)bi * kBlock + threadIdx.x; i < n;
-       i += (unsigned long long)nb * kBlock) {
+  constexpr int kCellsPerBlock = kBlock / 4;
+  const unsigned long long quad = threadIdx.x >> 2;
+  const bool lead = (threadIdx.x & 3) == 0;
+  // trip count is uniform over the quad (same i for its 4 lanes)
+  for (unsigned long long i = (unsigned long long)bi * kCellsPerBlock + quad; i < n;
+       i += (unsigned long long)nb * kCellsPerBlock) {
     const long long c = worklist[i];
     double Ust[NV], Un[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) Ust[q] = A.Uo[q * A.so + c];
     int it = 0;
     const double X0[4] = {xs[0 * ncell + i], xs[1 * ncell + i], xs[2 * ncell + i], xs[3 * ncell + i]};
-    const int st = rr::implicit_newton(Ust, A.cdt, opac_at(op.kappa, op.kappa0, c),
-                                       opac_at(op.sigma, op.sigma0, c), K, X0, xs[4 * ncell + i], Un, it);
-    bool fin = true;
+    const int st = rr::implicit_newton_quad(Ust, A.cdt, opac_at(op.kappa, op.kappa0, c),
+                                            opac_at(op.sigma, op.sigma0, c), K, X0, xs[4 * ncell + i], Un, it);
+    if (lead) {
+      bool fin = true;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      A.Uo[q * A.so + c] = Un[q];
-      fin = fin && isfinite(Un[q]);
+      for (int q = 0; q < NV; ++q) {
+        A.Uo[q * A.so + c] = Un[q];
+        fin = fin && isfinite(Un[q]);
+      }
+      if (st != rr::IMP_DONE) fimp += 1;
+      if (!fin) fnf += 1;
+      if ((st != rr::IMP_DONE || !fin) && (unsigned long long)c < bad) bad = (unsigned long long)c;
+      its = ((unsigned int)it > its) ? (unsigned int)it : its;
     }
-    if (st != rr::IMP_DONE) fimp += 1;
-    if (!fin) fnf += 1;
-    if ((st != rr::IMP_DONE || !fin) && (unsigned long long)c < bad) bad = (unsigned long long)c;
-    its = ((unsigned int)it > its) ? (unsigned int)it : its;
   }
   report_add(rep, blkmax, bi, 0, 0, fimp, fnf, bad, 0, its);
 }
@@ -982,9 +989,10 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   return RRMHD_OK;
 }
 
-// Blocks of the Newton pass per simulation: about one per 16 cell blocks.
+// Blocks of the Newton pass per simulation (64 cells per block): about one per
+// 4 cell blocks.
 long long newton_blocks_for(long long ncell_blocks, unsigned int cap) {
-  long long b = ncell_blocks / 16;
+  long long b = ncell_blocks / 4;
   if (b < 1) b = 1;
   if (b > (long long)cap) b = cap;
   return b;
@@ -1152,7 +1160,7 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   {
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    c->newton_blocks = (unsigned int)(2 * ncu);  // 2 blocks of 4 waves per CU = 2 waves per SIMD
+    c->newton_blocks = (unsigned int)(4 * ncu);  // 64 cells (4 lanes each) per block
   }
   if (hipHostMalloc(&c->host, sizeof(DevReport) + sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete c;
@@ -1352,7 +1360,7 @@ rrmhd_status rrmhd_batch_init(rrmhd_batch** out, int max_sims, void* workspace, 
   ok = ok && hipHostMalloc((void**)&b->hsmax, sizeof(double) * max_sims, hipHostMallocDefault) == hipSuccess;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  b->newton_cap = (unsigned int)(2 * ncu);
+  b->newton_cap = (unsigned int)(4 * ncu);
   if (!ok) {
     rrmhd_batch_destroy(b);
     return RRMHD_E_DEVICE;

@@ -920,6 +920,133 @@ __device__ __forceinline__ int implicit_newton(const double Us[NV], double h, do
   return IMP_DONE;
 }
 
+// Phase 2 on a quad of 4 lanes (lanes 4k..4k+3 of a wave, all on the same
+// cell and all active together): lane j builds Jacobian column j and tries
+// line-search step 2^-(j + 4r) in round r; the quad then shares the results.
+// The selections equal those of implicit_newton (first acceptable step in
+// the order 1, 1/2, 1/4, ...), so the result is the same bit for bit.
+__device__ __forceinline__ double quad_get(double v, int base, int k) { return __shfl(v, base + k, 64); }
+
+__device__ __forceinline__ int implicit_newton_quad(const double Us[NV], double h, double kap, double sig,
+                                                    const Phys& K, const double X0[4], double Z0, double Un[NV],
+                                                    int& iters) {
+  const int lane = threadIdx.x & 63;
+  const int j = lane & 3;
+  const int base = lane & ~3;
+  ImpIn in;
+  iters = 0;
+  bool conv = false;
+  double X[4];
+  bool floored = false;
+  if (imp_prepare(Us, K, in, floored)) {
+    X[0] = X0[0]; X[1] = X0[1]; X[2] = X0[2]; X[3] = X0[3];
+    ImpSys sy;
+    double Zg = Z0, R[4];
+    int it = 0, c2p_it = 0;
+    if (imp_build(X, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sy, c2p_it)) {
+      Zg = sy.Z;
+      imp_residual(sy, X, R);
+      double sprev = 0.0;
+      for (int n = 0; n < K.imp_maxit; ++n) {
+        ++it;
+        double bd[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bd[i] = sy.b[i] / sy.C[i][i];
+        const double sc = dmax(vmaxabs4(X), vmaxabs4(bd));
+        const double del = 1e-8 * sc;
+        // column j on lane j
+        double col[4] = {0.0, 0.0, 0.0, 0.0};
+        double okc;
+        {
+          double Xp[4] = {X[0], X[1], X[2], X[3]};
+          Xp[j] = Xp[j] + del;
+          ImpSys sp;
+          okc = imp_build(Xp, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sp, c2p_it) ? 1.0 : 0.0;
+          if (okc != 0.0) {
+            double Rp[4];
+            imp_residual(sp, Xp, Rp);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) col[i] = (Rp[i] - R[i]) / del;
+          }
+        }
+        // the sequential rule stops at the first failing column: any failure breaks
+        const double okall = quad_get(okc, base, 0) * quad_get(okc, base, 1) * quad_get(okc, base, 2) *
+                             quad_get(okc, base, 3);
+        if (okall == 0.0) break;
+        double J[4][4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) J[i][k] = quad_get(col[i], base, k);
+        double nR[4] = {-R[0], -R[1], -R[2], -R[3]}, dX[4];
+        if (!solve4(J, nR, dX)) break;
+        const double rn = vmaxabs4(R);
+        const double dn = vmaxabs4(dX);
+        bool acc = false;
+        double Xt[4], Rt[4], Zt = 0.0, bt[4], Ct[4];
+        double lam0 = 1.0;
+        for (int round = 0; round < 3 && !acc; ++round) {
+          double lam = lam0;
+          for (int k = 0; k < j; ++k) lam = 0.5 * lam;
+          double mx[4], mr[4], mb[4], mc[4], mz = 0.0, good = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) { mx[i] = X[i] + lam * dX[i]; mr[i] = 0.0; mb[i] = 0.0; mc[i] = 1.0; }
+          ImpSys st;
+          if (mx[0] > 0.0 && imp_build(mx, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, st, c2p_it)) {
+            imp_residual(st, mx, mr);
+            if (vmaxabs4(mr) < rn || lam * dn <= 1e-10 * sc) {
+              good = 1.0;
+              mz = st.Z;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) { mb[i] = st.b[i]; mc[i] = st.C[i][i]; }
+            }
+          }
+          // first acceptable lane in order 0..3
+          int pick = -1;
+#pragma unroll
+          for (int k = 3; k >= 0; --k)
+            if (quad_get(good, base, k) != 0.0) pick = k;
+          if (pick >= 0) {
+            acc = true;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              Xt[i] = quad_get(mx[i], base, pick);
+              Rt[i] = quad_get(mr[i], base, pick);
+              bt[i] = quad_get(mb[i], base, pick);
+              Ct[i] = quad_get(mc[i], base, pick);
+            }
+            Zt = quad_get(mz, base, pick);
+          }
+          lam0 = 0.5 * (0.5 * (0.5 * (0.5 * lam0)));
+        }
+        if (!acc) break;
+        double stp[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          stp[i] = Xt[i] - X[i];
+          X[i] = Xt[i];
+          R[i] = Rt[i];
+          sy.b[i] = bt[i];
+          sy.C[i][i] = Ct[i];
+        }
+        Zg = Zt;
+        const double sn = vmaxabs4(stp);
+        if (sn <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
+        if (n > 0 && sn <= 1e-9 * sc && sn >= sprev) { conv = true; break; }
+        sprev = sn;
+      }
+    }
+    iters = it;
+  }
+  if (!conv) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Un[q] = Us[q];
+    return IMP_FAILED;
+  }
+  imp_finish(X, Us, in, Un);
+  return IMP_DONE;
+}
+
 // ---------------------------------------------------------------------------
 // Signal speed bound of a cell in direction d: relativistic fast-speed bound
 // with a^2 = cs^2 + ca^2 - cs^2 ca^2 for the fluid, M1 eigenvalues
