@@ -157,6 +157,24 @@ rrmhd_status rrmhd_step(rrmhd_ctx* ctx, double* U, const rrmhd_grid* g, double d
 rrmhd_status rrmhd_max_speed(rrmhd_ctx* ctx, const double* U, const rrmhd_grid* g,
                              double* smax_host);
 
+/* nsteps IMEX steps (as rrmhd_step), each with its time step taken on the
+ * device from the state at the start of the step: dt = (cfl * min_d dx_d) /
+ * s_max, s_max as rrmhd_max_speed computes it (CFL condition, Section 3.2;
+ * signal speeds of eqs. lam1-lam3). The result is bitwise that of calling
+ * rrmhd_max_speed and then rrmhd_step with that dt on the host, nsteps times,
+ * but nothing waits on the host: the work is enqueued on the context's stream
+ * (so a caller may also capture it in a HIP graph). The first stage's
+ * primitive recovery and the signal speeds share one pass, so a recovery
+ * failure in the step's initial state is counted once in the report (the
+ * separate calls count it in both). A step whose s_max is 0 or not a number
+ * runs with dt = 0 and adds one to the report's nonfinite count.
+ * cfl: > 0. dt_out: optional caller-owned DEVICE array of nsteps doubles that
+ * receives each step's dt (NULL: not written). U as in rrmhd_step.
+ * Errors: RRMHD_E_INVALID for a grid of another shape, cfl not > 0 and finite
+ * or nsteps < 0 (nothing enqueued); RRMHD_E_DEVICE on a launch failure. */
+rrmhd_status rrmhd_advance(rrmhd_ctx* ctx, double* U, const rrmhd_grid* g, double cfl, int nsteps,
+                           const rrmhd_opacities* opac, double* dt_out);
+
 /* Diagnostic: the face fluxes of the first stage for state U (recovery,
  * reconstruction and PVM-int flux, Section 3.2). Fh: device, the directions
  * one after another, each [12][faces_d] with faces_d = prod(n) with n_d + 1

@@ -594,8 +594,10 @@ static real vmaxabs4(const real a[4]) {
 // gas's), Newton on R(X) = C(X) X - b(X) with a forward-difference Jacobian
 // and step halving finishes from the last admissible iterate. Both reach the
 // same root of the backward-Euler system.
+// Zg0: recovery Z of the stage's cell state (warm start of the first
+// recovery at X*; 0 for a cold start).
 static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OPar& P,
-                         const Consts& K, real Un[NV], int* iters, int* c2p_it, int* floored) {
+                         const Consts& K, real Un[NV], int* iters, int* c2p_it, int* floored, real Zg0) {
   const real Et = Us[4] + Us[8];
   real St[3];
   for (int j = 0; j < 3; ++j) St[j] = Us[1 + j] + Us[9 + j];
@@ -628,7 +630,7 @@ static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OP
   }
   real X[4] = {Ul[8], Ul[9], Ul[10], Ul[11]};
   ImpSys sy;
-  real Zg = 0.0;
+  real Zg = Zg0;
   int it = 0;
   bool conv = false;
   bool have = false;
@@ -663,7 +665,7 @@ static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OP
     const bool from_picard = built && capped && npic > 1 && dlast < dprev;
     if (!from_picard) {
       for (int i = 0; i < 4; ++i) X[i] = Xg[i];
-      Zg = 0.0;
+      Zg = Zg0;
     }
     real R[4];
     if (imp_build(X, Ul, Et, St, h, kap, sig, P, K, Zg, sy, c2p_it)) {
@@ -818,6 +820,7 @@ static long long map_cell(const Grid& G, int i, int j, int k, int dir) {
 struct CellPrim {
   std::vector<double> V;      // [12][ncell]
   std::vector<double> taup;   // D (kappa + sigma), optical depth per unit length
+  std::vector<double> Z;      // recovered Z = rho h W^2 (0 where recovery failed)
   std::vector<double> inV;    // inflow primitives [12][ntrans]
   std::vector<double> intaup;
 };
@@ -836,6 +839,7 @@ static long long stage_prims(const Grid& G, const OPar& P, const Consts& K, cons
   const long long vs = G.g.var_stride;
   cp.V.assign((size_t)NV * N, 0.0);
   cp.taup.assign(N, 0.0);
+  cp.Z.assign(N, 0.0);
   long long nfail = 0;
   long long fb = -1;
   int mit = 0;
@@ -846,10 +850,12 @@ static long long stage_prims(const Grid& G, const OPar& P, const Consts& K, cons
     load_U(U, vs, c, Uc);
     if (c2p(Uc, P, K, real(0.0), Vc, &Z, &it) != 0) {
       c2p_fallback(Uc, P, Vc);
+      Z = 0.0;
       nfail += 1;
 #pragma omp critical
       { if (fb < 0 || c < fb) fb = c; }
     }
+    cp.Z[c] = dv(Z);
     mit = std::max(mit, it);
     for (int q = 0; q < NV; ++q) cp.V[q * N + c] = dv(Vc[q]);
     cp.taup[c] = dv(Uc[0] * (real(opac_at(kap, kap0, c)) + real(opac_at(sig, sig0, c))));
@@ -1012,7 +1018,8 @@ static int step_impl(const OGrid& og, const OPar& P, double* U, const double* ka
       }
       real Unc[NV];
       int iters = 0, cit = 0, fl = 0;
-      const int st = implicit_cell(Ust, cdt, real(opac_at(kap, kap0, c)), real(opac_at(sig, sig0, c)), P, K, Unc, &iters, &cit, &fl);
+      const int st = implicit_cell(Ust, cdt, real(opac_at(kap, kap0, c)), real(opac_at(sig, sig0, c)), P, K, Unc, &iters, &cit, &fl,
+                                   real(cp.Z[c]));
       if (st != 0) nimp += 1;
       nfl += fl;
       mit = std::max(mit, iters);
@@ -1126,7 +1133,7 @@ void or_implicit(long long n, const double* Us, long long su, const double* h, c
     real Uc[NV], Uo[NV];
     for (int q = 0; q < NV; ++q) Uc[q] = Us[q * su + c];
     int it = 0, cit = 0, fl = 0;
-    int st = implicit_cell(Uc, real(h[c]), real(kap[c]), real(sig[c]), *P, K, Uo, &it, &cit, &fl);
+    int st = implicit_cell(Uc, real(h[c]), real(kap[c]), real(sig[c]), *P, K, Uo, &it, &cit, &fl, real(0.0));
     for (int q = 0; q < NV; ++q) Un[q * sn + c] = dv(Uo[q]);
     if (status) status[c] = st;
     if (iters) iters[c] = it;

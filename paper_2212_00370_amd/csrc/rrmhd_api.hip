@@ -188,18 +188,49 @@ __global__ void __launch_bounds__(kBlock) k_c2p(long long n, const double* __res
   report_add(rep, blkmax, blockIdx.x, fail, 0, 0, 0, bad, its, 0);
 }
 
+// Block maximum of per-thread signal speeds s -> partial[lb] (wave butterfly,
+// then the waves in order).
+__device__ __forceinline__ void block_max_to(double s, double* __restrict__ partial, long long lb) {
+  __shared__ double red[kBlock / kWave];
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) s = rr::dmax(s, __shfl_xor(s, o, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / kWave; ++w) m = rr::dmax(m, red[w]);
+    partial[lb] = m;
+  }
+}
+
+// Largest signal speed of one cell with primitives v over the active directions.
+__device__ __forceinline__ double cell_signal_speed(const GridDev& G, const double v[NV], const Phys& K) {
+  rr::Aux a;
+  rr::prim_aux(v, K, a);
+  double s = rr::dmax(0.0, rr::cell_speed<0>(v, a, K));
+  if (G.ndim > 1) s = rr::dmax(s, rr::cell_speed<1>(v, a, K));
+  if (G.ndim > 2) s = rr::dmax(s, rr::cell_speed<2>(v, a, K));
+  return s;
+}
+
 // Stage primitives: interior cells (c < N) from U, inflow cells from inflow_U.
 // Vp: [12][Np], taup: [Np] = D (kappa + sigma). lb: block index within the
 // simulation. Cell 0 also clears the stage's Newton work-list counter.
+// With a non-null `partial`, the block also writes the maximum signal speed of
+// its interior cells to partial[lb] (lb < blocks over the N interior cells);
+// the recovered primitives are those a separate signal-speed pass computes.
 __device__ __forceinline__ void prims_block(long long lb, const GridDev& G, const double* __restrict__ U,
                                             long long su, const double* __restrict__ inU, const Opac& op,
                                             double* __restrict__ Vp, double* __restrict__ taup, long long np,
                                             const Phys& K, DevReport* rep, unsigned int* blkmax,
-                                            unsigned long long* wcount) {
+                                            unsigned long long* wcount, double* __restrict__ Zc,
+                                            double* __restrict__ partial = nullptr) {
   const long long c = lb * kBlock + threadIdx.x;
   if (c == 0) *wcount = 0;
   unsigned long long fail = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
+  double s = 0.0;
   if (c < G.N + G.nt) {
     double u[NV], v[NV], Z = 0.0;
     int it = 0;
@@ -216,22 +247,39 @@ __device__ __forceinline__ void prims_block(long long lb, const GridDev& G, cons
     }
     if (rr::c2p(u, K, 0.0, v, Z, it) != 0) {
       rr::c2p_fallback(u, K, v);
+      Z = 0.0;
       if (c < G.N) { fail = 1; bad = (unsigned long long)c; }
     }
-    if (c < G.N) its = (unsigned int)it;
+    if (c < G.N) {
+      its = (unsigned int)it;
+      Zc[c] = Z;
+      if (partial) s = cell_signal_speed(G, v, K);
+    }
 #pragma unroll
     for (int q = 0; q < NV; ++q) Vp[q * np + c] = v[q];
     taup[c] = u[0] * (opac_at(op.kappa, op.kappa0, oc) + opac_at(op.sigma, op.sigma0, oc));
   }
   report_add(rep, blkmax, lb, fail, 0, 0, 0, bad, its, 0);
+  if (partial && lb * kBlock < G.N) block_max_to(s, partial, lb);
 }
 
 __global__ void __launch_bounds__(kBlock) k_prims(GridDev G, const double* __restrict__ U, long long su,
                                                   const double* __restrict__ inU, Opac op,
                                                   double* __restrict__ Vp, double* __restrict__ taup,
                                                   long long np, Phys K, DevReport* rep, unsigned int* blkmax,
-                                                  unsigned long long* wcount) {
-  prims_block(blockIdx.x, G, U, su, inU, op, Vp, taup, np, K, rep, blkmax, wcount);
+                                                  unsigned long long* wcount, double* Zc) {
+  prims_block(blockIdx.x, G, U, su, inU, op, Vp, taup, np, K, rep, blkmax, wcount, Zc);
+}
+
+// Stage primitives of the first stage and the signal-speed block maxima in one
+// pass (the step's time step is then formed on the device).
+__global__ void __launch_bounds__(kBlock) k_prims_speed(GridDev G, const double* __restrict__ U, long long su,
+                                                        const double* __restrict__ inU, Opac op,
+                                                        double* __restrict__ Vp, double* __restrict__ taup,
+                                                        long long np, Phys K, DevReport* rep, unsigned int* blkmax,
+                                                        unsigned long long* wcount, double* Zc,
+                                                        double* __restrict__ partial) {
+  prims_block(blockIdx.x, G, U, su, inU, op, Vp, taup, np, K, rep, blkmax, wcount, Zc, partial);
 }
 
 struct FaceArgs {
@@ -377,10 +425,17 @@ struct StageArgs {
   double* Uo;
   long long so;
   const void* Fh[3];   // double (FP64 path) or float (mixed path)
+  const double* Zc;    // recovery Z of the stage state per cell (warm start)
   long long nf[3];
   double idx[3];
   double a0, a1, cdt;
+  // Time step held on the device: when dtp is set, the stage uses
+  // cdt = cc * dtp[0] instead of cdt.
+  const double* dtp;
+  double cc;
 };
+
+__device__ __forceinline__ double stage_cdt(const StageArgs& A) { return A.dtp ? A.cc * A.dtp[0] : A.cdt; }
 
 // Flux divergence and stage combination, then phase 1 of the implicit solve
 // (Picard). Cells that need the Newton phase get their explicit state U*
@@ -394,6 +449,7 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
   const FT* F0 = (const FT*)A.Fh[0];
   const FT* F1 = (const FT*)A.Fh[1];
   const FT* F2 = (const FT*)A.Fh[2];
+  const double cdt = stage_cdt(A);
   const long long c = lb * kBlock + threadIdx.x;
   unsigned long long fimp = 0, fnf = 0, ffl = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
@@ -416,13 +472,13 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
       double div = ((double)F0[q * A.nf[0] + fm[0] + fs[0]] - (double)F0[q * A.nf[0] + fm[0]]) * A.idx[0];
       if (G.ndim > 1) div = div + ((double)F1[q * A.nf[1] + fm[1] + fs[1]] - (double)F1[q * A.nf[1] + fm[1]]) * A.idx[1];
       if (G.ndim > 2) div = div + ((double)F2[q * A.nf[2] + fm[2] + fs[2]] - (double)F2[q * A.nf[2] + fm[2]]) * A.idx[2];
-      Ust[q] = (A.a0 * A.U0[q * A.s0 + c] + A.a1 * A.Us[q * A.ss + c]) - A.cdt * div;
+      Ust[q] = (A.a0 * A.U0[q * A.s0 + c] + A.a1 * A.Us[q * A.ss + c]) - cdt * div;
     }
     double Un[NV];
     int it = 0;
     bool floored = false;
-    const int st = rr::implicit_picard(Ust, A.cdt, opac_at(op.kappa, op.kappa0, c),
-                                       opac_at(op.sigma, op.sigma0, c), K, Un, it, floored, X0, Z0);
+    const int st = rr::implicit_picard(Ust, cdt, opac_at(op.kappa, op.kappa0, c),
+                                       opac_at(op.sigma, op.sigma0, c), K, Un, it, floored, X0, Z0, A.Zc[c]);
     its = (unsigned int)it;
     ffl = floored ? 1 : 0;
     if (st == rr::IMP_NEED_NEWTON) {
@@ -482,6 +538,7 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, long l
                                               const unsigned long long* wcount) {
   const double* xs = (const double*)(worklist + ncell);
   const unsigned long long n = *wcount;
+  const double cdt = stage_cdt(A);
   unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
   constexpr int kCellsPerBlock = kBlock / 4;
@@ -496,7 +553,7 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, long l
     for (int q = 0; q < NV; ++q) Ust[q] = A.Uo[q * A.so + c];
     int it = 0;
     const double X0[4] = {xs[0 * ncell + i], xs[1 * ncell + i], xs[2 * ncell + i], xs[3 * ncell + i]};
-    const int st = rr::implicit_newton_quad(Ust, A.cdt, opac_at(op.kappa, op.kappa0, c),
+    const int st = rr::implicit_newton_quad(Ust, cdt, opac_at(op.kappa, op.kappa0, c),
                                             opac_at(op.sigma, op.sigma0, c), K, X0, xs[4 * ncell + i], Un, it);
     if (lead) {
       bool fin = true;
@@ -524,7 +581,6 @@ k_newton(long long ncell, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned
 __device__ __forceinline__ void speed_block(long long lb, const GridDev& G, const double* __restrict__ U,
                                             long long su, const Phys& K, double* __restrict__ partial,
                                             DevReport* rep, unsigned int* blkmax) {
-  __shared__ double red[kBlock / kWave];
   const long long c = lb * kBlock + threadIdx.x;
   double s = 0.0;
   unsigned long long fail = 0, bad = ULLONG_MAX;
@@ -538,23 +594,10 @@ __device__ __forceinline__ void speed_block(long long lb, const GridDev& G, cons
       fail = 1;
       bad = (unsigned long long)c;
     }
-    rr::Aux a;
-    rr::prim_aux(v, K, a);
-    s = rr::dmax(s, rr::cell_speed<0>(v, a, K));
-    if (G.ndim > 1) s = rr::dmax(s, rr::cell_speed<1>(v, a, K));
-    if (G.ndim > 2) s = rr::dmax(s, rr::cell_speed<2>(v, a, K));
+    s = cell_signal_speed(G, v, K);
   }
   report_add(rep, blkmax, lb, fail, 0, 0, 0, bad, 0, 0);
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) s = rr::dmax(s, __shfl_xor(s, o, kWave));
-  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = red[0];
-#pragma unroll
-    for (int w = 1; w < kBlock / kWave; ++w) m = rr::dmax(m, red[w]);
-    partial[lb] = m;
-  }
+  block_max_to(s, partial, lb);
 }
 
 __global__ void __launch_bounds__(kBlock) k_speed(GridDev G, const double* __restrict__ U, long long su,
@@ -585,6 +628,24 @@ __global__ void __launch_bounds__(kBlock) k_reduce_max(const double* __restrict_
   reduce_max_block(partial, n, out);
 }
 
+// Signal speed, then the step's time step dt = (cfl dx_min) / s_max into
+// sd[1] (and dt_out[k] when given). A dt that is not finite and >= 0 (zero or
+// NaN speed) becomes 0 and is counted as a non-finite result.
+__global__ void __launch_bounds__(kBlock) k_reduce_dt(const double* __restrict__ partial, long long n,
+                                                      double* __restrict__ sd, double cfl_dx, DevReport* rep,
+                                                      double* __restrict__ dt_out, int k) {
+  reduce_max_block(partial, n, sd);
+  if (threadIdx.x == 0) {
+    double dt = cfl_dx / sd[0];
+    if (!(dt >= 0.0) || !(dt < 1e300)) {
+      dt = 0.0;
+      atomicAdd(&rep->nonfinite, 1ull);
+    }
+    sd[1] = dt;
+    if (dt_out) dt_out[k] = dt;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Batched kernels: one launch covers every simulation of a batch. Each block
 // finds its simulation by binary search in a block-offset table and works on
@@ -605,6 +666,7 @@ struct SimDesc {
   const double* inflow_U;
   long long* work;
   unsigned long long* wcount;
+  double* Zc;
   DevReport* rep;
   unsigned int* blkmax;
   double* partial;
@@ -640,6 +702,9 @@ __device__ __forceinline__ StageArgs stage_args(const SimDesc& D, int stage, int
   A.a0 = a0;
   A.a1 = a1;
   A.cdt = c * D.dt;
+  A.dtp = nullptr;
+  A.cc = c;
+  A.Zc = D.Zc;
   return A;
 }
 
@@ -651,7 +716,7 @@ __global__ void __launch_bounds__(kBlock) k_prims_b(const SimDesc* __restrict__ 
   const double* Us = (stage == 0) ? D.U : D.Us;
   const long long ss = (stage == 0) ? D.vs : D.ns;
   prims_block(blockIdx.x - o[s], D.G, Us, ss, D.inflow_U, D.op, D.Vp, D.taup, D.FA.np, D.K, D.rep, D.blkmax,
-              D.wcount);
+              D.wcount, D.Zc);
 }
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
@@ -840,7 +905,8 @@ struct Layout {
   long long npartial;
   long long nb_faces[3];
   long long nblkmax;  // block slots for the iteration maxima
-  size_t off_Vp, off_taup, off_Us, off_Fh[3], off_partial, off_smax, off_rep, off_blkmax, off_work, off_wcount, total;
+  size_t off_Vp, off_taup, off_Us, off_Fh[3], off_partial, off_smax, off_rep, off_blkmax, off_work, off_wcount, off_Zc,
+      total;
 };
 
 Layout make_layout(const rrmhd_grid* g) {
@@ -868,11 +934,12 @@ Layout make_layout(const rrmhd_grid* g) {
   L.off_Us = o; o = align256(o + sizeof(double) * NV * L.Ns);
   for (int d = 0; d < 3; ++d) { L.off_Fh[d] = o; o = align256(o + sizeof(double) * NV * L.nf[d]); }
   L.off_partial = o; o = align256(o + sizeof(double) * L.npartial);
-  L.off_smax = o; o = align256(o + sizeof(double));
+  L.off_smax = o; o = align256(o + 2 * sizeof(double));
   L.off_rep = o; o = align256(o + sizeof(DevReport));
   L.off_blkmax = o; o = align256(o + sizeof(unsigned int) * 2 * L.nblkmax);
   L.off_work = o; o = align256(o + sizeof(long long) * L.N + sizeof(double) * 5 * L.N);  // cells + [5][N] starts
   L.off_wcount = o; o = align256(o + sizeof(unsigned long long));
+  L.off_Zc = o; o = align256(o + sizeof(double) * L.N);
   L.total = o;
   return L;
 }
@@ -907,6 +974,7 @@ struct rrmhd_ctx {
   unsigned int* blkmax;
   long long* work;              // cells left to the Newton phase of the implicit solve
   unsigned long long* wcount;
+  double* Zc;                   // recovery Z of the stage state per cell
   hipStream_t stream;
   unsigned int newton_blocks;
   void* host;  // pinned: DevReport + one double
@@ -957,15 +1025,19 @@ Opac make_opac(const rrmhd_opacities* o) {
 }
 
 // Stage primitives and face fluxes of state Us (stride ss) into `out[d]`.
+// have_prims: the stage primitives of Us are already in the workspace.
 rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, long long ss,
-                          const Opac& op, double* const out[3]) {
+                          const Opac& op, double* const out[3], bool have_prims = false) {
   const Layout& L = c->L;
   const GridDev G = make_griddev(g, L);
-  int pe = prof_begin(c, RRMHD_K_PRIMS, L.N + L.nt);
-  k_prims<<<nblocks(L.N + L.nt), kBlock, 0, c->stream>>>(G, Us, ss, g->inflow_U, op, c->Vp, c->taup,
-                                                           L.Np, c->K, c->rep, c->blkmax, c->wcount);
-  prof_end(c, pe);
-  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  int pe;
+  if (!have_prims) {
+    pe = prof_begin(c, RRMHD_K_PRIMS, L.N + L.nt);
+    k_prims<<<nblocks(L.N + L.nt), kBlock, 0, c->stream>>>(G, Us, ss, g->inflow_U, op, c->Vp, c->taup,
+                                                             L.Np, c->K, c->rep, c->blkmax, c->wcount, c->Zc);
+    prof_end(c, pe);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  }
   FaceArgs A;
   A.Vp = c->Vp;
   A.taup = c->taup;
@@ -1026,6 +1098,7 @@ SimDesc make_desc(rrmhd_ctx* c, double* U, const rrmhd_opacities* opac, double d
   D.inflow_U = g->inflow_U;
   D.work = c->work;
   D.wcount = c->wcount;
+  D.Zc = c->Zc;
   D.rep = c->rep;
   D.blkmax = c->blkmax;
   D.partial = c->partial;
@@ -1153,6 +1226,7 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   c->blkmax = (unsigned int*)(c->ws + L.off_blkmax);
   c->work = (long long*)(c->ws + L.off_work);
   c->wcount = (unsigned long long*)(c->ws + L.off_wcount);
+  c->Zc = (double*)(c->ws + L.off_Zc);
   c->stream = (hipStream_t)hip_stream;
   c->host = nullptr;
   c->prof = false;
@@ -1199,12 +1273,15 @@ rrmhd_status rrmhd_face_fluxes(rrmhd_ctx* c, const double* U, const rrmhd_opacit
   return stage_fluxes(c, &c->grid, U, c->grid.var_stride, make_opac(opac), out);
 }
 
-rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt, const rrmhd_opacities* opac) {
-  if (!c || !U || !same_shape(c, g) || !grid_valid(g)) return RRMHD_E_INVALID;
-  if (!(dt >= 0.0) || !(dt < 1e300)) return RRMHD_E_INVALID;
+namespace {
+
+// The stages of one IMEX step. dt_dev: when set, the time step is read on the
+// device from dt_dev[0] (dt unused), and the first stage's primitives are
+// already in the workspace.
+rrmhd_status step_stages(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt, const double* dt_dev,
+                         const Opac& op) {
   const Layout& L = c->L;
   const GridDev G = make_griddev(g, L);
-  const Opac op = make_opac(opac);
   const long long vs = g->var_stride;
   // Stage coefficients (a0, a1, c) of U* = a0 U^(0) + a1 U^(s) + c dt L(U^(s)).
   double co[3][3];
@@ -1222,7 +1299,7 @@ rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt,
   for (int s = 0; s < ns; ++s) {
     const double* Us = (s == 0) ? U : c->Us;
     const long long ss = (s == 0) ? vs : L.Ns;
-    const rrmhd_status st = stage_fluxes(c, g, Us, ss, op, fl);
+    const rrmhd_status st = stage_fluxes(c, g, Us, ss, op, fl, s == 0 && dt_dev != nullptr);
     if (st != RRMHD_OK) return st;
     StageArgs A;
     A.U0 = U; A.s0 = vs;
@@ -1238,6 +1315,9 @@ rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt,
     A.a0 = co[s][0];
     A.a1 = co[s][1];
     A.cdt = co[s][2] * dt;
+    A.dtp = dt_dev;
+    A.cc = co[s][2];
+    A.Zc = c->Zc;
     int pe = prof_begin(c, RRMHD_K_UPDATE, L.N);
     if (c->par.precision == RRMHD_MIXED)
       k_update<float><<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
@@ -1251,6 +1331,39 @@ rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt,
     k_newton<<<nbn, kBlock, 0, c->stream>>>(L.N, A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
     prof_end(c, pe);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  }
+  return RRMHD_OK;
+}
+
+}  // namespace
+
+rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt, const rrmhd_opacities* opac) {
+  if (!c || !U || !same_shape(c, g) || !grid_valid(g)) return RRMHD_E_INVALID;
+  if (!(dt >= 0.0) || !(dt < 1e300)) return RRMHD_E_INVALID;
+  return step_stages(c, U, g, dt, nullptr, make_opac(opac));
+}
+
+rrmhd_status rrmhd_advance(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double cfl, int nsteps,
+                           const rrmhd_opacities* opac, double* dt_out) {
+  if (!c || !U || !same_shape(c, g) || !grid_valid(g)) return RRMHD_E_INVALID;
+  if (!(cfl > 0.0) || !(cfl < 1e300) || nsteps < 0) return RRMHD_E_INVALID;
+  const Layout& L = c->L;
+  const GridDev G = make_griddev(g, L);
+  const Opac op = make_opac(opac);
+  double dxmin = g->dx[0];
+  for (int d = 1; d < g->ndim; ++d) dxmin = (g->dx[d] < dxmin) ? g->dx[d] : dxmin;
+  const double cfl_dx = cfl * dxmin;
+  for (int k = 0; k < nsteps; ++k) {
+    int pe = prof_begin(c, RRMHD_K_PRIMS, L.N + L.nt);
+    k_prims_speed<<<nblocks(L.N + L.nt), kBlock, 0, c->stream>>>(G, U, g->var_stride, g->inflow_U, op, c->Vp,
+                                                                  c->taup, L.Np, c->K, c->rep, c->blkmax,
+                                                                  c->wcount, c->Zc, c->partial);
+    prof_end(c, pe);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    k_reduce_dt<<<1, kBlock, 0, c->stream>>>(c->partial, L.npartial, c->smax, cfl_dx, c->rep, dt_out, k);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    const rrmhd_status st = step_stages(c, U, g, 0.0, c->smax + 1, op);
+    if (st != RRMHD_OK) return st;
   }
   return RRMHD_OK;
 }

@@ -770,9 +770,11 @@ enum { IMP_DONE = 0, IMP_FAILED = 1, IMP_NEED_NEWTON = 2 };
 // Phase 1. IMP_DONE: Un holds the result; IMP_FAILED: Un = Us;
 // IMP_NEED_NEWTON: phase 2 must finish the cell from X0 (warm start Z0): the
 // last Picard iterate if Picard was still contracting at its cap, else X*.
+// Zg0: recovery Z of the stage's cell state, the warm start of the first
+// recovery at X* (0: cold).
 __device__ __forceinline__ int implicit_picard(const double Us[NV], double h, double kap, double sig,
                                                const Phys& K, double Un[NV], int& iters, bool& floored,
-                                               double X0[4], double& Z0) {
+                                               double X0[4], double& Z0, double Zg0) {
   ImpIn in;
   iters = 0;
   if (!imp_prepare(Us, K, in, floored)) {
@@ -782,7 +784,7 @@ __device__ __forceinline__ int implicit_picard(const double Us[NV], double h, do
   }
   double X[4] = {in.Ul[8], in.Ul[9], in.Ul[10], in.Ul[11]};
   ImpSys sy;
-  double Zg = 0.0;
+  double Zg = Zg0;
   int it = 0, c2p_it = 0;
   bool conv = false, have = false, built = false, capped = false;
   const int npic = (K.imp_method == 1) ? 0 : ((K.imp_method == 2) ? K.imp_maxit : K.imp_picard_it);
@@ -825,7 +827,7 @@ __device__ __forceinline__ int implicit_picard(const double Us[NV], double h, do
     } else {
 #pragma unroll
       for (int i = 0; i < 4; ++i) X0[i] = in.Ul[8 + i];
-      Z0 = 0.0;
+      Z0 = Zg0;
     }
     return IMP_NEED_NEWTON;
   }

@@ -69,6 +69,7 @@ SIGNATURES = {
     "rrmhd_cons_to_prim": ([_vp, _vp, _vp], C.c_int),
     "rrmhd_step": ([_vp, _vp, _vp, _d, _vp], C.c_int),
     "rrmhd_max_speed": ([_vp, _vp, _vp, _vp], C.c_int),
+    "rrmhd_advance": ([_vp, _vp, _vp, _d, C.c_int, _vp, _vp], C.c_int),
     "rrmhd_face_fluxes": ([_vp, _vp, _vp, _vp], C.c_int),
     "rrmhd_profile_enable": ([_vp, C.c_int], C.c_int),
     "rrmhd_profile_read": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
@@ -144,6 +145,16 @@ def rrmhd_cons_to_prim(ctx, U, V) -> None:
 
 def rrmhd_step(ctx, U, grid: rrmhd_grid, dt: float, opac: rrmhd_opacities) -> None:
     _check(_lib.rrmhd_step(ctx, _ptr(U), C.byref(grid), float(dt), C.byref(opac)), "rrmhd_step")
+
+
+def rrmhd_advance(ctx, U, grid: rrmhd_grid, cfl: float, nsteps: int, opac: rrmhd_opacities, dt_out=None) -> None:
+    """nsteps steps with the time step formed on the device; enqueued.
+    dt_out: optional device tensor of nsteps float64 receiving each dt."""
+    if dt_out is not None:
+        import torch
+        assert dt_out.dtype == torch.float64 and dt_out.is_cuda and dt_out.numel() >= nsteps
+    _check(_lib.rrmhd_advance(ctx, _ptr(U), C.byref(grid), float(cfl), int(nsteps), C.byref(opac),
+                              None if dt_out is None else _ptr(dt_out)), "rrmhd_advance")
 
 
 def rrmhd_max_speed(ctx, U, grid: rrmhd_grid) -> float:
@@ -320,6 +331,9 @@ class Solver:
 
     def max_speed(self, U):
         return rrmhd_max_speed(self.ctx, U, self.grid)
+
+    def advance(self, U, cfl, nsteps, opac, dt_out=None):
+        rrmhd_advance(self.ctx, U, self.grid, cfl, nsteps, opac, dt_out)
 
     def face_fluxes(self, U, opac):
         sizes = []

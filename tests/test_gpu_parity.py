@@ -190,6 +190,88 @@ def test_step_2d_full_size(R, oracle, torch_mod):
     assert bit
 
 
+# ------------------------------------------------- time step on the device ----
+def advance_compare(R, oracle, torch, P, steps, **kw):
+    """rrmhd_advance (time step formed on the device, no host wait) against
+    the oracle's loop of signal speed, dt = (cfl dx_min) / s_max and step, and
+    against the library's own loop with the time step on the host."""
+    p, op, g, og, s, U, opac = make_case(R, oracle, torch, P, **kw)
+    Ud = dev(torch, U)
+    dts = torch.full((steps,), -1.0, dtype=torch.float64, device="cuda:0")
+    s.advance(Ud, P.cfl, steps, opac, dts)
+    rep_g = s.report()
+    Ug, dtg = host(Ud), host(dts)
+    # the library's host-dt loop
+    Uh = dev(torch, U)
+    for k in range(steps):
+        s.step(Uh, P.cfl * min(P.dx) / s.max_speed(Uh), opac)
+    s.report()
+    assert np.array_equal(host(Uh), Ug)
+    s.close()
+    # the oracle
+    Uo = U
+    fails = dict(c2p=0, imp=0, pvm=0)
+    for k in range(steps):
+        sm, _ = oracle.max_speed(og, Uo, op)
+        h = P.cfl * min(P.dx) / sm
+        assert dtg[k] == h, (k, dtg[k], h)
+        Uo, st, rep_o = oracle.step(og, Uo, h, P.kappa, P.sigma, op)
+        fails["c2p"] += rep_o.c2p_fail
+        fails["imp"] += rep_o.imp_fail
+        fails["pvm"] += rep_o.pvm_fallback
+    assert relerr(Ug, Uo) <= TOL
+    assert rep_g["imp_fail"] == fails["imp"] and rep_g["pvm_fallback"] == fails["pvm"]
+    assert rep_g["c2p_fail"] == fails["c2p"] and rep_g["nonfinite"] == 0
+    return np.array_equal(Ug, Uo)
+
+
+@pytest.mark.parametrize("seed", [0, 3, 5])
+def test_advance_1d_riemann(R, oracle, torch_mod, seed):
+    assert advance_compare(R, oracle, torch_mod, I.riemann_1d(seed), steps=4)
+
+
+def test_advance_1d_rk3(R, oracle, torch_mod):
+    assert advance_compare(R, oracle, torch_mod, I.riemann_1d(4), steps=3, rk_order=3)
+
+
+def test_advance_2d_small(R, oracle, torch_mod):
+    assert advance_compare(R, oracle, torch_mod, I.blast_2d(0, 72, 50), steps=4)
+
+
+def test_advance_2d_mixed_matches_host_loop(R, oracle, torch_mod):
+    """Mixed precision: the device-dt run equals the host-dt run bitwise."""
+    P = I.blast_2d(1, 64, 48)
+    p, op, g, og, s, U, opac = make_case(R, oracle, torch_mod, P, precision=R.MIXED)
+    Ua, Ub = dev(torch_mod, U), dev(torch_mod, U)
+    s.advance(Ua, P.cfl, 3, opac)
+    for k in range(3):
+        s.step(Ub, P.cfl * min(P.dx) / s.max_speed(Ub), opac)
+    assert np.array_equal(host(Ua), host(Ub))
+    s.close()
+
+
+def test_advance_edge_cases(R, oracle, torch_mod):
+    P = I.blast_2d(0, 40, 24)
+    p, op, g, og, s, U, opac = make_case(R, oracle, torch_mod, P)
+    Ud = dev(torch_mod, U)
+    s.advance(Ud, P.cfl, 0, opac)           # nothing to do
+    assert np.array_equal(host(Ud), U)
+    for bad in (0.0, -0.5, float("nan"), float("inf")):
+        with pytest.raises(R.RRMHDError):
+            s.advance(Ud, bad, 1, opac)
+    with pytest.raises(R.RRMHDError):
+        s.advance(Ud, P.cfl, -1, opac)
+    assert np.array_equal(host(Ud), U)
+    s.close()
+
+
+def test_advance_2d_full_size(R, oracle, torch_mod):
+    """512^2 blast in the benchmark's launch configuration (rrmhd_advance),
+    two steps against the oracle."""
+    oracle.threads(0)
+    assert advance_compare(R, oracle, torch_mod, I.blast_2d(0, 512), steps=2)
+
+
 # ---------------------------------------------------------------------- 3D ----
 def beam_case(R, oracle, torch, P, **kw):
     p = lib_params(R, gamma=P.gamma, a_rad=P.a_rad, **kw)
