@@ -28,6 +28,20 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
+// Picard iterations of the implicit solve done in the update pass; a cell
+// still iterating there continues, unchanged, in the work-list pass.
+#ifndef RRMHD_PICARD_SPLIT
+#define RRMHD_PICARD_SPLIT 9
+#endif
+constexpr int kPicardSplit = RRMHD_PICARD_SPLIT;
+// Minimum waves per SIMD the register allocation of the face and update
+// kernels targets (a hint to the compiler; fewer registers, some spilled).
+#ifndef RRMHD_FACES_WAVES
+#define RRMHD_FACES_WAVES 2
+#endif
+#ifndef RRMHD_UPDATE_WAVES
+#define RRMHD_UPDATE_WAVES 3
+#endif
 
 struct DevReport {
   unsigned long long c2p_fail, pvm_fallback, imp_fail, nonfinite, e_floor_hits;
@@ -216,7 +230,7 @@ __device__ __forceinline__ double cell_signal_speed(const GridDev& G, const doub
 
 // Stage primitives: interior cells (c < N) from U, inflow cells from inflow_U.
 // Vp: [12][Np], taup: [Np] = D (kappa + sigma). lb: block index within the
-// simulation. Cell 0 also clears the stage's Newton work-list counter.
+// simulation. Cell 0 also clears the Newton work-list counter wcount (if set).
 // With a non-null `partial`, the block also writes the maximum signal speed of
 // its interior cells to partial[lb] (lb < blocks over the N interior cells);
 // the recovered primitives are those a separate signal-speed pass computes.
@@ -227,7 +241,7 @@ __device__ __forceinline__ void prims_block(long long lb, const GridDev& G, cons
                                             unsigned long long* wcount, double* __restrict__ Zc,
                                             double* __restrict__ partial = nullptr) {
   const long long c = lb * kBlock + threadIdx.x;
-  if (c == 0) *wcount = 0;
+  if (c == 0 && wcount) *wcount = 0;
   unsigned long long fail = 0, bad = ULLONG_MAX;
   unsigned int its = 0;
   double s = 0.0;
@@ -412,8 +426,10 @@ __device__ __forceinline__ void faces_block(long long lb, const GridDev& G, cons
 // the FP64 and transcendental latency than one wave with no spills.
 // FT = double: FP64 path; FT = float: mixed-precision path.
 template <typename FT>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
-k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_FACES_WAVES)))
+k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, unsigned long long* wreset) {
+  // the work-list counter of the update pass that follows (not read here)
+  if (wreset && blockIdx.x == 0 && threadIdx.x == 0) *wreset = 0;
   faces_block<sizeof(FT) == sizeof(float)>(blockIdx.x, G, A, K, rep, blkmax);
 }
 
@@ -425,7 +441,7 @@ struct StageArgs {
   double* Uo;
   long long so;
   const void* Fh[3];   // double (FP64 path) or float (mixed path)
-  const double* Zc;    // recovery Z of the stage state per cell (warm start)
+  double* Zc;          // recovery Z of the stage state per cell (warm start)
   long long nf[3];
   double idx[3];
   double a0, a1, cdt;
@@ -433,13 +449,53 @@ struct StageArgs {
   // cdt = cc * dtp[0] instead of cdt.
   const double* dtp;
   double cc;
+  // Picard iterations the update pass runs before it hands a cell to the
+  // work-list pass (which continues the same iteration).
+  int m_split;
+  // Next stage's primitives: with nextp set, each cell's recovery from its
+  // output state is done where the cell finishes (Vp, taup, Zc of the next
+  // stage); with speed also set, the signal-speed block maxima go to
+  // partial[update block] and partial[npart + work-list block].
+  int nextp, speed;
+  double* Vp;
+  double* taup;
+  long long np;
+  double* partial;
+  long long npart;
 };
 
 __device__ __forceinline__ double stage_cdt(const StageArgs& A) { return A.dtp ? A.cc * A.dtp[0] : A.cdt; }
 
+// Stage primitives of interior cell c from its new state Un (as prims_block
+// computes them); returns the cell's signal speed when A.speed is set.
+__device__ __forceinline__ double next_prims(const GridDev& G, const StageArgs& A, const Opac& op, const Phys& K,
+                                             long long c, const double Un[NV], unsigned long long& fail,
+                                             unsigned long long& bad, unsigned int& c2p_its) {
+  double v[NV], Z = 0.0;
+  int it = 0;
+  if (rr::c2p(Un, K, 0.0, v, Z, it) != 0) {
+    rr::c2p_fallback(Un, K, v);
+    Z = 0.0;
+    fail += 1;
+    if ((unsigned long long)c < bad) bad = (unsigned long long)c;
+  }
+  c2p_its = ((unsigned int)it > c2p_its) ? (unsigned int)it : c2p_its;
+  A.Zc[c] = Z;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) A.Vp[q * A.np + c] = v[q];
+  A.taup[c] = Un[0] * (opac_at(op.kappa, op.kappa0, c) + opac_at(op.sigma, op.sigma0, c));
+  return A.speed ? cell_signal_speed(G, v, K) : 0.0;
+}
+
+// Work-list entry of a cell handed to the second pass, planes of `xs`:
+// 0-3 X, 4 Zg, 5 dlast, 6 dprev, 7 Picard solves so far, 8 next Picard index m
+// (a Picard state to continue), or m = -1 with X, Zg the Newton start point.
+constexpr int kWorkPlanes = 9;
+
 // Flux divergence and stage combination, then phase 1 of the implicit solve
-// (Picard). Cells that need the Newton phase get their explicit state U*
-// written to the output and are appended to `worklist` (one atomic per wave).
+// (Picard, up to A.m_split iterations). Cells that need more (the rest of
+// Picard, or Newton) get their explicit state U* written to the output and
+// are appended to `worklist` (one atomic per wave) with their Picard state.
 // FT: storage type of the face fluxes; the divergence is accumulated in FP64
 // either way (differences of stored values are exact in FP64 for FP32 data).
 template <typename FT>
@@ -451,10 +507,12 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
   const FT* F2 = (const FT*)A.Fh[2];
   const double cdt = stage_cdt(A);
   const long long c = lb * kBlock + threadIdx.x;
-  unsigned long long fimp = 0, fnf = 0, ffl = 0, bad = ULLONG_MAX;
-  unsigned int its = 0;
+  unsigned long long fimp = 0, fnf = 0, ffl = 0, fc2p = 0, bad = ULLONG_MAX;
+  unsigned int its = 0, cits = 0;
+  double spd = 0.0;
   bool newton = false;
-  double X0[4] = {0.0, 0.0, 0.0, 0.0}, Z0 = 0.0;
+  rr::PicardState S;
+  S.m = -1;
   if (c < G.N) {
     const int ci[3] = {(int)(c % G.n[0]), (int)((c / G.n[0]) % G.n[1]), (int)(c / ((long long)G.n[0] * G.n[1]))};
     long long fm[3], fs[3];
@@ -475,13 +533,30 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
       Ust[q] = (A.a0 * A.U0[q * A.s0 + c] + A.a1 * A.Us[q * A.ss + c]) - cdt * div;
     }
     double Un[NV];
-    int it = 0;
     bool floored = false;
-    const int st = rr::implicit_picard(Ust, cdt, opac_at(op.kappa, op.kappa0, c),
-                                       opac_at(op.sigma, op.sigma0, c), K, Un, it, floored, X0, Z0, A.Zc[c]);
-    its = (unsigned int)it;
+    rr::ImpIn in;
+    int st;
+    const double Zg0 = A.Zc[c];
+    S.it = 0;
+    if (!rr::imp_prepare(Ust, K, in, floored)) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) Un[q] = Ust[q];
+      st = rr::IMP_FAILED;
+    } else {
+      double X0[4], Z0;
+      rr::picard_start(in, Zg0, S);
+      st = rr::picard_run(Ust, in, cdt, opac_at(op.kappa, op.kappa0, c), opac_at(op.sigma, op.sigma0, c), K, S,
+                          A.m_split, Zg0, Un, X0, Z0);
+      if (st == rr::IMP_NEED_NEWTON) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) S.X[i] = X0[i];
+        S.Zg = Z0;
+        S.m = -1;
+      }
+    }
+    its = (unsigned int)S.it;
     ffl = floored ? 1 : 0;
-    if (st == rr::IMP_NEED_NEWTON) {
+    if (st == rr::IMP_NEED_NEWTON || st == rr::IMP_PENDING) {
       newton = true;
 #pragma unroll
       for (int q = 0; q < NV; ++q) A.Uo[q * A.so + c] = Ust[q];
@@ -495,6 +570,7 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
       if (st != rr::IMP_DONE) fimp = 1;
       if (!fin) fnf = 1;
       if (st != rr::IMP_DONE || !fin) bad = (unsigned long long)c;
+      if (A.nextp) spd = next_prims(G, A, op, K, c, Un, fc2p, bad, cits);
     }
   }
   // Append the cells that need phase 2.
@@ -509,38 +585,45 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
                                                            __builtin_amdgcn_mbcnt_lo((unsigned int)mask, 0u));
       const unsigned long long slot = base + below;
       worklist[slot] = c;
-      // Newton start point and warm start, [5][N] planes
       double* xs = (double*)(worklist + G.N);
-      xs[0 * G.N + slot] = X0[0];
-      xs[1 * G.N + slot] = X0[1];
-      xs[2 * G.N + slot] = X0[2];
-      xs[3 * G.N + slot] = X0[3];
-      xs[4 * G.N + slot] = Z0;
+      xs[0 * G.N + slot] = S.X[0];
+      xs[1 * G.N + slot] = S.X[1];
+      xs[2 * G.N + slot] = S.X[2];
+      xs[3 * G.N + slot] = S.X[3];
+      xs[4 * G.N + slot] = S.Zg;
+      xs[5 * G.N + slot] = S.dlast;
+      xs[6 * G.N + slot] = S.dprev;
+      xs[7 * G.N + slot] = (double)S.it;
+      xs[8 * G.N + slot] = (double)S.m;
     }
   }
-  report_add(rep, blkmax, lb, 0, 0, fimp, fnf, bad, 0, its, ffl);
+  report_add(rep, blkmax, lb, fc2p, 0, fimp, fnf, bad, cits, its, ffl);
+  if (A.speed) block_max_to(spd, A.partial, lb);
 }
 
 template <typename FT>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_UPDATE_WAVES)))
 k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
          long long* worklist, unsigned long long* wcount) {
   update_block<FT>(blockIdx.x, G, A, op, K, rep, blkmax, worklist, wcount);
 }
 
-// Phase 2 of the implicit solve (Newton) for the cells in `worklist`; the
-// explicit state U* was left in the output by the update pass. Each cell is
-// handled by a quad of 4 lanes (see implicit_newton_quad); grid-stride over
-// the list with blocks bi = 0..nb-1 (64 cells per block).
-__device__ __forceinline__ void newton_blocks(long long bi, long long nb, long long ncell, const StageArgs& A,
+// Second pass of the implicit solve for the cells in `worklist` (the rest of
+// the Picard phase, then Newton where needed); the explicit state U* was left
+// in the output by the update pass. Each cell is handled by a quad of 4
+// lanes (see implicit_newton_quad); grid-stride over the list with blocks
+// bi = 0..nb-1 (64 cells per block).
+__device__ __forceinline__ void newton_blocks(long long bi, long long nb, const GridDev& G, const StageArgs& A,
                                               const Opac& op, const Phys& K, DevReport* rep, unsigned int* blkmax,
                                               const long long* __restrict__ worklist,
                                               const unsigned long long* wcount) {
+  const long long ncell = G.N;
   const double* xs = (const double*)(worklist + ncell);
   const unsigned long long n = *wcount;
   const double cdt = stage_cdt(A);
-  unsigned long long fimp = 0, fnf = 0, bad = ULLONG_MAX;
-  unsigned int its = 0;
+  unsigned long long fimp = 0, fnf = 0, fc2p = 0, bad = ULLONG_MAX;
+  unsigned int its = 0, cits = 0;
+  double spd = 0.0;
   constexpr int kCellsPerBlock = kBlock / 4;
   const unsigned long long quad = threadIdx.x >> 2;
   const bool lead = (threadIdx.x & 3) == 0;
@@ -551,10 +634,27 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, long l
     double Ust[NV], Un[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) Ust[q] = A.Uo[q * A.so + c];
+    const double kap = opac_at(op.kappa, op.kappa0, c), sig = opac_at(op.sigma, op.sigma0, c);
+    rr::PicardState S;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) S.X[k] = xs[k * ncell + i];
+    S.Zg = xs[4 * ncell + i];
+    S.dlast = xs[5 * ncell + i];
+    S.dprev = xs[6 * ncell + i];
+    S.it = (int)xs[7 * ncell + i];
+    S.m = (int)xs[8 * ncell + i];
+    double X0[4] = {S.X[0], S.X[1], S.X[2], S.X[3]}, Z0 = S.Zg;
+    int st = rr::IMP_NEED_NEWTON;
+    if (S.m >= 0) {
+      // continue the Picard phase (the 4 lanes of the quad alike)
+      rr::ImpIn in;
+      bool floored = false;
+      rr::imp_prepare(Ust, K, in, floored);  // succeeded in the update pass
+      st = rr::picard_run(Ust, in, cdt, kap, sig, K, S, 0x7fffffff, A.Zc[c], Un, X0, Z0);
+    }
     int it = 0;
-    const double X0[4] = {xs[0 * ncell + i], xs[1 * ncell + i], xs[2 * ncell + i], xs[3 * ncell + i]};
-    const int st = rr::implicit_newton_quad(Ust, cdt, opac_at(op.kappa, op.kappa0, c),
-                                            opac_at(op.sigma, op.sigma0, c), K, X0, xs[4 * ncell + i], Un, it);
+    if (st == rr::IMP_NEED_NEWTON) st = rr::implicit_newton_quad(Ust, cdt, kap, sig, K, X0, Z0, Un, it);
+    it += S.it;
     if (lead) {
       bool fin = true;
 #pragma unroll
@@ -566,15 +666,17 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, long l
       if (!fin) fnf += 1;
       if ((st != rr::IMP_DONE || !fin) && (unsigned long long)c < bad) bad = (unsigned long long)c;
       its = ((unsigned int)it > its) ? (unsigned int)it : its;
+      if (A.nextp) spd = rr::dmax(spd, next_prims(G, A, op, K, c, Un, fc2p, bad, cits));
     }
   }
-  report_add(rep, blkmax, bi, 0, 0, fimp, fnf, bad, 0, its);
+  report_add(rep, blkmax, bi, fc2p, 0, fimp, fnf, bad, cits, its);
+  if (A.speed) block_max_to(spd, A.partial, A.npart + bi);
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_newton(long long ncell, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
+k_newton(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
          const long long* __restrict__ worklist, const unsigned long long* wcount) {
-  newton_blocks(blockIdx.x, gridDim.x, ncell, A, op, K, rep, blkmax, worklist, wcount);
+  newton_blocks(blockIdx.x, gridDim.x, G, A, op, K, rep, blkmax, worklist, wcount);
 }
 
 // Per-block maximum of the cell signal speeds -> partial[lb].
@@ -705,6 +807,14 @@ __device__ __forceinline__ StageArgs stage_args(const SimDesc& D, int stage, int
   A.dtp = nullptr;
   A.cc = c;
   A.Zc = D.Zc;
+  A.m_split = 0x7fffffff;
+  A.nextp = 0;
+  A.speed = 0;
+  A.Vp = nullptr;
+  A.taup = nullptr;
+  A.np = 0;
+  A.partial = nullptr;
+  A.npart = 0;
   return A;
 }
 
@@ -745,7 +855,7 @@ __global__ void __launch_bounds__(kBlock) k_newton_b(const SimDesc* __restrict__
   const int s = find_sim(o, nsim, blockIdx.x);
   const SimDesc& D = T[s];
   const StageArgs A = stage_args(D, stage, last, a0, a1, c);
-  newton_blocks(blockIdx.x - o[s], o[s + 1] - o[s], D.G.N, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
+  newton_blocks(blockIdx.x - o[s], o[s + 1] - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
 }
 
 __global__ void __launch_bounds__(kBlock) k_speed_b(const SimDesc* __restrict__ T, const long long* __restrict__ off,
@@ -933,12 +1043,13 @@ Layout make_layout(const rrmhd_grid* g) {
   L.off_taup = o; o = align256(o + sizeof(double) * L.Np);
   L.off_Us = o; o = align256(o + sizeof(double) * NV * L.Ns);
   for (int d = 0; d < 3; ++d) { L.off_Fh[d] = o; o = align256(o + sizeof(double) * NV * L.nf[d]); }
-  L.off_partial = o; o = align256(o + sizeof(double) * L.npartial);
+  // signal-speed block maxima: cell blocks, then work-list blocks (<= cell blocks)
+  L.off_partial = o; o = align256(o + sizeof(double) * 2 * L.npartial);
   L.off_smax = o; o = align256(o + 2 * sizeof(double));
   L.off_rep = o; o = align256(o + sizeof(DevReport));
   L.off_blkmax = o; o = align256(o + sizeof(unsigned int) * 2 * L.nblkmax);
-  L.off_work = o; o = align256(o + sizeof(long long) * L.N + sizeof(double) * 5 * L.N);  // cells + [5][N] starts
-  L.off_wcount = o; o = align256(o + sizeof(unsigned long long));
+  L.off_work = o; o = align256(o + sizeof(long long) * L.N + sizeof(double) * kWorkPlanes * L.N);  // cells + state
+  L.off_wcount = o; o = align256(o + 2 * sizeof(unsigned long long));  // one per stage parity
   L.off_Zc = o; o = align256(o + sizeof(double) * L.N);
   L.total = o;
   return L;
@@ -973,7 +1084,8 @@ struct rrmhd_ctx {
   DevReport* rep;
   unsigned int* blkmax;
   long long* work;              // cells left to the Newton phase of the implicit solve
-  unsigned long long* wcount;
+  unsigned long long* wcount;   // two counters, alternating between stages
+  unsigned long long stage_ctr;
   double* Zc;                   // recovery Z of the stage state per cell
   hipStream_t stream;
   unsigned int newton_blocks;
@@ -1026,15 +1138,17 @@ Opac make_opac(const rrmhd_opacities* o) {
 
 // Stage primitives and face fluxes of state Us (stride ss) into `out[d]`.
 // have_prims: the stage primitives of Us are already in the workspace.
+// wreset: work-list counter of the following update pass, cleared here.
 rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, long long ss,
-                          const Opac& op, double* const out[3], bool have_prims = false) {
+                          const Opac& op, double* const out[3], bool have_prims = false,
+                          unsigned long long* wreset = nullptr) {
   const Layout& L = c->L;
   const GridDev G = make_griddev(g, L);
   int pe;
   if (!have_prims) {
     pe = prof_begin(c, RRMHD_K_PRIMS, L.N + L.nt);
     k_prims<<<nblocks(L.N + L.nt), kBlock, 0, c->stream>>>(G, Us, ss, g->inflow_U, op, c->Vp, c->taup,
-                                                             L.Np, c->K, c->rep, c->blkmax, c->wcount, c->Zc);
+                                                             L.Np, c->K, c->rep, c->blkmax, nullptr, c->Zc);
     prof_end(c, pe);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   }
@@ -1053,9 +1167,9 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   }
   pe = prof_begin(c, RRMHD_K_FACES, A.nf[0] + A.nf[1] + A.nf[2]);
   if (c->par.precision == RRMHD_MIXED)
-    k_faces<float><<<(unsigned int)nbt, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax);
+    k_faces<float><<<(unsigned int)nbt, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset);
   else
-    k_faces<double><<<(unsigned int)nbt, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax);
+    k_faces<double><<<(unsigned int)nbt, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset);
   prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   return RRMHD_OK;
@@ -1226,6 +1340,7 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   c->blkmax = (unsigned int*)(c->ws + L.off_blkmax);
   c->work = (long long*)(c->ws + L.off_work);
   c->wcount = (unsigned long long*)(c->ws + L.off_wcount);
+  c->stage_ctr = 0;
   c->Zc = (double*)(c->ws + L.off_Zc);
   c->stream = (hipStream_t)hip_stream;
   c->host = nullptr;
@@ -1275,11 +1390,20 @@ rrmhd_status rrmhd_face_fluxes(rrmhd_ctx* c, const double* U, const rrmhd_opacit
 
 namespace {
 
+// Blocks of the single-simulation work-list pass: a few per CU, at most one
+// per cell block.
+unsigned int worklist_blocks(const rrmhd_ctx* c) {
+  const long long nb = nblocks(c->L.N);
+  return (unsigned int)((nb < c->newton_blocks) ? nb : c->newton_blocks);
+}
+
 // The stages of one IMEX step. dt_dev: when set, the time step is read on the
-// device from dt_dev[0] (dt unused), and the first stage's primitives are
-// already in the workspace.
+// device from dt_dev[0] (dt unused). prims0: the first stage's primitives are
+// already in the workspace. prims_after: also recover the primitives of the
+// step's result (the next step's first stage) and the signal-speed block
+// maxima, cell blocks then work-list blocks, into `partial`.
 rrmhd_status step_stages(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt, const double* dt_dev,
-                         const Opac& op) {
+                         const Opac& op, bool prims0, bool prims_after) {
   const Layout& L = c->L;
   const GridDev G = make_griddev(g, L);
   const long long vs = g->var_stride;
@@ -1296,10 +1420,14 @@ rrmhd_status step_stages(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt
     ns = 2;
   }
   double* const fl[3] = {c->Fh[0], c->Fh[1], c->Fh[2]};
+  const unsigned int nbn = worklist_blocks(c);
   for (int s = 0; s < ns; ++s) {
+    // work-list counters alternate between stages
+    unsigned long long* wc = c->wcount + (c->stage_ctr & 1);
+    c->stage_ctr += 1;
     const double* Us = (s == 0) ? U : c->Us;
     const long long ss = (s == 0) ? vs : L.Ns;
-    const rrmhd_status st = stage_fluxes(c, g, Us, ss, op, fl, s == 0 && dt_dev != nullptr);
+    const rrmhd_status st = stage_fluxes(c, g, Us, ss, op, fl, (s == 0) ? prims0 : true, wc);
     if (st != RRMHD_OK) return st;
     StageArgs A;
     A.U0 = U; A.s0 = vs;
@@ -1318,17 +1446,23 @@ rrmhd_status step_stages(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt
     A.dtp = dt_dev;
     A.cc = co[s][2];
     A.Zc = c->Zc;
+    A.m_split = kPicardSplit;
+    A.nextp = (!last || prims_after) ? 1 : 0;
+    A.speed = (last && prims_after) ? 1 : 0;
+    A.Vp = c->Vp;
+    A.taup = c->taup;
+    A.np = L.Np;
+    A.partial = c->partial;
+    A.npart = L.npartial;
     int pe = prof_begin(c, RRMHD_K_UPDATE, L.N);
     if (c->par.precision == RRMHD_MIXED)
-      k_update<float><<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
+      k_update<float><<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, wc);
     else
-      k_update<double><<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
+      k_update<double><<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, wc);
     prof_end(c, pe);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-    // Grid-stride over the work list; a few blocks per CU.
-    const unsigned int nbn = (unsigned int)((nblocks(L.N) < c->newton_blocks) ? nblocks(L.N) : c->newton_blocks);
     pe = prof_begin(c, RRMHD_K_NEWTON, L.N);
-    k_newton<<<nbn, kBlock, 0, c->stream>>>(L.N, A, op, c->K, c->rep, c->blkmax, c->work, c->wcount);
+    k_newton<<<nbn, kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, wc);
     prof_end(c, pe);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   }
@@ -1340,7 +1474,7 @@ rrmhd_status step_stages(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt
 rrmhd_status rrmhd_step(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt, const rrmhd_opacities* opac) {
   if (!c || !U || !same_shape(c, g) || !grid_valid(g)) return RRMHD_E_INVALID;
   if (!(dt >= 0.0) || !(dt < 1e300)) return RRMHD_E_INVALID;
-  return step_stages(c, U, g, dt, nullptr, make_opac(opac));
+  return step_stages(c, U, g, dt, nullptr, make_opac(opac), false, false);
 }
 
 rrmhd_status rrmhd_advance(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double cfl, int nsteps,
@@ -1353,16 +1487,21 @@ rrmhd_status rrmhd_advance(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double 
   double dxmin = g->dx[0];
   for (int d = 1; d < g->ndim; ++d) dxmin = (g->dx[d] < dxmin) ? g->dx[d] : dxmin;
   const double cfl_dx = cfl * dxmin;
+  const long long nred = L.npartial + worklist_blocks(c);
   for (int k = 0; k < nsteps; ++k) {
-    int pe = prof_begin(c, RRMHD_K_PRIMS, L.N + L.nt);
-    k_prims_speed<<<nblocks(L.N + L.nt), kBlock, 0, c->stream>>>(G, U, g->var_stride, g->inflow_U, op, c->Vp,
-                                                                  c->taup, L.Np, c->K, c->rep, c->blkmax,
-                                                                  c->wcount, c->Zc, c->partial);
-    prof_end(c, pe);
+    if (k == 0) {
+      // later steps get their primitives and speeds from the previous step
+      int pe = prof_begin(c, RRMHD_K_PRIMS, L.N + L.nt);
+      k_prims_speed<<<nblocks(L.N + L.nt), kBlock, 0, c->stream>>>(G, U, g->var_stride, g->inflow_U, op, c->Vp,
+                                                                    c->taup, L.Np, c->K, c->rep, c->blkmax,
+                                                                    nullptr, c->Zc, c->partial);
+      prof_end(c, pe);
+      if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    }
+    k_reduce_dt<<<1, kBlock, 0, c->stream>>>(c->partial, (k == 0) ? L.npartial : nred, c->smax, cfl_dx, c->rep,
+                                             dt_out, k);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-    k_reduce_dt<<<1, kBlock, 0, c->stream>>>(c->partial, L.npartial, c->smax, cfl_dx, c->rep, dt_out, k);
-    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-    const rrmhd_status st = step_stages(c, U, g, 0.0, c->smax + 1, op);
+    const rrmhd_status st = step_stages(c, U, g, 0.0, c->smax + 1, op, true, k + 1 < nsteps);
     if (st != RRMHD_OK) return st;
   }
   return RRMHD_OK;

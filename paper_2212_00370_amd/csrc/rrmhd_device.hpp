@@ -765,38 +765,53 @@ __device__ __forceinline__ void imp_finish(double X[4], const double Us[NV], con
   for (int j = 0; j < 3; ++j) Un[9 + j] = X[1 + j];
 }
 
-enum { IMP_DONE = 0, IMP_FAILED = 1, IMP_NEED_NEWTON = 2 };
+enum { IMP_DONE = 0, IMP_FAILED = 1, IMP_NEED_NEWTON = 2, IMP_PENDING = 3 };
 
-// Phase 1. IMP_DONE: Un holds the result; IMP_FAILED: Un = Us;
-// IMP_NEED_NEWTON: phase 2 must finish the cell from X0 (warm start Z0): the
-// last Picard iterate if Picard was still contracting at its cap, else X*.
-// Zg0: recovery Z of the stage's cell state, the warm start of the first
-// recovery at X* (0: cold).
-__device__ __forceinline__ int implicit_picard(const double Us[NV], double h, double kap, double sig,
-                                               const Phys& K, double Un[NV], int& iters, bool& floored,
-                                               double X0[4], double& Z0, double Zg0) {
-  ImpIn in;
-  iters = 0;
-  if (!imp_prepare(Us, K, in, floored)) {
+// State of the Picard phase between iterations: iterate X, warm start Zg of
+// the next recovery, the last two update norms, solves done, next index m.
+struct PicardState {
+  double X[4];
+  double Zg, dlast, dprev;
+  int it, m;
+};
+
+__device__ __forceinline__ void picard_start(const ImpIn& in, double Zg0, PicardState& S) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) Un[q] = Us[q];
-    return IMP_FAILED;
-  }
-  double X[4] = {in.Ul[8], in.Ul[9], in.Ul[10], in.Ul[11]};
+  for (int i = 0; i < 4; ++i) S.X[i] = in.Ul[8 + i];
+  S.Zg = Zg0;
+  S.dlast = 0.0;
+  S.dprev = 0.0;
+  S.it = 0;
+  S.m = 0;
+}
+
+// Picard iterations m = S.m, S.m + 1, ... of phase 1. Stopping before
+// iteration m_lim leaves S exactly as an uninterrupted run has it there
+// (IMP_PENDING), so a later call continues the same sequence. Otherwise:
+// IMP_DONE: Un holds the result; IMP_FAILED: Un = Us; IMP_NEED_NEWTON: phase 2
+// must finish the cell from X0 (warm start Z0): the last Picard iterate if
+// Picard was still contracting at its cap, else X* (with Zg0, the recovery Z
+// of the stage's cell state).
+__device__ __forceinline__ int picard_run(const double Us[NV], const ImpIn& in, double h, double kap, double sig,
+                                          const Phys& K, PicardState& S, int m_lim, double Zg0, double Un[NV],
+                                          double X0[4], double& Z0) {
   ImpSys sy;
-  double Zg = Zg0;
-  int it = 0, c2p_it = 0;
-  bool conv = false, have = false, built = false, capped = false;
+  int c2p_it = 0;
+  bool conv = false, built = false, capped = false;
+  bool have = S.m > 0;  // the build at m = 0 succeeded
   const int npic = (K.imp_method == 1) ? 0 : ((K.imp_method == 2) ? K.imp_maxit : K.imp_picard_it);
-  double dlast = 0.0, dprev = 0.0;
-  for (int m = 0; m <= npic; ++m) {
-    built = imp_build(X, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sy, c2p_it);
+  for (int m = S.m; m <= npic; ++m) {
+    if (m >= m_lim) {
+      S.m = m;
+      return IMP_PENDING;
+    }
+    built = imp_build(S.X, in.Ul, in.Et, in.St, h, kap, sig, K, S.Zg, sy, c2p_it);
     if (!built) break;
-    Zg = sy.Z;
+    S.Zg = sy.Z;
     if (m == 0) have = true;
-    if (m > 0 && dlast <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
+    if (m > 0 && S.dlast <= K.imp_tol * vmaxabs4(S.X)) { conv = true; break; }
     if (m == npic) { capped = true; break; }
-    if (m > 1 && K.imp_method == 0 && dlast > dprev) break;
+    if (m > 1 && K.imp_method == 0 && S.dlast > S.dprev) break;
     double A[4][4], bb[4], Xn[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -805,25 +820,24 @@ __device__ __forceinline__ int implicit_picard(const double Us[NV], double h, do
       for (int j = 0; j < 4; ++j) A[i][j] = sy.C[i][j];
     }
     if (!solve4(A, bb, Xn)) break;
-    ++it;
+    ++S.it;
     if (!(Xn[0] > 0.0) || !isfinite(Xn[0]) || !isfinite(Xn[1]) || !isfinite(Xn[2]) || !isfinite(Xn[3])) break;
     double dd[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { dd[i] = Xn[i] - X[i]; X[i] = Xn[i]; }
-    dprev = dlast;
-    dlast = vmaxabs4(dd);
+    for (int i = 0; i < 4; ++i) { dd[i] = Xn[i] - S.X[i]; S.X[i] = Xn[i]; }
+    S.dprev = S.dlast;
+    S.dlast = vmaxabs4(dd);
   }
-  iters = it;
   if (conv) {
-    imp_finish(X, Us, in, Un);
+    imp_finish(S.X, Us, in, Un);
     return IMP_DONE;
   }
   if (have && K.imp_method != 2) {
-    const bool from_picard = built && capped && npic > 1 && dlast < dprev;
+    const bool from_picard = built && capped && npic > 1 && S.dlast < S.dprev;
     if (from_picard) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) X0[i] = X[i];
-      Z0 = Zg;
+      for (int i = 0; i < 4; ++i) X0[i] = S.X[i];
+      Z0 = S.Zg;
     } else {
 #pragma unroll
       for (int i = 0; i < 4; ++i) X0[i] = in.Ul[8 + i];
@@ -834,6 +848,24 @@ __device__ __forceinline__ int implicit_picard(const double Us[NV], double h, do
 #pragma unroll
   for (int q = 0; q < NV; ++q) Un[q] = Us[q];
   return IMP_FAILED;
+}
+
+// Phase 1 in one piece (iters: Picard solves).
+__device__ __forceinline__ int implicit_picard(const double Us[NV], double h, double kap, double sig,
+                                               const Phys& K, double Un[NV], int& iters, bool& floored,
+                                               double X0[4], double& Z0, double Zg0) {
+  ImpIn in;
+  iters = 0;
+  if (!imp_prepare(Us, K, in, floored)) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Un[q] = Us[q];
+    return IMP_FAILED;
+  }
+  PicardState S;
+  picard_start(in, Zg0, S);
+  const int st = picard_run(Us, in, h, kap, sig, K, S, 0x7fffffff, Zg0, Un, X0, Z0);
+  iters = S.it;
+  return st;
 }
 
 // Phase 2: Newton from X0 with warm start Z0. Returns IMP_DONE or
