@@ -26,7 +26,15 @@ using rr::Phys;
 
 namespace {
 
-constexpr int kBlock = 256;
+// One wave per workgroup: waves of the face and cell kernels take very
+// different times (iteration counts vary per cell), and a wave that finishes
+// frees its slot at once instead of waiting for the rest of a larger group.
+#ifndef RRMHD_BLOCK
+#define RRMHD_BLOCK 64
+#endif
+constexpr int kBlock = RRMHD_BLOCK;
+// Workgroup size of the single-block reductions over per-block partials.
+constexpr int kRedBlock = 1024;
 constexpr int kWave = 64;
 // Picard iterations of the implicit solve done in the update pass; a cell
 // still iterating there continues, unchanged, in the work-list pass.
@@ -710,9 +718,9 @@ __global__ void __launch_bounds__(kBlock) k_speed(GridDev G, const double* __res
 
 __device__ __forceinline__ void reduce_max_block(const double* __restrict__ partial, long long n,
                                                  double* __restrict__ out) {
-  __shared__ double red[kBlock / kWave];
+  __shared__ double red[kRedBlock / kWave];
   double s = 0.0;
-  for (long long i = threadIdx.x; i < n; i += kBlock) s = rr::dmax(s, partial[i]);
+  for (long long i = threadIdx.x; i < n; i += kRedBlock) s = rr::dmax(s, partial[i]);
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) s = rr::dmax(s, __shfl_xor(s, o, kWave));
   if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
@@ -720,12 +728,12 @@ __device__ __forceinline__ void reduce_max_block(const double* __restrict__ part
   if (threadIdx.x == 0) {
     double m = red[0];
 #pragma unroll
-    for (int w = 1; w < kBlock / kWave; ++w) m = rr::dmax(m, red[w]);
+    for (int w = 1; w < kRedBlock / kWave; ++w) m = rr::dmax(m, red[w]);
     out[0] = rr::dmin(m, 1.0);
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_reduce_max(const double* __restrict__ partial, long long n,
+__global__ void __launch_bounds__(kRedBlock) k_reduce_max(const double* __restrict__ partial, long long n,
                                                        double* __restrict__ out) {
   reduce_max_block(partial, n, out);
 }
@@ -733,7 +741,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_max(const double* __restrict_
 // Signal speed, then the step's time step dt = (cfl dx_min) / s_max into
 // sd[1] (and dt_out[k] when given). A dt that is not finite and >= 0 (zero or
 // NaN speed) becomes 0 and is counted as a non-finite result.
-__global__ void __launch_bounds__(kBlock) k_reduce_dt(const double* __restrict__ partial, long long n,
+__global__ void __launch_bounds__(kRedBlock) k_reduce_dt(const double* __restrict__ partial, long long n,
                                                       double* __restrict__ sd, double cfl_dx, DevReport* rep,
                                                       double* __restrict__ dt_out, int k) {
   reduce_max_block(partial, n, sd);
@@ -866,7 +874,7 @@ __global__ void __launch_bounds__(kBlock) k_speed_b(const SimDesc* __restrict__ 
   speed_block(blockIdx.x - o[s], D.G, D.U, D.vs, D.K, D.partial, D.rep, D.blkmax);
 }
 
-__global__ void __launch_bounds__(kBlock) k_reduce_max_b(const SimDesc* __restrict__ T, double* __restrict__ smax) {
+__global__ void __launch_bounds__(kRedBlock) k_reduce_max_b(const SimDesc* __restrict__ T, double* __restrict__ smax) {
   const SimDesc& D = T[blockIdx.x];
   reduce_max_block(D.partial, D.npartial, smax + blockIdx.x);
 }
@@ -883,8 +891,8 @@ __global__ void __launch_bounds__(kBlock) k_report_reset(DevReport* rep, unsigne
 }
 
 // Fold the per-block iteration maxima into the report (single block).
-__global__ void __launch_bounds__(kBlock) k_report_fold(DevReport* rep, const unsigned int* blkmax, long long nblk) {
-  __shared__ unsigned int red[2][kBlock / kWave];
+__global__ void __launch_bounds__(kRedBlock) k_report_fold(DevReport* rep, const unsigned int* blkmax, long long nblk) {
+  __shared__ unsigned int red[2][kRedBlock / kWave];
   unsigned int a = 0, b = 0;
   for (long long i = threadIdx.x; i < nblk; i += blockDim.x) {
     a = (blkmax[2 * i] > a) ? blkmax[2 * i] : a;
@@ -895,7 +903,7 @@ __global__ void __launch_bounds__(kBlock) k_report_fold(DevReport* rep, const un
   if ((threadIdx.x & (kWave - 1)) == 0) { red[0][threadIdx.x / kWave] = a; red[1][threadIdx.x / kWave] = b; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < kBlock / kWave; ++w) {
+    for (int w = 1; w < kRedBlock / kWave; ++w) {
       a = (red[0][w] > a) ? red[0][w] : a;
       b = (red[1][w] > b) ? red[1][w] : b;
     }
@@ -1175,7 +1183,7 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   return RRMHD_OK;
 }
 
-// Blocks of the Newton pass per simulation (64 cells per block): about one per
+// Blocks of the Newton pass per simulation (kBlock/4 cells per block): about one per
 // 4 cell blocks.
 long long newton_blocks_for(long long ncell_blocks, unsigned int cap) {
   long long b = ncell_blocks / 4;
@@ -1349,7 +1357,7 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   {
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    c->newton_blocks = (unsigned int)(4 * ncu);  // 64 cells (4 lanes each) per block
+    c->newton_blocks = (unsigned int)(4 * ncu * (256 / kBlock));  // kBlock/4 cells (4 lanes each) per block
   }
   if (hipHostMalloc(&c->host, sizeof(DevReport) + sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete c;
@@ -1498,7 +1506,7 @@ rrmhd_status rrmhd_advance(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double 
       prof_end(c, pe);
       if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
     }
-    k_reduce_dt<<<1, kBlock, 0, c->stream>>>(c->partial, (k == 0) ? L.npartial : nred, c->smax, cfl_dx, c->rep,
+    k_reduce_dt<<<1, kRedBlock, 0, c->stream>>>(c->partial, (k == 0) ? L.npartial : nred, c->smax, cfl_dx, c->rep,
                                              dt_out, k);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
     const rrmhd_status st = step_stages(c, U, g, 0.0, c->smax + 1, op, true, k + 1 < nsteps);
@@ -1515,7 +1523,7 @@ rrmhd_status rrmhd_max_speed(rrmhd_ctx* c, const double* U, const rrmhd_grid* g,
   k_speed<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, U, g->var_stride, c->K, c->partial, c->rep, c->blkmax);
   prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-  k_reduce_max<<<1, kBlock, 0, c->stream>>>(c->partial, L.npartial, c->smax);
+  k_reduce_max<<<1, kRedBlock, 0, c->stream>>>(c->partial, L.npartial, c->smax);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   double* h = (double*)((char*)c->host + sizeof(DevReport));
   if (hipMemcpyAsync(h, c->smax, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return RRMHD_E_DEVICE;
@@ -1527,7 +1535,7 @@ rrmhd_status rrmhd_max_speed(rrmhd_ctx* c, const double* U, const rrmhd_grid* g,
 rrmhd_status rrmhd_report_sync(rrmhd_ctx* c, rrmhd_report* out) {
   if (!c || !out) return RRMHD_E_INVALID;
   DevReport* h = (DevReport*)c->host;
-  k_report_fold<<<1, kBlock, 0, c->stream>>>(c->rep, c->blkmax, c->L.nblkmax);
+  k_report_fold<<<1, kRedBlock, 0, c->stream>>>(c->rep, c->blkmax, c->L.nblkmax);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   if (hipMemcpyAsync(h, c->rep, sizeof(DevReport), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return RRMHD_E_DEVICE;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return RRMHD_E_DEVICE;
@@ -1612,7 +1620,7 @@ rrmhd_status rrmhd_batch_init(rrmhd_batch** out, int max_sims, void* workspace, 
   ok = ok && hipHostMalloc((void**)&b->hsmax, sizeof(double) * max_sims, hipHostMallocDefault) == hipSuccess;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  b->newton_cap = (unsigned int)(4 * ncu);
+  b->newton_cap = (unsigned int)(4 * ncu * (256 / kBlock));
   if (!ok) {
     rrmhd_batch_destroy(b);
     return RRMHD_E_DEVICE;
@@ -1631,7 +1639,7 @@ rrmhd_status rrmhd_max_speed_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* c
   if (st != RRMHD_OK) return st;
   k_speed_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, nsim);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-  k_reduce_max_b<<<(unsigned int)nsim, kBlock, 0, b->stream>>>(b->table, b->smax);
+  k_reduce_max_b<<<(unsigned int)nsim, kRedBlock, 0, b->stream>>>(b->table, b->smax);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   if (hipMemcpyAsync(b->hsmax, b->smax, sizeof(double) * nsim, hipMemcpyDeviceToHost, b->stream) != hipSuccess)
     return RRMHD_E_DEVICE;
