@@ -647,7 +647,6 @@ static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OP
     if (!built) break;
     Zg = sy.Z;
     if (m == 0) have = true;
-    if (m > 0 && dlast <= P.imp_tol * xscale(X)) { conv = true; break; }
     if (m == npic) { capped = true; break; }
     if (m > 1 && P.imp_method == 0 && dlast > dprev) break;
     real A[4][4], bb[4], Xn[4];
@@ -659,6 +658,9 @@ static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OP
     for (int i = 0; i < 4; ++i) { dd[i] = Xn[i] - X[i]; X[i] = Xn[i]; }
     dprev = dlast;
     dlast = vmaxabs4(dd);
+    // converged once the update is below tolerance; the system is not built
+    // again at the accepted iterate
+    if (dlast <= P.imp_tol * xscale(X)) { conv = true; break; }
   }
   if (!conv && have && P.imp_method != 2) {
     // Newton phase (its system is rebuilt at the start point).

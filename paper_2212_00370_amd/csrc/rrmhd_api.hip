@@ -532,14 +532,34 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
       fm[d] = (long long)ci[0] + (long long)fn0 * ((long long)ci[1] + (long long)fn1 * ci[2]);
       fs[d] = (d == 0) ? 1 : ((d == 1) ? (long long)fn0 : (long long)fn0 * fn1);
     }
-    double Ust[NV];
+    // The x and y face loads and the two states are issued together (one
+    // round of memory latency instead of one per variable). In 1D the y
+    // addresses stay inside the x buffer and the values are not used.
+    FT fp[2][NV], fq[2][NV];
+    double u0[NV], us[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-      double div = ((double)F0[q * A.nf[0] + fm[0] + fs[0]] - (double)F0[q * A.nf[0] + fm[0]]) * A.idx[0];
-      if (G.ndim > 1) div = div + ((double)F1[q * A.nf[1] + fm[1] + fs[1]] - (double)F1[q * A.nf[1] + fm[1]]) * A.idx[1];
-      if (G.ndim > 2) div = div + ((double)F2[q * A.nf[2] + fm[2] + fs[2]] - (double)F2[q * A.nf[2] + fm[2]]) * A.idx[2];
-      Ust[q] = (A.a0 * A.U0[q * A.s0 + c] + A.a1 * A.Us[q * A.ss + c]) - cdt * div;
+      fp[0][q] = F0[q * A.nf[0] + fm[0] + fs[0]];
+      fq[0][q] = F0[q * A.nf[0] + fm[0]];
+      fp[1][q] = F1[q * A.nf[1] + fm[1] + fs[1]];
+      fq[1][q] = F1[q * A.nf[1] + fm[1]];
+      u0[q] = A.U0[q * A.s0 + c];
+      us[q] = A.Us[q * A.ss + c];
     }
+    double div[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      div[q] = ((double)fp[0][q] - (double)fq[0][q]) * A.idx[0];
+      if (G.ndim > 1) div[q] = div[q] + ((double)fp[1][q] - (double)fq[1][q]) * A.idx[1];
+    }
+    if (G.ndim > 2) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q)
+        div[q] = div[q] + ((double)F2[q * A.nf[2] + fm[2] + fs[2]] - (double)F2[q * A.nf[2] + fm[2]]) * A.idx[2];
+    }
+    double Ust[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Ust[q] = (A.a0 * u0[q] + A.a1 * us[q]) - cdt * div[q];
     double Un[NV];
     bool floored = false;
     rr::ImpIn in;

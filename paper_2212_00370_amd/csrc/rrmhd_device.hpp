@@ -809,7 +809,6 @@ __device__ __forceinline__ int picard_run(const double Us[NV], const ImpIn& in, 
     if (!built) break;
     S.Zg = sy.Z;
     if (m == 0) have = true;
-    if (m > 0 && S.dlast <= K.imp_tol * vmaxabs4(S.X)) { conv = true; break; }
     if (m == npic) { capped = true; break; }
     if (m > 1 && K.imp_method == 0 && S.dlast > S.dprev) break;
     double A[4][4], bb[4], Xn[4];
@@ -827,6 +826,9 @@ __device__ __forceinline__ int picard_run(const double Us[NV], const ImpIn& in, 
     for (int i = 0; i < 4; ++i) { dd[i] = Xn[i] - S.X[i]; S.X[i] = Xn[i]; }
     S.dprev = S.dlast;
     S.dlast = vmaxabs4(dd);
+    // converged once the update is below tolerance; the system is not built
+    // again at the accepted iterate
+    if (S.dlast <= K.imp_tol * vmaxabs4(S.X)) { conv = true; break; }
   }
   if (conv) {
     imp_finish(S.X, Us, in, Un);
