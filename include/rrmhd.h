@@ -182,16 +182,20 @@ rrmhd_status rrmhd_advance(rrmhd_ctx* ctx, double* U, const rrmhd_grid* g, doubl
 rrmhd_status rrmhd_face_fluxes(rrmhd_ctx* ctx, const double* U, const rrmhd_opacities* opac,
                                double* Fh);
 
-/* Diagnostic kernel timing. While enabled, each launch of the library's
- * kernels is bracketed by HIP events recorded on the context's stream (up to
- * 8192 launches; further launches are not timed). Kernel classes:
+/* Diagnostic kernel timing. Each launch of a selected kernel class is
+ * bracketed by HIP events recorded on the context's stream (up to 8192
+ * launches; further launches are not timed). Kernel classes:
  * RRMHD_K_PRIMS (cell recovery), RRMHD_K_FACES (reconstruction + PVM-int face
  * flux), RRMHD_K_UPDATE (flux divergence + Picard phase of the implicit
  * solve), RRMHD_K_NEWTON (Newton phase for the cells Picard left), and
- * RRMHD_K_SPEED (signal speeds). Enabling clears earlier records. Allocates host-side event
- * objects only. */
+ * RRMHD_K_SPEED (signal speeds). `enable` is a bit mask, bit k selecting
+ * class k (RRMHD_PROFILE_ALL: every class; 0: timing off); other values are
+ * RRMHD_E_INVALID. Each event pair serializes the stream around the launch it
+ * brackets, so select only what is needed. Enabling clears earlier records.
+ * Allocates host-side event objects only. */
 enum { RRMHD_K_PRIMS = 0, RRMHD_K_FACES = 1, RRMHD_K_UPDATE = 2, RRMHD_K_SPEED = 3, RRMHD_K_NEWTON = 4,
        RRMHD_K_COUNT = 5 };
+enum { RRMHD_PROFILE_ALL = (1 << RRMHD_K_COUNT) - 1 };
 rrmhd_status rrmhd_profile_enable(rrmhd_ctx* ctx, int enable);
 
 /* Totals of the timed launches of kernel class k since enabling: summed

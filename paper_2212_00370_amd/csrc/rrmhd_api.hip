@@ -1119,7 +1119,7 @@ struct rrmhd_ctx {
   unsigned int newton_blocks;
   void* host;  // pinned: DevReport + one double
   // Diagnostic timing (rrmhd_profile_*).
-  bool prof;
+  int prof;                     // bit k: launches of kernel class k are timed
   std::vector<hipEvent_t> ev;   // pairs: start, stop
   std::vector<int> ev_kind;
   std::vector<long long> ev_units;
@@ -1132,7 +1132,7 @@ constexpr int kMaxTimed = 8192;
 
 // Record the start event of a timed launch; returns the pair index or -1.
 int prof_begin(rrmhd_ctx* c, int kind, long long units) {
-  if (!c->prof || c->ev_used >= kMaxTimed) return -1;
+  if (!((c->prof >> kind) & 1) || c->ev_used >= kMaxTimed) return -1;
   const int i = c->ev_used++;
   c->ev_kind[i] = kind;
   c->ev_units[i] = units;
@@ -1372,7 +1372,7 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   c->Zc = (double*)(c->ws + L.off_Zc);
   c->stream = (hipStream_t)hip_stream;
   c->host = nullptr;
-  c->prof = false;
+  c->prof = 0;
   c->ev_used = 0;
   {
     int dev = 0, ncu = 256;
@@ -1572,7 +1572,7 @@ rrmhd_status rrmhd_report_sync(rrmhd_ctx* c, rrmhd_report* out) {
 }
 
 rrmhd_status rrmhd_profile_enable(rrmhd_ctx* c, int enable) {
-  if (!c) return RRMHD_E_INVALID;
+  if (!c || enable < 0 || enable >= (1 << RRMHD_K_COUNT)) return RRMHD_E_INVALID;
   if (enable && c->ev.empty()) {
     c->ev.resize(2 * kMaxTimed);
     c->ev_kind.resize(kMaxTimed);
@@ -1580,7 +1580,7 @@ rrmhd_status rrmhd_profile_enable(rrmhd_ctx* c, int enable) {
     for (auto& e : c->ev)
       if (hipEventCreate(&e) != hipSuccess) return RRMHD_E_DEVICE;
   }
-  c->prof = enable != 0;
+  c->prof = enable;
   if (enable) c->ev_used = 0;
   return RRMHD_OK;
 }

@@ -22,6 +22,7 @@ BETA_ALL, BETA_RAD_ONLY, BETA_OFF = 0, 1, 2
 IMP_PICARD_NEWTON, IMP_NEWTON, IMP_PICARD = 0, 1, 2
 FP64, MIXED = 0, 1
 K_PRIMS, K_FACES, K_UPDATE, K_SPEED, K_NEWTON = 0, 1, 2, 3, 4
+PROFILE_ALL = (1 << 5) - 1
 
 
 class rrmhd_grid(C.Structure):
@@ -167,8 +168,11 @@ def rrmhd_face_fluxes(ctx, U, opac: rrmhd_opacities, Fh) -> None:
     _check(_lib.rrmhd_face_fluxes(ctx, _ptr(U), C.byref(opac), _ptr(Fh)), "rrmhd_face_fluxes")
 
 
-def rrmhd_profile_enable(ctx, enable: bool = True) -> None:
-    _check(_lib.rrmhd_profile_enable(ctx, int(bool(enable))), "rrmhd_profile_enable")
+def rrmhd_profile_enable(ctx, enable=True) -> None:
+    """enable: True (every kernel class), False (off) or a bit mask of
+    (1 << K_*) classes."""
+    mask = (PROFILE_ALL if enable else 0) if isinstance(enable, bool) else int(enable)
+    _check(_lib.rrmhd_profile_enable(ctx, mask), "rrmhd_profile_enable")
 
 
 def rrmhd_profile_read(ctx, k: int):

@@ -342,3 +342,24 @@ def test_step_3d_beam_subbox_256(R, oracle, torch_mod):
     Uo, st, rep_o = oracle.step(og, U, dt, P.kappa, P.sigma, op)
     assert np.array_equal(host(Ud), Uo), relerr(host(Ud), Uo)
     s.close()
+
+
+def test_profile_mask(R, oracle, torch_mod):
+    """Kernel timing selects launches by class mask; invalid masks are rejected."""
+    P = I.blast_2d(0, 48)
+    p, op, g, og, s, U, opac = make_case(R, oracle, torch_mod, P)
+    Ud = dev(torch_mod, U)
+    R.rrmhd_profile_enable(s.ctx, 1 << R.K_FACES)
+    s.advance(Ud, P.cfl, 2, opac)
+    ms, n, units = R.rrmhd_profile_read(s.ctx, R.K_FACES)
+    assert n == 4 and ms > 0 and units == 4 * (2 * 49 * 48)
+    assert R.rrmhd_profile_read(s.ctx, R.K_UPDATE)[1] == 0
+    R.rrmhd_profile_enable(s.ctx, True)
+    s.advance(Ud, P.cfl, 1, opac)
+    assert R.rrmhd_profile_read(s.ctx, R.K_UPDATE)[1] == 2 and R.rrmhd_profile_read(s.ctx, R.K_FACES)[1] == 2
+    for bad in (-1, 1 << 5):
+        with pytest.raises(R.RRMHDError):
+            R.rrmhd_profile_enable(s.ctx, bad)
+    R.rrmhd_profile_enable(s.ctx, False)
+    s.report()
+    s.close()
