@@ -267,8 +267,10 @@ def main():
     U = U0.clone()
     torch.cuda.synchronize()
     # Inside the timed region only the face kernel (the roofline's kernel) is
-    # bracketed by HIP events: each event pair serializes the stream.
+    # bracketed by HIP events, every 7th launch (odd, so both stages are
+    # sampled; each event pair serializes the stream around its launch).
     R.rrmhd_profile_enable(solver.ctx, 1 << R.K_FACES)
+    R.rrmhd_profile_stride(solver.ctx, 7)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run(U, args.steps)
@@ -278,6 +280,7 @@ def main():
     rep = solver.report()
     prof = {"faces": R.rrmhd_profile_read(solver.ctx, R.K_FACES)}
     R.rrmhd_profile_enable(solver.ctx, False)
+    R.rrmhd_profile_stride(solver.ctx, 1)
     # Per-kernel breakdown from a separate short run with every launch timed
     # ("prims": stage recoveries, the first stage's fused with the speeds).
     Ub = U0.clone()

@@ -198,6 +198,10 @@ enum { RRMHD_K_PRIMS = 0, RRMHD_K_FACES = 1, RRMHD_K_UPDATE = 2, RRMHD_K_SPEED =
 enum { RRMHD_PROFILE_ALL = (1 << RRMHD_K_COUNT) - 1 };
 rrmhd_status rrmhd_profile_enable(rrmhd_ctx* ctx, int enable);
 
+/* Time only every stride-th launch of each selected class (counted from the
+ * last rrmhd_profile_enable; default 1). stride < 1: RRMHD_E_INVALID. */
+rrmhd_status rrmhd_profile_stride(rrmhd_ctx* ctx, int stride);
+
 /* Totals of the timed launches of kernel class k since enabling: summed
  * event time in ms, number of launches and work units (cells or faces)
  * those launches processed. Synchronizes on the last recorded event. */

@@ -1120,6 +1120,8 @@ struct rrmhd_ctx {
   void* host;  // pinned: DevReport + one double
   // Diagnostic timing (rrmhd_profile_*).
   int prof;                     // bit k: launches of kernel class k are timed
+  int prof_stride;              // ... every prof_stride-th launch of the class
+  long long prof_seen[RRMHD_K_COUNT];
   std::vector<hipEvent_t> ev;   // pairs: start, stop
   std::vector<int> ev_kind;
   std::vector<long long> ev_units;
@@ -1133,6 +1135,7 @@ constexpr int kMaxTimed = 8192;
 // Record the start event of a timed launch; returns the pair index or -1.
 int prof_begin(rrmhd_ctx* c, int kind, long long units) {
   if (!((c->prof >> kind) & 1) || c->ev_used >= kMaxTimed) return -1;
+  if ((c->prof_seen[kind]++) % c->prof_stride != 0) return -1;
   const int i = c->ev_used++;
   c->ev_kind[i] = kind;
   c->ev_units[i] = units;
@@ -1373,6 +1376,8 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   c->stream = (hipStream_t)hip_stream;
   c->host = nullptr;
   c->prof = 0;
+  c->prof_stride = 1;
+  for (int k = 0; k < RRMHD_K_COUNT; ++k) c->prof_seen[k] = 0;
   c->ev_used = 0;
   {
     int dev = 0, ncu = 256;
@@ -1581,7 +1586,16 @@ rrmhd_status rrmhd_profile_enable(rrmhd_ctx* c, int enable) {
       if (hipEventCreate(&e) != hipSuccess) return RRMHD_E_DEVICE;
   }
   c->prof = enable;
-  if (enable) c->ev_used = 0;
+  if (enable) {
+    c->ev_used = 0;
+    for (int k = 0; k < RRMHD_K_COUNT; ++k) c->prof_seen[k] = 0;
+  }
+  return RRMHD_OK;
+}
+
+rrmhd_status rrmhd_profile_stride(rrmhd_ctx* c, int stride) {
+  if (!c || stride < 1) return RRMHD_E_INVALID;
+  c->prof_stride = stride;
   return RRMHD_OK;
 }
 

@@ -73,6 +73,7 @@ SIGNATURES = {
     "rrmhd_advance": ([_vp, _vp, _vp, _d, C.c_int, _vp, _vp], C.c_int),
     "rrmhd_face_fluxes": ([_vp, _vp, _vp, _vp], C.c_int),
     "rrmhd_profile_enable": ([_vp, C.c_int], C.c_int),
+    "rrmhd_profile_stride": ([_vp, C.c_int], C.c_int),
     "rrmhd_profile_read": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
     "rrmhd_report_sync": ([_vp, _vp], C.c_int),
     "rrmhd_batch_workspace_bytes": ([C.c_int], C.c_size_t),
@@ -173,6 +174,10 @@ def rrmhd_profile_enable(ctx, enable=True) -> None:
     (1 << K_*) classes."""
     mask = (PROFILE_ALL if enable else 0) if isinstance(enable, bool) else int(enable)
     _check(_lib.rrmhd_profile_enable(ctx, mask), "rrmhd_profile_enable")
+
+
+def rrmhd_profile_stride(ctx, stride: int) -> None:
+    _check(_lib.rrmhd_profile_stride(ctx, int(stride)), "rrmhd_profile_stride")
 
 
 def rrmhd_profile_read(ctx, k: int):

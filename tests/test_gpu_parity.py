@@ -357,9 +357,16 @@ def test_profile_mask(R, oracle, torch_mod):
     R.rrmhd_profile_enable(s.ctx, True)
     s.advance(Ud, P.cfl, 1, opac)
     assert R.rrmhd_profile_read(s.ctx, R.K_UPDATE)[1] == 2 and R.rrmhd_profile_read(s.ctx, R.K_FACES)[1] == 2
+    R.rrmhd_profile_enable(s.ctx, 1 << R.K_FACES)
+    R.rrmhd_profile_stride(s.ctx, 3)
+    s.advance(Ud, P.cfl, 4, opac)          # 8 face launches: the 1st, 4th and 7th are timed
+    assert R.rrmhd_profile_read(s.ctx, R.K_FACES)[1] == 3
+    R.rrmhd_profile_stride(s.ctx, 1)
     for bad in (-1, 1 << 5):
         with pytest.raises(R.RRMHDError):
             R.rrmhd_profile_enable(s.ctx, bad)
+    with pytest.raises(R.RRMHDError):
+        R.rrmhd_profile_stride(s.ctx, 0)
     R.rrmhd_profile_enable(s.ctx, False)
     s.report()
     s.close()
