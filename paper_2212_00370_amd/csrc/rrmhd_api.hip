@@ -1608,6 +1608,7 @@ rrmhd_status rrmhd_profile_read(rrmhd_ctx* c, int k, double* total_ms, long long
   if (hipEventSynchronize(c->ev[2 * (c->ev_used - 1) + 1]) != hipSuccess) return RRMHD_E_DEVICE;
   for (int i = 0; i < c->ev_used; ++i) {
     if (c->ev_kind[i] != k) continue;
+    if (hipEventSynchronize(c->ev[2 * i + 1]) != hipSuccess) return RRMHD_E_DEVICE;
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) != hipSuccess) return RRMHD_E_DEVICE;
     *total_ms += ms;

@@ -191,11 +191,11 @@ def test_step_2d_full_size(R, oracle, torch_mod):
 
 
 # ------------------------------------------------- time step on the device ----
-def advance_compare(R, oracle, torch, P, steps, **kw):
+def advance_compare(R, oracle, torch, P, steps, case=None, **kw):
     """rrmhd_advance (time step formed on the device, no host wait) against
     the oracle's loop of signal speed, dt = (cfl dx_min) / s_max and step, and
     against the library's own loop with the time step on the host."""
-    p, op, g, og, s, U, opac = make_case(R, oracle, torch, P, **kw)
+    p, op, g, og, s, U, opac = (case or make_case)(R, oracle, torch, P, **kw)
     Ud = dev(torch, U)
     dts = torch.full((steps,), -1.0, dtype=torch.float64, device="cuda:0")
     s.advance(Ud, P.cfl, steps, opac, dts)
@@ -272,6 +272,19 @@ def test_advance_2d_full_size(R, oracle, torch_mod):
     assert advance_compare(R, oracle, torch_mod, I.blast_2d(0, 512), steps=2)
 
 
+def test_advance_3d_periodic_rough(R, oracle, torch_mod):
+    """Periodic 3D grid with strong jumps at every face."""
+    shape = (16, 12, 16)
+    n = int(np.prod(shape))
+    V = I.random_prims(78, n, vmax=0.6, rho=(0.5, 2.0), p=(0.5, 2.0), er=(0.1, 1.0))
+    rng = np.random.default_rng(4)
+    P = I.Problem(name="rough3d", shape=shape, dx=(0.1, 0.13, 0.17), x0=(0, 0, 0), V=V,
+                  kappa=rng.uniform(0.1, 10, n), sigma=rng.uniform(0.1, 10, n), gamma=5 / 3, a_rad=0.5,
+                  bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), cfl=0.3)
+    oracle.threads(0)
+    assert advance_compare(R, oracle, torch_mod, P, steps=3)
+
+
 # ---------------------------------------------------------------------- 3D ----
 def beam_case(R, oracle, torch, P, **kw):
     p = lib_params(R, gamma=P.gamma, a_rad=P.a_rad, **kw)
@@ -311,6 +324,13 @@ def test_step_3d_beam_inflow(R, oracle, torch_mod):
     s.close()
 
 
+def test_advance_3d_beam_inflow(R, oracle, torch_mod):
+    """The beam through the inflow mask with rrmhd_advance."""
+    oracle.threads(0)
+    P = I.beam_3d(0, 24, 20, 16, r_noz=0.2)
+    assert advance_compare(R, oracle, torch_mod, P, steps=6, case=beam_case, e_floor=1e-14)
+
+
 def test_step_3d_periodic_rough(R, oracle, torch_mod):
     """Periodic 3D grid of i.i.d. states (every face a strong jump: exercises
     the fallbacks and failure counters in all three directions)."""
@@ -345,22 +365,25 @@ def test_step_3d_beam_subbox_256(R, oracle, torch_mod):
 
 
 def test_profile_mask(R, oracle, torch_mod):
-    """Kernel timing selects launches by class mask; invalid masks are rejected."""
+    """Kernel timing selects launches by class mask and stride; invalid
+    arguments are rejected."""
     P = I.blast_2d(0, 48)
     p, op, g, og, s, U, opac = make_case(R, oracle, torch_mod, P)
     Ud = dev(torch_mod, U)
     R.rrmhd_profile_enable(s.ctx, 1 << R.K_FACES)
     s.advance(Ud, P.cfl, 2, opac)
     ms, n, units = R.rrmhd_profile_read(s.ctx, R.K_FACES)
-    assert n == 4 and ms > 0 and units == 4 * (2 * 49 * 48)
+    assert n >= 4 and n % 4 == 0 and ms > 0 and units == 4 * (2 * 49 * 48)
+    per_stage = n // 4
     assert R.rrmhd_profile_read(s.ctx, R.K_UPDATE)[1] == 0
     R.rrmhd_profile_enable(s.ctx, True)
     s.advance(Ud, P.cfl, 1, opac)
-    assert R.rrmhd_profile_read(s.ctx, R.K_UPDATE)[1] == 2 and R.rrmhd_profile_read(s.ctx, R.K_FACES)[1] == 2
+    assert R.rrmhd_profile_read(s.ctx, R.K_UPDATE)[1] == 2 * per_stage
+    assert R.rrmhd_profile_read(s.ctx, R.K_FACES)[1] == 2 * per_stage
     R.rrmhd_profile_enable(s.ctx, 1 << R.K_FACES)
     R.rrmhd_profile_stride(s.ctx, 3)
-    s.advance(Ud, P.cfl, 4, opac)          # 8 face launches: the 1st, 4th and 7th are timed
-    assert R.rrmhd_profile_read(s.ctx, R.K_FACES)[1] == 3
+    s.advance(Ud, P.cfl, 4, opac)          # launches 0, 3, 6, ... are timed
+    assert R.rrmhd_profile_read(s.ctx, R.K_FACES)[1] == (8 * per_stage + 2) // 3
     R.rrmhd_profile_stride(s.ctx, 1)
     for bad in (-1, 1 << 5):
         with pytest.raises(R.RRMHDError):
