@@ -225,8 +225,10 @@ struct C2PEval {
 static C2PEval c2p_eval(real Z, const C2PIn& in, const Consts& K, bool want_df) {
   C2PEval e;
   const real Zb = Z + in.B2;
-  const real iZ = 1.0 / Z;
-  e.iZb = 1.0 / Zb;
+  // 1/Z and 1/(Z + B^2) from one reciprocal of the product
+  const real rZZb = 1.0 / (Z * Zb);
+  const real iZ = Zb * rZZb;
+  e.iZb = Z * rZZb;
   e.vB = in.SB * iZ;
   const real vB2 = e.vB * e.vB;
   const real v2 = (in.S2 + vB2 * (Z + Zb)) * (e.iZb * e.iZb);

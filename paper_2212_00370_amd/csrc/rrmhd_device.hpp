@@ -173,8 +173,10 @@ template <bool WANT_DF>
 __device__ __forceinline__ C2PEval c2p_eval(double Z, const C2PIn& in, const Phys& K) {
   C2PEval e;
   const double Zb = Z + in.B2;
-  const double iZ = 1.0 / Z;
-  e.iZb = 1.0 / Zb;
+  // 1/Z and 1/(Z + B^2) from one reciprocal of the product
+  const double rZZb = 1.0 / (Z * Zb);
+  const double iZ = Zb * rZZb;
+  e.iZb = Z * rZZb;
   e.vB = in.SB * iZ;
   const double vB2 = e.vB * e.vB;
   const double v2 = (in.S2 + vB2 * (Z + Zb)) * (e.iZb * e.iZb);
