@@ -171,7 +171,8 @@ def test_step_1d_riemann(R, oracle, torch_mod, seed):
 
 
 @pytest.mark.parametrize("kw", [dict(beta_mode=0), dict(beta_mode=2), dict(pvm_k=0), dict(pvm_k=1),
-                                dict(pvm_k=4), dict(recon=0), dict(rk_order=3), dict(imp_method=1)])
+                                dict(pvm_k=4), dict(recon=0), dict(rk_order=3), dict(imp_method=1),
+                                dict(imp_picard_it=12), dict(imp_method=2)])
 def test_step_1d_variants(R, oracle, torch_mod, kw):
     worst, bit = one_step_compare(R, oracle, torch_mod, I.riemann_1d(4), steps=2, **kw)
     assert bit
@@ -236,6 +237,12 @@ def test_advance_1d_rk3(R, oracle, torch_mod):
 
 def test_advance_2d_small(R, oracle, torch_mod):
     assert advance_compare(R, oracle, torch_mod, I.blast_2d(0, 72, 50), steps=4)
+
+
+def test_advance_2d_long_picard(R, oracle, torch_mod):
+    """Picard cap above the update pass's share of iterations: cells still
+    iterating there continue in the work-list pass, exactly."""
+    assert advance_compare(R, oracle, torch_mod, I.blast_2d(0, 72, 50), steps=3, imp_picard_it=12)
 
 
 def test_advance_2d_mixed_matches_host_loop(R, oracle, torch_mod):
