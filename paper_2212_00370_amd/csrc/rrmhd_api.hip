@@ -836,11 +836,12 @@ __device__ __forceinline__ StageArgs stage_args(const SimDesc& D, int stage, int
   A.cc = c;
   A.Zc = D.Zc;
   A.m_split = 0x7fffffff;
-  A.nextp = 0;
+  // the next stage's primitives where each cell finishes (not after the last)
+  A.nextp = last ? 0 : 1;
   A.speed = 0;
-  A.Vp = nullptr;
-  A.taup = nullptr;
-  A.np = 0;
+  A.Vp = D.Vp;
+  A.taup = D.taup;
+  A.np = D.FA.np;
   A.partial = nullptr;
   A.npart = 0;
   return A;
@@ -862,6 +863,8 @@ k_faces_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, int 
   const long long* o = off + OFF_FACES * (nsim + 1);
   const int s = find_sim(o, nsim, blockIdx.x);
   const SimDesc& D = T[s];
+  // the work-list counter of this simulation's update pass that follows
+  if (blockIdx.x == o[s] && threadIdx.x == 0) *D.wcount = 0;
   if (D.mixed) faces_block<true>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
   else faces_block<false>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
 }
@@ -1706,8 +1709,11 @@ rrmhd_status rrmhd_step_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, d
   }
   for (int s = 0; s < ns; ++s) {
     const int last = (s == ns - 1) ? 1 : 0;
-    k_prims_b<<<(unsigned int)tot[OFF_PRIMS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s);
-    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    // later stages get their primitives from the passes that finish each cell
+    if (s == 0) {
+      k_prims_b<<<(unsigned int)tot[OFF_PRIMS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s);
+      if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    }
     k_faces_b<<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off, nsim);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
     k_update_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s, last, co[s][0],
