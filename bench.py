@@ -215,7 +215,7 @@ def main():
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate / measured capacity")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for {args.gpus}); "
               "multi-GPU sharding is designed but not built", file=sys.stderr)
         sys.exit(2)
 
