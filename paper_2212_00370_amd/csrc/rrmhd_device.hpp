@@ -180,15 +180,16 @@ __device__ __forceinline__ C2PEval c2p_eval(double Z, const C2PIn& in, const Phy
   e.vB = in.SB * iZ;
   const double vB2 = e.vB * e.vB;
   const double v2 = (in.S2 + vB2 * (Z + Zb)) * (e.iZb * e.iZb);
-  e.ok = false;
-  e.l2 = 0.0; e.iW = 0.0; e.rho = 0.0; e.p = 0.0; e.f = 0.0; e.df = 0.0;
-  if (!(v2 < 1.0)) return e;
+  // Evaluated without early exits (branch-free in a wave); where the state is
+  // inadmissible (v^2 >= 1 or p <= 0) ok is false and the other fields are
+  // not used.
   e.l2 = 1.0 - v2;
   e.iW = sqrt(e.l2);
   e.rho = in.D * e.iW;
   e.p = K.gm1g * (Z * e.l2 - e.rho);
-  if (!(e.p > 0.0)) return e;
-  e.ok = true;
+  e.ok = (v2 < 1.0) && (e.p > 0.0);
+  e.f = 0.0;
+  e.df = 0.0;
   if (!WANT_DF) return e;
   e.f = (((Z + in.B2) - e.p) - 0.5 * (in.B2 * e.l2)) - (0.5 * vB2 + in.Et);
   const double dv2 = -2.0 * (in.S2 + (vB2 * (3.0 * (Z * Zb) + in.B2 * in.B2)) * iZ) *
