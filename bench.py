@@ -32,6 +32,23 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "RRMHD+M1 zone-updates/s FP64 vs mixed; p50/p99 serve latency"
 
 
+KERNEL_SOURCES = ("paper_2212_00370_amd/csrc/rrmhd_api.hip", "paper_2212_00370_amd/csrc/rrmhd_device.hpp",
+                  "include/rrmhd.h")
+
+
+def kernel_sources_digest() -> str:
+    """SHA-256 over the sources the kernels are built from. HBM counters
+    stored under profiles/ carry the digest of the sources they were taken
+    with; a mismatch means the kernels changed since and the stored traffic
+    no longer describes them."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def load_json(path):
     try:
         with open(path) as f:
@@ -311,7 +328,7 @@ def main():
         achieved = flops_per_launch / mean_s / 1e12
         traffic = None
         tr = load_json(os.path.join(ROOT, "profiles", f"traffic_k_faces_blast2d_{args.n}.json"))
-        if tr:
+        if tr and tr.get("sources_sha256") == kernel_sources_digest():
             traffic = tr.get("hbm_bytes_per_launch")
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
