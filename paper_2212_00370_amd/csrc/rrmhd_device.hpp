@@ -85,6 +85,16 @@ __device__ __forceinline__ void p2c(const R V[NV], const AuxT<R>& a, R U[NV]) {
   for (int q = 5; q < NV; ++q) U[q] = V[q];
 }
 
+// Rows 0..7 of eq. eqU.
+__device__ __forceinline__ void p2c8(const double V[8], const Aux& a, double U[8]) {
+  U[0] = a.D;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) U[1 + j] = a.wtot * V[1 + j] - a.b0 * a.b[j];
+  U[4] = ((a.wtot - a.ps) - a.b0 * a.b0) - a.D;
+#pragma unroll
+  for (int q = 5; q < 8; ++q) U[q] = V[q];
+}
+
 // Row d of the M1 radiation pressure P = D_r E_r (eq. xi); n n := 0 when F = 0.
 // The FP32 instantiation works with the reduced flux f = F/E_r (|f| <~ 1):
 // products of raw F_r components underflow FP32 where E_r ~ 1e-11.
@@ -132,6 +142,30 @@ __device__ __forceinline__ void m1_row(R E, const R F[3], R P[3]) {
       for (int j = 0; j < 3; ++j) P[j] = (j == d) ? E * ca : R(0);
     }
   }
+}
+
+// Rows 0..7 of eq. eqF (fluid and magnetic field) in direction d.
+template <int d, typename R>
+__device__ __forceinline__ void flux_mhd(const R V[8], const AuxT<R>& a, R F[8]) {
+  const R vd = V[1 + d];
+  F[0] = a.D * vd;
+  const R wv = a.wtot * vd;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    if (j == d) F[1 + j] = (wv * V[1 + j] + a.ps) - a.b[d] * a.b[j];
+    else        F[1 + j] = wv * V[1 + j] - a.b[d] * a.b[j];
+  }
+  F[4] = (wv - a.b0 * a.b[d]) - a.D * vd;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) F[5 + j] = vd * V[5 + j] - V[5 + d] * V[1 + j];
+}
+
+// Rows 8..11 of eq. eqF from Vr = (E_r, F_r): they involve the radiation
+// variables only.
+template <int d, typename R>
+__device__ __forceinline__ void flux_rad(const R Vr[4], R F[4]) {
+  F[0] = Vr[1 + d];
+  m1_row<d, R>(Vr[0], &Vr[1], &F[1]);
 }
 
 // eq. eqF in direction d.
@@ -202,7 +236,10 @@ __device__ __forceinline__ C2PEval c2p_eval(double Z, const C2PIn& in, const Phy
 
 // Returns 0 on success. Zguess > 0 warm-starts; otherwise the rest-frame
 // estimate gamma (E - B^2/2) - (gamma - 1) D is used.
-__device__ __forceinline__ int c2p(const double U[NV], const Phys& K, double Zguess, double V[NV],
+// NU = NV: full state; NU = 8: fluid and magnetic field only (the radiation
+// variables are not involved in the recovery).
+template <int NU = NV>
+__device__ __forceinline__ int c2p(const double U[NU], const Phys& K, double Zguess, double V[NU],
                                    double& Zout, int& nit) {
   C2PIn in;
   in.D = U[0];
@@ -213,7 +250,7 @@ __device__ __forceinline__ int c2p(const double U[NV], const Phys& K, double Zgu
   in.S2 = (in.S[0] * in.S[0] + in.S[1] * in.S[1]) + in.S[2] * in.S[2];
   in.SB = (in.S[0] * in.B[0] + in.S[1] * in.B[1]) + in.S[2] * in.B[2];
 #pragma unroll
-  for (int q = 5; q < NV; ++q) V[q] = U[q];
+  for (int q = 5; q < NU; ++q) V[q] = U[q];
   nit = 0;
   if (!(in.D > 0.0) || !isfinite(in.Et) || !isfinite(in.S2) || !isfinite(in.B2)) return 1;
   double lo = in.D;
@@ -228,22 +265,22 @@ __device__ __forceinline__ int c2p(const double U[NV], const Phys& K, double Zgu
   }
   bool conv = false;
   int it = 0;
+  // One straight-line body per iteration (selects instead of branches):
+  // an inadmissible Z (ok false) raises lo and bisects; f = 0 stops at Z.
   while (it < K.c2p_maxit) {
     ++it;
     const C2PEval e = c2p_eval<true>(Z, in, K);
-    double Zn;
-    if (!e.ok) {
-      lo = Z;
-      Zn = 0.5 * (lo + hi);
-    } else {
-      if (e.f == 0.0) { conv = true; break; }
-      if (e.f > 0.0) hi = Z; else lo = Z;
-      Zn = Z - e.f / e.df;
-      if (!(e.df > 0.0) || !(Zn > lo && Zn < hi)) Zn = 0.5 * (lo + hi);
-    }
+    const bool up = e.ok && (e.f > 0.0);
+    hi = up ? Z : hi;
+    lo = up ? lo : Z;
+    const double Zt = Z - e.f / e.df;
+    const bool take = e.ok && (e.df > 0.0) && (Zt > lo && Zt < hi);
+    const double Zn = take ? Zt : 0.5 * (lo + hi);
+    const bool hit = e.ok && (e.f == 0.0);
     const double dZ = dabs(Zn - Z);
-    Z = Zn;
-    if (dZ <= K.c2p_tol * Z) { conv = true; break; }
+    conv = hit || (dZ <= K.c2p_tol * Zn);
+    Z = hit ? Z : Zn;
+    if (conv) break;
   }
   nit = it;
   if (!conv) return 2;
@@ -267,9 +304,10 @@ __device__ __forceinline__ void c2p_fallback(const double U[NV], const Phys& K, 
 
 // Recovery of an intermediate PVM state: reuse V_m when the fluid part of U
 // equals U_m's bit for bit (recovery depends on it only), else warm-start.
-__device__ __forceinline__ bool recover_near(const double U[NV], const double Um[NV],
-                                             const double Vm[NV], double Zm, const Phys& K,
-                                             double V[NV], int& nit) {
+template <int NU = NV>
+__device__ __forceinline__ bool recover_near(const double U[NU], const double Um[NU],
+                                             const double Vm[NU], double Zm, const Phys& K,
+                                             double V[NU], int& nit) {
   bool same = true;
 #pragma unroll
   for (int q = 0; q < 8; ++q) same = same && (U[q] == Um[q]);
@@ -277,12 +315,12 @@ __device__ __forceinline__ bool recover_near(const double U[NV], const double Um
 #pragma unroll
     for (int q = 0; q < 5; ++q) V[q] = Vm[q];
 #pragma unroll
-    for (int q = 5; q < NV; ++q) V[q] = U[q];
+    for (int q = 5; q < NU; ++q) V[q] = U[q];
     nit = 0;
     return true;
   }
   double Z = 0.0;
-  return c2p(U, K, Zm, V, Z, nit) == 0;
+  return c2p<NU>(U, K, Zm, V, Z, nit) == 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -338,99 +376,151 @@ __device__ __forceinline__ void limit_rad_flux(R V[NV]) {
 // Y(w) = [F(U_m + F(U_m + eps w) - F(U_m)) - F(U_m)] / eps ~ A(U_m)^2 w;
 // Horner over x^2 gives U_M ~ p_k(A) U_0; F^ = (F_L + F_R)/2 - beta U_M / 2.
 // A failed intermediate recovery drops the face to p_0 = 1 (Rusanov).
+//
+// The flux rows of the radiation variables (8..11) depend on those variables
+// only, and rows 0..7 do not depend on them, so A(U) is block diagonal and
+// every step of the chain acts on the two blocks separately. The radiation
+// block (no recovery) runs first; the fluid/magnetic block follows with
+// 8-wide states. Each component sees exactly the operations of the
+// 12-wide chain.
 template <int d>
 __device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV], double tauL,
                                          double tauR, const Phys& K, double Fh[NV],
                                          int& fallback, int& c2p_its) {
-  // Only (F_L + F_R)/2, U_0 and U_m are needed past this point.
-  double Fa[NV], U0[NV], Um[NV];
+  const double beta = 1.0 / dmax(dmax(tauL, tauR), 1.0);
+  // Radiation rows with the chain's dissipation (Rok) and with p_0 = 1 (Rfb).
+  double Rok[4], Rfb[4];
   {
-    double UL[NV], UR[NV], FL[NV], FR[NV];
+    double Fa[4], U0[4], Um[4], w[4];
+    {
+      double FL[4], FR[4];
+      flux_rad<d, double>(&VL[8], FL);
+      flux_rad<d, double>(&VR[8], FR);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        U0[q] = VR[8 + q] - VL[8 + q];
+        Um[q] = 0.5 * (VL[8 + q] + VR[8 + q]);
+        Fa[q] = 0.5 * (FL[q] + FR[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = U0[q];
+    if (K.M > 0) {
+      double Fm[4];
+      flux_rad<d, double>(Um, Fm);
+      for (int l = 0; l < K.M; ++l) {
+        double Ue[4], Fe[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ue[q] = Um[q] + K.eps * w[q];
+        flux_rad<d, double>(Ue, Fe);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ue[q] = Um[q] + (Fe[q] - Fm[q]);
+        flux_rad<d, double>(Ue, Fe);
+        const double cnext = K.coef[K.M - 1 - l];
+        if (l == 0) {
+          const double ctop = K.coef[K.M];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w[q] = ctop * ((Fe[q] - Fm[q]) * K.ieps) + cnext * U0[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w[q] = (Fe[q] - Fm[q]) * K.ieps + cnext * U0[q];
+        }
+      }
+    }
+    const double bq = (K.beta_mode == 2) ? 1.0 : beta;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Rok[q] = Fa[q] - 0.5 * (bq * w[q]);
+      Rfb[q] = Fa[q] - 0.5 * (bq * U0[q]);
+    }
+  }
+  // Fluid and magnetic rows. Only (F_L + F_R)/2, U_0 and U_m are needed past
+  // the reconstruction.
+  double Fa[8], U0[8], Um[8];
+  {
+    double UL[8], UR[8], FL[8], FR[8];
     {
       Aux aL;
       prim_aux(VL, K, aL);
-      p2c(VL, aL, UL);
-      flux<d>(VL, aL, FL);
+      p2c8(VL, aL, UL);
+      flux_mhd<d, double>(VL, aL, FL);
     }
     {
       Aux aR;
       prim_aux(VR, K, aR);
-      p2c(VR, aR, UR);
-      flux<d>(VR, aR, FR);
+      p2c8(VR, aR, UR);
+      flux_mhd<d, double>(VR, aR, FR);
     }
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
+    for (int q = 0; q < 8; ++q) {
       U0[q] = UR[q] - UL[q];
       Um[q] = 0.5 * (UL[q] + UR[q]);
       Fa[q] = 0.5 * (FL[q] + FR[q]);
     }
   }
-  const double beta = 1.0 / dmax(dmax(tauL, tauR), 1.0);
   fallback = 0;
   c2p_its = 0;
-  double w[NV];
+  double w[8];
   bool ok = true;
-  if (K.M == 0) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) w[q] = U0[q];
-  } else {
-    double Vm[NV], Zm = 0.0;
+  for (int q = 0; q < 8; ++q) w[q] = U0[q];
+  if (K.M > 0) {
+    double Vm[8], Zm = 0.0;
     int it = 0;
-    if (c2p(Um, K, 0.0, Vm, Zm, it) != 0) ok = false;
+    if (c2p<8>(Um, K, 0.0, Vm, Zm, it) != 0) ok = false;
     c2p_its += it;
-    double Fm[NV];
+    double Fm[8];
     if (ok) {
       Aux am;
       prim_aux(Vm, K, am);
-      flux<d>(Vm, am, Fm);
+      flux_mhd<d, double>(Vm, am, Fm);
     } else {
 #pragma unroll
-      for (int q = 0; q < NV; ++q) Fm[q] = 0.0;
+      for (int q = 0; q < 8; ++q) Fm[q] = 0.0;
     }
-#pragma unroll
-    for (int q = 0; q < NV; ++q) w[q] = U0[q];
     for (int l = 0; l < K.M && ok; ++l) {
-      double Ue[NV], Ve[NV], Fe[NV];
+      double Ue[8], Ve[8], Fe[8];
 #pragma unroll
-      for (int q = 0; q < NV; ++q) Ue[q] = Um[q] + K.eps * w[q];
-      if (!recover_near(Ue, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
+      for (int q = 0; q < 8; ++q) Ue[q] = Um[q] + K.eps * w[q];
+      if (!recover_near<8>(Ue, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
       c2p_its += it;
       {
         Aux ae;
         prim_aux(Ve, K, ae);
-        flux<d>(Ve, ae, Fe);
+        flux_mhd<d, double>(Ve, ae, Fe);
       }
-      double Ut[NV];
 #pragma unroll
-      for (int q = 0; q < NV; ++q) Ut[q] = Um[q] + (Fe[q] - Fm[q]);
-      if (!recover_near(Ut, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
+      for (int q = 0; q < 8; ++q) Ue[q] = Um[q] + (Fe[q] - Fm[q]);
+      if (!recover_near<8>(Ue, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
       c2p_its += it;
       {
         Aux at;
         prim_aux(Ve, K, at);
-        flux<d>(Ve, at, Fe);
+        flux_mhd<d, double>(Ve, at, Fe);
       }
       const double cnext = K.coef[K.M - 1 - l];
       if (l == 0) {
         const double ctop = K.coef[K.M];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) w[q] = ctop * ((Fe[q] - Fm[q]) * K.ieps) + cnext * U0[q];
+        for (int q = 0; q < 8; ++q) w[q] = ctop * ((Fe[q] - Fm[q]) * K.ieps) + cnext * U0[q];
       } else {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) w[q] = (Fe[q] - Fm[q]) * K.ieps + cnext * U0[q];
+        for (int q = 0; q < 8; ++q) w[q] = (Fe[q] - Fm[q]) * K.ieps + cnext * U0[q];
       }
     }
     if (!ok) {
       fallback = 1;
 #pragma unroll
-      for (int q = 0; q < NV; ++q) w[q] = U0[q];
+      for (int q = 0; q < 8; ++q) w[q] = U0[q];
     }
   }
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    const double bq = (K.beta_mode == 2 || (K.beta_mode == 1 && q < 8)) ? 1.0 : beta;
+  for (int q = 0; q < 8; ++q) {
+    const double bq = (K.beta_mode == 1 || K.beta_mode == 2) ? 1.0 : beta;
     Fh[q] = Fa[q] - 0.5 * (bq * w[q]);
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Fh[8 + q] = ok ? Rok[q] : Rfb[q];
 }
 
 // ---------------------------------------------------------------------------

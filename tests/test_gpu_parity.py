@@ -136,7 +136,7 @@ def test_face_fluxes_2d_ragged(R, oracle, torch_mod):
 
 
 # ---------------------------------------------------------------- one step ----
-def one_step_compare(R, oracle, torch, P, dt=None, steps=1, **kw):
+def one_step_compare(R, oracle, torch, P, dt=None, steps=1, reports=None, **kw):
     p, op, g, og, s, U, opac = make_case(R, oracle, torch, P, **kw)
     Ud = dev(torch, U)
     worst = 0.0
@@ -144,18 +144,21 @@ def one_step_compare(R, oracle, torch, P, dt=None, steps=1, **kw):
     for k in range(steps):
         Uin = host(Ud)
         sm_g = s.max_speed(Ud)
-        sm_o, _ = oracle.max_speed(og, Uin, op)
+        sm_o, nf_speed = oracle.max_speed(og, Uin, op)
         assert sm_g == sm_o
         h = P.cfl * min(P.dx) / sm_g if dt is None else dt
         s.step(Ud, h, opac)
         rep_g = s.report()
         Uo, st, rep_o = oracle.step(og, Uin, h, P.kappa, P.sigma, op)
+        if reports is not None:
+            reports.append(rep_o)
         Ug = host(Ud)
         e = relerr(Ug, Uo)
         worst = max(worst, e)
         bit = bit and np.array_equal(Ug, Uo)
         assert e <= TOL, (k, e)
-        assert rep_g["c2p_fail"] == rep_o.c2p_fail
+        # the report also counts the recoveries of the signal-speed pass
+        assert rep_g["c2p_fail"] == rep_o.c2p_fail + nf_speed
         assert rep_g["imp_fail"] == rep_o.imp_fail
         assert rep_g["pvm_fallback"] == rep_o.pvm_fallback
         assert rep_g["first_bad_cell"] == rep_o.first_bad_cell
@@ -172,7 +175,7 @@ def test_step_1d_riemann(R, oracle, torch_mod, seed):
 
 @pytest.mark.parametrize("kw", [dict(beta_mode=0), dict(beta_mode=2), dict(pvm_k=0), dict(pvm_k=1),
                                 dict(pvm_k=4), dict(recon=0), dict(rk_order=3), dict(imp_method=1),
-                                dict(imp_picard_it=12), dict(imp_method=2)])
+                                dict(imp_picard_it=12), dict(imp_method=2), dict(c2p_maxit=1)])
 def test_step_1d_variants(R, oracle, torch_mod, kw):
     worst, bit = one_step_compare(R, oracle, torch_mod, I.riemann_1d(4), steps=2, **kw)
     assert bit
@@ -181,6 +184,17 @@ def test_step_1d_variants(R, oracle, torch_mod, kw):
 def test_step_2d_small(R, oracle, torch_mod):
     worst, bit = one_step_compare(R, oracle, torch_mod, I.blast_2d(0, 64, 40), steps=3)
     assert bit
+
+
+def test_step_2d_failure_paths(R, oracle, torch_mod):
+    """A one-iteration cap on primitive recovery: most recoveries fail, so the
+    PVM chain drops faces to p_0 = 1 in both directions (thousands per step),
+    cells take the recovery fallback and the implicit solve fails where its
+    recoveries do. All of it is counted and must match the oracle bit for bit."""
+    reps = []
+    worst, bit = one_step_compare(R, oracle, torch_mod, I.blast_2d(0, 64, 40), steps=3, reports=reps, c2p_maxit=1)
+    assert bit
+    assert all(r.pvm_fallback > 1000 and r.c2p_fail > 0 and r.imp_fail > 0 for r in reps)
 
 
 def test_step_2d_full_size(R, oracle, torch_mod):
