@@ -241,13 +241,18 @@ static C2PEval c2p_eval(real Z, const C2PIn& in, const Consts& K, bool want_df) 
   if (!(e.p > real(0.0))) return e;
   e.ok = true;
   if (!want_df) return e;
-  e.f = (((Z + in.B2) - e.p) - 0.5 * (in.B2 * e.l2)) - (0.5 * vB2 + in.Et);
+  const real f = (((Z + in.B2) - e.p) - 0.5 * (in.B2 * e.l2)) - (0.5 * vB2 + in.Et);
   // d(v^2)/dZ = -2 [S^2 + (S.B/Z)^2 (3 Z (Z+B^2) + B^4)/Z] / (Z+B^2)^3
   const real dv2 = -2.0 * (in.S2 + (vB2 * (3.0 * (Z * Zb) + in.B2 * in.B2)) * iZ) *
                    ((e.iZb * e.iZb) * e.iZb);
-  const real W = 1.0 / e.iW;
-  const real dp = K.gm1g * (e.l2 + dv2 * (0.5 * (in.D * W) - Z));
-  e.df = ((1.0 - dp) + 0.5 * (in.B2 * dv2)) + vB2 * iZ;
+  // f and f' are returned multiplied by 1/W > 0 (same signs, same Newton
+  // quotient), which needs no 1/(1/W):
+  //   f'/W = 1/W - [(gamma-1)/gamma] (l2/W + dv2 (D/2 - Z/W))
+  //          + (B^2/2) dv2 /W + (S.B)^2/Z^3 /W,
+  // from dp/dZ = [(gamma-1)/gamma] (l2 + dv2 (D W/2 - Z)).
+  e.f = f * e.iW;
+  const real dpw = K.gm1g * (e.l2 * e.iW + dv2 * (0.5 * in.D - Z * e.iW));
+  e.df = ((e.iW - dpw) + (0.5 * (in.B2 * dv2)) * e.iW) + (vB2 * iZ) * e.iW;
   return e;
 }
 

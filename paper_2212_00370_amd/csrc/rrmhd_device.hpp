@@ -225,12 +225,13 @@ __device__ __forceinline__ C2PEval c2p_eval(double Z, const C2PIn& in, const Phy
   e.f = 0.0;
   e.df = 0.0;
   if (!WANT_DF) return e;
-  e.f = (((Z + in.B2) - e.p) - 0.5 * (in.B2 * e.l2)) - (0.5 * vB2 + in.Et);
+  const double f = (((Z + in.B2) - e.p) - 0.5 * (in.B2 * e.l2)) - (0.5 * vB2 + in.Et);
   const double dv2 = -2.0 * (in.S2 + (vB2 * (3.0 * (Z * Zb) + in.B2 * in.B2)) * iZ) *
                      ((e.iZb * e.iZb) * e.iZb);
-  const double W = 1.0 / e.iW;
-  const double dp = K.gm1g * (e.l2 + dv2 * (0.5 * (in.D * W) - Z));
-  e.df = ((1.0 - dp) + 0.5 * (in.B2 * dv2)) + vB2 * iZ;
+  // f and f' times 1/W > 0: same signs and Newton quotient, no 1/(1/W).
+  e.f = f * e.iW;
+  const double dpw = K.gm1g * (e.l2 * e.iW + dv2 * (0.5 * in.D - Z * e.iW));
+  e.df = ((e.iW - dpw) + (0.5 * (in.B2 * dv2)) * e.iW) + (vB2 * iZ) * e.iW;
   return e;
 }
 
