@@ -63,7 +63,8 @@ enum { RRMHD_FP64 = 0, RRMHD_MIXED = 1 };
  * inflow_mask is set and copies elsewhere. */
 typedef struct {
   int ndim;                         /* 1, 2 or 3                                          */
-  int n[3];                         /* interior cells per axis; unused axes must be 1     */
+  int n[3];                         /* interior cells per axis; unused axes must be 1;
+                                       n0*n1*n2 < 2^31                                    */
   double dx[3];                     /* cell sizes                                         */
   int bc_lo[3], bc_hi[3];           /* rrmhd_bc per axis side                             */
   long long var_stride;             /* elements between variable planes, >= n0*n1*n2     */

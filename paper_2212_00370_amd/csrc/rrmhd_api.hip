@@ -323,9 +323,15 @@ __device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, l
   if (d == 0) fn0 += 1;
   if (d == 1) fn1 += 1;
   int c[3];
-  c[0] = (int)(f % fn0);
-  c[1] = (int)((f / fn0) % fn1);
-  c[2] = (int)(f / ((long long)fn0 * fn1));
+  {
+    // 32-bit index arithmetic: face counts stay below 2^32 (grid_valid)
+    const unsigned int fu = (unsigned int)f, u0 = (unsigned int)fn0, u1 = (unsigned int)fn1;
+    const unsigned int q0 = fu / u0;
+    c[0] = (int)(fu - q0 * u0);
+    const unsigned int q1 = q0 / u1;
+    c[1] = (int)(q0 - q1 * u1);
+    c[2] = (int)q1;
+  }
   double Vs[4][NV];
   double tp[4];
 #pragma unroll
@@ -366,9 +372,15 @@ __device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs
   if (d == 0) fn0 += 1;
   if (d == 1) fn1 += 1;
   int c[3];
-  c[0] = (int)(f % fn0);
-  c[1] = (int)((f / fn0) % fn1);
-  c[2] = (int)(f / ((long long)fn0 * fn1));
+  {
+    // 32-bit index arithmetic: face counts stay below 2^32 (grid_valid)
+    const unsigned int fu = (unsigned int)f, u0 = (unsigned int)fn0, u1 = (unsigned int)fn1;
+    const unsigned int q0 = fu / u0;
+    c[0] = (int)(fu - q0 * u0);
+    const unsigned int q1 = q0 / u1;
+    c[1] = (int)(q0 - q1 * u1);
+    c[2] = (int)q1;
+  }
   float Vs[4][NV];
   float tp[4];
 #pragma unroll
@@ -522,7 +534,16 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
   rr::PicardState S;
   S.m = -1;
   if (c < G.N) {
-    const int ci[3] = {(int)(c % G.n[0]), (int)((c / G.n[0]) % G.n[1]), (int)(c / ((long long)G.n[0] * G.n[1]))};
+    int ci[3];
+    {
+      // 32-bit index arithmetic: fewer than 2^31 cells (grid_valid)
+      const unsigned int cu = (unsigned int)c, u0 = (unsigned int)G.n[0], u1 = (unsigned int)G.n[1];
+      const unsigned int q0 = cu / u0;
+      ci[0] = (int)(cu - q0 * u0);
+      const unsigned int q1 = q0 / u1;
+      ci[1] = (int)(q0 - q1 * u1);
+      ci[2] = (int)q1;
+    }
     long long fm[3], fs[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -968,7 +989,9 @@ bool grid_valid(const rrmhd_grid* g) {
     }
   }
   const long long N = grid_cells(g);
-  if (N > (1LL << 40)) return false;
+  // fewer than 2^31 cells: cell and face indices (at most 2N faces per
+  // direction) then fit the kernels' 32-bit index arithmetic
+  if (N >= (1LL << 31)) return false;
   if (g->var_stride < N) return false;
   if (g->bc_lo[g->ndim - 1] == RRMHD_BC_INFLOW && (!g->inflow_U || !g->inflow_mask)) return false;
   return true;

@@ -102,6 +102,11 @@ def test_workspace_bytes(R):
     bad = _grid(R, (16, 16))
     bad.dx[0] = 0.0
     assert R._lib.rrmhd_workspace_bytes(C.byref(bad), C.byref(p)) == 0
+    # 2^31 cells: beyond the kernels' 32-bit index range
+    big = _grid(R, (1 << 16, 1 << 15))
+    assert R._lib.rrmhd_workspace_bytes(C.byref(big), C.byref(p)) == 0
+    ok = _grid(R, (1 << 16, (1 << 15) - 1))
+    assert R._lib.rrmhd_workspace_bytes(C.byref(ok), C.byref(p)) > 0
     bad = _grid(R, (16, 16))
     bad.bc_hi[0] = R.BC_INFLOW
     assert R._lib.rrmhd_workspace_bytes(C.byref(bad), C.byref(p)) == 0
