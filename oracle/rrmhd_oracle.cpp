@@ -137,11 +137,11 @@ struct Aux {
   real D;             // rho W
 };
 
-static void prim_aux(const real V[NV], const Consts& K, Aux& a) {
+// From l2 = 1 - v^2 and iW = 1/W = sqrt(l2) of the state.
+static void prim_aux_lw(const real V[NV], real l2, real iW, const Consts& K, Aux& a) {
   const real vx = V[1], vy = V[2], vz = V[3];
-  const real v2 = (vx * vx + vy * vy) + vz * vz;
-  a.l2 = 1.0 - v2;
-  a.iW = rsqrt_(a.l2);
+  a.l2 = l2;
+  a.iW = iW;
   a.W = 1.0 / a.iW;
   const real vB = (vx * V[5] + vy * V[6]) + vz * V[7];
   a.b0 = a.W * vB;
@@ -152,6 +152,12 @@ static void prim_aux(const real V[NV], const Consts& K, Aux& a) {
   a.wtot = (rhoh + a.bb) * (a.W * a.W);
   a.ps = V[4] + 0.5 * a.bb;
   a.D = V[0] * a.W;
+}
+
+static void prim_aux(const real V[NV], const Consts& K, Aux& a) {
+  const real v2 = (V[1] * V[1] + V[2] * V[2]) + V[3] * V[3];
+  const real l2 = 1.0 - v2;
+  prim_aux_lw(V, l2, rsqrt_(l2), K, a);
 }
 
 // Primitive -> conserved map, eq. eqU.
@@ -260,8 +266,10 @@ static C2PEval c2p_eval(real Z, const C2PIn& in, const Consts& K, bool want_df) 
 // intermediate states of the PVM chain and inside the implicit solve); the
 // cold start is the rest-frame estimate Z0 = gamma (E - B^2/2) - (gamma-1) D,
 // exact for a fluid at rest.
+// lw (optional): 1 - v^2 and 1/W of the recovered state, as the final
+// evaluation at the converged Z forms them.
 static int c2p(const real U[NV], const OPar& P, const Consts& K, real Zguess,
-               real V[NV], real* Zout, int* nit) {
+               real V[NV], real* Zout, int* nit, real* lw = nullptr) {
   C2PIn in;
   in.D = U[0];
   for (int j = 0; j < 3; ++j) { in.S[j] = U[1 + j]; in.B[j] = U[5 + j]; }
@@ -309,6 +317,7 @@ static int c2p(const real U[NV], const OPar& P, const Consts& K, real Zguess,
   for (int j = 0; j < 3; ++j) V[1 + j] = (in.S[j] + e.vB * in.B[j]) * e.iZb;
   V[4] = e.p;
   *Zout = Z;
+  if (lw) { lw[0] = e.l2; lw[1] = e.iW; }
   return 0;
 }
 
@@ -359,17 +368,20 @@ struct FaceOut { int fallback; int c2p_it; };
 // U_m's bit for bit the known V_m is reused (this makes the chain exact for
 // U_0 = 0 and for perturbations that leave the fluid untouched).
 static bool recover_near(const real U[NV], const real Um[NV], const real Vm[NV], real Zm,
-                         const OPar& P, const Consts& K, real V[NV], int* nit) {
+                         const real lwm[2], const OPar& P, const Consts& K, real V[NV], int* nit,
+                         real lw[2]) {
   bool same = true;
   for (int q = 0; q < 8; ++q) same = same && (U[q] == Um[q]);
   if (same) {
     for (int q = 0; q < 5; ++q) V[q] = Vm[q];
     for (int q = 5; q < NV; ++q) V[q] = U[q];
     *nit = 0;
+    lw[0] = lwm[0];
+    lw[1] = lwm[1];
     return true;
   }
   real Z = 0.0;
-  return c2p(U, P, K, Zm, V, &Z, nit) == 0;
+  return c2p(U, P, K, Zm, V, &Z, nit, lw) == 0;
 }
 
 static void pvm_face(const real VL[NV], const real VR[NV], real tauL, real tauR, int d,
@@ -391,26 +403,27 @@ static void pvm_face(const real VL[NV], const real VR[NV], real tauL, real tauR,
   if (M == 0) {
     for (int q = 0; q < NV; ++q) Uk[q] = U0[q];
   } else {
-    real Vm[NV], Zm = 0.0;
+    // Fluxes of recovered states take 1 - v^2 and 1/W from the recovery.
+    real Vm[NV], Zm = 0.0, lwm[2] = {0.0, 0.0};
     int it = 0;
-    if (c2p(Um, P, K, real(0.0), Vm, &Zm, &it) != 0) ok = false;
+    if (c2p(Um, P, K, real(0.0), Vm, &Zm, &it, lwm) != 0) ok = false;
     fo.c2p_it += it;
     real Fm[NV];
-    if (ok) { Aux am; prim_aux(Vm, K, am); flux(Vm, am, d, Fm); }
+    if (ok) { Aux am; prim_aux_lw(Vm, lwm[0], lwm[1], K, am); flux(Vm, am, d, Fm); }
     const real ieps = 1.0 / P.pvm_eps;
     real w[NV];
     for (int q = 0; q < NV; ++q) w[q] = U0[q];
     for (int l = 0; l < M && ok; ++l) {
       // Y(w)
-      real Ue[NV], Ve[NV], Fe[NV], Ut[NV], Vt[NV], Ft[NV];
+      real Ue[NV], Ve[NV], Fe[NV], Ut[NV], Vt[NV], Ft[NV], lwe[2], lwt[2];
       for (int q = 0; q < NV; ++q) Ue[q] = Um[q] + P.pvm_eps * w[q];
-      if (!recover_near(Ue, Um, Vm, Zm, P, K, Ve, &it)) { ok = false; fo.c2p_it += it; break; }
+      if (!recover_near(Ue, Um, Vm, Zm, lwm, P, K, Ve, &it, lwe)) { ok = false; fo.c2p_it += it; break; }
       fo.c2p_it += it;
-      { Aux ae; prim_aux(Ve, K, ae); flux(Ve, ae, d, Fe); }
+      { Aux ae; prim_aux_lw(Ve, lwe[0], lwe[1], K, ae); flux(Ve, ae, d, Fe); }
       for (int q = 0; q < NV; ++q) Ut[q] = Um[q] + (Fe[q] - Fm[q]);
-      if (!recover_near(Ut, Um, Vm, Zm, P, K, Vt, &it)) { ok = false; fo.c2p_it += it; break; }
+      if (!recover_near(Ut, Um, Vm, Zm, lwm, P, K, Vt, &it, lwt)) { ok = false; fo.c2p_it += it; break; }
       fo.c2p_it += it;
-      { Aux at; prim_aux(Vt, K, at); flux(Vt, at, d, Ft); }
+      { Aux at; prim_aux_lw(Vt, lwt[0], lwt[1], K, at); flux(Vt, at, d, Ft); }
       const real cnext = coef[M - 1 - l];
       if (l == 0) {
         const real ctop = coef[M];
@@ -522,13 +535,13 @@ static bool imp_build(const real X[4], const real Us[NV], real Et, const real St
   Uf[8] = X[0];
   for (int j = 0; j < 3; ++j) Uf[9 + j] = X[1 + j];
   int it = 0;
-  real Z = 0.0;
-  if (c2p(Uf, P, K, Zg, Vf, &Z, &it) != 0) { *c2p_it += it; return false; }
+  real Z = 0.0, lw[2];
+  if (c2p(Uf, P, K, Zg, Vf, &Z, &it, lw) != 0) { *c2p_it += it; return false; }
   *c2p_it += it;
   sy.Z = Z;
   const real rho = Vf[0], p = Vf[4];
-  const real v2 = (Vf[1] * Vf[1] + Vf[2] * Vf[2]) + Vf[3] * Vf[3];
-  const real iW = rsqrt_(1.0 - v2);
+  // 1/W of the fluid state as the recovery formed it
+  const real iW = lw[1];
   const real W = 1.0 / iW;
   real u[3];
   for (int j = 0; j < 3; ++j) u[j] = W * Vf[1 + j];

@@ -74,6 +74,24 @@ __device__ __forceinline__ void prim_aux(const R V[NV], R g1, AuxT<R>& a) {
 
 __device__ __forceinline__ void prim_aux(const double V[NV], const Phys& K, Aux& a) { prim_aux<double>(V, K.g1, a); }
 
+// prim_aux of a recovered state, with 1 - v^2 and 1/W as the recovery formed them.
+__device__ __forceinline__ void prim_aux_w(const double V[NV], const double lw[2], const Phys& K, Aux& a) {
+  const double vx = V[1], vy = V[2], vz = V[3];
+  a.l2 = lw[0];
+  a.iW = lw[1];
+  a.W = 1.0 / a.iW;
+  const double vB = (vx * V[5] + vy * V[6]) + vz * V[7];
+  a.b0 = a.W * vB;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) a.b[j] = V[5 + j] * a.iW + V[1 + j] * a.b0;
+  const double B2 = (V[5] * V[5] + V[6] * V[6]) + V[7] * V[7];
+  a.bb = B2 * a.l2 + vB * vB;
+  const double rhoh = V[0] + K.g1 * V[4];
+  a.wtot = (rhoh + a.bb) * (a.W * a.W);
+  a.ps = V[4] + 0.5 * a.bb;
+  a.D = V[0] * a.W;
+}
+
 // eq. eqU
 template <typename R>
 __device__ __forceinline__ void p2c(const R V[NV], const AuxT<R>& a, R U[NV]) {
@@ -241,7 +259,7 @@ __device__ __forceinline__ C2PEval c2p_eval(double Z, const C2PIn& in, const Phy
 // variables are not involved in the recovery).
 template <int NU = NV>
 __device__ __forceinline__ int c2p(const double U[NU], const Phys& K, double Zguess, double V[NU],
-                                   double& Zout, int& nit) {
+                                   double& Zout, int& nit, double* lw = nullptr) {
   C2PIn in;
   in.D = U[0];
 #pragma unroll
@@ -292,6 +310,7 @@ __device__ __forceinline__ int c2p(const double U[NU], const Phys& K, double Zgu
   for (int j = 0; j < 3; ++j) V[1 + j] = (in.S[j] + e.vB * in.B[j]) * e.iZb;
   V[4] = e.p;
   Zout = Z;
+  if (lw) { lw[0] = e.l2; lw[1] = e.iW; }
   return 0;
 }
 
@@ -308,7 +327,8 @@ __device__ __forceinline__ void c2p_fallback(const double U[NV], const Phys& K, 
 template <int NU = NV>
 __device__ __forceinline__ bool recover_near(const double U[NU], const double Um[NU],
                                              const double Vm[NU], double Zm, const Phys& K,
-                                             double V[NU], int& nit) {
+                                             double V[NU], int& nit, const double* lwm = nullptr,
+                                             double* lw = nullptr) {
   bool same = true;
 #pragma unroll
   for (int q = 0; q < 8; ++q) same = same && (U[q] == Um[q]);
@@ -318,10 +338,11 @@ __device__ __forceinline__ bool recover_near(const double U[NU], const double Um
 #pragma unroll
     for (int q = 5; q < NU; ++q) V[q] = U[q];
     nit = 0;
+    if (lw) { lw[0] = lwm[0]; lw[1] = lwm[1]; }
     return true;
   }
   double Z = 0.0;
-  return c2p<NU>(U, K, Zm, V, Z, nit) == 0;
+  return c2p<NU>(U, K, Zm, V, Z, nit, lw) == 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -466,37 +487,37 @@ __device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV
 #pragma unroll
   for (int q = 0; q < 8; ++q) w[q] = U0[q];
   if (K.M > 0) {
-    double Vm[8], Zm = 0.0;
+    double Vm[8], Zm = 0.0, lwm[2] = {0.0, 0.0};
     int it = 0;
-    if (c2p<8>(Um, K, 0.0, Vm, Zm, it) != 0) ok = false;
+    if (c2p<8>(Um, K, 0.0, Vm, Zm, it, lwm) != 0) ok = false;
     c2p_its += it;
     double Fm[8];
     if (ok) {
       Aux am;
-      prim_aux(Vm, K, am);
+      prim_aux_w(Vm, lwm, K, am);
       flux_mhd<d, double>(Vm, am, Fm);
     } else {
 #pragma unroll
       for (int q = 0; q < 8; ++q) Fm[q] = 0.0;
     }
     for (int l = 0; l < K.M && ok; ++l) {
-      double Ue[8], Ve[8], Fe[8];
+      double Ue[8], Ve[8], Fe[8], lw[2];
 #pragma unroll
       for (int q = 0; q < 8; ++q) Ue[q] = Um[q] + K.eps * w[q];
-      if (!recover_near<8>(Ue, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
+      if (!recover_near<8>(Ue, Um, Vm, Zm, K, Ve, it, lwm, lw)) { ok = false; c2p_its += it; break; }
       c2p_its += it;
       {
         Aux ae;
-        prim_aux(Ve, K, ae);
+        prim_aux_w(Ve, lw, K, ae);
         flux_mhd<d, double>(Ve, ae, Fe);
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) Ue[q] = Um[q] + (Fe[q] - Fm[q]);
-      if (!recover_near<8>(Ue, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
+      if (!recover_near<8>(Ue, Um, Vm, Zm, K, Ve, it, lwm, lw)) { ok = false; c2p_its += it; break; }
       c2p_its += it;
       {
         Aux at;
-        prim_aux(Ve, K, at);
+        prim_aux_w(Ve, lw, K, at);
         flux_mhd<d, double>(Ve, at, Fe);
       }
       const double cnext = K.coef[K.M - 1 - l];
@@ -726,13 +747,12 @@ __device__ __forceinline__ bool imp_build(const double X[4], const double Ul[NV]
 #pragma unroll
   for (int j = 0; j < 3; ++j) Uf[9 + j] = X[1 + j];
   int it = 0;
-  double Z = 0.0;
-  if (c2p(Uf, K, Zg, Vf, Z, it) != 0) { c2p_it += it; return false; }
+  double Z = 0.0, lw[2];
+  if (c2p(Uf, K, Zg, Vf, Z, it, lw) != 0) { c2p_it += it; return false; }
   c2p_it += it;
   sy.Z = Z;
   const double rho = Vf[0], p = Vf[4];
-  const double v2 = (Vf[1] * Vf[1] + Vf[2] * Vf[2]) + Vf[3] * Vf[3];
-  const double iW = sqrt(1.0 - v2);
+  const double iW = lw[1];
   const double W = 1.0 / iW;
   double u[3];
 #pragma unroll
