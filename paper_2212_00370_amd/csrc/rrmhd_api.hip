@@ -9,7 +9,8 @@
 // All kernels read and write structure-of-arrays float64 planes in HBM; one
 // thread owns one face or one cell, so the step is race-free and needs no
 // floating-point atomics. The CFL speed uses a per-block maximum in LDS and a
-// second single-block pass (deterministic, no memset).
+// second single-block pass (deterministic, no memset); in rrmhd_advance that
+// pass is block 0 of the step's first face launch.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -442,15 +443,58 @@ __device__ __forceinline__ void faces_block(long long lb, const GridDev& G, cons
   report_add(rep, blkmax, lb, 0, fb, 0, 0, ULLONG_MAX, its, 0);
 }
 
+// The step's time step from the signal-speed block maxima of the previous
+// pass: s_max = min(max partial, 1), dt = (cfl dx_min) / s_max into sd[1]
+// (and dt_out[k] when given); a dt that is not finite and >= 0 becomes 0 and
+// is counted as non-finite. partial == nullptr: nothing to do.
+struct DtReduce {
+  const double* partial;
+  long long n;
+  double* sd;
+  double cfl_dx;
+  double* dt_out;
+  int k;
+};
+
+__device__ __forceinline__ void dt_block(const DtReduce& R, DevReport* rep) {
+  double s = 0.0;
+#pragma unroll 16
+  for (long long i = threadIdx.x; i < R.n; i += kBlock) s = rr::dmax(s, R.partial[i]);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) s = rr::dmax(s, __shfl_xor(s, o, kWave));
+  if (threadIdx.x == 0) {
+    const double m = rr::dmin(s, 1.0);
+    R.sd[0] = m;
+    double dt = R.cfl_dx / m;
+    if (!(dt >= 0.0) || !(dt < 1e300)) {
+      dt = 0.0;
+      atomicAdd(&rep->nonfinite, 1ull);
+    }
+    R.sd[1] = dt;
+    if (R.dt_out) R.dt_out[R.k] = dt;
+  }
+}
+
 // Two waves per SIMD (at the price of a few spilled registers) hide more of
 // the FP64 and transcendental latency than one wave with no spills.
-// FT = double: FP64 path; FT = float: mixed-precision path.
+// FT = double: FP64 path; FT = float: mixed-precision path. With R.partial
+// set, block 0 forms the step's time step (dt_block) and blocks 1.. take the
+// faces: the update pass, the first reader of dt, runs after this launch.
 template <typename FT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_FACES_WAVES)))
-k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, unsigned long long* wreset) {
+k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, unsigned long long* wreset,
+        DtReduce R) {
   // the work-list counter of the update pass that follows (not read here)
   if (wreset && blockIdx.x == 0 && threadIdx.x == 0) *wreset = 0;
-  faces_block<sizeof(FT) == sizeof(float)>(blockIdx.x, G, A, K, rep, blkmax);
+  if (R.partial) {
+    if (blockIdx.x == 0) {
+      dt_block(R, rep);
+      return;
+    }
+    faces_block<sizeof(FT) == sizeof(float)>(blockIdx.x - 1, G, A, K, rep, blkmax);
+  } else {
+    faces_block<sizeof(FT) == sizeof(float)>(blockIdx.x, G, A, K, rep, blkmax);
+  }
 }
 
 struct StageArgs {
@@ -777,24 +821,6 @@ __device__ __forceinline__ void reduce_max_block(const double* __restrict__ part
 __global__ void __launch_bounds__(kRedBlock) k_reduce_max(const double* __restrict__ partial, long long n,
                                                        double* __restrict__ out) {
   reduce_max_block(partial, n, out);
-}
-
-// Signal speed, then the step's time step dt = (cfl dx_min) / s_max into
-// sd[1] (and dt_out[k] when given). A dt that is not finite and >= 0 (zero or
-// NaN speed) becomes 0 and is counted as a non-finite result.
-__global__ void __launch_bounds__(kRedBlock) k_reduce_dt(const double* __restrict__ partial, long long n,
-                                                      double* __restrict__ sd, double cfl_dx, DevReport* rep,
-                                                      double* __restrict__ dt_out, int k) {
-  reduce_max_block(partial, n, sd);
-  if (threadIdx.x == 0) {
-    double dt = cfl_dx / sd[0];
-    if (!(dt >= 0.0) || !(dt < 1e300)) {
-      dt = 0.0;
-      atomicAdd(&rep->nonfinite, 1ull);
-    }
-    sd[1] = dt;
-    if (dt_out) dt_out[k] = dt;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1198,7 +1224,7 @@ Opac make_opac(const rrmhd_opacities* o) {
 // wreset: work-list counter of the following update pass, cleared here.
 rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, long long ss,
                           const Opac& op, double* const out[3], bool have_prims = false,
-                          unsigned long long* wreset = nullptr) {
+                          unsigned long long* wreset = nullptr, const DtReduce* red = nullptr) {
   const Layout& L = c->L;
   const GridDev G = make_griddev(g, L);
   int pe;
@@ -1222,11 +1248,14 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
     A.dx[d] = on ? g->dx[d] : 1.0;
     nbt += A.nb[d];
   }
+  DtReduce R{};
+  if (red) R = *red;
+  const unsigned int nlaunch = (unsigned int)(nbt + (R.partial ? 1 : 0));
   pe = prof_begin(c, RRMHD_K_FACES, A.nf[0] + A.nf[1] + A.nf[2]);
   if (c->par.precision == RRMHD_MIXED)
-    k_faces<float><<<(unsigned int)nbt, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset);
+    k_faces<float><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R);
   else
-    k_faces<double><<<(unsigned int)nbt, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset);
+    k_faces<double><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R);
   prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   return RRMHD_OK;
@@ -1462,7 +1491,7 @@ unsigned int worklist_blocks(const rrmhd_ctx* c) {
 // step's result (the next step's first stage) and the signal-speed block
 // maxima, cell blocks then work-list blocks, into `partial`.
 rrmhd_status step_stages(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt, const double* dt_dev,
-                         const Opac& op, bool prims0, bool prims_after) {
+                         const Opac& op, bool prims0, bool prims_after, const DtReduce* red = nullptr) {
   const Layout& L = c->L;
   const GridDev G = make_griddev(g, L);
   const long long vs = g->var_stride;
@@ -1486,7 +1515,8 @@ rrmhd_status step_stages(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt
     c->stage_ctr += 1;
     const double* Us = (s == 0) ? U : c->Us;
     const long long ss = (s == 0) ? vs : L.Ns;
-    const rrmhd_status st = stage_fluxes(c, g, Us, ss, op, fl, (s == 0) ? prims0 : true, wc);
+    const rrmhd_status st = stage_fluxes(c, g, Us, ss, op, fl, (s == 0) ? prims0 : true, wc,
+                                         (s == 0) ? red : nullptr);
     if (st != RRMHD_OK) return st;
     StageArgs A;
     A.U0 = U; A.s0 = vs;
@@ -1557,10 +1587,15 @@ rrmhd_status rrmhd_advance(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double 
       prof_end(c, pe);
       if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
     }
-    k_reduce_dt<<<1, kRedBlock, 0, c->stream>>>(c->partial, (k == 0) ? L.npartial : nred, c->smax, cfl_dx, c->rep,
-                                             dt_out, k);
-    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-    const rrmhd_status st = step_stages(c, U, g, 0.0, c->smax + 1, op, true, k + 1 < nsteps);
+    // the step's dt is formed by block 0 of the first face launch
+    DtReduce red;
+    red.partial = c->partial;
+    red.n = (k == 0) ? L.npartial : nred;
+    red.sd = c->smax;
+    red.cfl_dx = cfl_dx;
+    red.dt_out = dt_out;
+    red.k = k;
+    const rrmhd_status st = step_stages(c, U, g, 0.0, c->smax + 1, op, true, k + 1 < nsteps, &red);
     if (st != RRMHD_OK) return st;
   }
   return RRMHD_OK;
