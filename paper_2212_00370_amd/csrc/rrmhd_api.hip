@@ -475,26 +475,73 @@ __device__ __forceinline__ void dt_block(const DtReduce& R, DevReport* rep) {
   }
 }
 
+// Dispatch order of the next update pass: its nb cell blocks sorted by
+// decreasing cost (the Picard solves of each block's slowest cell in the
+// previous update pass), so that the slow blocks start in the first round of
+// waves and the partial last round holds fast ones. Counting sort in one
+// block; the order within a cost class is arbitrary (blocks are independent,
+// so results do not depend on it). cost == nullptr: nothing to do.
+struct BlockOrder {
+  const unsigned int* cost;
+  unsigned int* perm;
+  long long nb;
+};
+
+constexpr int kCostClasses = 32;
+
+__device__ __forceinline__ void order_block(const BlockOrder& O) {
+  __shared__ unsigned int cnt[kCostClasses];
+  if (threadIdx.x < kCostClasses) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (long long i = threadIdx.x; i < O.nb; i += kBlock) {
+    const unsigned int k = O.cost[i];
+    atomicAdd(&cnt[(k < kCostClasses) ? k : kCostClasses - 1], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int s = 0;
+    for (int k = kCostClasses - 1; k >= 0; --k) {
+      const unsigned int n = cnt[k];
+      cnt[k] = s;
+      s += n;
+    }
+  }
+  __syncthreads();
+  for (long long i = threadIdx.x; i < O.nb; i += kBlock) {
+    const unsigned int k = O.cost[i];
+    const unsigned int pos = atomicAdd(&cnt[(k < kCostClasses) ? k : kCostClasses - 1], 1u);
+    O.perm[pos] = (unsigned int)i;
+  }
+}
+
 // Two waves per SIMD (at the price of a few spilled registers) hide more of
 // the FP64 and transcendental latency than one wave with no spills.
-// FT = double: FP64 path; FT = float: mixed-precision path. With R.partial
-// set, block 0 forms the step's time step (dt_block) and blocks 1.. take the
-// faces: the update pass, the first reader of dt, runs after this launch.
+// FT = double: FP64 path; FT = float: mixed-precision path. The first
+// blocks do the step's time step (dt_block, with R.partial set) and the next
+// update pass's block order (order_block, with O.cost set); the rest take the
+// faces. The update pass, which reads both, runs after this launch.
 template <typename FT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_FACES_WAVES)))
 k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, unsigned long long* wreset,
-        DtReduce R) {
+        DtReduce R, BlockOrder O) {
   // the work-list counter of the update pass that follows (not read here)
   if (wreset && blockIdx.x == 0 && threadIdx.x == 0) *wreset = 0;
+  long long b = blockIdx.x;
   if (R.partial) {
-    if (blockIdx.x == 0) {
+    if (b == 0) {
       dt_block(R, rep);
       return;
     }
-    faces_block<sizeof(FT) == sizeof(float)>(blockIdx.x - 1, G, A, K, rep, blkmax);
-  } else {
-    faces_block<sizeof(FT) == sizeof(float)>(blockIdx.x, G, A, K, rep, blkmax);
+    b -= 1;
   }
+  if (O.cost) {
+    if (b == 0) {
+      order_block(O);
+      return;
+    }
+    b -= 1;
+  }
+  faces_block<sizeof(FT) == sizeof(float)>(b, G, A, K, rep, blkmax);
 }
 
 struct StageArgs {
@@ -526,6 +573,10 @@ struct StageArgs {
   long long np;
   double* partial;
   long long npart;
+  // Dispatch order of the cell blocks (perm[blockIdx] = block; nullptr:
+  // identity) and each block's cost, written for the next ordering.
+  const unsigned int* perm;
+  unsigned int* cost;
 };
 
 __device__ __forceinline__ double stage_cdt(const StageArgs& A) { return A.dtp ? A.cc * A.dtp[0] : A.cdt; }
@@ -691,6 +742,11 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
     }
   }
   report_add(rep, blkmax, lb, fc2p, 0, fimp, fnf, bad, cits, its, ffl);
+  if (A.cost) {
+    // the block's cost: Picard solves of its slowest cell (one wave per block)
+    const unsigned int wm = wave_max_u32(its);
+    if (threadIdx.x == 0) A.cost[lb] = wm;
+  }
   if (A.speed) block_max_to(spd, A.partial, lb);
 }
 
@@ -698,7 +754,8 @@ template <typename FT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_UPDATE_WAVES)))
 k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
          long long* worklist, unsigned long long* wcount) {
-  update_block<FT>(blockIdx.x, G, A, op, K, rep, blkmax, worklist, wcount);
+  const long long lb = A.perm ? (long long)A.perm[blockIdx.x] : (long long)blockIdx.x;
+  update_block<FT>(lb, G, A, op, K, rep, blkmax, worklist, wcount);
 }
 
 // Second pass of the implicit solve for the cells in `worklist` (the rest of
@@ -891,6 +948,8 @@ __device__ __forceinline__ StageArgs stage_args(const SimDesc& D, int stage, int
   A.np = D.FA.np;
   A.partial = nullptr;
   A.npart = 0;
+  A.perm = nullptr;
+  A.cost = nullptr;
   return A;
 }
 
@@ -961,6 +1020,10 @@ __global__ void __launch_bounds__(kBlock) k_report_reset(DevReport* rep, unsigne
 }
 
 // Fold the per-block iteration maxima into the report (single block).
+__global__ void __launch_bounds__(kBlock) k_zero_u32(unsigned int* p, long long n) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) p[i] = 0u;
+}
+
 __global__ void __launch_bounds__(kRedBlock) k_report_fold(DevReport* rep, const unsigned int* blkmax, long long nblk) {
   __shared__ unsigned int red[2][kRedBlock / kWave];
   unsigned int a = 0, b = 0;
@@ -1096,7 +1159,7 @@ struct Layout {
   long long nb_faces[3];
   long long nblkmax;  // block slots for the iteration maxima
   size_t off_Vp, off_taup, off_Us, off_Fh[3], off_partial, off_smax, off_rep, off_blkmax, off_work, off_wcount, off_Zc,
-      total;
+      off_cost, off_perm, total;
 };
 
 Layout make_layout(const rrmhd_grid* g) {
@@ -1131,6 +1194,9 @@ Layout make_layout(const rrmhd_grid* g) {
   L.off_work = o; o = align256(o + sizeof(long long) * L.N + sizeof(double) * kWorkPlanes * L.N);  // cells + state
   L.off_wcount = o; o = align256(o + 2 * sizeof(unsigned long long));  // one per stage parity
   L.off_Zc = o; o = align256(o + sizeof(double) * L.N);
+  // update-pass block costs and dispatch order (cell blocks)
+  L.off_cost = o; o = align256(o + sizeof(unsigned int) * L.npartial);
+  L.off_perm = o; o = align256(o + sizeof(unsigned int) * L.npartial);
   L.total = o;
   return L;
 }
@@ -1167,6 +1233,8 @@ struct rrmhd_ctx {
   unsigned long long* wcount;   // two counters, alternating between stages
   unsigned long long stage_ctr;
   double* Zc;                   // recovery Z of the stage state per cell
+  unsigned int* cost;           // per cell block: cost in the last update pass
+  unsigned int* perm;           // dispatch order of the next update pass
   hipStream_t stream;
   unsigned int newton_blocks;
   void* host;  // pinned: DevReport + one double
@@ -1250,12 +1318,16 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   }
   DtReduce R{};
   if (red) R = *red;
-  const unsigned int nlaunch = (unsigned int)(nbt + (R.partial ? 1 : 0));
+  BlockOrder O;
+  O.cost = c->cost;
+  O.perm = c->perm;
+  O.nb = L.npartial;
+  const unsigned int nlaunch = (unsigned int)(nbt + (R.partial ? 1 : 0) + 1);
   pe = prof_begin(c, RRMHD_K_FACES, A.nf[0] + A.nf[1] + A.nf[2]);
   if (c->par.precision == RRMHD_MIXED)
-    k_faces<float><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R);
+    k_faces<float><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
   else
-    k_faces<double><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R);
+    k_faces<double><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
   prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   return RRMHD_OK;
@@ -1428,6 +1500,8 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   c->wcount = (unsigned long long*)(c->ws + L.off_wcount);
   c->stage_ctr = 0;
   c->Zc = (double*)(c->ws + L.off_Zc);
+  c->cost = (unsigned int*)(c->ws + L.off_cost);
+  c->perm = (unsigned int*)(c->ws + L.off_perm);
   c->stream = (hipStream_t)hip_stream;
   c->host = nullptr;
   c->prof = 0;
@@ -1444,6 +1518,7 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
     return RRMHD_E_DEVICE;
   }
   k_report_reset<<<64, kBlock, 0, c->stream>>>(c->rep, c->blkmax, 2 * L.nblkmax);
+  if (launch_ok() == RRMHD_OK) k_zero_u32<<<64, kBlock, 0, c->stream>>>(c->cost, L.npartial);
   if (launch_ok() != RRMHD_OK) {
     hipHostFree(c->host);
     delete c;
@@ -1543,6 +1618,8 @@ rrmhd_status step_stages(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt
     A.np = L.Np;
     A.partial = c->partial;
     A.npart = L.npartial;
+    A.perm = c->perm;
+    A.cost = c->cost;
     int pe = prof_begin(c, RRMHD_K_UPDATE, L.N);
     if (c->par.precision == RRMHD_MIXED)
       k_update<float><<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, wc);
