@@ -44,12 +44,14 @@ constexpr int kWave = 64;
 #endif
 constexpr int kPicardSplit = RRMHD_PICARD_SPLIT;
 // Minimum waves per SIMD the register allocation of the face and update
-// kernels targets (a hint to the compiler; fewer registers, some spilled).
+// kernels targets (a hint to the compiler). Two each: both then fit their
+// registers without spilling, and the update pass's 4096 one-wave blocks
+// (512^2 cells) fill exactly two rounds of 2048 slots.
 #ifndef RRMHD_FACES_WAVES
 #define RRMHD_FACES_WAVES 2
 #endif
 #ifndef RRMHD_UPDATE_WAVES
-#define RRMHD_UPDATE_WAVES 3
+#define RRMHD_UPDATE_WAVES 2
 #endif
 
 struct DevReport {
