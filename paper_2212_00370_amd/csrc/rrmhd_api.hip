@@ -34,6 +34,7 @@ namespace {
 #define RRMHD_BLOCK 64
 #endif
 constexpr int kBlock = RRMHD_BLOCK;
+static_assert(kBlock == rr::kParkLanes, "the PVM chain's LDS slots assume one-wave workgroups");
 // Workgroup size of the single-block reductions over per-block partials.
 constexpr int kRedBlock = 1024;
 constexpr int kWave = 64;
@@ -44,11 +45,16 @@ constexpr int kWave = 64;
 #endif
 constexpr int kPicardSplit = RRMHD_PICARD_SPLIT;
 // Minimum waves per SIMD the register allocation of the face and update
-// kernels targets (a hint to the compiler). Two each: both then fit their
-// registers without spilling, and the update pass's 4096 one-wave blocks
-// (512^2 cells) fill exactly two rounds of 2048 slots.
+// kernels targets (a hint to the compiler). FP64 faces: three (168 VGPRs,
+// with the PVM chain's start-to-end values in LDS; 12 one-wave blocks of
+// 12.5 KB LDS per CU); mixed-precision faces and the update pass: two (no
+// spills; the update pass's 4096 one-wave blocks at 512^2 cells fill two
+// rounds of 2048 slots).
 #ifndef RRMHD_FACES_WAVES
-#define RRMHD_FACES_WAVES 2
+#define RRMHD_FACES_WAVES 3
+#endif
+#ifndef RRMHD_FACES_WAVES_MIXED
+#define RRMHD_FACES_WAVES_MIXED 2
 #endif
 #ifndef RRMHD_UPDATE_WAVES
 #define RRMHD_UPDATE_WAVES 2
@@ -516,14 +522,15 @@ __device__ __forceinline__ void order_block(const BlockOrder& O) {
   }
 }
 
-// Two waves per SIMD (at the price of a few spilled registers) hide more of
-// the FP64 and transcendental latency than one wave with no spills.
+// More waves per SIMD hide more of the FP64 and transcendental latency (three
+// with 18 spilled registers beat two with none by 7 %).
 // FT = double: FP64 path; FT = float: mixed-precision path. The first
 // blocks do the step's time step (dt_block, with R.partial set) and the next
 // update pass's block order (order_block, with O.cost set); the rest take the
 // faces. The update pass, which reads both, runs after this launch.
 template <typename FT>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_FACES_WAVES)))
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(FT) == sizeof(double) ? RRMHD_FACES_WAVES : RRMHD_FACES_WAVES_MIXED)))
 k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, unsigned long long* wreset,
         DtReduce R, BlockOrder O) {
   // the work-list counter of the update pass that follows (not read here)

@@ -394,6 +394,19 @@ __device__ __forceinline__ void limit_rad_flux(R V[NV]) {
 }
 
 // ---------------------------------------------------------------------------
+// LDS slots per lane for values the FP64 PVM chain keeps from its start to its
+// end, so that they occupy no registers during the chain: (F_L + F_R)/2 of
+// rows 0..7 (slots 0..7), the two candidate radiation rows (8..15) and U_0 of
+// rows 0..7 (16..23). Workgroups of kParkLanes threads; slot k of thread t
+// at [k * kParkLanes + t].
+constexpr int kParkSlots = 24;
+constexpr int kParkLanes = 64;
+__device__ __forceinline__ double* park_lane() {
+  __shared__ double park[kParkSlots * kParkLanes];
+  return park + threadIdx.x;
+}
+
+// ---------------------------------------------------------------------------
 // Jacobian-free PVM-int face flux (Section 3.2, PVM algorithm; eq. beta).
 // Y(w) = [F(U_m + F(U_m + eps w) - F(U_m)) - F(U_m)] / eps ~ A(U_m)^2 w;
 // Horner over x^2 gives U_M ~ p_k(A) U_0; F^ = (F_L + F_R)/2 - beta U_M / 2.
@@ -410,8 +423,9 @@ __device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV
                                          double tauR, const Phys& K, double Fh[NV],
                                          int& fallback, int& c2p_its) {
   const double beta = 1.0 / dmax(dmax(tauL, tauR), 1.0);
-  // Radiation rows with the chain's dissipation (Rok) and with p_0 = 1 (Rfb).
-  double Rok[4], Rfb[4];
+  double* sh = park_lane();
+  // Radiation rows with the chain's dissipation (slots 8..11) and with
+  // p_0 = 1 (slots 12..15).
   {
     double Fa[4], U0[4], Um[4], w[4];
     {
@@ -452,13 +466,13 @@ __device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV
     const double bq = (K.beta_mode == 2) ? 1.0 : beta;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      Rok[q] = Fa[q] - 0.5 * (bq * w[q]);
-      Rfb[q] = Fa[q] - 0.5 * (bq * U0[q]);
+      sh[(8 + q) * kParkLanes] = Fa[q] - 0.5 * (bq * w[q]);
+      sh[(12 + q) * kParkLanes] = Fa[q] - 0.5 * (bq * U0[q]);
     }
   }
   // Fluid and magnetic rows. Only (F_L + F_R)/2, U_0 and U_m are needed past
   // the reconstruction.
-  double Fa[8], U0[8], Um[8];
+  double Um[8], w[8];
   {
     double UL[8], UR[8], FL[8], FR[8];
     {
@@ -475,17 +489,15 @@ __device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      U0[q] = UR[q] - UL[q];
+      w[q] = UR[q] - UL[q];
+      sh[(16 + q) * kParkLanes] = w[q];  // U_0
       Um[q] = 0.5 * (UL[q] + UR[q]);
-      Fa[q] = 0.5 * (FL[q] + FR[q]);
+      sh[q * kParkLanes] = 0.5 * (FL[q] + FR[q]);  // (F_L + F_R)/2
     }
   }
   fallback = 0;
   c2p_its = 0;
-  double w[8];
   bool ok = true;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) w[q] = U0[q];
   if (K.M > 0) {
     double Vm[8], Zm = 0.0, lwm[2] = {0.0, 0.0};
     int it = 0;
@@ -524,25 +536,25 @@ __device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV
       if (l == 0) {
         const double ctop = K.coef[K.M];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) w[q] = ctop * ((Fe[q] - Fm[q]) * K.ieps) + cnext * U0[q];
+        for (int q = 0; q < 8; ++q) w[q] = ctop * ((Fe[q] - Fm[q]) * K.ieps) + cnext * sh[(16 + q) * kParkLanes];
       } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) w[q] = (Fe[q] - Fm[q]) * K.ieps + cnext * U0[q];
+        for (int q = 0; q < 8; ++q) w[q] = (Fe[q] - Fm[q]) * K.ieps + cnext * sh[(16 + q) * kParkLanes];
       }
     }
     if (!ok) {
       fallback = 1;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) w[q] = U0[q];
+      for (int q = 0; q < 8; ++q) w[q] = sh[(16 + q) * kParkLanes];
     }
   }
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const double bq = (K.beta_mode == 1 || K.beta_mode == 2) ? 1.0 : beta;
-    Fh[q] = Fa[q] - 0.5 * (bq * w[q]);
+    Fh[q] = sh[q * kParkLanes] - 0.5 * (bq * w[q]);
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) Fh[8 + q] = ok ? Rok[q] : Rfb[q];
+  for (int q = 0; q < 4; ++q) Fh[8 + q] = ok ? sh[(8 + q) * kParkLanes] : sh[(12 + q) * kParkLanes];
 }
 
 // ---------------------------------------------------------------------------
