@@ -45,16 +45,16 @@ constexpr int kWave = 64;
 #endif
 constexpr int kPicardSplit = RRMHD_PICARD_SPLIT;
 // Minimum waves per SIMD the register allocation of the face and update
-// kernels targets (a hint to the compiler). FP64 faces: three (168 VGPRs,
-// with the PVM chain's start-to-end values in LDS; 12 one-wave blocks of
-// 12.5 KB LDS per CU); mixed-precision faces and the update pass: two (no
-// spills; the update pass's 4096 one-wave blocks at 512^2 cells fill two
-// rounds of 2048 slots).
+// kernels targets (a hint to the compiler). Faces: three, with the PVM
+// chain's start-to-end values in LDS (FP64: 168 VGPRs and 12.5 KB LDS per
+// one-wave block; mixed precision: 136 VGPRs, 6.5 KB). Update pass: two (no
+// spills; its 4096 one-wave blocks at 512^2 cells fill two rounds of 2048
+// slots).
 #ifndef RRMHD_FACES_WAVES
 #define RRMHD_FACES_WAVES 3
 #endif
 #ifndef RRMHD_FACES_WAVES_MIXED
-#define RRMHD_FACES_WAVES_MIXED 2
+#define RRMHD_FACES_WAVES_MIXED 3
 #endif
 #ifndef RRMHD_UPDATE_WAVES
 #define RRMHD_UPDATE_WAVES 2

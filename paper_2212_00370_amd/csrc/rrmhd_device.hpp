@@ -104,7 +104,8 @@ __device__ __forceinline__ void p2c(const R V[NV], const AuxT<R>& a, R U[NV]) {
 }
 
 // Rows 0..7 of eq. eqU.
-__device__ __forceinline__ void p2c8(const double V[8], const Aux& a, double U[8]) {
+template <typename R>
+__device__ __forceinline__ void p2c8(const R V[8], const AuxT<R>& a, R U[8]) {
   U[0] = a.D;
 #pragma unroll
   for (int j = 0; j < 3; ++j) U[1 + j] = a.wtot * V[1 + j] - a.b0 * a.b[j];
@@ -564,8 +565,10 @@ __device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV
 // rounding (U_m + eps w == U_m), so the chain keeps the paper's form
 // U_m + eps w with eps = eps32 = 2^-12, about the square root of the FP32
 // unit roundoff, which balances truncation and rounding error.
-__device__ __forceinline__ bool recover_near_mixed(const float U[NV], const float Um[NV], const float Vm[NV],
-                                                   double Zm, const Phys& K, float V[NV], int& nit) {
+// recover_near for the FP32 chain's fluid block (8-wide): the recovery
+// itself in FP64.
+__device__ __forceinline__ bool recover_near_mixed(const float U[8], const float Um[8], const float Vm[8],
+                                                   double Zm, const Phys& K, float V[8], int& nit) {
   bool same = true;
 #pragma unroll
   for (int q = 0; q < 8; ++q) same = same && (U[q] == Um[q]);
@@ -573,122 +576,178 @@ __device__ __forceinline__ bool recover_near_mixed(const float U[NV], const floa
 #pragma unroll
     for (int q = 0; q < 5; ++q) V[q] = Vm[q];
 #pragma unroll
-    for (int q = 5; q < NV; ++q) V[q] = U[q];
+    for (int q = 5; q < 8; ++q) V[q] = U[q];
     nit = 0;
     return true;
   }
-  double Ud[NV], Vd[NV], Z = 0.0;
+  double Ud[8], Vd[8], Z = 0.0;
 #pragma unroll
-  for (int q = 0; q < NV; ++q) Ud[q] = (double)U[q];
-  if (c2p(Ud, K, Zm, Vd, Z, nit) != 0) return false;
+  for (int q = 0; q < 8; ++q) Ud[q] = (double)U[q];
+  if (c2p<8>(Ud, K, Zm, Vd, Z, nit) != 0) return false;
 #pragma unroll
   for (int q = 0; q < 5; ++q) V[q] = (float)Vd[q];
 #pragma unroll
-  for (int q = 5; q < NV; ++q) V[q] = U[q];
+  for (int q = 5; q < 8; ++q) V[q] = U[q];
   return true;
 }
 
+// LDS slots of the FP32 chain (as park_lane for the FP64 chain): (F_L + F_R)/2
+// and U_0 of rows 0..7 (slots 0..7, 16..23), the two candidate radiation rows
+// (8..15).
+__device__ __forceinline__ float* park_lane_f() {
+  __shared__ float park[kParkSlots * kParkLanes];
+  return park + threadIdx.x;
+}
+
+// The same block-diagonal split as pvm_face: radiation rows first, then the
+// fluid and magnetic rows with 8-wide states.
 template <int d>
 __device__ __forceinline__ void pvm_face_mixed(const float VL[NV], const float VR[NV], float tauL, float tauR,
                                                const Phys& K, float Fh[NV], int& fallback, int& c2p_its) {
   const float g1 = (float)K.g1;
-  float Fa[NV], U0[NV], Um[NV];
+  const float beta = 1.0f / fmaxf(fmaxf(tauL, tauR), 1.0f);
+  const float h = (float)K.eps32;
+  const float ih = 1.0f / h;
+  float* sh = park_lane_f();
   {
-    float UL[NV], UR[NV], FL[NV], FR[NV];
+    float Fa[4], U0[4], Um[4], w[4];
+    {
+      float FL[4], FR[4];
+      flux_rad<d, float>(&VL[8], FL);
+      flux_rad<d, float>(&VR[8], FR);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        U0[q] = VR[8 + q] - VL[8 + q];
+        Um[q] = 0.5f * (VL[8 + q] + VR[8 + q]);
+        Fa[q] = 0.5f * (FL[q] + FR[q]);
+        w[q] = U0[q];
+      }
+    }
+    if (K.M > 0) {
+      float Fm[4];
+      flux_rad<d, float>(Um, Fm);
+      for (int l = 0; l < K.M; ++l) {
+        float Ue[4], Fe[4], Y[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ue[q] = Um[q] + h * w[q];
+        flux_rad<d, float>(Ue, Fe);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ue[q] = Um[q] + (Fe[q] - Fm[q]);
+        flux_rad<d, float>(Ue, Fe);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Y[q] = (Fe[q] - Fm[q]) * ih;
+        const float cnext = (float)K.coef[K.M - 1 - l];
+        if (l == 0) {
+          const float ctop = (float)K.coef[K.M];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w[q] = ctop * Y[q] + cnext * U0[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w[q] = Y[q] + cnext * U0[q];
+        }
+      }
+    }
+    const float bq = (K.beta_mode == 2) ? 1.0f : beta;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sh[(8 + q) * kParkLanes] = Fa[q] - 0.5f * (bq * w[q]);
+      sh[(12 + q) * kParkLanes] = Fa[q] - 0.5f * (bq * U0[q]);
+    }
+  }
+  float Um[8], w[8];
+  {
+    float UL[8], UR[8], FL[8], FR[8];
     {
       AuxT<float> aL;
       prim_aux<float>(VL, g1, aL);
-      p2c<float>(VL, aL, UL);
-      flux<d, float>(VL, aL, FL);
+      p2c8<float>(VL, aL, UL);
+      flux_mhd<d, float>(VL, aL, FL);
     }
     {
       AuxT<float> aR;
       prim_aux<float>(VR, g1, aR);
-      p2c<float>(VR, aR, UR);
-      flux<d, float>(VR, aR, FR);
+      p2c8<float>(VR, aR, UR);
+      flux_mhd<d, float>(VR, aR, FR);
     }
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      U0[q] = UR[q] - UL[q];
+    for (int q = 0; q < 8; ++q) {
+      w[q] = UR[q] - UL[q];
+      sh[(16 + q) * kParkLanes] = w[q];  // U_0
       Um[q] = 0.5f * (UL[q] + UR[q]);
-      Fa[q] = 0.5f * (FL[q] + FR[q]);
+      sh[q * kParkLanes] = 0.5f * (FL[q] + FR[q]);
     }
   }
-  const float beta = 1.0f / fmaxf(fmaxf(tauL, tauR), 1.0f);
   fallback = 0;
   c2p_its = 0;
-  float w[NV];
   bool ok = true;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) w[q] = U0[q];
   if (K.M > 0) {
-    float Vm[NV], Fm[NV];
+    float Vm[8], Fm[8];
     double Zm = 0.0;
     int it = 0;
     {
-      double Ud[NV], Vd[NV];
+      double Ud[8], Vd[8];
 #pragma unroll
-      for (int q = 0; q < NV; ++q) Ud[q] = (double)Um[q];
-      if (c2p(Ud, K, 0.0, Vd, Zm, it) != 0) ok = false;
+      for (int q = 0; q < 8; ++q) Ud[q] = (double)Um[q];
+      if (c2p<8>(Ud, K, 0.0, Vd, Zm, it) != 0) ok = false;
 #pragma unroll
       for (int q = 0; q < 5; ++q) Vm[q] = (float)Vd[q];
 #pragma unroll
-      for (int q = 5; q < NV; ++q) Vm[q] = Um[q];
+      for (int q = 5; q < 8; ++q) Vm[q] = Um[q];
     }
     c2p_its += it;
     if (ok) {
       AuxT<float> am;
       prim_aux<float>(Vm, g1, am);
-      flux<d, float>(Vm, am, Fm);
+      flux_mhd<d, float>(Vm, am, Fm);
     }
-    const float h = (float)K.eps32;
-    const float ih = 1.0f / h;
     for (int l = 0; l < K.M && ok; ++l) {
-      float Y[NV];
+      float Y[8];
       {
-        float Ue[NV], Ve[NV], Fe[NV];
+        float Ue[8], Ve[8], Fe[8];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) Ue[q] = Um[q] + h * w[q];
+        for (int q = 0; q < 8; ++q) Ue[q] = Um[q] + h * w[q];
         if (!recover_near_mixed(Ue, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
         c2p_its += it;
         {
           AuxT<float> ae;
           prim_aux<float>(Ve, g1, ae);
-          flux<d, float>(Ve, ae, Fe);
+          flux_mhd<d, float>(Ve, ae, Fe);
         }
 #pragma unroll
-        for (int q = 0; q < NV; ++q) Ue[q] = Um[q] + (Fe[q] - Fm[q]);
+        for (int q = 0; q < 8; ++q) Ue[q] = Um[q] + (Fe[q] - Fm[q]);
         if (!recover_near_mixed(Ue, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
         c2p_its += it;
         {
           AuxT<float> at;
           prim_aux<float>(Ve, g1, at);
-          flux<d, float>(Ve, at, Fe);
+          flux_mhd<d, float>(Ve, at, Fe);
         }
 #pragma unroll
-        for (int q = 0; q < NV; ++q) Y[q] = (Fe[q] - Fm[q]) * ih;
+        for (int q = 0; q < 8; ++q) Y[q] = (Fe[q] - Fm[q]) * ih;
       }
       const float cnext = (float)K.coef[K.M - 1 - l];
       if (l == 0) {
         const float ctop = (float)K.coef[K.M];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) w[q] = ctop * Y[q] + cnext * U0[q];
+        for (int q = 0; q < 8; ++q) w[q] = ctop * Y[q] + cnext * sh[(16 + q) * kParkLanes];
       } else {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) w[q] = Y[q] + cnext * U0[q];
+        for (int q = 0; q < 8; ++q) w[q] = Y[q] + cnext * sh[(16 + q) * kParkLanes];
       }
     }
     if (!ok) {
       fallback = 1;
 #pragma unroll
-      for (int q = 0; q < NV; ++q) w[q] = U0[q];
+      for (int q = 0; q < 8; ++q) w[q] = sh[(16 + q) * kParkLanes];
     }
   }
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    const float bq = (K.beta_mode == 2 || (K.beta_mode == 1 && q < 8)) ? 1.0f : beta;
-    Fh[q] = Fa[q] - 0.5f * (bq * w[q]);
+  for (int q = 0; q < 8; ++q) {
+    const float bq = (K.beta_mode == 1 || K.beta_mode == 2) ? 1.0f : beta;
+    Fh[q] = sh[q * kParkLanes] - 0.5f * (bq * w[q]);
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Fh[8 + q] = ok ? sh[(8 + q) * kParkLanes] : sh[(12 + q) * kParkLanes];
 }
 
 // ---------------------------------------------------------------------------
