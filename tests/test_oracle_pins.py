@@ -8,6 +8,7 @@ of eqs. g0/gi).
 """
 from fractions import Fraction
 import math
+import os
 
 import numpy as np
 import pytest
@@ -84,13 +85,22 @@ def exact_internal_poly(k):
     return p
 
 
+def _printed_p3():
+    """alpha_0..alpha_4 from tests/golden (Section 3.2, explicit form of p_3)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pvm_int8_p3_coefficients.txt")
+    vals = [Fraction(ln.strip()) for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(vals) == 5
+    return vals
+
+
 def test_pvm_int8_coefficients_match_paper(oracle):
-    """Section 3.2: p_3(x) = x^2(x^2(x^2(a0 x^2 + a1) + a2) + a3) + a4 with
-    a = (-1/128, 3/32, -23/64, 31/32, 39/128) (printed values)."""
+    """Section 3.2: p_3(x) = x^2(x^2(x^2(a0 x^2 + a1) + a2) + a3) + a4 with the
+    printed alpha_0..alpha_4; the oracle's coefficients of x^0 .. x^8 are
+    alpha_4 .. alpha_0, and so is the exact expansion of eq. iterat."""
+    printed = list(reversed(_printed_p3()))          # x^0 .. x^8
     c = oracle.poly_coef(3)
-    printed = [39 / 128, 31 / 32, -23 / 64, 3 / 32, -1 / 128]   # x^0 .. x^8
-    assert list(c) == printed
-    assert [Fraction(x) for x in exact_internal_poly(3)] == [Fraction(x) for x in printed]
+    assert [Fraction(x) for x in c] == printed
+    assert [Fraction(x) for x in exact_internal_poly(3)] == printed
 
 
 @pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
