@@ -1037,115 +1037,14 @@ __device__ __forceinline__ int picard_run(const double Us[NV], const ImpIn& in, 
   return IMP_FAILED;
 }
 
-// Phase 1 in one piece (iters: Picard solves).
-__device__ __forceinline__ int implicit_picard(const double Us[NV], double h, double kap, double sig,
-                                               const Phys& K, double Un[NV], int& iters, bool& floored,
-                                               double X0[4], double& Z0, double Zg0) {
-  ImpIn in;
-  iters = 0;
-  if (!imp_prepare(Us, K, in, floored)) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) Un[q] = Us[q];
-    return IMP_FAILED;
-  }
-  PicardState S;
-  picard_start(in, Zg0, S);
-  const int st = picard_run(Us, in, h, kap, sig, K, S, 0x7fffffff, Zg0, Un, X0, Z0);
-  iters = S.it;
-  return st;
-}
-
-// Phase 2: Newton from X0 with warm start Z0. Returns IMP_DONE or
-// IMP_FAILED (then Un = Us).
-__device__ __forceinline__ int implicit_newton(const double Us[NV], double h, double kap, double sig,
-                                               const Phys& K, const double X0[4], double Z0, double Un[NV],
-                                               int& iters) {
-  ImpIn in;
-  iters = 0;
-  bool conv = false;
-  double X[4];
-  bool floored = false;
-  if (imp_prepare(Us, K, in, floored)) {
-    X[0] = X0[0]; X[1] = X0[1]; X[2] = X0[2]; X[3] = X0[3];
-    ImpSys sy;
-    double Zg = Z0, R[4];
-    int it = 0, c2p_it = 0;
-    if (imp_build(X, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sy, c2p_it)) {
-      Zg = sy.Z;
-      imp_residual(sy, X, R);
-      double sprev = 0.0;
-      for (int n = 0; n < K.imp_maxit; ++n) {
-        ++it;
-        double bd[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) bd[i] = sy.b[i] / sy.C[i][i];
-        const double sc = dmax(vmaxabs4(X), vmaxabs4(bd));
-        const double del = 1e-8 * sc;
-        double J[4][4];
-        bool okj = true;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (okj) {
-            double Xp[4] = {X[0], X[1], X[2], X[3]};
-            Xp[j] = Xp[j] + del;
-            ImpSys sp;
-            if (!imp_build(Xp, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sp, c2p_it)) {
-              okj = false;
-            } else {
-              double Rp[4];
-              imp_residual(sp, Xp, Rp);
-#pragma unroll
-              for (int i = 0; i < 4; ++i) J[i][j] = (Rp[i] - R[i]) / del;
-            }
-          }
-        }
-        if (!okj) break;
-        double nR[4] = {-R[0], -R[1], -R[2], -R[3]}, dX[4];
-        if (!solve4(J, nR, dX)) break;
-        const double rn = vmaxabs4(R);
-        const double dn = vmaxabs4(dX);
-        double lam = 1.0;
-        bool acc = false;
-        double Xt[4], Rt[4];
-        ImpSys st;
-        for (int ls = 0; ls < 12; ++ls) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) Xt[i] = X[i] + lam * dX[i];
-          if (Xt[0] > 0.0 && imp_build(Xt, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, st, c2p_it)) {
-            imp_residual(st, Xt, Rt);
-            if (vmaxabs4(Rt) < rn || lam * dn <= 1e-10 * sc) { acc = true; break; }
-          }
-          lam = 0.5 * lam;
-        }
-        if (!acc) break;
-        double stp[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) { stp[i] = Xt[i] - X[i]; X[i] = Xt[i]; R[i] = Rt[i]; }
-        sy = st;
-        Zg = st.Z;
-        const double sn = vmaxabs4(stp);
-        if (sn <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
-        // at the rounding floor: a tiny step that no longer shrinks
-        if (n > 0 && sn <= 1e-9 * sc && sn >= sprev) { conv = true; break; }
-        sprev = sn;
-      }
-    }
-    iters = it;
-  }
-  if (!conv) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) Un[q] = Us[q];
-    return IMP_FAILED;
-  }
-  imp_finish(X, Us, in, Un);
-  return IMP_DONE;
-}
-
-// Phase 2 on a quad of 4 lanes (lanes 4k..4k+3 of a wave, all on the same
-// cell and all active together): lane j builds Jacobian column j and tries
-// line-search step 2^-(j + 4r) in round r; the quad then shares the results.
-// The selections equal those of implicit_newton (first acceptable step in
-// the order 1, 1/2, 1/4, ...), so the result is the same bit for bit.
+// Phase 2, Newton on C(X) X - b(X) from X0 (warm start Z0), on a quad of 4
+// lanes (lanes 4k..4k+3 of a wave, all on the same cell and all active
+// together): lane j builds Jacobian column j (forward difference, step
+// 1e-8 max(|X|, |b_i/C_ii|)) and tries line-search step 2^-(j + 4r) in round
+// r; the quad then shares the results. The selections are those of one lane
+// doing it all in order (columns 0..3, stopping at the first that fails;
+// the first acceptable step of 1, 1/2, 1/4, ...), so the result is the same
+// bit for bit. Returns IMP_DONE or IMP_FAILED (then Un = Us).
 __device__ __forceinline__ double quad_get(double v, int base, int k) { return __shfl(v, base + k, 64); }
 
 __device__ __forceinline__ int implicit_newton_quad(const double Us[NV], double h, double kap, double sig,
