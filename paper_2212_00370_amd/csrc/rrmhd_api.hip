@@ -1265,15 +1265,17 @@ constexpr int kMaxTimed = 8192;
 int prof_begin(rrmhd_ctx* c, int kind, long long units) {
   if (!((c->prof >> kind) & 1) || c->ev_used >= kMaxTimed) return -1;
   if ((c->prof_seen[kind]++) % c->prof_stride != 0) return -1;
-  const int i = c->ev_used++;
+  const int i = c->ev_used;
+  if (hipEventRecord(c->ev[2 * i], c->stream) != hipSuccess) return -1;  // launch left untimed
+  c->ev_used = i + 1;
   c->ev_kind[i] = kind;
   c->ev_units[i] = units;
-  hipEventRecord(c->ev[2 * i], c->stream);
   return i;
 }
 
 void prof_end(rrmhd_ctx* c, int i) {
-  if (i >= 0) hipEventRecord(c->ev[2 * i + 1], c->stream);
+  // a pair whose stop event could not be recorded is left out of the totals
+  if (i >= 0 && hipEventRecord(c->ev[2 * i + 1], c->stream) != hipSuccess) c->ev_kind[i] = -1;
 }
 
 rrmhd_status launch_ok() {
@@ -1519,7 +1521,9 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   c->ev_used = 0;
   {
     int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+      ncu = 256;
     c->newton_blocks = (unsigned int)(4 * ncu * (256 / kBlock));  // kBlock/4 cells (4 lanes each) per block
   }
   if (hipHostMalloc(&c->host, sizeof(DevReport) + sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -1529,7 +1533,7 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   k_report_reset<<<64, kBlock, 0, c->stream>>>(c->rep, c->blkmax, 2 * L.nblkmax);
   if (launch_ok() == RRMHD_OK) k_zero_u32<<<64, kBlock, 0, c->stream>>>(c->cost, L.npartial);
   if (launch_ok() != RRMHD_OK) {
-    hipHostFree(c->host);
+    (void)hipHostFree(c->host);
     delete c;
     return RRMHD_E_DEVICE;
   }
@@ -1726,11 +1730,17 @@ rrmhd_status rrmhd_report_sync(rrmhd_ctx* c, rrmhd_report* out) {
 rrmhd_status rrmhd_profile_enable(rrmhd_ctx* c, int enable) {
   if (!c || enable < 0 || enable >= (1 << RRMHD_K_COUNT)) return RRMHD_E_INVALID;
   if (enable && c->ev.empty()) {
-    c->ev.resize(2 * kMaxTimed);
-    c->ev_kind.resize(kMaxTimed);
-    c->ev_units.resize(kMaxTimed);
-    for (auto& e : c->ev)
-      if (hipEventCreate(&e) != hipSuccess) return RRMHD_E_DEVICE;
+    // all events or none: a partial set would be taken as created next time
+    std::vector<hipEvent_t> ev(2 * kMaxTimed, nullptr);
+    for (size_t n = 0; n < ev.size(); ++n) {
+      if (hipEventCreate(&ev[n]) != hipSuccess) {
+        for (size_t m = 0; m < n; ++m) (void)hipEventDestroy(ev[m]);
+        return RRMHD_E_DEVICE;
+      }
+    }
+    c->ev.swap(ev);
+    c->ev_kind.assign(kMaxTimed, -1);
+    c->ev_units.assign(kMaxTimed, 0);
   }
   c->prof = enable;
   if (enable) {
@@ -1767,9 +1777,10 @@ rrmhd_status rrmhd_profile_read(rrmhd_ctx* c, int k, double* total_ms, long long
 
 void rrmhd_destroy(rrmhd_ctx* c) {
   if (!c) return;
-  hipStreamSynchronize(c->stream);
-  for (auto& e : c->ev) hipEventDestroy(e);
-  if (c->host) hipHostFree(c->host);
+  // teardown: nothing to report an error to; release what can be released
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev) (void)hipEventDestroy(e);
+  if (c->host) (void)hipHostFree(c->host);
   delete c;
 }
 
@@ -1801,7 +1812,9 @@ rrmhd_status rrmhd_batch_init(rrmhd_batch** out, int max_sims, void* workspace, 
   }
   ok = ok && hipHostMalloc((void**)&b->hsmax, sizeof(double) * max_sims, hipHostMallocDefault) == hipSuccess;
   int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+    ncu = 256;
   b->newton_cap = (unsigned int)(4 * ncu * (256 / kBlock));
   if (!ok) {
     rrmhd_batch_destroy(b);
@@ -1872,12 +1885,13 @@ rrmhd_status rrmhd_step_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, d
 
 void rrmhd_batch_destroy(rrmhd_batch* b) {
   if (!b) return;
-  hipStreamSynchronize(b->stream);
+  // teardown: nothing to report an error to; release what can be released
+  (void)hipStreamSynchronize(b->stream);
   for (int k = 0; k < 2; ++k) {
-    if (b->host[k]) hipHostFree(b->host[k]);
-    if (b->ev[k]) hipEventDestroy(b->ev[k]);
+    if (b->host[k]) (void)hipHostFree(b->host[k]);
+    if (b->ev[k]) (void)hipEventDestroy(b->ev[k]);
   }
-  if (b->hsmax) hipHostFree(b->hsmax);
+  if (b->hsmax) (void)hipHostFree(b->hsmax);
   delete b;
 }
 
