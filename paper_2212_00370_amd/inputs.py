@@ -17,6 +17,8 @@ Workloads (shapes and value ranges of the paper's test problems, Section 4):
   * ``beam_3d``     -- relativistic magnetised beam (Lorentz factor 7) injected
     through a nozzle in the z = 0 face into an optically thick ambient medium,
     outflow elsewhere.
+  * ``alfven_1d``   -- the large-amplitude circularly polarised Alfven wave of
+    Section 4.1 (no radiation coupling), periodic on [0, 2 pi], gamma = 4/3.
   * ``serving_mix`` -- request mixes for the serving loop.
   * ``random_prims`` -- i.i.d. admissible states for unit-level checks.
 """
@@ -134,6 +136,36 @@ def riemann_1d(seed: int, n: int = 400) -> Problem:
     return Problem(name=f"riemann1d_s{seed}_n{n}", shape=(n,), dx=(dx,), x0=(0.0,), V=V, kappa=kap,
                    sigma=sig, gamma=5.0 / 3.0, a_rad=st["a_rad"], bc_lo=(OUTFLOW,) * 3,
                    bc_hi=(OUTFLOW,) * 3, cfl=0.4, t_end=0.4)
+
+
+def alfven_1d(n: int) -> Problem:
+    """Large-amplitude circularly polarised Alfven wave (Section 4.1, after
+    Del Zanna et al.): rho_0 = 1, h_0 = 5 (p_0 = 1 for gamma = 4/3), B_0 = 1,
+    amplitude A = sqrt(2 / (7 + 3 sqrt 5)), one wavelength on [0, 2 pi],
+    v_y = -A cos x, v_z = -A sin x, B_y = -B_0 v_y / v_a, B_z = -B_0 v_z / v_a
+    at cell centres, periodic. The paper's run: PVM-int-8, RK3, CFL 0.3, one
+    period T = 2 pi / v_a (``t_end``). Radiation is a passive uniform field
+    (E_r = 1e-8, F_r = 0, kappa = sigma = 0)."""
+    gamma = 4.0 / 3.0
+    rho0, h0, B0 = 1.0, 5.0, 1.0
+    p0 = (h0 - 1.0) * rho0 * (gamma - 1.0) / gamma
+    amp = math.sqrt(2.0 / (7.0 + 3.0 * math.sqrt(5.0)))
+    va = math.sqrt(B0 ** 2 * (1.0 - amp ** 2) / (rho0 * h0 + B0 ** 2 * (1.0 - amp ** 2)))
+    length = 2.0 * math.pi
+    dx = length / n
+    x = (np.arange(n) + 0.5) * dx
+    V = np.zeros((NV, n))
+    V[0] = rho0
+    V[2] = -amp * np.cos(2.0 * math.pi * x / length)
+    V[3] = -amp * np.sin(2.0 * math.pi * x / length)
+    V[4] = p0
+    V[5] = B0
+    V[6] = -B0 * V[2] / va
+    V[7] = -B0 * V[3] / va
+    V[8] = 1e-8
+    return Problem(name=f"alfven1d_n{n}", shape=(n,), dx=(dx,), x0=(0.0,), V=V, kappa=np.zeros(n),
+                   sigma=np.zeros(n), gamma=gamma, a_rad=0.0, bc_lo=(PERIODIC,) * 3, bc_hi=(PERIODIC,) * 3,
+                   cfl=0.3, t_end=length / va, extra={"v_a": va, "amplitude": amp})
 
 
 def blast_2d(seed: int = 0, nx: int = 512, ny: int | None = None, steps: int = 200,

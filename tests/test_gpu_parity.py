@@ -3,6 +3,8 @@ identical seeded inputs. FP64 gate: <= 1e-12 relative per step (the library
 and the oracle evaluate every expression in the same order, so the expected
 difference is zero; the tests also record whether results are bit-identical).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -195,6 +197,37 @@ def test_step_2d_failure_paths(R, oracle, torch_mod):
     worst, bit = one_step_compare(R, oracle, torch_mod, I.blast_2d(0, 64, 40), steps=3, reports=reps, c2p_maxit=1)
     assert bit
     assert all(r.pvm_fallback > 1000 and r.c2p_fail > 0 and r.imp_fail > 0 for r in reps)
+
+
+def test_alfven_wave_period_matches_oracle_and_table4(R, oracle, torch_mod):
+    """Section 4.1: the circularly polarised Alfven wave at N = 64, PVM-int-8,
+    MinMod, RK3, CFL 0.3, for one full period (366 steps, the last clipped to
+    T). The GPU state equals the oracle's bit for bit, and its L1(v_z) is the
+    printed Table 4 value (tests/golden) within 3 %."""
+    torch = torch_mod
+    P = I.alfven_1d(64)
+    p, op, g, og, s, U, opac = make_case(R, oracle, torch, P, rk_order=3, recon=R.RECON_MINMOD)
+    Ud = dev(torch, U)
+    Uo = U
+    t, n = 0.0, 0
+    while t < P.t_end * (1 - 1e-14):
+        sm = s.max_speed(Ud)
+        assert sm == oracle.max_speed(og, Uo, op)[0]
+        h = min(P.cfl * P.dx[0] / sm, P.t_end - t)
+        s.step(Ud, h, opac)
+        Uo, st, _ = oracle.step(og, Uo, h, P.kappa, P.sigma, op)
+        t += h
+        n += 1
+    rep = s.report()
+    Ug = host(Ud)
+    s.close()
+    assert rep["c2p_fail"] == 0 and rep["imp_fail"] == 0 and rep["pvm_fallback"] == 0
+    assert np.array_equal(Ug, Uo), relerr(Ug, Uo)
+    V, _, st, _ = oracle.c2p(Ug, op)
+    l1 = float(np.mean(np.abs(V[3] - P.V[3])))
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "alfven_pvm_int8_table4.txt")
+    printed = {int(r.split()[0]): float(r.split()[2]) for r in open(path) if r.strip() and not r.startswith("#")}
+    assert l1 == pytest.approx(printed[64], rel=3e-2), (n, l1)
 
 
 def test_step_2d_full_size(R, oracle, torch_mod):
