@@ -167,3 +167,50 @@ def test_alfven_wave_reproduces_table4(oracle, recon):
         assert all(1.8 < o < 2.1 for o in orders), orders
     else:
         assert all(0.45 < o < 0.85 for o in orders), orders
+
+
+def test_alfven_error_decreases_with_pvm_order(oracle):
+    """eq. iterat: p_k approximates |x| from above and decreases with k, so the
+    numerical viscosity, and the Alfven-wave error with it, falls with k; the
+    degree-16 member stays close to PVM-int-8 (Section 5 reports the two alike)."""
+    P = I.alfven_1d(64)
+    errs = []
+    for k in (1, 2, 3, 4):
+        par = oracle.params(gamma=P.gamma, a_rad=P.a_rad, rk_order=3, recon=1, pvm_k=k)
+        g = oracle.make_grid(P.shape, P.dx, bc_lo=P.bc_lo, bc_hi=P.bc_hi)
+        U, _, _ = run(oracle, g, oracle.p2c(P.V, par), par, 0.0, 0.0, P.cfl, t_end=P.t_end, dx=P.dx)
+        V, _, _, _ = oracle.c2p(U, par)
+        errs.append(float(np.mean(np.abs(V[3] - P.V[3]))))
+    assert all(a > b for a, b in zip(errs, errs[1:])), errs
+    assert abs(errs[3] - errs[2]) < 0.1 * errs[2], errs
+
+
+def _swap_xy(V, nx, ny):
+    """[q, j nx + i] -> [q', i ny + j] with the x and y components exchanged."""
+    W = V.reshape(V.shape[0], ny, nx).transpose(0, 2, 1).reshape(V.shape[0], -1)
+    return np.ascontiguousarray(W[[0, 2, 1, 3, 4, 6, 5, 7, 8, 10, 9, 11]])
+
+
+def test_xy_transpose_symmetry_bitwise(oracle):
+    """Exchanging x and y (grid, cell sizes and vector components) commutes with
+    the explicit scheme bit for bit: every sum over components is written as
+    (x + y) + z and every per-direction operation is generic in d. A wrong
+    direction index or a transposed operand breaks it. The opacities are zero
+    here: the implicit 4x4 elimination of a coupled cell orders its rows
+    E, F_x, F_y, F_z, which the exchange permutes."""
+    P = I.blast_2d(0, 48, 40)
+    nx, ny = P.shape
+    par = oracle.params(gamma=P.gamma, a_rad=P.a_rad)
+    g = oracle.make_grid((nx, ny), P.dx, P.bc_lo, P.bc_hi)
+    gt = oracle.make_grid((ny, nx), (P.dx[1], P.dx[0]), P.bc_lo, P.bc_hi)
+    U = oracle.p2c(P.V, par)
+    Ut = oracle.p2c(_swap_xy(P.V, nx, ny), par)
+    assert np.array_equal(Ut, _swap_xy(U, nx, ny))
+    for _ in range(3):
+        s, _ = oracle.max_speed(g, U, par)
+        assert oracle.max_speed(gt, Ut, par)[0] == s
+        dt = P.cfl * min(P.dx) / s
+        U, st, _ = oracle.step(g, U, dt, 0.0, 0.0, par)
+        Ut, st2, _ = oracle.step(gt, Ut, dt, 0.0, 0.0, par)
+        assert st == 0 and st2 == 0
+        assert np.array_equal(Ut, _swap_xy(U, nx, ny))
