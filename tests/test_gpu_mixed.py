@@ -77,3 +77,35 @@ def test_mixed_riemann_1d(R, oracle, seed):
     assert rep["c2p_fail"] == 0 and rep["imp_fail"] == 0
     assert out[1]["rho"] < 1e-4
     assert out[60]["rho"] < 1e-2
+
+
+def test_mixed_alfven_wave_matches_table4(R, oracle):
+    """Section 4.1, Table 4 (tests/golden): the mixed-precision path on the
+    circularly polarised Alfven wave (N = 64, MinMod, RK3, CFL 0.3, one
+    period) gives the printed L1(v_z) within 5 %, as the FP64 path does within
+    3 %."""
+    import os
+    import torch
+    P = I.alfven_1d(64)
+    p = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=R.MIXED, rk_order=3,
+                               recon=R.RECON_MINMOD)
+    op = oracle.params(gamma=P.gamma, a_rad=P.a_rad)
+    g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
+    s = R.Solver(g, p)
+    Ud = torch.from_numpy(oracle.p2c(P.V, op)).to("cuda:0")
+    opac = R.make_opacities(torch.from_numpy(P.kappa).to("cuda:0"), torch.from_numpy(P.sigma).to("cuda:0"))
+    t = 0.0
+    while t < P.t_end * (1 - 1e-14):
+        h = min(P.cfl * P.dx[0] / s.max_speed(Ud), P.t_end - t)
+        s.step(Ud, h, opac)
+        t += h
+    rep = s.report()
+    U = Ud.cpu().numpy()
+    s.close()
+    assert rep["c2p_fail"] == 0 and rep["imp_fail"] == 0 and rep["pvm_fallback"] == 0
+    V, _, st, _ = oracle.c2p(U, op)
+    assert np.all(st == 0)
+    l1 = float(np.mean(np.abs(V[3] - P.V[3])))
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "alfven_pvm_int8_table4.txt")
+    printed = {int(r.split()[0]): float(r.split()[2]) for r in open(path) if r.strip() and not r.startswith("#")}
+    assert l1 == pytest.approx(printed[64], rel=5e-2), l1
