@@ -1,6 +1,7 @@
 // Plain FP64 CPU oracle for one IMEX step of relativistic radiation MHD under
-// the gray M1 closure, with PLM MinMod reconstruction and the Jacobian-free
-// PVM-int face flux (Lopez-Miralles, Marti & Perucho, CPC, arXiv 2212.00370).
+// the gray M1 closure, with PLM reconstruction (MinMod, MC, VanLeer) and the
+// Jacobian-free PVM-int face flux (Lopez-Miralles, Marti & Perucho, CPC,
+// arXiv 2212.00370).
 //
 // TEST INFRASTRUCTURE ONLY. This file is the slow, obviously-correct
 // reference that the GPU library is checked against. Only the test suite, the
@@ -83,7 +84,7 @@ struct OPar {
   double p_floor;
   int pvm_k;         // degree index k of the internal polynomial, deg = 2^k
   int beta_mode;     // 0: beta scales all 12 components; 1: radiation rows only; 2: beta = 1
-  int recon;         // 0: Godunov (piecewise constant); 1: PLM MinMod
+  int recon;         // 0: Godunov (piecewise constant); PLM with 1: MinMod, 2: MC, 3: VanLeer
   int rk_order;      // 2: SSP-RK2 analogue; 3: the paper's IMEX RK3
   int c2p_maxit;
   int imp_maxit;
@@ -446,21 +447,49 @@ static void pvm_face(const real VL[NV], const real VR[NV], real tauL, real tauR,
 }
 
 // ---------------------------------------------------------------------------
-// PLM reconstruction (Section 3.2, reconstruction paragraph).
-// minmod(a, b) = a or b, whichever is smaller in magnitude, if they share a
-// sign, else 0. A cell whose reconstructed face values give |v|^2 >= 1 falls
-// back to zeroth order on both of its faces. After reconstruction the face
-// radiation flux is limited to |F_r| <= E_r by rescaling.
+// PLM reconstruction (Section 3.2, reconstruction paragraph: MinMod, MC or
+// VanLeer slopes). With a = V_i - V_{i-1} and b = V_{i+1} - V_i, every limiter
+// gives 0 unless a and b share a sign, and then
+//   MinMod   (Roe):        a or b, whichever is smaller in magnitude;
+//   MC       (van Leer 77): the smallest in magnitude of 2a, 2b, (a + b)/2;
+//   VanLeer  (van Leer 74): the harmonic form 2ab / (a + b).
+// A cell whose reconstructed face values give |v|^2 >= 1 falls back to zeroth
+// order on both of its faces. After reconstruction the face radiation flux is
+// limited to |F_r| <= E_r by rescaling.
+static inline bool same_sign(real a, real b) {
+  return (a > real(0.0) && b > real(0.0)) || (a < real(0.0) && b < real(0.0));
+}
+
 static inline real minmod(real a, real b) {
-  if ((a > real(0.0) && b > real(0.0)) || (a < real(0.0) && b < real(0.0)))
-    return (rabs(a) < rabs(b)) ? a : b;
+  if (same_sign(a, b)) return (rabs(a) < rabs(b)) ? a : b;
   return real(0.0);
+}
+
+static inline real mc_slope(real a, real b) {
+  if (!same_sign(a, b)) return real(0.0);
+  const real ta = real(2.0) * a, tb = real(2.0) * b, c = real(0.5) * (a + b);
+  const real m = (rabs(ta) < rabs(tb)) ? ta : tb;
+  return (rabs(c) < rabs(m)) ? c : m;
+}
+
+static inline real vanleer_slope(real a, real b) {
+  if (!same_sign(a, b)) return real(0.0);
+  return (real(2.0) * (a * b)) / (a + b);
+}
+
+static inline real limited_slope(int recon, real a, real b) {
+  switch (recon) {
+    case 1: return minmod(a, b);
+    case 2: return mc_slope(a, b);
+    case 3: return vanleer_slope(a, b);
+    default: return real(0.0);
+  }
 }
 
 static void cell_slopes(const real Vm[NV], const real Vc[NV], const real Vp[NV], int recon,
                         real s[NV]) {
-  for (int q = 0; q < NV; ++q) s[q] = (recon == 1) ? minmod(Vc[q] - Vm[q], Vp[q] - Vc[q]) : real(0.0);
-  if (recon == 1) {
+  for (int q = 0; q < NV; ++q) s[q] = limited_slope(recon, Vc[q] - Vm[q], Vp[q] - Vc[q]);
+  if (recon != 0) {
     real lo[3], hi[3];
     for (int j = 0; j < 3; ++j) { lo[j] = Vc[1 + j] - 0.5 * s[1 + j]; hi[j] = Vc[1 + j] + 0.5 * s[1 + j]; }
     const real v2lo = (lo[0] * lo[0] + lo[1] * lo[1]) + lo[2] * lo[2];

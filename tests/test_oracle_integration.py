@@ -132,23 +132,30 @@ def test_diffusion_limit_matches_heat_kernel(oracle, sigma):
 
 
 def _table4():
-    """Section 4.1, Table 4 rows (tests/golden): N -> (Godunov, MinMod)."""
+    """Section 4.1, Table 4 rows (tests/golden): N -> (Godunov, MinMod, MC, VanLeer)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "alfven_pvm_int8_table4.txt")
     rows = {}
     for ln in open(path):
         if ln.strip() and not ln.startswith("#"):
-            n, god, mm = ln.split()
-            rows[int(n)] = (float(god), float(mm))
+            n, *errs = ln.split()
+            rows[int(n)] = tuple(float(e) for e in errs)
     return rows
 
 
-@pytest.mark.parametrize("recon", [0, 1])
+# relative tolerance per reconstruction (Godunov, MinMod, MC, VanLeer): the
+# paper's time-step sequence and last-step clipping are not printed, which
+# moves the second-order rows by a few per cent
+_TABLE4_REL = (1e-3, 3e-2, 5e-2, 5e-2)
+
+
+@pytest.mark.parametrize("recon", [0, 1, 2, 3])
 def test_alfven_wave_reproduces_table4(oracle, recon):
     """Section 4.1: the circularly polarised Alfven wave, PVM-int-8 with RK3
     and CFL 0.3, run for one period; L1(v_z) against the initial state must
-    reproduce the printed Table 4 row (Godunov to 0.1 %, MinMod to 3 %: the
-    paper's time step and last-step clipping are not printed), with the
-    observed orders ~1 and ~2."""
+    reproduce the printed Table 4 row of each reconstruction (Section 3.2:
+    Godunov, MinMod, MC, VanLeer), with the observed orders ~1 and ~2. The
+    PLM rows differ from one another by 30 % or more at N = 16..64, so a
+    wrong limiter fails its row."""
     table = _table4()
     errs = {}
     for n in (16, 32, 64, 128):
@@ -160,11 +167,11 @@ def test_alfven_wave_reproduces_table4(oracle, recon):
         V, _, st, _ = oracle.c2p(U, par)
         assert np.all(st == 0)
         errs[n] = float(np.mean(np.abs(V[3] - P.V[3])))
-        printed = table[n][0 if recon == 0 else 1]
-        assert errs[n] == pytest.approx(printed, rel=1e-3 if recon == 0 else 3e-2), (n, errs[n], printed)
+        printed = table[n][recon]
+        assert errs[n] == pytest.approx(printed, rel=_TABLE4_REL[recon]), (n, errs[n], printed)
     orders = [math.log2(errs[n] / errs[2 * n]) for n in (32, 64)]
-    if recon == 1:
-        assert all(1.8 < o < 2.1 for o in orders), orders
+    if recon != 0:
+        assert all(1.8 < o < 2.45 for o in orders), orders
     else:
         assert all(0.45 < o < 0.85 for o in orders), orders
 
