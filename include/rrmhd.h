@@ -46,7 +46,9 @@ typedef enum {
 } rrmhd_status;
 
 typedef enum { RRMHD_BC_PERIODIC = 0, RRMHD_BC_OUTFLOW = 1, RRMHD_BC_INFLOW = 2 } rrmhd_bc;
-enum { RRMHD_RECON_GODUNOV = 0, RRMHD_RECON_MINMOD = 1 };
+/* Reconstruction (Section 3.2): piecewise constant, or PLM with the MinMod, MC
+ * or VanLeer slope limiter. */
+enum { RRMHD_RECON_GODUNOV = 0, RRMHD_RECON_MINMOD = 1, RRMHD_RECON_MC = 2, RRMHD_RECON_VANLEER = 3 };
 enum { RRMHD_BETA_ALL = 0, RRMHD_BETA_RAD_ONLY = 1, RRMHD_BETA_OFF = 2 };
 enum { RRMHD_IMP_PICARD_NEWTON = 0, RRMHD_IMP_NEWTON = 1, RRMHD_IMP_PICARD = 2 };
 /* Precision of the explicit step. RRMHD_FP64: everything in binary64.

@@ -3,7 +3,7 @@
 // One IMEX step (Section 3.1 of Lopez-Miralles, Marti & Perucho, CPC,
 // arXiv 2212.00370) is, per Runge-Kutta stage:
 //   k_prims   : cell primitive recovery of the stage state -> V, D(kappa+sigma)
-//   k_faces<d>: per face, PLM MinMod + PVM-int flux (Section 3.2) -> F^_d
+//   k_faces   : per face of every direction, PLM + PVM-int flux (Section 3.2) -> F^_d
 //   k_update  : U* = a0 U^(0) + a1 U^(s) - c dt sum_d dF^_d/dx_d (eq. explicit)
 //               followed by the per-cell implicit source solve (Section 3.3)
 // All kernels read and write structure-of-arrays float64 planes in HBM; one
@@ -323,9 +323,11 @@ struct FaceArgs {
   double dx[3];
 };
 
-// One face of direction d: PLM MinMod on the 4-cell stencil, |F_r| <= E_r,
-// then the PVM-int flux with beta from the two adjacent cells.
-template <int d>
+// One face of direction d: PLM on the 4-cell stencil, |F_r| <= E_r,
+// then the PVM-int flux with beta from the two adjacent cells. REC >= 0 fixes
+// the limiter at compile time (the launch picks the MinMod copy when K.recon
+// is MinMod); REC < 0 reads K.recon.
+template <int d, int REC>
 __device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, long long f, const Phys& K,
                                           unsigned long long& fb, unsigned int& its) {
   int fn0 = G.n[0], fn1 = G.n[1];
@@ -353,8 +355,8 @@ __device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, l
     tp[s] = A.taup[m];
   }
   double sa[NV], sb[NV];
-  rr::cell_slopes(Vs[0], Vs[1], Vs[2], K.recon, sa);
-  rr::cell_slopes(Vs[1], Vs[2], Vs[3], K.recon, sb);
+  rr::cell_slopes<double, REC>(Vs[0], Vs[1], Vs[2], K.recon, sa);
+  rr::cell_slopes<double, REC>(Vs[1], Vs[2], Vs[3], K.recon, sb);
   double VL[NV], VR[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) { VL[q] = Vs[1][q] + 0.5 * sa[q]; VR[q] = Vs[2][q] - 0.5 * sb[q]; }
@@ -374,7 +376,7 @@ __device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, l
 
 // Mixed precision: the same stencil in FP32 (FP64 recoveries inside), FP32
 // fluxes out.
-template <int d>
+template <int d, int REC>
 __device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs& A, long long f, const Phys& K,
                                                 unsigned long long& fb, unsigned int& its) {
   int fn0 = G.n[0], fn1 = G.n[1];
@@ -402,8 +404,8 @@ __device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs
     tp[s] = (float)A.taup[m];
   }
   float sa[NV], sb[NV];
-  rr::cell_slopes<float>(Vs[0], Vs[1], Vs[2], K.recon, sa);
-  rr::cell_slopes<float>(Vs[1], Vs[2], Vs[3], K.recon, sb);
+  rr::cell_slopes<float, REC>(Vs[0], Vs[1], Vs[2], K.recon, sa);
+  rr::cell_slopes<float, REC>(Vs[1], Vs[2], Vs[3], K.recon, sb);
   float VL[NV], VR[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) { VL[q] = Vs[1][q] + 0.5f * sa[q]; VR[q] = Vs[2][q] - 0.5f * sb[q]; }
@@ -424,7 +426,7 @@ __device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs
 // Face fluxes of all directions in one launch: blocks [0, nb0) take x faces,
 // the next nb1 blocks y faces, then z. The direction is uniform per block.
 // MIXED selects the mixed-precision stencil (FP32 fluxes out).
-template <bool MIXED>
+template <bool MIXED, int REC>
 __device__ __forceinline__ void faces_block(long long lb, const GridDev& G, const FaceArgs& A, const Phys& K,
                                             DevReport* rep, unsigned int* blkmax) {
   long long b = lb;
@@ -439,13 +441,13 @@ __device__ __forceinline__ void faces_block(long long lb, const GridDev& G, cons
   unsigned int its = 0;
   if (f < A.nf[d]) {
     if constexpr (!MIXED) {
-      if (d == 0) face_body<0>(G, A, f, K, fb, its);
-      else if (d == 1) face_body<1>(G, A, f, K, fb, its);
-      else face_body<2>(G, A, f, K, fb, its);
+      if (d == 0) face_body<0, REC>(G, A, f, K, fb, its);
+      else if (d == 1) face_body<1, REC>(G, A, f, K, fb, its);
+      else face_body<2, REC>(G, A, f, K, fb, its);
     } else {
-      if (d == 0) face_body_mixed<0>(G, A, f, K, fb, its);
-      else if (d == 1) face_body_mixed<1>(G, A, f, K, fb, its);
-      else face_body_mixed<2>(G, A, f, K, fb, its);
+      if (d == 0) face_body_mixed<0, REC>(G, A, f, K, fb, its);
+      else if (d == 1) face_body_mixed<1, REC>(G, A, f, K, fb, its);
+      else face_body_mixed<2, REC>(G, A, f, K, fb, its);
     }
   }
   report_add(rep, blkmax, lb, 0, fb, 0, 0, ULLONG_MAX, its, 0);
@@ -528,7 +530,7 @@ __device__ __forceinline__ void order_block(const BlockOrder& O) {
 // blocks do the step's time step (dt_block, with R.partial set) and the next
 // update pass's block order (order_block, with O.cost set); the rest take the
 // faces. The update pass, which reads both, runs after this launch.
-template <typename FT>
+template <typename FT, int REC>
 __global__ void __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(sizeof(FT) == sizeof(double) ? RRMHD_FACES_WAVES : RRMHD_FACES_WAVES_MIXED)))
 k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, unsigned long long* wreset,
@@ -550,7 +552,7 @@ k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, uns
     }
     b -= 1;
   }
-  faces_block<sizeof(FT) == sizeof(float)>(b, G, A, K, rep, blkmax);
+  faces_block<sizeof(FT) == sizeof(float), REC>(b, G, A, K, rep, blkmax);
 }
 
 struct StageArgs {
@@ -980,8 +982,8 @@ k_faces_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, int 
   const SimDesc& D = T[s];
   // the work-list counter of this simulation's update pass that follows
   if (blockIdx.x == o[s] && threadIdx.x == 0) *D.wcount = 0;
-  if (D.mixed) faces_block<true>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
-  else faces_block<false>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
+  if (D.mixed) faces_block<true, -1>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
+  else faces_block<false, -1>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
 }
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
@@ -1102,7 +1104,7 @@ bool params_valid(const rrmhd_params* p) {
   if (!(p->pvm_eps > 0.0)) return false;
   if (p->pvm_k < 0 || p->pvm_k > 4) return false;
   if (p->beta_mode < 0 || p->beta_mode > 2) return false;
-  if (p->recon < 0 || p->recon > 1) return false;
+  if (p->recon < 0 || p->recon > 3) return false;
   if (p->rk_order != 2 && p->rk_order != 3) return false;
   if (p->c2p_maxit < 1 || p->imp_maxit < 1 || p->imp_picard_it < 0) return false;
   if (p->imp_method < 0 || p->imp_method > 2) return false;
@@ -1335,10 +1337,14 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   O.nb = L.npartial;
   const unsigned int nlaunch = (unsigned int)(nbt + (R.partial ? 1 : 0) + 1);
   pe = prof_begin(c, RRMHD_K_FACES, A.nf[0] + A.nf[1] + A.nf[2]);
-  if (c->par.precision == RRMHD_MIXED)
-    k_faces<float><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
-  else
-    k_faces<double><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+  const bool mm = c->K.recon == RRMHD_RECON_MINMOD;
+  if (c->par.precision == RRMHD_MIXED) {
+    if (mm) k_faces<float, 1><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    else k_faces<float, -1><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+  } else {
+    if (mm) k_faces<double, 1><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    else k_faces<double, -1><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+  }
   prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   return RRMHD_OK;

@@ -347,19 +347,37 @@ __device__ __forceinline__ bool recover_near(const double U[NU], const double Um
 }
 
 // ---------------------------------------------------------------------------
-// PLM MinMod with the Godunov fallback for |v|^2 >= 1 and the |F_r| <= E_r
-// limit (Section 3.2, reconstruction).
+// PLM with the Godunov fallback for |v|^2 >= 1 and the |F_r| <= E_r limit
+// (Section 3.2, reconstruction). With a = V_i - V_{i-1}, b = V_{i+1} - V_i
+// the slope is 0 unless a and b share a sign, else MinMod: the smaller of a, b
+// in magnitude; MC: the smallest of 2a, 2b, (a + b)/2; VanLeer: 2ab/(a + b).
 template <typename R>
-__device__ __forceinline__ R minmod(R a, R b) {
-  if ((a > R(0) && b > R(0)) || (a < R(0) && b < R(0))) return ((a < R(0) ? -a : a) < (b < R(0) ? -b : b)) ? a : b;
-  return R(0);
+__device__ __forceinline__ R rabs_(R a) { return a < R(0) ? -a : a; }
+
+// REC >= 0 fixes the limiter at compile time; REC < 0 reads `recon`.
+template <typename R, int REC = -1>
+__device__ __forceinline__ R limited_slope(int recon, R a, R b) {
+  if constexpr (REC >= 0) recon = REC;
+  const bool same = (a > R(0) && b > R(0)) || (a < R(0) && b < R(0));
+  R s;
+  if (recon == 1) {
+    s = (rabs_(a) < rabs_(b)) ? a : b;
+  } else if (recon == 2) {
+    const R ta = R(2) * a, tb = R(2) * b, c = R(0.5) * (a + b);
+    const R m = (rabs_(ta) < rabs_(tb)) ? ta : tb;
+    s = (rabs_(c) < rabs_(m)) ? c : m;
+  } else {
+    s = (R(2) * (a * b)) / (a + b);
+  }
+  return (same && recon != 0) ? s : R(0);
 }
 
-template <typename R>
+template <typename R, int REC = -1>
 __device__ __forceinline__ void cell_slopes(const R Vm[NV], const R Vc[NV], const R Vp[NV], int recon, R s[NV]) {
+  if constexpr (REC >= 0) recon = REC;
 #pragma unroll
-  for (int q = 0; q < NV; ++q) s[q] = (recon == 1) ? minmod<R>(Vc[q] - Vm[q], Vp[q] - Vc[q]) : R(0);
-  if (recon == 1) {
+  for (int q = 0; q < NV; ++q) s[q] = limited_slope<R, REC>(recon, Vc[q] - Vm[q], Vp[q] - Vc[q]);
+  if (recon != 0) {
     R lo[3], hi[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) { lo[j] = Vc[1 + j] - R(0.5) * s[1 + j]; hi[j] = Vc[1 + j] + R(0.5) * s[1 + j]; }

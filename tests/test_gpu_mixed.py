@@ -79,16 +79,16 @@ def test_mixed_riemann_1d(R, oracle, seed):
     assert out[60]["rho"] < 1e-2
 
 
-def test_mixed_alfven_wave_matches_table4(R, oracle):
+@pytest.mark.parametrize("recon,rel", [(1, 5e-2), (2, 6e-2), (3, 6e-2)])
+def test_mixed_alfven_wave_matches_table4(R, oracle, recon, rel):
     """Section 4.1, Table 4 (tests/golden): the mixed-precision path on the
-    circularly polarised Alfven wave (N = 64, MinMod, RK3, CFL 0.3, one
-    period) gives the printed L1(v_z) within 5 %, as the FP64 path does within
-    3 %."""
+    circularly polarised Alfven wave (N = 64, RK3, CFL 0.3, one period) gives
+    the printed L1(v_z) of the MinMod, MC and VanLeer rows within 5-6 %, 1 %
+    wider than the FP64 path."""
     import os
     import torch
     P = I.alfven_1d(64)
-    p = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=R.MIXED, rk_order=3,
-                               recon=R.RECON_MINMOD)
+    p = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=R.MIXED, rk_order=3, recon=recon)
     op = oracle.params(gamma=P.gamma, a_rad=P.a_rad)
     g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
     s = R.Solver(g, p)
@@ -107,5 +107,5 @@ def test_mixed_alfven_wave_matches_table4(R, oracle):
     assert np.all(st == 0)
     l1 = float(np.mean(np.abs(V[3] - P.V[3])))
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "alfven_pvm_int8_table4.txt")
-    printed = {int(r.split()[0]): float(r.split()[2]) for r in open(path) if r.strip() and not r.startswith("#")}
-    assert l1 == pytest.approx(printed[64], rel=5e-2), l1
+    printed = {int(r.split()[0]): float(r.split()[1 + recon]) for r in open(path) if r.strip() and not r.startswith("#")}
+    assert l1 == pytest.approx(printed[64], rel=rel), l1
