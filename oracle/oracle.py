@@ -40,7 +40,7 @@ class OPar(C.Structure):
         ("rho_floor", C.c_double), ("p_floor", C.c_double),
         ("pvm_k", C.c_int), ("beta_mode", C.c_int), ("recon", C.c_int), ("rk_order", C.c_int),
         ("c2p_maxit", C.c_int), ("imp_maxit", C.c_int), ("imp_picard_it", C.c_int),
-        ("imp_method", C.c_int), ("e_floor", C.c_double),
+        ("imp_method", C.c_int), ("e_floor", C.c_double), ("solver", C.c_int),
     ]
 
 
@@ -63,8 +63,10 @@ class OReport(C.Structure):
 DEFAULTS = dict(
     gamma=5.0 / 3.0, a_rad=1.0, t_coeff=1.0, pvm_eps=1e-8, c2p_tol=1e-12, imp_tol=1e-13,
     rho_floor=1e-12, p_floor=1e-12, pvm_k=3, beta_mode=1, recon=1, rk_order=2,
-    c2p_maxit=100, imp_maxit=50, imp_picard_it=8, imp_method=0, e_floor=0.0,
+    c2p_maxit=100, imp_maxit=50, imp_picard_it=8, imp_method=0, e_floor=0.0, solver=0,
 )
+
+SOLVER_PVM, SOLVER_HLL = 0, 1
 
 
 def params(**kw) -> OPar:
@@ -88,6 +90,9 @@ def _setup(lib):
     lib.or_flux.argtypes = [ll, vp, ll, i, vp, vp, ll]; lib.or_flux.restype = None
     lib.or_c2p.argtypes = [ll, vp, ll, vp, vp, vp, ll, vp, vp, vp]; lib.or_c2p.restype = None
     lib.or_pvm_face.argtypes = [ll, vp, vp, ll, vp, vp, i, vp, vp, ll, vp, vp]; lib.or_pvm_face.restype = None
+    lib.or_hll_face.argtypes = [ll, vp, vp, ll, vp, vp, i, vp, vp, ll, vp]; lib.or_hll_face.restype = None
+    lib.or_fast_speeds.argtypes = [ll, vp, ll, i, vp, vp, vp, vp]; lib.or_fast_speeds.restype = None
+    lib.or_rad_speeds.argtypes = [ll, vp, ll, i, vp, vp]; lib.or_rad_speeds.restype = None
     lib.or_poly_coef.argtypes = [i, vp]; lib.or_poly_coef.restype = i
     lib.or_implicit.argtypes = [ll, vp, ll, vp, vp, vp, vp, vp, ll, vp, vp]; lib.or_implicit.restype = None
     lib.or_four_force.argtypes = [ll, vp, ll, vp, vp, vp, vp, ll]; lib.or_four_force.restype = None
@@ -163,6 +168,36 @@ def pvm_face(VL, VR, tauL, tauR, d, par=None):
     lib().or_pvm_face(n, _dp(VL), _dp(VR), n, _dp(tauL), _dp(tauR), d, C.byref(par), _dp(Fh), n,
                       _dp(fb), _dp(its))
     return Fh, fb, its
+
+
+def hll_face(VL, VR, tauL, tauR, d, par=None):
+    """Rad-HLL face flux; returns (F^, Newton steps of the four quartic roots)."""
+    VL = _soa(VL); VR = _soa(VR); n = VL.shape[1]
+    assert VR.shape == VL.shape
+    tauL = np.ascontiguousarray(np.broadcast_to(tauL, (n,)), dtype=np.float64)
+    tauR = np.ascontiguousarray(np.broadcast_to(tauR, (n,)), dtype=np.float64)
+    Fh = np.empty_like(VL)
+    its = np.zeros(n, np.int32)
+    par = par or params()
+    lib().or_hll_face(n, _dp(VL), _dp(VR), n, _dp(tauL), _dp(tauR), d, C.byref(par), _dp(Fh), n, _dp(its))
+    return Fh, its
+
+
+def fast_speeds(V, d, par=None):
+    """(lambda_min, lambda_max, Newton steps) of the magnetofluid block per state."""
+    V = _soa(V); n = V.shape[1]
+    lo = np.empty(n); hi = np.empty(n); its = np.zeros(n, np.int32)
+    par = par or params()
+    lib().or_fast_speeds(n, _dp(V), n, d, C.byref(par), _dp(lo), _dp(hi), _dp(its))
+    return lo, hi, its
+
+
+def rad_speeds(V, d):
+    """(lambda_r1, lambda_r3) of the M1 radiation block per state."""
+    V = _soa(V); n = V.shape[1]
+    l1 = np.empty(n); l3 = np.empty(n)
+    lib().or_rad_speeds(n, _dp(V), n, d, _dp(l1), _dp(l3))
+    return l1, l3
 
 
 def poly_coef(k):

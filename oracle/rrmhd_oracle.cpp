@@ -91,6 +91,7 @@ struct OPar {
   int imp_picard_it; // Picard (lagged) iterations before Newton takes over
   int imp_method;    // 0: Picard then Newton; 1: Newton only; 2: Picard only
   double e_floor;    // > 0: a non-positive explicit E_r is raised to this (counted); 0: failure
+  int solver;        // 0: PVM-int (Section 3.2); 1: Rad-HLL (Section 3.2, Radiative HLL)
 };
 
 struct OGrid {
@@ -793,6 +794,29 @@ static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OP
 }
 
 // ---------------------------------------------------------------------------
+// The outer M1 eigenvalues lambda_r1 <= lambda_r3 of a radiation state in
+// direction d (eqs. lam1, lam2, lam3): f = |F|/E (capped at 1), theta the
+// angle between F and e_d (cos(theta) = 0 when F = 0).
+static void rad_speeds(const real V[NV], int d, real& l1, real& l3) {
+  const real E = V[8];
+  const real FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
+  real f = 0.0, cth = 0.0;
+  if (FF > real(0.0)) {
+    const real Fn = rsqrt_(FF);
+    f = rmin(Fn / E, real(1.0));
+    cth = V[9 + d] / Fn;
+  }
+  const real f2 = f * f;
+  const real r43 = 4.0 - 3.0 * f2;
+  const real sr = rsqrt_(r43);
+  real zz = (2.0 / 3.0) * (r43 - sr) + (2.0 * (cth * cth)) * ((2.0 - f2) - sr);
+  zz = (zz > real(0.0)) ? zz : real(0.0);
+  const real zeta = rsqrt_(zz);
+  l1 = (f * cth - zeta) / sr;
+  l3 = (f * cth + zeta) / sr;
+}
+
+// ---------------------------------------------------------------------------
 // Signal speed bound of one cell in direction d (for the CFL condition).
 // Fluid: the relativistic fast-speed bound with a^2 = cs^2 + ca^2 - cs^2 ca^2,
 //   lambda = [v_d (1 - a^2) +- sqrt(a^2 (1 - v^2)(1 - v^2 a^2 - v_d^2 (1 - a^2)))]
@@ -816,24 +840,131 @@ static real cell_speed(const real V[NV], int d, const OPar& P, const Consts& K) 
   const real lp = (vd * (1.0 - a2) + sq) / den;
   const real lm = (vd * (1.0 - a2) - sq) / den;
   real s = rmax(rabs(lp), rabs(lm));
-  const real E = V[8];
-  const real FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
-  real f = 0.0, cth = 0.0;
-  if (FF > real(0.0)) {
-    const real Fn = rsqrt_(FF);
-    f = rmin(Fn / E, real(1.0));
-    cth = V[9 + d] / Fn;
-  }
-  const real f2 = f * f;
-  const real r43 = 4.0 - 3.0 * f2;
-  const real sr = rsqrt_(r43);
-  real zz = (2.0 / 3.0) * (r43 - sr) + (2.0 * (cth * cth)) * ((2.0 - f2) - sr);
-  zz = (zz > real(0.0)) ? zz : real(0.0);
-  const real zeta = rsqrt_(zz);
-  const real l1 = (f * cth - zeta) / sr;
-  const real l3 = (f * cth + zeta) / sr;
+  real l1, l3;
+  rad_speeds(V, d, l1, l3);
   s = rmax(s, rmax(rabs(l1), rabs(l3)));
   return s;
+}
+
+// ---------------------------------------------------------------------------
+// Rad-HLL face flux (Section 3.2, Radiative HLL). The magnetofluid rows 0..7
+// and the radiation rows 8..11 each take the HLL flux with speeds of their own
+// block of the Jacobian (eq. jacobian):
+//   F^ = F_L                                          if lambda_L > 0,
+//        F_R                                          if lambda_R < 0,
+//        (lambda_R F_L - lambda_L F_R + lambda_R lambda_L (U_R - U_L))
+//          / (lambda_R - lambda_L)                    otherwise,
+// and, when lambda_L = lambda_R = 0, (F_L + F_R)/2 (reading: a fan of zero
+// width, which the formula leaves undefined).
+//
+// Magnetofluid speeds: the extreme eigenvalues of the RMHD block, i.e. the
+// smallest and the largest root of the quartic of Anile (1989), written as in
+// Mignone & Bodo (2006),
+//   Q(l) = w (1 - cs^2) a^4 - (1 - l^2) [(w cs^2 + |b|^2) a^2 - cs^2 B~^2],
+//   a = W (l - v_d),   B~ = b^d - l b^0,   w = rho h,   cs^2 = gamma p / w.
+// Its four roots (the fast and slow magnetosonic speeds) are real and lie in
+// (-1, 1), and Q(+-1) > 0. A polynomial with only real roots is increasing
+// and convex to the right of its largest root (and decreasing and convex to
+// the left of its smallest), so Newton's iteration from l = 1 falls
+// monotonically to the largest root and from l = -1 rises to the smallest
+// (reading: the paper names a root finder without giving it). The iteration
+// stops when Q or Q' no longer has the sign it has outside the roots, when an
+// iterate no longer moves, or after kQuartIt steps; an early stop leaves the
+// speed outside the root, which only widens the HLL fan. Each state gives
+// (min, max); the face takes the min over L and R and the max over L and R.
+//
+// Radiation speeds: lambda_r1 and lambda_r3 of both states (eqs. lam1..lam3),
+// the smaller r1 and the larger r3, limited by eq. limits with the optical
+// depth tau = max(tau_L, tau_R) of the two cells next to the face (reading:
+// the same cell depths that give beta of the PVM flux).
+static const int kQuartIt = 40;
+
+struct QuartIn {
+  real w1cs;  // w (1 - cs^2)
+  real wcsb;  // w cs^2 + |b|^2
+  real cs2, W2, vd, bd, b0;
+};
+
+static void quartic(const QuartIn& q, real l, real& Q, real& dQ) {
+  const real x = l - q.vd;
+  const real a2 = q.W2 * (x * x);
+  const real Bt = q.bd - l * q.b0;
+  const real om = 1.0 - l * l;
+  const real br = q.wcsb * a2 - q.cs2 * (Bt * Bt);
+  Q = q.w1cs * (a2 * a2) - om * br;
+  // d(a^2)/dl = 2 W^2 (l - v_d), d(B~^2)/dl = -2 b^0 B~
+  const real da2 = 2.0 * (q.W2 * x);
+  const real dbr = q.wcsb * da2 + 2.0 * (q.cs2 * (q.b0 * Bt));
+  dQ = ((2.0 * q.w1cs) * (a2 * da2) + (2.0 * l) * br) - om * dbr;
+}
+
+static void fast_speeds(const real V[NV], const Aux& a, int d, const OPar& P, const Consts& K,
+                        real& lmin, real& lmax, int* iters) {
+  QuartIn q;
+  const real w = V[0] + K.g1 * V[4];
+  q.cs2 = (P.gamma * V[4]) / w;
+  q.w1cs = w * (1.0 - q.cs2);
+  q.wcsb = w * q.cs2 + a.bb;
+  q.W2 = a.W * a.W;
+  q.vd = V[1 + d];
+  q.bd = a.b[d];
+  q.b0 = a.b0;
+  int n = 0;
+  real l = 1.0;
+  for (int it = 0; it < kQuartIt; ++it) {
+    real Q, dQ;
+    quartic(q, l, Q, dQ);
+    if (!(Q > real(0.0)) || !(dQ > real(0.0))) break;
+    const real ln = l - Q / dQ;
+    if (!(ln < l)) break;
+    l = ln;
+    ++n;
+  }
+  lmax = l;
+  l = -1.0;
+  for (int it = 0; it < kQuartIt; ++it) {
+    real Q, dQ;
+    quartic(q, l, Q, dQ);
+    if (!(Q > real(0.0)) || !(dQ < real(0.0))) break;
+    const real ln = l - Q / dQ;
+    if (!(ln > l)) break;
+    l = ln;
+    ++n;
+  }
+  lmin = l;
+  if (iters) *iters = n;
+}
+
+static void hll_rows(const real FL[NV], const real FR[NV], const real UL[NV], const real UR[NV],
+                     real lL, real lR, int q0, int q1, real Fh[NV]) {
+  for (int q = q0; q < q1; ++q) {
+    if (lL > real(0.0)) Fh[q] = FL[q];
+    else if (lR < real(0.0)) Fh[q] = FR[q];
+    else if (lR > lL) Fh[q] = ((lR * FL[q] - lL * FR[q]) + (lR * lL) * (UR[q] - UL[q])) / (lR - lL);
+    else Fh[q] = 0.5 * (FL[q] + FR[q]);
+  }
+}
+
+static void hll_face(const real VL[NV], const real VR[NV], real tauL, real tauR, int d,
+                     const OPar& P, const Consts& K, real Fh[NV], FaceOut& fo) {
+  Aux aL, aR;
+  prim_aux(VL, K, aL);
+  prim_aux(VR, K, aR);
+  real UL[NV], UR[NV], FL[NV], FR[NV];
+  p2c(VL, aL, UL); flux(VL, aL, d, FL);
+  p2c(VR, aR, UR); flux(VR, aR, d, FR);
+  real mnL, mxL, mnR, mxR;
+  int itL = 0, itR = 0;
+  fast_speeds(VL, aL, d, P, K, mnL, mxL, &itL);
+  fast_speeds(VR, aR, d, P, K, mnR, mxR, &itR);
+  hll_rows(FL, FR, UL, UR, rmin(mnL, mnR), rmax(mxL, mxR), 0, 8, Fh);
+  real r1L, r3L, r1R, r3R;
+  rad_speeds(VL, d, r1L, r3L);
+  rad_speeds(VR, d, r1R, r3R);
+  const real lim = 4.0 / (3.0 * rmax(tauL, tauR));
+  hll_rows(FL, FR, UL, UR, rmax(rmin(r1L, r1R), -lim), rmin(rmax(r3L, r3R), lim), 8, NV, Fh);
+  fo.fallback = 0;
+  fo.c2p_it = itL + itR;
 }
 
 // ---------------------------------------------------------------------------
@@ -988,7 +1119,8 @@ static long long stage_faces(const Grid& G, const OPar& P, const Consts& K, cons
     const real tauL = tp[1] * dxd, tauR = tp[2] * dxd;
     real Fq[NV];
     FaceOut fo;
-    pvm_face(VL, VR, tauL, tauR, d, P, K, coef, M, Fq, fo);
+    if (P.solver == 1) hll_face(VL, VR, tauL, tauR, d, P, K, Fq, fo);
+    else pvm_face(VL, VR, tauL, tauR, d, P, K, coef, M, Fq, fo);
     nfb += fo.fallback;
     for (int q = 0; q < NV; ++q) Fh[q * nf + f] = dv(Fq[q]);
   }
@@ -1167,6 +1299,52 @@ void or_pvm_face(long long n, const double* VL, const double* VR, long long sv, 
     for (int q = 0; q < NV; ++q) Fh[q * sf + c] = dv(Fq[q]);
     if (fallback) fallback[c] = fo.fallback;
     if (c2p_its) c2p_its[c] = fo.c2p_it;
+  }
+}
+
+// Rad-HLL face flux from given reconstructed states; iters: Newton steps of
+// the four quartic roots.
+void or_hll_face(long long n, const double* VL, const double* VR, long long sv, const double* tauL,
+                 const double* tauR, int d, const OPar* P, double* Fh, long long sf, int* iters) {
+  const Consts K = consts_of(*P);
+  for (long long c = 0; c < n; ++c) {
+    real L[NV], Rr[NV], Fq[NV];
+    for (int q = 0; q < NV; ++q) { L[q] = VL[q * sv + c]; Rr[q] = VR[q * sv + c]; }
+    FaceOut fo;
+    hll_face(L, Rr, real(tauL[c]), real(tauR[c]), d, *P, K, Fq, fo);
+    for (int q = 0; q < NV; ++q) Fh[q * sf + c] = dv(Fq[q]);
+    if (iters) iters[c] = fo.c2p_it;
+  }
+}
+
+// Smallest and largest magnetofluid characteristic speed of each state in
+// direction d (the extreme roots of the RMHD quartic).
+void or_fast_speeds(long long n, const double* V, long long sv, int d, const OPar* P, double* lmin,
+                    double* lmax, int* iters) {
+  const Consts K = consts_of(*P);
+  for (long long c = 0; c < n; ++c) {
+    real X[NV];
+    for (int q = 0; q < NV; ++q) X[q] = V[q * sv + c];
+    Aux a;
+    prim_aux(X, K, a);
+    real mn, mx;
+    int it = 0;
+    fast_speeds(X, a, d, *P, K, mn, mx, &it);
+    lmin[c] = dv(mn);
+    lmax[c] = dv(mx);
+    if (iters) iters[c] = it;
+  }
+}
+
+// The outer M1 eigenvalues lambda_r1, lambda_r3 of each radiation state.
+void or_rad_speeds(long long n, const double* V, long long sv, int d, double* l1, double* l3) {
+  for (long long c = 0; c < n; ++c) {
+    real X[NV];
+    for (int q = 0; q < NV; ++q) X[q] = V[q * sv + c];
+    real a, b;
+    rad_speeds(X, d, a, b);
+    l1[c] = dv(a);
+    l3[c] = dv(b);
   }
 }
 
