@@ -57,12 +57,12 @@ def load_json(path):
         return None
 
 
-def cpu_baseline(P, steps: int):
+def cpu_baseline(P, steps: int, solver: int = 0):
     """The CPU oracle (as it stands, OpenMP over cells) on the first `steps`
     steps of the same workload from the same initial state."""
     from oracle import oracle as O
     nthreads = O.threads(0)
-    par = O.params(gamma=P.gamma, a_rad=P.a_rad, beta_mode=1)
+    par = O.params(gamma=P.gamma, a_rad=P.a_rad, beta_mode=1, solver=solver)
     g = O.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
     U = O.p2c(P.V, par)
     t0 = time.perf_counter()
@@ -227,6 +227,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--solver", choices=("pvm", "hll"), default="pvm",
+                    help="face flux: PVM-int-8 (the method) or Rad-HLL (the paper's comparison solver)")
     ap.add_argument("--mode", choices=("step", "serving", "beam3d", "copycal"), default="step")
     ap.add_argument("--requests", type=int, default=120)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate / measured capacity")
@@ -262,7 +264,12 @@ def main():
         return
     P = I.blast_2d(args.seed, args.n, steps=args.steps)
     mixed = args.precision == "mixed"
-    params = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=R.MIXED if mixed else R.FP64)
+    hll = args.solver == "hll"
+    if hll and mixed:
+        print("Rad-HLL runs in FP64 only", file=sys.stderr)
+        sys.exit(2)
+    params = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=R.MIXED if mixed else R.FP64,
+                                    solver=R.SOLVER_HLL if hll else R.SOLVER_PVM)
     grid = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
     solver = R.Solver(grid, params, device=dev)
     V = torch.from_numpy(P.V).to(dev)
@@ -318,7 +325,7 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
 
     # roofline of the dominant kernel (face fluxes)
-    ops = load_json(os.path.join(ROOT, "oracle", f"opcount_blast2d_{args.n}.json"))
+    ops = load_json(os.path.join(ROOT, "oracle", f"opcount_blast2d_{args.n}{'_hll' if hll else ''}.json"))
     fms, flaunch, ffaces = prof["faces"]
     roof = None
     if ops and flaunch > 0 and not mixed:
@@ -327,12 +334,12 @@ def main():
         flops_per_launch = per_face * ffaces / flaunch
         achieved = flops_per_launch / mean_s / 1e12
         traffic = None
-        tr = load_json(os.path.join(ROOT, "profiles", f"traffic_k_faces_blast2d_{args.n}.json"))
+        tr = None if hll else load_json(os.path.join(ROOT, "profiles", f"traffic_k_faces_blast2d_{args.n}.json"))
         if tr and tr.get("sources_sha256") == kernel_sources_digest():
             traffic = tr.get("hbm_bytes_per_launch")
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_faces (PLM MinMod + PVM-int-8 face flux)",
+                "kernel": "k_faces (PLM MinMod + " + ("Rad-HLL" if hll else "PVM-int-8") + " face flux)",
                 "ops_per_face": round(per_face, 1), "faces_per_launch": ffaces // flaunch,
                 "mean_launch_ms": round(1e3 * mean_s, 4)}
 
@@ -351,15 +358,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D RRMHD+M1 magnetised blast {P.shape[0]}x{P.shape[1]} "
                                f"{'mixed FP32/FP64' if mixed else 'FP64'}, seed {args.seed}, "
-                               f"PVM-int-8, PLM MinMod, IMEX RK2, CFL {P.cfl}, {args.steps} steps",
-                   "cells": P.ncell, "precision": args.precision, "beta_mode": "radiation rows"},
+                               f"{'Rad-HLL' if hll else 'PVM-int-8'}, PLM MinMod, IMEX RK2, CFL {P.cfl}, "
+                               f"{args.steps} steps",
+                   "cells": P.ncell, "precision": args.precision, "solver": args.solver,
+                   "beta_mode": "radiation rows" if not hll else None},
         "roofline": roof,
         "kernels_ms_per_step": breakdown,
         "kernels_ms_per_step_note": "separate run of min(steps, 20) steps with every launch timed",
         "failures": {k: rep[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(P, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(P, args.cpu_steps, R.SOLVER_HLL if hll else R.SOLVER_PVM)
     print(json.dumps(out), flush=True)
 
 

@@ -51,6 +51,13 @@ typedef enum { RRMHD_BC_PERIODIC = 0, RRMHD_BC_OUTFLOW = 1, RRMHD_BC_INFLOW = 2 
 enum { RRMHD_RECON_GODUNOV = 0, RRMHD_RECON_MINMOD = 1, RRMHD_RECON_MC = 2, RRMHD_RECON_VANLEER = 3 };
 enum { RRMHD_BETA_ALL = 0, RRMHD_BETA_RAD_ONLY = 1, RRMHD_BETA_OFF = 2 };
 enum { RRMHD_IMP_PICARD_NEWTON = 0, RRMHD_IMP_NEWTON = 1, RRMHD_IMP_PICARD = 2 };
+/* Face flux (Section 3.2). RRMHD_SOLVER_PVM: the Jacobian-free PVM-int flux
+ * with the opacity factor beta. RRMHD_SOLVER_HLL: Rad-HLL, the HLL flux with
+ * separate signal speeds for the magnetofluid rows (extreme roots of the RMHD
+ * quartic) and the radiation rows (eqs. lam1-lam3, limited by eq. limits);
+ * FP64 only (precision RRMHD_MIXED with it is RRMHD_E_INVALID), and not
+ * available to the batched entry points. */
+enum { RRMHD_SOLVER_PVM = 0, RRMHD_SOLVER_HLL = 1 };
 /* Precision of the explicit step. RRMHD_FP64: everything in binary64.
  * RRMHD_MIXED: reconstruction, fluxes and the PVM Horner / finite-difference
  * arithmetic in binary32 with a relative difference step pvm_eps_mixed; all
@@ -98,6 +105,7 @@ typedef struct {
   double e_floor;   /* 0 (default): a non-positive E_r entering the implicit solve fails
                        the cell; > 0: it is raised to e_floor keeping tau + E_r and
                        S + F_r (the gas pays), and counted in e_floor_hits           */
+  int solver;       /* RRMHD_SOLVER_*: face flux of the explicit step                 */
 } rrmhd_params;
 
 /* Gray comoving opacities per unit mass (eqs. g0, gi): device arrays [ncell]

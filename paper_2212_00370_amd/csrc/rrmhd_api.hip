@@ -3,7 +3,8 @@
 // One IMEX step (Section 3.1 of Lopez-Miralles, Marti & Perucho, CPC,
 // arXiv 2212.00370) is, per Runge-Kutta stage:
 //   k_prims   : cell primitive recovery of the stage state -> V, D(kappa+sigma)
-//   k_faces   : per face of every direction, PLM + PVM-int flux (Section 3.2) -> F^_d
+//   k_faces   : per face of every direction, PLM + PVM-int or Rad-HLL flux
+//               (Section 3.2) -> F^_d
 //   k_update  : U* = a0 U^(0) + a1 U^(s) - c dt sum_d dF^_d/dx_d (eq. explicit)
 //               followed by the per-cell implicit source solve (Section 3.3)
 // All kernels read and write structure-of-arrays float64 planes in HBM; one
@@ -55,6 +56,9 @@ constexpr int kPicardSplit = RRMHD_PICARD_SPLIT;
 #endif
 #ifndef RRMHD_FACES_WAVES_MIXED
 #define RRMHD_FACES_WAVES_MIXED 3
+#endif
+#ifndef RRMHD_FACES_WAVES_HLL
+#define RRMHD_FACES_WAVES_HLL 4
 #endif
 #ifndef RRMHD_UPDATE_WAVES
 #define RRMHD_UPDATE_WAVES 2
@@ -327,7 +331,7 @@ struct FaceArgs {
 // then the PVM-int flux with beta from the two adjacent cells. REC >= 0 fixes
 // the limiter at compile time (the launch picks the MinMod copy when K.recon
 // is MinMod); REC < 0 reads K.recon.
-template <int d, int REC>
+template <int d, int REC, bool HLL>
 __device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, long long f, const Phys& K,
                                           unsigned long long& fb, unsigned int& its) {
   int fn0 = G.n[0], fn1 = G.n[1];
@@ -365,7 +369,8 @@ __device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, l
   const double tauL = tp[1] * A.dx[d], tauR = tp[2] * A.dx[d];
   double Fq[NV];
   int fallback = 0, cit = 0;
-  rr::pvm_face<d>(VL, VR, tauL, tauR, K, Fq, fallback, cit);
+  if constexpr (HLL) rr::hll_face<d>(VL, VR, tauL, tauR, K, Fq);
+  else rr::pvm_face<d>(VL, VR, tauL, tauR, K, Fq, fallback, cit);
   double* out = A.Fh[d];
   const long long nf = A.nf[d];
 #pragma unroll
@@ -426,7 +431,7 @@ __device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs
 // Face fluxes of all directions in one launch: blocks [0, nb0) take x faces,
 // the next nb1 blocks y faces, then z. The direction is uniform per block.
 // MIXED selects the mixed-precision stencil (FP32 fluxes out).
-template <bool MIXED, int REC>
+template <bool MIXED, int REC, bool HLL = false>
 __device__ __forceinline__ void faces_block(long long lb, const GridDev& G, const FaceArgs& A, const Phys& K,
                                             DevReport* rep, unsigned int* blkmax) {
   long long b = lb;
@@ -441,9 +446,9 @@ __device__ __forceinline__ void faces_block(long long lb, const GridDev& G, cons
   unsigned int its = 0;
   if (f < A.nf[d]) {
     if constexpr (!MIXED) {
-      if (d == 0) face_body<0, REC>(G, A, f, K, fb, its);
-      else if (d == 1) face_body<1, REC>(G, A, f, K, fb, its);
-      else face_body<2, REC>(G, A, f, K, fb, its);
+      if (d == 0) face_body<0, REC, HLL>(G, A, f, K, fb, its);
+      else if (d == 1) face_body<1, REC, HLL>(G, A, f, K, fb, its);
+      else face_body<2, REC, HLL>(G, A, f, K, fb, its);
     } else {
       if (d == 0) face_body_mixed<0, REC>(G, A, f, K, fb, its);
       else if (d == 1) face_body_mixed<1, REC>(G, A, f, K, fb, its);
@@ -530,9 +535,10 @@ __device__ __forceinline__ void order_block(const BlockOrder& O) {
 // blocks do the step's time step (dt_block, with R.partial set) and the next
 // update pass's block order (order_block, with O.cost set); the rest take the
 // faces. The update pass, which reads both, runs after this launch.
-template <typename FT, int REC>
+template <typename FT, int REC, bool HLL>
 __global__ void __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(sizeof(FT) == sizeof(double) ? RRMHD_FACES_WAVES : RRMHD_FACES_WAVES_MIXED)))
+__attribute__((amdgpu_waves_per_eu(HLL ? RRMHD_FACES_WAVES_HLL
+                                       : (sizeof(FT) == sizeof(double) ? RRMHD_FACES_WAVES : RRMHD_FACES_WAVES_MIXED))))
 k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, unsigned long long* wreset,
         DtReduce R, BlockOrder O) {
   // the work-list counter of the update pass that follows (not read here)
@@ -552,7 +558,7 @@ k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, uns
     }
     b -= 1;
   }
-  faces_block<sizeof(FT) == sizeof(float), REC>(b, G, A, K, rep, blkmax);
+  faces_block<sizeof(FT) == sizeof(float), REC, HLL>(b, G, A, K, rep, blkmax);
 }
 
 struct StageArgs {
@@ -1112,6 +1118,8 @@ bool params_valid(const rrmhd_params* p) {
   if (!(p->e_floor >= 0.0)) return false;
   if (p->precision != RRMHD_FP64 && p->precision != RRMHD_MIXED) return false;
   if (!(p->pvm_eps_mixed > 0.0 && p->pvm_eps_mixed < 0.5)) return false;
+  if (p->solver != RRMHD_SOLVER_PVM && p->solver != RRMHD_SOLVER_HLL) return false;
+  if (p->solver == RRMHD_SOLVER_HLL && p->precision != RRMHD_FP64) return false;
   return true;
 }
 
@@ -1338,12 +1346,14 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   const unsigned int nlaunch = (unsigned int)(nbt + (R.partial ? 1 : 0) + 1);
   pe = prof_begin(c, RRMHD_K_FACES, A.nf[0] + A.nf[1] + A.nf[2]);
   const bool mm = c->K.recon == RRMHD_RECON_MINMOD;
-  if (c->par.precision == RRMHD_MIXED) {
-    if (mm) k_faces<float, 1><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
-    else k_faces<float, -1><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+  if (c->par.solver == RRMHD_SOLVER_HLL) {
+    k_faces<double, -1, true><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+  } else if (c->par.precision == RRMHD_MIXED) {
+    if (mm) k_faces<float, 1, false><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    else k_faces<float, -1, false><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
   } else {
-    if (mm) k_faces<double, 1><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
-    else k_faces<double, -1><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    if (mm) k_faces<double, 1, false><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    else k_faces<double, -1, false><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
   }
   prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
@@ -1453,6 +1463,7 @@ rrmhd_status batch_check(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, const 
   for (int s = 0; s < nsim; ++s) {
     if (!ctx[s] || !U[s]) return RRMHD_E_INVALID;
     if (ctx[s]->par.rk_order != ctx[0]->par.rk_order) return RRMHD_E_INVALID;
+    if (ctx[s]->par.solver != RRMHD_SOLVER_PVM) return RRMHD_E_INVALID;
     for (int t = 0; t < s; ++t)
       if (ctx[t] == ctx[s]) return RRMHD_E_INVALID;  // each context's workspace is used once per launch
   }

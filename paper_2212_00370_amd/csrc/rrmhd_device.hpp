@@ -1186,6 +1186,29 @@ __device__ __forceinline__ int implicit_newton_quad(const double Us[NV], double 
 }
 
 // ---------------------------------------------------------------------------
+// The outer M1 eigenvalues lambda_r1 <= lambda_r3 in direction d (eqs.
+// lam1-lam3): f = |F|/E capped at 1, cos(theta) = F_d/|F| (0 when F = 0).
+template <int d>
+__device__ __forceinline__ void rad_speeds(const double V[NV], double& l1, double& l3) {
+  const double E = V[8];
+  const double FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
+  double f = 0.0, cth = 0.0;
+  if (FF > 0.0) {
+    const double Fn = sqrt(FF);
+    f = dmin(Fn / E, 1.0);
+    cth = V[9 + d] / Fn;
+  }
+  const double f2 = f * f;
+  const double r43 = 4.0 - 3.0 * f2;
+  const double sr = sqrt(r43);
+  double zz = (2.0 / 3.0) * (r43 - sr) + (2.0 * (cth * cth)) * ((2.0 - f2) - sr);
+  zz = (zz > 0.0) ? zz : 0.0;
+  const double zeta = sqrt(zz);
+  l1 = (f * cth - zeta) / sr;
+  l3 = (f * cth + zeta) / sr;
+}
+
+// ---------------------------------------------------------------------------
 // Signal speed bound of a cell in direction d: relativistic fast-speed bound
 // with a^2 = cs^2 + ca^2 - cs^2 ca^2 for the fluid, M1 eigenvalues
 // lambda_r1, lambda_r3 (eqs. lam1-lam3) for the radiation.
@@ -1205,24 +1228,121 @@ __device__ __forceinline__ double cell_speed(const double V[NV], const Aux& a, c
   const double lp = (vd * (1.0 - a2) + sq) / den;
   const double lm = (vd * (1.0 - a2) - sq) / den;
   double s = dmax(dabs(lp), dabs(lm));
-  const double E = V[8];
-  const double FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
-  double f = 0.0, cth = 0.0;
-  if (FF > 0.0) {
-    const double Fn = sqrt(FF);
-    f = dmin(Fn / E, 1.0);
-    cth = V[9 + d] / Fn;
-  }
-  const double f2 = f * f;
-  const double r43 = 4.0 - 3.0 * f2;
-  const double sr = sqrt(r43);
-  double zz = (2.0 / 3.0) * (r43 - sr) + (2.0 * (cth * cth)) * ((2.0 - f2) - sr);
-  zz = (zz > 0.0) ? zz : 0.0;
-  const double zeta = sqrt(zz);
-  const double l1 = (f * cth - zeta) / sr;
-  const double l3 = (f * cth + zeta) / sr;
+  double l1, l3;
+  rad_speeds<d>(V, l1, l3);
   s = dmax(s, dmax(dabs(l1), dabs(l3)));
   return s;
+}
+
+// ---------------------------------------------------------------------------
+// Rad-HLL face flux (Section 3.2, Radiative HLL): the HLL flux of eq.
+// F^hll, applied to the magnetofluid rows 0..7 and to the radiation rows
+// 8..11 with the signal speeds of each block of the Jacobian (eq. jacobian).
+//
+// Magnetofluid speeds: the smallest and largest roots of the RMHD quartic
+// (Anile 1989), Q(l) = w (1 - cs^2) a^4 - (1 - l^2)[(w cs^2 + |b|^2) a^2 -
+// cs^2 B~^2] with a = W (l - v_d), B~ = b^d - l b^0, w = rho h. All roots are
+// real and inside (-1, 1), so Newton's iteration from l = +1 (l = -1) moves
+// monotonically down (up) to the largest (smallest) root; it stops when Q or
+// Q' changes the sign it has outside the roots, when an iterate stalls, or
+// after kQuartIt steps, and an early stop only widens the fan. The four roots
+// of a face (min and max of the L and R states) advance together in one
+// straight-line loop, each frozen once its own test stops it: the values are
+// those of four separate loops, with four independent dependency chains for
+// the FP64 pipeline.
+//
+// Radiation speeds: lambda_r1 and lambda_r3 (eqs. lam1-lam3) of both states,
+// limited to |lambda| <= 4/(3 tau) (eq. limits) with tau the larger optical
+// depth of the two cells next to the face. A fan of zero width takes the mean
+// of F_L and F_R.
+constexpr int kQuartIt = 40;
+
+struct QuartIn {
+  double w1cs, wcsb, cs2, W2, vd, bd, b0;
+};
+
+__device__ __forceinline__ void quartic(const QuartIn& q, double l, double& Q, double& dQ) {
+  const double x = l - q.vd;
+  const double a2 = q.W2 * (x * x);
+  const double Bt = q.bd - l * q.b0;
+  const double om = 1.0 - l * l;
+  const double br = q.wcsb * a2 - q.cs2 * (Bt * Bt);
+  Q = q.w1cs * (a2 * a2) - om * br;
+  const double da2 = 2.0 * (q.W2 * x);
+  const double dbr = q.wcsb * da2 + 2.0 * (q.cs2 * (q.b0 * Bt));
+  dQ = ((2.0 * q.w1cs) * (a2 * da2) + (2.0 * l) * br) - om * dbr;
+}
+
+template <int d>
+__device__ __forceinline__ QuartIn quartic_in(const double V[NV], const Aux& a, const Phys& K) {
+  QuartIn q;
+  const double w = V[0] + K.g1 * V[4];
+  q.cs2 = (K.gamma * V[4]) / w;
+  q.w1cs = w * (1.0 - q.cs2);
+  q.wcsb = w * q.cs2 + a.bb;
+  q.W2 = a.W * a.W;
+  q.vd = V[1 + d];
+  q.bd = a.b[d];
+  q.b0 = a.b0;
+  return q;
+}
+
+// lam[0], lam[1]: min and max of state L; lam[2], lam[3]: of state R.
+__device__ __forceinline__ void fast_speeds2(const QuartIn& qL, const QuartIn& qR, double lam[4]) {
+  bool run[4] = {true, true, true, true};
+  lam[0] = -1.0; lam[1] = 1.0; lam[2] = -1.0; lam[3] = 1.0;
+  for (int it = 0; it < kQuartIt; ++it) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double Q, dQ;
+      quartic((r < 2) ? qL : qR, lam[r], Q, dQ);
+      const bool up = (r & 1) == 0;  // the smallest root is approached from below
+      const bool side = (Q > 0.0) && (up ? (dQ < 0.0) : (dQ > 0.0));
+      const double ln = lam[r] - Q / dQ;
+      const bool moves = up ? (ln > lam[r]) : (ln < lam[r]);
+      run[r] = run[r] && side && moves;
+      lam[r] = run[r] ? ln : lam[r];
+    }
+    if (!(run[0] || run[1] || run[2] || run[3])) break;
+  }
+}
+
+__device__ __forceinline__ void hll_rows(const double* FL, const double* FR, const double* UL, const double* UR,
+                                         double lL, double lR, int n, double* Fh) {
+#pragma unroll
+  for (int q = 0; q < n; ++q) {
+    const double h = ((lR * FL[q] - lL * FR[q]) + (lR * lL) * (UR[q] - UL[q])) / (lR - lL);
+    const double m = 0.5 * (FL[q] + FR[q]);
+    Fh[q] = (lL > 0.0) ? FL[q] : ((lR < 0.0) ? FR[q] : ((lR > lL) ? h : m));
+  }
+}
+
+template <int d>
+__device__ __forceinline__ void hll_face(const double VL[NV], const double VR[NV], double tauL, double tauR,
+                                         const Phys& K, double Fh[NV]) {
+  // radiation block: its variables are both primitive and conserved
+  {
+    double r1L, r3L, r1R, r3R;
+    rad_speeds<d>(VL, r1L, r3L);
+    rad_speeds<d>(VR, r1R, r3R);
+    const double lim = 4.0 / (3.0 * dmax(tauL, tauR));
+    double FL[4], FR[4];
+    flux_rad<d>(VL + 8, FL);
+    flux_rad<d>(VR + 8, FR);
+    hll_rows(FL, FR, VL + 8, VR + 8, dmax(dmin(r1L, r1R), -lim), dmin(dmax(r3L, r3R), lim), 4, Fh + 8);
+  }
+  // magnetofluid block
+  Aux aL, aR;
+  prim_aux(VL, K, aL);
+  prim_aux(VR, K, aR);
+  double lam[4];
+  fast_speeds2(quartic_in<d>(VL, aL, K), quartic_in<d>(VR, aR, K), lam);
+  double UL[8], UR[8], FL[8], FR[8];
+  p2c8(VL, aL, UL);
+  flux_mhd<d>(VL, aL, FL);
+  p2c8(VR, aR, UR);
+  flux_mhd<d>(VR, aR, FR);
+  hll_rows(FL, FR, UL, UR, dmin(lam[0], lam[2]), dmax(lam[1], lam[3]), 8, Fh);
 }
 
 }  // namespace rr

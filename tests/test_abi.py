@@ -79,6 +79,7 @@ def test_default_params(R):
     assert p.precision == R.FP64 and p.beta_mode == R.BETA_RAD_ONLY
     assert p.pvm_eps_mixed == 2.0 ** -12 and p.e_floor == 0.0
     assert p.gamma == 5.0 / 3.0
+    assert p.solver == R.SOLVER_PVM
 
 
 def _grid(R, n):
@@ -113,6 +114,15 @@ def test_workspace_bytes(R):
     q = R.rrmhd_params()
     R._lib.rrmhd_default_params(C.byref(q))
     q.gamma = 0.5
+    assert R._lib.rrmhd_workspace_bytes(C.byref(_grid(R, (16, 16))), C.byref(q)) == 0
+    # Rad-HLL: FP64 only; unknown solvers are refused
+    R._lib.rrmhd_default_params(C.byref(q))
+    q.solver = R.SOLVER_HLL
+    assert R._lib.rrmhd_workspace_bytes(C.byref(_grid(R, (16, 16))), C.byref(q)) > 0
+    q.precision = R.MIXED
+    assert R._lib.rrmhd_workspace_bytes(C.byref(_grid(R, (16, 16))), C.byref(q)) == 0
+    q.precision = R.FP64
+    q.solver = 2
     assert R._lib.rrmhd_workspace_bytes(C.byref(_grid(R, (16, 16))), C.byref(q)) == 0
     assert R._lib.rrmhd_batch_workspace_bytes(0) == 0
     assert R._lib.rrmhd_batch_workspace_bytes(8) > 0

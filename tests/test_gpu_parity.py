@@ -54,7 +54,7 @@ def oracle_params(oracle, p):
                          c2p_tol=p.c2p_tol, imp_tol=p.imp_tol, rho_floor=p.rho_floor, p_floor=p.p_floor,
                          pvm_k=p.pvm_k, beta_mode=p.beta_mode, recon=p.recon, rk_order=p.rk_order,
                          c2p_maxit=p.c2p_maxit, imp_maxit=p.imp_maxit, imp_picard_it=p.imp_picard_it,
-                         imp_method=p.imp_method, e_floor=p.e_floor)
+                         imp_method=p.imp_method, e_floor=p.e_floor, solver=p.solver)
 
 
 def make_case(R, oracle, torch, P, **kw):
