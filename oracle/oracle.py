@@ -93,6 +93,7 @@ def _setup(lib):
     lib.or_hll_face.argtypes = [ll, vp, vp, ll, vp, vp, i, vp, vp, ll, vp]; lib.or_hll_face.restype = None
     lib.or_fast_speeds.argtypes = [ll, vp, ll, i, vp, vp, vp, vp]; lib.or_fast_speeds.restype = None
     lib.or_rad_speeds.argtypes = [ll, vp, ll, i, vp, vp]; lib.or_rad_speeds.restype = None
+    lib.or_quartic.argtypes = [ll, vp, ll, i, vp, vp, vp]; lib.or_quartic.restype = None
     lib.or_poly_coef.argtypes = [i, vp]; lib.or_poly_coef.restype = i
     lib.or_implicit.argtypes = [ll, vp, ll, vp, vp, vp, vp, vp, ll, vp, vp]; lib.or_implicit.restype = None
     lib.or_four_force.argtypes = [ll, vp, ll, vp, vp, vp, vp, ll]; lib.or_four_force.restype = None
@@ -190,6 +191,16 @@ def fast_speeds(V, d, par=None):
     par = par or params()
     lib().or_fast_speeds(n, _dp(V), n, d, C.byref(par), _dp(lo), _dp(hi), _dp(its))
     return lo, hi, its
+
+
+def quartic(V, d, lam, par=None):
+    """(Q, Q', Q'') of the RMHD quartic of each state at lam (array [3, n])."""
+    V = _soa(V); n = V.shape[1]
+    lam = np.ascontiguousarray(np.broadcast_to(lam, (n,)), dtype=np.float64)
+    out = np.empty((3, n))
+    par = par or params()
+    lib().or_quartic(n, _dp(V), n, d, C.byref(par), _dp(lam), _dp(out))
+    return out
 
 
 def rad_speeds(V, d):

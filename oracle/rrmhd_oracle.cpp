@@ -863,21 +863,23 @@ static real cell_speed(const real V[NV], int d, const OPar& P, const Consts& K) 
 //   Q(l) = w (1 - cs^2) a^4 - (1 - l^2) [(w cs^2 + |b|^2) a^2 - cs^2 B~^2],
 //   a = W (l - v_d),   B~ = b^d - l b^0,   w = rho h,   cs^2 = gamma p / w.
 // Its four roots (the fast and slow magnetosonic speeds) are real and lie in
-// (-1, 1), and Q(+-1) > 0. A polynomial with only real roots is increasing
-// and convex to the right of its largest root (and decreasing and convex to
-// the left of its smallest), so Newton's iteration from l = 1 falls
-// monotonically to the largest root and from l = -1 rises to the smallest
-// (reading: the paper names a root finder without giving it). The iteration
-// stops when Q or Q' no longer has the sign it has outside the roots, when an
-// iterate no longer moves, or after kQuartIt steps; an early stop leaves the
-// speed outside the root, which only widens the HLL fan. Each state gives
-// (min, max); the face takes the min over L and R and the max over L and R.
+// (-1, 1), and Q(+-1) > 0. For a polynomial of degree n with only real roots,
+// Laguerre's iteration
+//   l <- l - n / (G +- sqrt((n - 1)(n H - G^2))),  G = Q'/Q,  H = G^2 - Q''/Q,
+// (sign: that of G, which is > 0 right of all roots and < 0 left of them)
+// started outside the roots moves monotonically, and cubically near the end,
+// to the nearest root: from l = 1 down to the largest, from l = -1 up to the
+// smallest (reading: the paper names a root finder without giving it). The
+// iteration stops when Q is no longer > 0, when an iterate no longer moves,
+// or after kQuartIt steps; an early stop leaves the speed outside the root,
+// which only widens the HLL fan. Each state gives (min, max); the face takes
+// the min over L and R and the max over L and R.
 //
 // Radiation speeds: lambda_r1 and lambda_r3 of both states (eqs. lam1..lam3),
 // the smaller r1 and the larger r3, limited by eq. limits with the optical
 // depth tau = max(tau_L, tau_R) of the two cells next to the face (reading:
 // the same cell depths that give beta of the PVM flux).
-static const int kQuartIt = 40;
+static const int kQuartIt = 20;
 
 struct QuartIn {
   real w1cs;  // w (1 - cs^2)
@@ -885,17 +887,39 @@ struct QuartIn {
   real cs2, W2, vd, bd, b0;
 };
 
-static void quartic(const QuartIn& q, real l, real& Q, real& dQ) {
+// Q, Q' and Q'' at l, from the factored form: with A = a^2 = W^2 (l - v_d)^2,
+// br = (w cs^2 + |b|^2) A - cs^2 B~^2 and om = 1 - l^2, Q = w (1 - cs^2) A^2 - om br.
+static void quartic(const QuartIn& q, real l, real& Q, real& dQ, real& d2Q) {
   const real x = l - q.vd;
-  const real a2 = q.W2 * (x * x);
+  const real A = q.W2 * (x * x);
   const real Bt = q.bd - l * q.b0;
   const real om = 1.0 - l * l;
-  const real br = q.wcsb * a2 - q.cs2 * (Bt * Bt);
-  Q = q.w1cs * (a2 * a2) - om * br;
-  // d(a^2)/dl = 2 W^2 (l - v_d), d(B~^2)/dl = -2 b^0 B~
-  const real da2 = 2.0 * (q.W2 * x);
-  const real dbr = q.wcsb * da2 + 2.0 * (q.cs2 * (q.b0 * Bt));
-  dQ = ((2.0 * q.w1cs) * (a2 * da2) + (2.0 * l) * br) - om * dbr;
+  const real br = q.wcsb * A - q.cs2 * (Bt * Bt);
+  Q = q.w1cs * (A * A) - om * br;
+  // A' = 2 W^2 (l - v_d), A'' = 2 W^2, B~' = -b^0, om' = -2 l, om'' = -2
+  const real dA = 2.0 * (q.W2 * x);
+  const real dbr = q.wcsb * dA + 2.0 * (q.cs2 * (q.b0 * Bt));
+  const real d2br = q.wcsb * (2.0 * q.W2) - 2.0 * (q.cs2 * (q.b0 * q.b0));
+  dQ = ((2.0 * q.w1cs) * (A * dA) + (2.0 * l) * br) - om * dbr;
+  d2Q = (((2.0 * q.w1cs) * (dA * dA + A * (2.0 * q.W2)) + 2.0 * br) + (4.0 * l) * dbr) - om * d2br;
+}
+
+// One Laguerre step for the quartic (n = 4) from l toward the root below
+// (down) or above (!down); returns false when the iteration has ended.
+static bool laguerre_step(const QuartIn& q, bool down, real& l) {
+  real Q, dQ, d2Q;
+  quartic(q, l, Q, dQ, d2Q);
+  if (!(Q > real(0.0))) return false;
+  const real iQ = 1.0 / Q;
+  const real G = dQ * iQ;
+  const real H = G * G - d2Q * iQ;
+  real t = 3.0 * (4.0 * H - G * G);
+  t = (t > real(0.0)) ? t : real(0.0);
+  const real sq = rsqrt_(t);
+  const real ln = l - 4.0 / (down ? (G + sq) : (G - sq));
+  if (!(down ? (ln < l) : (ln > l))) return false;
+  l = ln;
+  return true;
 }
 
 static void fast_speeds(const real V[NV], const Aux& a, int d, const OPar& P, const Consts& K,
@@ -911,26 +935,10 @@ static void fast_speeds(const real V[NV], const Aux& a, int d, const OPar& P, co
   q.b0 = a.b0;
   int n = 0;
   real l = 1.0;
-  for (int it = 0; it < kQuartIt; ++it) {
-    real Q, dQ;
-    quartic(q, l, Q, dQ);
-    if (!(Q > real(0.0)) || !(dQ > real(0.0))) break;
-    const real ln = l - Q / dQ;
-    if (!(ln < l)) break;
-    l = ln;
-    ++n;
-  }
+  for (int it = 0; it < kQuartIt && laguerre_step(q, true, l); ++it) ++n;
   lmax = l;
   l = -1.0;
-  for (int it = 0; it < kQuartIt; ++it) {
-    real Q, dQ;
-    quartic(q, l, Q, dQ);
-    if (!(Q > real(0.0)) || !(dQ < real(0.0))) break;
-    const real ln = l - Q / dQ;
-    if (!(ln > l)) break;
-    l = ln;
-    ++n;
-  }
+  for (int it = 0; it < kQuartIt && laguerre_step(q, false, l); ++it) ++n;
   lmin = l;
   if (iters) *iters = n;
 }
@@ -1333,6 +1341,32 @@ void or_fast_speeds(long long n, const double* V, long long sv, int d, const OPa
     lmin[c] = dv(mn);
     lmax[c] = dv(mx);
     if (iters) iters[c] = it;
+  }
+}
+
+// Q, Q' and Q'' of the RMHD quartic of each state in direction d at l[c].
+void or_quartic(long long n, const double* V, long long sv, int d, const OPar* P, const double* l,
+                double* out /* [3][n] */) {
+  const Consts K = consts_of(*P);
+  for (long long c = 0; c < n; ++c) {
+    real X[NV];
+    for (int q = 0; q < NV; ++q) X[q] = V[q * sv + c];
+    Aux a;
+    prim_aux(X, K, a);
+    QuartIn qi;
+    const real w = X[0] + K.g1 * X[4];
+    qi.cs2 = (P->gamma * X[4]) / w;
+    qi.w1cs = w * (1.0 - qi.cs2);
+    qi.wcsb = w * qi.cs2 + a.bb;
+    qi.W2 = a.W * a.W;
+    qi.vd = X[1 + d];
+    qi.bd = a.b[d];
+    qi.b0 = a.b0;
+    real Q, dQ, d2Q;
+    quartic(qi, real(l[c]), Q, dQ, d2Q);
+    out[c] = dv(Q);
+    out[n + c] = dv(dQ);
+    out[2 * n + c] = dv(d2Q);
   }
 }
 

@@ -102,31 +102,56 @@ def test_fast_speeds_of_field_aligned_flow_add_relativistically(oracle):
     np.testing.assert_allclose(lo[keep], ((v - c) / (1 - v * c))[keep], rtol=0, atol=1e-13)
 
 
+def _numpy_quartic(V, c, d):
+    """The quartic of state c in direction d as a numpy polynomial, built from
+    its definition with numpy's polynomial arithmetic."""
+    P = np.polynomial.Polynomial
+    rho, p = V[0, c], V[4, c]
+    v, Bv = V[1:4, c], V[5:8, c]
+    W = 1 / math.sqrt(1 - v @ v)
+    b0 = W * (v @ Bv)
+    b = Bv / W + v * b0
+    bb = Bv @ Bv / W ** 2 + (v @ Bv) ** 2
+    w = rho + GAMMA / (GAMMA - 1) * p
+    cs2 = GAMMA * p / w
+    a = W * P([-v[d], 1.0])
+    Bt = P([b[d], -b0])
+    return w * (1 - cs2) * a ** 4 - P([1.0, 0.0, -1.0]) * ((w * cs2 + bb) * a ** 2 - cs2 * Bt ** 2)
+
+
+def test_quartic_value_and_derivatives(oracle):
+    """Q, Q' and Q'' that the root finder evaluates (factored form, derivatives
+    written out) equal numpy's expansion of the same polynomial and its
+    derivatives, at points across [-1, 1]."""
+    rng = np.random.default_rng(8)
+    n = 200
+    V = _states(rng, n, vmax=0.99, bscale=3.0)
+    par = oracle.params(gamma=GAMMA)
+    lam = rng.uniform(-1, 1, n)
+    for d in range(3):
+        out = oracle.quartic(V, d, lam, par)
+        for c in range(n):
+            Q = _numpy_quartic(V, c, d)
+            ref = (Q(lam[c]), Q.deriv()(lam[c]), Q.deriv(2)(lam[c]))
+            scale = [np.abs(Q.coef).sum() * (k + 1) ** 2 for k in range(3)]
+            for k in range(3):
+                assert abs(out[k, c] - ref[k]) <= 1e-12 * scale[k], (d, c, k, out[k, c], ref[k])
+
+
 def test_fast_speeds_are_the_extreme_roots_of_the_quartic(oracle):
     """General states: the speeds equal the largest and smallest real roots
     numpy finds (companion-matrix eigenvalues) for the same quartic, and lie
-    in (-1, 1)."""
+    in (-1, 1); Laguerre's iteration gets there in a few steps."""
     rng = np.random.default_rng(5)
     n = 300
     V = _states(rng, n, vmax=0.99, bscale=3.0)
     par = oracle.params(gamma=GAMMA)
-    P = np.polynomial.Polynomial
     for d in range(3):
         lo, hi, its = oracle.fast_speeds(V, d, par)
         assert np.all(-1 < lo) and np.all(lo <= hi) and np.all(hi < 1)
+        assert its.max() <= 16 and its.mean() < 9, (its.max(), its.mean())
         for c in range(n):
-            rho, p = V[0, c], V[4, c]
-            v, Bv = V[1:4, c], V[5:8, c]
-            W = 1 / math.sqrt(1 - v @ v)
-            b0 = W * (v @ Bv)
-            b = Bv / W + v * b0
-            bb = Bv @ Bv / W ** 2 + (v @ Bv) ** 2
-            w = rho + GAMMA / (GAMMA - 1) * p
-            cs2 = GAMMA * p / w
-            a = W * P([-v[d], 1.0])
-            Bt = P([b[d], -b0])
-            Q = w * (1 - cs2) * a ** 4 - P([1.0, 0.0, -1.0]) * ((w * cs2 + bb) * a ** 2 - cs2 * Bt ** 2)
-            r = Q.roots()
+            r = _numpy_quartic(V, c, d).roots()
             r = np.sort(r[np.abs(r.imag) < 1e-6].real)
             assert abs(r[-1] - hi[c]) < 1e-9 and abs(r[0] - lo[c]) < 1e-9, (d, c, r, lo[c], hi[c])
 
