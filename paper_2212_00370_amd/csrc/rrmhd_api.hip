@@ -58,7 +58,7 @@ constexpr int kPicardSplit = RRMHD_PICARD_SPLIT;
 #define RRMHD_FACES_WAVES_MIXED 3
 #endif
 #ifndef RRMHD_FACES_WAVES_HLL
-#define RRMHD_FACES_WAVES_HLL 4
+#define RRMHD_FACES_WAVES_HLL 3
 #endif
 #ifndef RRMHD_UPDATE_WAVES
 #define RRMHD_UPDATE_WAVES 2

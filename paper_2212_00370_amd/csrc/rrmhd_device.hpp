@@ -1242,11 +1242,12 @@ __device__ __forceinline__ double cell_speed(const double V[NV], const Aux& a, c
 // Magnetofluid speeds: the smallest and largest roots of the RMHD quartic
 // (Anile 1989), Q(l) = w (1 - cs^2) a^4 - (1 - l^2)[(w cs^2 + |b|^2) a^2 -
 // cs^2 B~^2] with a = W (l - v_d), B~ = b^d - l b^0, w = rho h. All roots are
-// real and inside (-1, 1), so Newton's iteration from l = +1 (l = -1) moves
-// monotonically down (up) to the largest (smallest) root; it stops when Q or
-// Q' changes the sign it has outside the roots, when an iterate stalls, or
-// after kQuartIt steps, and an early stop only widens the fan. The four roots
-// of a face (min and max of the L and R states) advance together in one
+// real and inside (-1, 1), so Laguerre's iteration for degree 4,
+// l <- l - 4/(G +- sqrt(3 (4H - G^2))), G = Q'/Q, H = G^2 - Q''/Q, moves
+// monotonically from l = +1 (l = -1) down (up) to the largest (smallest) root,
+// cubically near it; it stops when Q is no longer > 0, when an iterate stalls,
+// or after kQuartIt steps, and an early stop only widens the fan. The four
+// roots of a face (min and max of the L and R states) advance together in one
 // straight-line loop, each frozen once its own test stops it: the values are
 // those of four separate loops, with four independent dependency chains for
 // the FP64 pipeline.
@@ -1255,22 +1256,26 @@ __device__ __forceinline__ double cell_speed(const double V[NV], const Aux& a, c
 // limited to |lambda| <= 4/(3 tau) (eq. limits) with tau the larger optical
 // depth of the two cells next to the face. A fan of zero width takes the mean
 // of F_L and F_R.
-constexpr int kQuartIt = 40;
+constexpr int kQuartIt = 20;
 
 struct QuartIn {
   double w1cs, wcsb, cs2, W2, vd, bd, b0;
 };
 
-__device__ __forceinline__ void quartic(const QuartIn& q, double l, double& Q, double& dQ) {
+// Q, Q', Q'' at l from the factored form (A = a^2, br = (w cs^2 + |b|^2) A -
+// cs^2 B~^2, om = 1 - l^2, Q = w (1 - cs^2) A^2 - om br).
+__device__ __forceinline__ void quartic(const QuartIn& q, double l, double& Q, double& dQ, double& d2Q) {
   const double x = l - q.vd;
-  const double a2 = q.W2 * (x * x);
+  const double A = q.W2 * (x * x);
   const double Bt = q.bd - l * q.b0;
   const double om = 1.0 - l * l;
-  const double br = q.wcsb * a2 - q.cs2 * (Bt * Bt);
-  Q = q.w1cs * (a2 * a2) - om * br;
-  const double da2 = 2.0 * (q.W2 * x);
-  const double dbr = q.wcsb * da2 + 2.0 * (q.cs2 * (q.b0 * Bt));
-  dQ = ((2.0 * q.w1cs) * (a2 * da2) + (2.0 * l) * br) - om * dbr;
+  const double br = q.wcsb * A - q.cs2 * (Bt * Bt);
+  Q = q.w1cs * (A * A) - om * br;
+  const double dA = 2.0 * (q.W2 * x);
+  const double dbr = q.wcsb * dA + 2.0 * (q.cs2 * (q.b0 * Bt));
+  const double d2br = q.wcsb * (2.0 * q.W2) - 2.0 * (q.cs2 * (q.b0 * q.b0));
+  dQ = ((2.0 * q.w1cs) * (A * dA) + (2.0 * l) * br) - om * dbr;
+  d2Q = (((2.0 * q.w1cs) * (dA * dA + A * (2.0 * q.W2)) + 2.0 * br) + (4.0 * l) * dbr) - om * d2br;
 }
 
 template <int d>
@@ -1294,13 +1299,17 @@ __device__ __forceinline__ void fast_speeds2(const QuartIn& qL, const QuartIn& q
   for (int it = 0; it < kQuartIt; ++it) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      double Q, dQ;
-      quartic((r < 2) ? qL : qR, lam[r], Q, dQ);
-      const bool up = (r & 1) == 0;  // the smallest root is approached from below
-      const bool side = (Q > 0.0) && (up ? (dQ < 0.0) : (dQ > 0.0));
-      const double ln = lam[r] - Q / dQ;
-      const bool moves = up ? (ln > lam[r]) : (ln < lam[r]);
-      run[r] = run[r] && side && moves;
+      const bool down = (r & 1) != 0;  // the largest root is approached from above
+      double Q, dQ, d2Q;
+      quartic((r < 2) ? qL : qR, lam[r], Q, dQ, d2Q);
+      const double iQ = 1.0 / Q;
+      const double G = dQ * iQ;
+      const double H = G * G - d2Q * iQ;
+      double t = 3.0 * (4.0 * H - G * G);
+      t = (t > 0.0) ? t : 0.0;
+      const double sq = sqrt(t);
+      const double ln = lam[r] - 4.0 / (down ? (G + sq) : (G - sq));
+      run[r] = run[r] && (Q > 0.0) && (down ? (ln < lam[r]) : (ln > lam[r]));
       lam[r] = run[r] ? ln : lam[r];
     }
     if (!(run[0] || run[1] || run[2] || run[3])) break;
