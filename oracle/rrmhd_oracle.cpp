@@ -23,6 +23,7 @@
 //                        so the same source yields the algorithmic operation
 //                        count of the method (results are bitwise unchanged).
 
+#include <cfloat>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -172,7 +173,11 @@ static void p2c(const real V[NV], const Aux& a, real U[NV]) {
 
 // M1 closure (Section 2.2, eq. xi): row d of P_r = D_r E_r with
 // D_r = (1-xi)/2 delta + (3 xi - 1)/2 n n, n = F/|F|, f = |F|/E,
-// xi = (3 + 4 f^2) / (5 + 2 sqrt(4 - 3 f^2)). n n is taken as 0 when F = 0.
+// xi = (3 + 4 f^2) / (5 + 2 sqrt(4 - 3 f^2)). n n is taken as 0 when F = 0,
+// and also when |F|^2 is below the smallest normal double (|F| < 1.5e-154):
+// there n n = F F / |F|^2 would divide by an underflowed |F|^2, while its
+// weight (3 xi - 1)/2 ~ f^2 is negligible.
+static const double kMinNormal = DBL_MIN;
 static void m1_row(real E, const real F[3], int d, real P[3]) {
   const real FF = (F[0] * F[0] + F[1] * F[1]) + F[2] * F[2];
   const real f2 = FF / (E * E);
@@ -182,7 +187,7 @@ static void m1_row(real E, const real F[3], int d, real P[3]) {
   const real xi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * s);
   const real ca = 0.5 * (1.0 - xi);
   const real cb = 0.5 * (3.0 * xi - 1.0);
-  if (FF > real(0.0)) {
+  if (FF >= real(kMinNormal)) {
     const real iFF = 1.0 / FF;
     for (int j = 0; j < 3; ++j) {
       const real nn = (F[d] * F[j]) * iFF;
@@ -589,7 +594,7 @@ static bool imp_build(const real X[4], const real Us[NV], real Et, const real St
   const real ca = 0.5 * (1.0 - xi);
   const real cb = 0.5 * (3.0 * xi - 1.0);
   real Dm[3][3];
-  if (FF > real(0.0)) {
+  if (FF >= real(kMinNormal)) {  // as in m1_row
     const real iFF = 1.0 / FF;
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {

@@ -168,6 +168,26 @@ def alfven_1d(n: int) -> Problem:
                    cfl=0.3, t_end=length / va, extra={"v_a": va, "amplitude": amp})
 
 
+def radiation_rp_1d(test: int, n: int = 256) -> Problem:
+    """Optically thin radiation Riemann problems of Section 4.2 (after Melon
+    Fuksman & Mignone): [-20, 20] with the jump at x = 0, outflow, t = 20.
+    Test 1: (E_r, F_x, F_y) = (1, 0, 1/2) | (1, 0, 0); Test 2: (1/10, 1/10, 0)
+    | (1, 0, 1). No matter-radiation coupling (kappa = sigma = 0): the fluid,
+    which the paper does not specify, is a uniform unmagnetised gas at rest
+    (rho = 1, p = 1). CFL 0.3 and RK3 as in the paper's other tests."""
+    states = {1: ((1.0, 0.0, 0.5), (1.0, 0.0, 0.0)), 2: ((0.1, 0.1, 0.0), (1.0, 0.0, 1.0))}
+    left, right = states[test]
+    dx = 40.0 / n
+    x = -20.0 + (np.arange(n) + 0.5) * dx
+    V = np.zeros((NV, n))
+    V[0] = 1.0
+    V[4] = 1.0
+    for q, (a, b) in zip((8, 9, 10), zip(left, right)):
+        V[q] = np.where(x < 0.0, a, b)
+    return Problem(name=f"radrp{test}_n{n}", shape=(n,), dx=(dx,), x0=(-20.0,), V=V, kappa=np.zeros(n),
+                   sigma=np.zeros(n), gamma=4.0 / 3.0, a_rad=0.0, cfl=0.3, t_end=20.0)
+
+
 def blast_2d(seed: int = 0, nx: int = 512, ny: int | None = None, steps: int = 200,
              e_bg: float = 0.0) -> Problem:
     """Magnetised cylindrical blast on [-1/2, 1/2]^2 (periodic).
