@@ -114,7 +114,13 @@ __device__ __forceinline__ void p2c8(const R V[8], const AuxT<R>& a, R U[8]) {
   for (int q = 5; q < 8; ++q) U[q] = V[q];
 }
 
-// Row d of the M1 radiation pressure P = D_r E_r (eq. xi); n n := 0 when F = 0.
+// Smallest normal double: |F|^2 below it counts as F = 0 in the closure's n n
+// term (F F / |F|^2 would divide by an underflowed |F|^2; the term's weight
+// (3 xi - 1)/2 ~ f^2 is negligible there).
+constexpr double kMinNormal = 0x1p-1022;
+
+// Row d of the M1 radiation pressure P = D_r E_r (eq. xi); n n := 0 when F = 0
+// (or |F|^2 < kMinNormal).
 // The FP32 instantiation works with the reduced flux f = F/E_r (|f| <~ 1):
 // products of raw F_r components underflow FP32 where E_r ~ 1e-11.
 template <int d, typename R>
@@ -149,7 +155,7 @@ __device__ __forceinline__ void m1_row(R E, const R F[3], R P[3]) {
     const R xi = (R(3) + R(4) * f2) / (R(5) + R(2) * s);
     const R ca = R(0.5) * (R(1) - xi);
     const R cb = R(0.5) * (R(3) * xi - R(1));
-    if (FF > R(0)) {
+    if (FF >= R(kMinNormal)) {
       const R iFF = R(1) / FF;
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
@@ -859,7 +865,7 @@ __device__ __forceinline__ bool imp_build(const double X[4], const double Ul[NV]
   const double ca = 0.5 * (1.0 - xi);
   const double cb = 0.5 * (3.0 * xi - 1.0);
   double Dm[3][3];
-  if (FF > 0.0) {
+  if (FF >= kMinNormal) {
     const double iFF = 1.0 / FF;
 #pragma unroll
     for (int i = 0; i < 3; ++i)

@@ -131,3 +131,30 @@ def test_hll_refusals(R, torch_mod):
         B.max_speed([s], [U])
     B.close()
     s.close()
+
+
+@pytest.mark.parametrize("solver", [0, HLL])
+def test_optically_thin_radiation_riemann_full_run(R, oracle, torch_mod, solver):
+    """Section 4.2, Test 1 on 256 cells with PLM VanLeer and RK3 to t = 20,
+    both solvers: bit for bit with the oracle at the end. Ahead of the fronts
+    F_r decays through the underflow range (|F_r|^2 below the smallest normal
+    double), which the closure treats as F_r = 0."""
+    torch = torch_mod
+    P = I.radiation_rp_1d(1, 256)
+    p, op, g, og, s, U, opac = make_case(R, oracle, torch, P, rk_order=3, recon=R.RECON_VANLEER, solver=solver)
+    Ud = dev(torch, U)
+    Uo = U
+    t = 0.0
+    while t < P.t_end * (1 - 1e-14):
+        sm = s.max_speed(Ud)
+        h = min(P.cfl * P.dx[0] / sm, P.t_end - t)
+        s.step(Ud, h, opac)
+        Uo, st, _ = oracle.step(og, Uo, h, P.kappa, P.sigma, op)
+        assert st == 0
+        t += h
+    rep = s.report()
+    Ug = host(Ud)
+    s.close()
+    assert rep["c2p_fail"] == 0 and rep["imp_fail"] == 0 and rep["nonfinite"] == 0
+    assert np.array_equal(Ug, Uo), relerr(Ug, Uo)
+    assert np.min(Ug[8]) > 0.0
