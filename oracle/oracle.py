@@ -66,7 +66,7 @@ DEFAULTS = dict(
     c2p_maxit=100, imp_maxit=50, imp_picard_it=8, imp_method=0, e_floor=0.0, solver=0,
 )
 
-SOLVER_PVM, SOLVER_HLL = 0, 1
+SOLVER_PVM, SOLVER_HLL, SOLVER_PVM_JVP = 0, 1, 2
 
 
 def params(**kw) -> OPar:
@@ -94,6 +94,7 @@ def _setup(lib):
     lib.or_fast_speeds.argtypes = [ll, vp, ll, i, vp, vp, vp, vp]; lib.or_fast_speeds.restype = None
     lib.or_rad_speeds.argtypes = [ll, vp, ll, i, vp, vp]; lib.or_rad_speeds.restype = None
     lib.or_quartic.argtypes = [ll, vp, ll, i, vp, vp, vp]; lib.or_quartic.restype = None
+    lib.or_jvp.argtypes = [ll, vp, vp, ll, i, vp, vp, ll, vp]; lib.or_jvp.restype = None
     lib.or_poly_coef.argtypes = [i, vp]; lib.or_poly_coef.restype = i
     lib.or_implicit.argtypes = [ll, vp, ll, vp, vp, vp, vp, vp, ll, vp, vp]; lib.or_implicit.restype = None
     lib.or_four_force.argtypes = [ll, vp, ll, vp, vp, vp, vp, ll]; lib.or_four_force.restype = None
@@ -191,6 +192,16 @@ def fast_speeds(V, d, par=None):
     par = par or params()
     lib().or_fast_speeds(n, _dp(V), n, d, C.byref(par), _dp(lo), _dp(hi), _dp(its))
     return lo, hi, its
+
+
+def jvp(U, w, d, par=None):
+    """Exact A(U) w (forward mode through the recovery) per state; (Aw, status)."""
+    U = _soa(U); w = _soa(w); n = U.shape[1]
+    assert w.shape == U.shape
+    Aw = np.empty_like(U); st = np.zeros(n, np.int32)
+    par = par or params()
+    lib().or_jvp(n, _dp(U), _dp(w), n, d, C.byref(par), _dp(Aw), n, _dp(st))
+    return Aw, st
 
 
 def quartic(V, d, lam, par=None):

@@ -66,6 +66,35 @@ static inline real rabs(real a) { return (a < real(0.0)) ? -a : a; }
 static inline real rmax(real a, real b) { return (a > b) ? a : b; }
 static inline real rmin(real a, real b) { return (a < b) ? a : b; }
 
+// Dual number v + d e with e^2 = 0: carrying d through an evaluation gives
+// the directional derivative of the result (forward mode). Constants enter
+// with d = 0, and every operation is written on (v, d) pairs so that mixed
+// constant-dual expressions are evaluated as dual-dual ones.
+struct Dual {
+  real v, d;
+  Dual() : v(0.0), d(0.0) {}
+  Dual(real a) : v(a), d(0.0) {}
+#ifdef ORACLE_COUNT_OPS
+  Dual(double a) : v(a), d(0.0) {}
+#endif
+  Dual(real a, real b) : v(a), d(b) {}
+};
+static inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+static inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+static inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+static inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.v * b.d + a.d * b.v); }
+static inline Dual operator/(Dual a, Dual b) {
+  const real q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+static inline Dual rsqrt_(Dual a) {
+  const real r = rsqrt_(a.v);
+  return Dual(r, a.d / (real(2.0) * r));
+}
+static inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
+static inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
+static inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
+
 // Variable order. Conserved U and primitive V share slots 5..11 (B, E_r, F_r
 // are both primitive and conserved; Section 2.1).
 enum { NV = 12 };
@@ -92,7 +121,8 @@ struct OPar {
   int imp_picard_it; // Picard (lagged) iterations before Newton takes over
   int imp_method;    // 0: Picard then Newton; 1: Newton only; 2: Picard only
   double e_floor;    // > 0: a non-positive explicit E_r is raised to this (counted); 0: failure
-  int solver;        // 0: PVM-int (Section 3.2); 1: Rad-HLL (Section 3.2, Radiative HLL)
+  int solver;        // 0: PVM-int (Section 3.2); 1: Rad-HLL (Section 3.2, Radiative HLL);
+                     // 2: PVM-int with exact Jacobian-vector products
 };
 
 struct OGrid {
@@ -132,28 +162,33 @@ static Consts consts_of(const OPar& P) {
 // eqs. eqU/eqF): W, b^0 = W (v.B), b^i = B^i/W + v^i b^0,
 // |b|^2 = B^2/W^2 + (v.B)^2, total enthalpy density rho h* = rho h + |b|^2
 // (the printed h* carries a typo gamma/rho for p/rho), p* = p + |b|^2/2.
-struct Aux {
-  real W, iW, l2;     // Lorentz factor, 1/W, 1/W^2 = 1 - v^2
-  real b0, b[3], bb;  // magnetic four-vector components and |b|^2
-  real wtot;          // rho h* W^2
-  real ps;            // total pressure p*
-  real D;             // rho W
+// Templated on the scalar T: `real` for the method itself, Dual (below) for
+// the forward-mode derivatives of the exact-JVP variant.
+template <class T>
+struct AuxT {
+  T W, iW, l2;     // Lorentz factor, 1/W, 1/W^2 = 1 - v^2
+  T b0, b[3], bb;  // magnetic four-vector components and |b|^2
+  T wtot;          // rho h* W^2
+  T ps;            // total pressure p*
+  T D;             // rho W
 };
+using Aux = AuxT<real>;
 
 // From l2 = 1 - v^2 and iW = 1/W = sqrt(l2) of the state.
-static void prim_aux_lw(const real V[NV], real l2, real iW, const Consts& K, Aux& a) {
-  const real vx = V[1], vy = V[2], vz = V[3];
+template <class T>
+static void prim_aux_lw(const T V[NV], T l2, T iW, const Consts& K, AuxT<T>& a) {
+  const T vx = V[1], vy = V[2], vz = V[3];
   a.l2 = l2;
   a.iW = iW;
-  a.W = 1.0 / a.iW;
-  const real vB = (vx * V[5] + vy * V[6]) + vz * V[7];
+  a.W = T(1.0) / a.iW;
+  const T vB = (vx * V[5] + vy * V[6]) + vz * V[7];
   a.b0 = a.W * vB;
   for (int j = 0; j < 3; ++j) a.b[j] = V[5 + j] * a.iW + V[1 + j] * a.b0;
-  const real B2 = (V[5] * V[5] + V[6] * V[6]) + V[7] * V[7];
+  const T B2 = (V[5] * V[5] + V[6] * V[6]) + V[7] * V[7];
   a.bb = B2 * a.l2 + vB * vB;
-  const real rhoh = V[0] + K.g1 * V[4];
+  const T rhoh = V[0] + T(K.g1) * V[4];
   a.wtot = (rhoh + a.bb) * (a.W * a.W);
-  a.ps = V[4] + 0.5 * a.bb;
+  a.ps = V[4] + T(0.5) * a.bb;
   a.D = V[0] * a.W;
 }
 
@@ -178,31 +213,33 @@ static void p2c(const real V[NV], const Aux& a, real U[NV]) {
 // there n n = F F / |F|^2 would divide by an underflowed |F|^2, while its
 // weight (3 xi - 1)/2 ~ f^2 is negligible.
 static const double kMinNormal = DBL_MIN;
-static void m1_row(real E, const real F[3], int d, real P[3]) {
-  const real FF = (F[0] * F[0] + F[1] * F[1]) + F[2] * F[2];
-  const real f2 = FF / (E * E);
-  real t = 4.0 - 3.0 * f2;
-  t = (t > real(0.0)) ? t : real(0.0);
-  const real s = rsqrt_(t);
-  const real xi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * s);
-  const real ca = 0.5 * (1.0 - xi);
-  const real cb = 0.5 * (3.0 * xi - 1.0);
-  if (FF >= real(kMinNormal)) {
-    const real iFF = 1.0 / FF;
+template <class T>
+static void m1_row(T E, const T F[3], int d, T P[3]) {
+  const T FF = (F[0] * F[0] + F[1] * F[1]) + F[2] * F[2];
+  const T f2 = FF / (E * E);
+  T t = T(4.0) - T(3.0) * f2;
+  t = (t > T(0.0)) ? t : T(0.0);
+  const T s = rsqrt_(t);
+  const T xi = (T(3.0) + T(4.0) * f2) / (T(5.0) + T(2.0) * s);
+  const T ca = T(0.5) * (T(1.0) - xi);
+  const T cb = T(0.5) * (T(3.0) * xi - T(1.0));
+  if (FF >= T(kMinNormal)) {
+    const T iFF = T(1.0) / FF;
     for (int j = 0; j < 3; ++j) {
-      const real nn = (F[d] * F[j]) * iFF;
+      const T nn = (F[d] * F[j]) * iFF;
       P[j] = (j == d) ? E * (ca + cb * nn) : E * (cb * nn);
     }
   } else {
-    for (int j = 0; j < 3; ++j) P[j] = (j == d) ? E * ca : real(0.0);
+    for (int j = 0; j < 3; ++j) P[j] = (j == d) ? E * ca : T(0.0);
   }
 }
 
 // Physical flux in direction d, eq. eqF.
-static void flux(const real V[NV], const Aux& a, int d, real F[NV]) {
-  const real vd = V[1 + d];
+template <class T>
+static void flux(const T V[NV], const AuxT<T>& a, int d, T F[NV]) {
+  const T vd = V[1 + d];
   F[0] = a.D * vd;
-  const real wv = a.wtot * vd;
+  const T wv = a.wtot * vd;
   for (int j = 0; j < 3; ++j) {
     if (j == d) F[1 + j] = (wv * V[1 + j] + a.ps) - a.b[d] * a.b[j];
     else        F[1 + j] = wv * V[1 + j] - a.b[d] * a.b[j];
@@ -445,6 +482,126 @@ static void pvm_face(const real VL[NV], const real VR[NV], real tauL, real tauR,
       fo.fallback = 1;
       for (int q = 0; q < NV; ++q) Uk[q] = U0[q];
     }
+  }
+  for (int q = 0; q < NV; ++q) {
+    const real bq = (P.beta_mode == 2 || (P.beta_mode == 1 && q < 8)) ? real(1.0) : beta;
+    Fh[q] = 0.5 * (FL[q] + FR[q]) - 0.5 * (bq * Uk[q]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exact-JVP variant of the PVM-int flux. The polynomial viscosity p_k(A) U_0
+// of eq. utilde is evaluated with the same Horner scheme in A^2, but each
+// product A w = (dF/dU)(U_m) w is the exact directional derivative of
+// U -> F(V(U)) at U_m, taken in forward mode (Dual), instead of the nested
+// finite differences with step eps of eq. iterat. The recovery V(U) is
+// differentiated implicitly: at its converged Z, the residual
+//   f(Z; U) = (Z + B^2) - p - B^2 (1 - v^2)/2 - (S.B/Z)^2/2 - (tau + D)
+// (the closed relations of eq. eqU, as in c2p_eval, not scaled) gives
+//   dZ = -(df/dU . w) / (df/dZ),
+// and V follows from Z by the same closed relations:
+//   v = (S + (S.B/Z) B)/(Z + B^2), 1 - v^2, 1/W = sqrt(1 - v^2),
+//   rho = D/W, p = (gamma-1)/gamma (Z (1 - v^2) - rho).
+// The radiation rows need no recovery (E_r, F_r are conserved and primitive).
+// A recovery failure at U_m drops the face to p_0 = 1, as in pvm_face.
+struct C2PInD {
+  Dual D, S[3], B[3], Et, B2, S2, SB;
+};
+
+static C2PInD c2p_in_dual(const real U[NV], const real w[NV]) {
+  C2PInD in;
+  in.D = Dual(U[0], w[0]);
+  for (int j = 0; j < 3; ++j) {
+    in.S[j] = Dual(U[1 + j], w[1 + j]);
+    in.B[j] = Dual(U[5 + j], w[5 + j]);
+  }
+  in.Et = Dual(U[4], w[4]) + in.D;
+  in.B2 = (in.B[0] * in.B[0] + in.B[1] * in.B[1]) + in.B[2] * in.B[2];
+  in.S2 = (in.S[0] * in.S[0] + in.S[1] * in.S[1]) + in.S[2] * in.S[2];
+  in.SB = (in.S[0] * in.B[0] + in.S[1] * in.B[1]) + in.S[2] * in.B[2];
+  return in;
+}
+
+// V (fluid part, with B), 1 - v^2 and 1/W from Z; and the residual f.
+static Dual c2p_closed(Dual Z, const C2PInD& in, const Consts& K, Dual V[NV], Dual& l2, Dual& iW) {
+  const Dual vB = in.SB / Z;
+  const Dual iZb = Dual(1.0) / (Z + in.B2);
+  const Dual v2 = (in.S2 + (vB * vB) * (Z + (Z + in.B2))) * (iZb * iZb);
+  l2 = Dual(1.0) - v2;
+  iW = rsqrt_(l2);
+  const Dual rho = in.D * iW;
+  const Dual p = Dual(K.gm1g) * (Z * l2 - rho);
+  V[0] = rho;
+  for (int j = 0; j < 3; ++j) V[1 + j] = (in.S[j] + vB * in.B[j]) * iZb;
+  V[4] = p;
+  for (int j = 0; j < 3; ++j) V[5 + j] = in.B[j];
+  return (((Z + in.B2) - p) - Dual(0.5) * (in.B2 * l2)) - (Dual(0.5) * (vB * vB) + in.Et);
+}
+
+// df/dZ at the converged Z of U_m.
+static real c2p_dfdZ(const real Um[NV], real Zm, const Consts& K) {
+  real zero[NV];
+  for (int q = 0; q < NV; ++q) zero[q] = 0.0;
+  const C2PInD in = c2p_in_dual(Um, zero);
+  Dual V[NV], l2, iW;
+  return c2p_closed(Dual(Zm, real(1.0)), in, K, V, l2, iW).d;
+}
+
+// A w at U_m (all 12 rows) in direction d.
+static void jvp_flux(const real Um[NV], real Zm, real fZ, const real w[NV], int d, const Consts& K,
+                     real Aw[NV]) {
+  const C2PInD in = c2p_in_dual(Um, w);
+  Dual V[NV], l2, iW;
+  const real fU = c2p_closed(Dual(Zm), in, K, V, l2, iW).d;
+  const real dZ = -(fU / fZ);
+  c2p_closed(Dual(Zm, dZ), in, K, V, l2, iW);
+  for (int q = 8; q < NV; ++q) V[q] = Dual(Um[q], w[q]);
+  AuxT<Dual> a;
+  prim_aux_lw(V, l2, iW, K, a);
+  Dual F[NV];
+  flux(V, a, d, F);
+  for (int q = 0; q < NV; ++q) Aw[q] = F[q].d;
+}
+
+static void pvm_face_jvp(const real VL[NV], const real VR[NV], real tauL, real tauR, int d,
+                         const OPar& P, const Consts& K, const double* coef, int M,
+                         real Fh[NV], FaceOut& fo) {
+  Aux aL, aR;
+  prim_aux(VL, K, aL);
+  prim_aux(VR, K, aR);
+  real UL[NV], UR[NV], FL[NV], FR[NV];
+  p2c(VL, aL, UL); flux(VL, aL, d, FL);
+  p2c(VR, aR, UR); flux(VR, aR, d, FR);
+  real U0[NV], Um[NV];
+  for (int q = 0; q < NV; ++q) { U0[q] = UR[q] - UL[q]; Um[q] = 0.5 * (UL[q] + UR[q]); }
+  const real beta = 1.0 / rmax(rmax(tauL, tauR), real(1.0));
+  fo.fallback = 0;
+  fo.c2p_it = 0;
+  real Uk[NV];
+  for (int q = 0; q < NV; ++q) Uk[q] = U0[q];
+  if (M > 0) {
+    real Vm[NV], Zm = 0.0;
+    int it = 0;
+    if (c2p(Um, P, K, real(0.0), Vm, &Zm, &it) != 0) {
+      fo.fallback = 1;
+    } else {
+      const real fZ = c2p_dfdZ(Um, Zm, K);
+      real w[NV], t1[NV], t2[NV];
+      for (int q = 0; q < NV; ++q) w[q] = U0[q];
+      for (int l = 0; l < M; ++l) {
+        jvp_flux(Um, Zm, fZ, w, d, K, t1);
+        jvp_flux(Um, Zm, fZ, t1, d, K, t2);
+        const real cnext = coef[M - 1 - l];
+        if (l == 0) {
+          const real ctop = coef[M];
+          for (int q = 0; q < NV; ++q) w[q] = ctop * t2[q] + cnext * U0[q];
+        } else {
+          for (int q = 0; q < NV; ++q) w[q] = t2[q] + cnext * U0[q];
+        }
+      }
+      for (int q = 0; q < NV; ++q) Uk[q] = w[q];
+    }
+    fo.c2p_it = it;
   }
   for (int q = 0; q < NV; ++q) {
     const real bq = (P.beta_mode == 2 || (P.beta_mode == 1 && q < 8)) ? real(1.0) : beta;
@@ -1133,6 +1290,7 @@ static long long stage_faces(const Grid& G, const OPar& P, const Consts& K, cons
     real Fq[NV];
     FaceOut fo;
     if (P.solver == 1) hll_face(VL, VR, tauL, tauR, d, P, K, Fq, fo);
+    else if (P.solver == 2) pvm_face_jvp(VL, VR, tauL, tauR, d, P, K, coef, M, Fq, fo);
     else pvm_face(VL, VR, tauL, tauR, d, P, K, coef, M, Fq, fo);
     nfb += fo.fallback;
     for (int q = 0; q < NV; ++q) Fh[q * nf + f] = dv(Fq[q]);
@@ -1308,7 +1466,8 @@ void or_pvm_face(long long n, const double* VL, const double* VR, long long sv, 
     real L[NV], Rr[NV], Fq[NV];
     for (int q = 0; q < NV; ++q) { L[q] = VL[q * sv + c]; Rr[q] = VR[q * sv + c]; }
     FaceOut fo;
-    pvm_face(L, Rr, real(tauL[c]), real(tauR[c]), d, *P, K, coef, M, Fq, fo);
+    if (P->solver == 2) pvm_face_jvp(L, Rr, real(tauL[c]), real(tauR[c]), d, *P, K, coef, M, Fq, fo);
+    else pvm_face(L, Rr, real(tauL[c]), real(tauR[c]), d, *P, K, coef, M, Fq, fo);
     for (int q = 0; q < NV; ++q) Fh[q * sf + c] = dv(Fq[q]);
     if (fallback) fallback[c] = fo.fallback;
     if (c2p_its) c2p_its[c] = fo.c2p_it;
@@ -1346,6 +1505,27 @@ void or_fast_speeds(long long n, const double* V, long long sv, int d, const OPa
     lmin[c] = dv(mn);
     lmax[c] = dv(mx);
     if (iters) iters[c] = it;
+  }
+}
+
+// A w at the conserved states U (exact JVP through the recovery), direction d;
+// status[c] != 0 where the recovery of U fails.
+void or_jvp(long long n, const double* U, const double* w, long long su, int d, const OPar* P, double* Aw,
+            long long sa, int* status) {
+  const Consts K = consts_of(*P);
+  for (long long c = 0; c < n; ++c) {
+    real X[NV], W[NV], V[NV], out[NV];
+    for (int q = 0; q < NV; ++q) { X[q] = U[q * su + c]; W[q] = w[q * su + c]; }
+    real Z = 0.0;
+    int it = 0;
+    const int st = c2p(X, *P, K, real(0.0), V, &Z, &it);
+    if (status) status[c] = st;
+    if (st != 0) {
+      for (int q = 0; q < NV; ++q) Aw[q * sa + c] = 0.0;
+      continue;
+    }
+    jvp_flux(X, Z, c2p_dfdZ(X, Z, K), W, d, K, out);
+    for (int q = 0; q < NV; ++q) Aw[q * sa + c] = dv(out[q]);
   }
 }
 
