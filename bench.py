@@ -227,8 +227,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
-    ap.add_argument("--solver", choices=("pvm", "hll"), default="pvm",
-                    help="face flux: PVM-int-8 (the method) or Rad-HLL (the paper's comparison solver)")
+    ap.add_argument("--solver", choices=("pvm", "hll", "jvp"), default="pvm",
+                    help="face flux: PVM-int-8 (the method), Rad-HLL (the paper's comparison solver) or "
+                         "PVM-int-8 with exact Jacobian-vector products")
     ap.add_argument("--mode", choices=("step", "serving", "beam3d", "copycal"), default="step")
     ap.add_argument("--requests", type=int, default=120)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate / measured capacity")
@@ -265,11 +266,13 @@ def main():
     P = I.blast_2d(args.seed, args.n, steps=args.steps)
     mixed = args.precision == "mixed"
     hll = args.solver == "hll"
-    if hll and mixed:
-        print("Rad-HLL runs in FP64 only", file=sys.stderr)
+    solver_id = {"pvm": R.SOLVER_PVM, "hll": R.SOLVER_HLL, "jvp": R.SOLVER_PVM_JVP}[args.solver]
+    solver_name = {"pvm": "PVM-int-8", "hll": "Rad-HLL", "jvp": "PVM-int-8 (exact JVP)"}[args.solver]
+    if args.solver != "pvm" and mixed:
+        print(f"{solver_name} runs in FP64 only", file=sys.stderr)
         sys.exit(2)
     params = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=R.MIXED if mixed else R.FP64,
-                                    solver=R.SOLVER_HLL if hll else R.SOLVER_PVM)
+                                    solver=solver_id)
     grid = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
     solver = R.Solver(grid, params, device=dev)
     V = torch.from_numpy(P.V).to(dev)
@@ -325,7 +328,8 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
 
     # roofline of the dominant kernel (face fluxes)
-    ops = load_json(os.path.join(ROOT, "oracle", f"opcount_blast2d_{args.n}{'_hll' if hll else ''}.json"))
+    sfx = {"pvm": "", "hll": "_hll", "jvp": "_jvp"}[args.solver]
+    ops = load_json(os.path.join(ROOT, "oracle", f"opcount_blast2d_{args.n}{sfx}.json"))
     fms, flaunch, ffaces = prof["faces"]
     roof = None
     if ops and flaunch > 0 and not mixed:
@@ -334,12 +338,13 @@ def main():
         flops_per_launch = per_face * ffaces / flaunch
         achieved = flops_per_launch / mean_s / 1e12
         traffic = None
-        tr = None if hll else load_json(os.path.join(ROOT, "profiles", f"traffic_k_faces_blast2d_{args.n}.json"))
+        tr = None if args.solver != "pvm" else load_json(
+            os.path.join(ROOT, "profiles", f"traffic_k_faces_blast2d_{args.n}.json"))
         if tr and tr.get("sources_sha256") == kernel_sources_digest():
             traffic = tr.get("hbm_bytes_per_launch")
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_faces (PLM MinMod + " + ("Rad-HLL" if hll else "PVM-int-8") + " face flux)",
+                "kernel": "k_faces (PLM MinMod + " + solver_name + " face flux)",
                 "ops_per_face": round(per_face, 1), "faces_per_launch": ffaces // flaunch,
                 "mean_launch_ms": round(1e3 * mean_s, 4)}
 
@@ -358,7 +363,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D RRMHD+M1 magnetised blast {P.shape[0]}x{P.shape[1]} "
                                f"{'mixed FP32/FP64' if mixed else 'FP64'}, seed {args.seed}, "
-                               f"{'Rad-HLL' if hll else 'PVM-int-8'}, PLM MinMod, IMEX RK2, CFL {P.cfl}, "
+                               f"{solver_name}, PLM MinMod, IMEX RK2, CFL {P.cfl}, "
                                f"{args.steps} steps",
                    "cells": P.ncell, "precision": args.precision, "solver": args.solver,
                    "beta_mode": "radiation rows" if not hll else None},
@@ -368,7 +373,7 @@ def main():
         "failures": {k: rep[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(P, args.cpu_steps, R.SOLVER_HLL if hll else R.SOLVER_PVM)
+        out["cpu_baseline"] = cpu_baseline(P, args.cpu_steps, solver_id)
     print(json.dumps(out), flush=True)
 
 

@@ -52,12 +52,15 @@ enum { RRMHD_RECON_GODUNOV = 0, RRMHD_RECON_MINMOD = 1, RRMHD_RECON_MC = 2, RRMH
 enum { RRMHD_BETA_ALL = 0, RRMHD_BETA_RAD_ONLY = 1, RRMHD_BETA_OFF = 2 };
 enum { RRMHD_IMP_PICARD_NEWTON = 0, RRMHD_IMP_NEWTON = 1, RRMHD_IMP_PICARD = 2 };
 /* Face flux (Section 3.2). RRMHD_SOLVER_PVM: the Jacobian-free PVM-int flux
- * with the opacity factor beta. RRMHD_SOLVER_HLL: Rad-HLL, the HLL flux with
- * separate signal speeds for the magnetofluid rows (extreme roots of the RMHD
- * quartic) and the radiation rows (eqs. lam1-lam3, limited by eq. limits);
- * FP64 only (precision RRMHD_MIXED with it is RRMHD_E_INVALID), and not
- * available to the batched entry points. */
-enum { RRMHD_SOLVER_PVM = 0, RRMHD_SOLVER_HLL = 1 };
+ * with the opacity factor beta (nested finite differences with step pvm_eps).
+ * RRMHD_SOLVER_HLL: Rad-HLL, the HLL flux with separate signal speeds for the
+ * magnetofluid rows (extreme roots of the RMHD quartic) and the radiation rows
+ * (eqs. lam1-lam3, limited by eq. limits). RRMHD_SOLVER_PVM_JVP: the same
+ * PVM-int polynomial with every Jacobian-vector product exact (forward-mode
+ * derivative through the primitive recovery) instead of a difference; pvm_eps
+ * is unused. HLL and PVM_JVP are FP64 only (precision RRMHD_MIXED with them is
+ * RRMHD_E_INVALID) and not available to the batched entry points. */
+enum { RRMHD_SOLVER_PVM = 0, RRMHD_SOLVER_HLL = 1, RRMHD_SOLVER_PVM_JVP = 2 };
 /* Precision of the explicit step. RRMHD_FP64: everything in binary64.
  * RRMHD_MIXED: reconstruction, fluxes and the PVM Horner / finite-difference
  * arithmetic in binary32 with a relative difference step pvm_eps_mixed; all

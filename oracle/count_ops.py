@@ -8,13 +8,13 @@ each) of
     per face, both directions;
   * the cell primitive recovery of a stage, per cell;
   * the implicit radiation-matter solve of the first stage, per cell.
-With --solver hll the run and the face count use Rad-HLL instead of
-PVM-int-8 (``opcount_blast2d_512_hll.json``).
+With --solver hll (jvp) the run and the face count use Rad-HLL (the exact-JVP
+PVM-int-8 flux) instead (``opcount_blast2d_512_hll.json``, ``..._jvp.json``).
 Writes ``opcount_blast2d_512.json`` next to this file. Test infrastructure:
 the GPU library does not read it; the benchmark reads the per-face figure to
 turn measured kernel time into achieved FLOP/s.
 
-usage: python oracle/count_ops.py [--n 512] [--snapshots 0,100,200] [--solver pvm|hll]
+usage: python oracle/count_ops.py [--n 512] [--snapshots 0,100,200] [--solver pvm|hll|jvp]
 """
 from __future__ import annotations
 
@@ -51,13 +51,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--snapshots", default="0,100,200")
-    ap.add_argument("--solver", choices=("pvm", "hll"), default="pvm")
+    ap.add_argument("--solver", choices=("pvm", "hll", "jvp"), default="pvm")
     args = ap.parse_args()
-    hll = args.solver == "hll"
+    sid = {"pvm": O.SOLVER_PVM, "hll": O.SOLVER_HLL, "jvp": O.SOLVER_PVM_JVP}[args.solver]
+    sname = {"pvm": "beta on radiation rows, PVM-int-8", "hll": "Rad-HLL",
+             "jvp": "beta on radiation rows, PVM-int-8 with exact JVP"}[args.solver]
     snaps = sorted(int(s) for s in args.snapshots.split(","))
     O.threads(0)
     P = I.blast_2d(0, args.n)
-    par = O.params(gamma=P.gamma, a_rad=P.a_rad, beta_mode=1, solver=O.SOLVER_HLL if hll else O.SOLVER_PVM)
+    par = O.params(gamma=P.gamma, a_rad=P.a_rad, beta_mode=1, solver=sid)
     g = O.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
     U = O.p2c(P.V, par)
     N = P.ncell
@@ -101,8 +103,7 @@ def main():
         rows.append(row)
     mean = lambda k: float(np.mean([r[k] for r in rows]))
     res = dict(
-        workload=(f"2D RRMHD+M1 blast {args.n}x{args.n}, seed 0, "
-                  + ("Rad-HLL" if hll else "beta on radiation rows, PVM-int-8") + ", PLM MinMod, RK2"),
+        workload=f"2D RRMHD+M1 blast {args.n}x{args.n}, seed 0, {sname}, PLM MinMod, RK2",
         counting="+ - * / sqrt of the oracle (op-counting build), one each; no fused multiply-add is used",
         snapshots=rows,
         faces_ops_per_face=mean("faces_ops_per_face"),
@@ -110,7 +111,8 @@ def main():
         implicit_ops_per_cell=mean("implicit_ops_per_cell"),
         divergence_ops_per_cell=12 * (2 * 2 + 3),
     )
-    with open(os.path.join(HERE, f"opcount_blast2d_{args.n}{'_hll' if hll else ''}.json"), "w") as f:
+    sfx = {"pvm": "", "hll": "_hll", "jvp": "_jvp"}[args.solver]
+    with open(os.path.join(HERE, f"opcount_blast2d_{args.n}{sfx}.json"), "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps({k: v for k, v in res.items() if k != "snapshots"}))
 

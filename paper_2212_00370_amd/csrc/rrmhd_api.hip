@@ -3,8 +3,8 @@
 // One IMEX step (Section 3.1 of Lopez-Miralles, Marti & Perucho, CPC,
 // arXiv 2212.00370) is, per Runge-Kutta stage:
 //   k_prims   : cell primitive recovery of the stage state -> V, D(kappa+sigma)
-//   k_faces   : per face of every direction, PLM + PVM-int or Rad-HLL flux
-//               (Section 3.2) -> F^_d
+//   k_faces   : per face of every direction, PLM + PVM-int (eps differences or
+//               exact JVP) or Rad-HLL flux (Section 3.2) -> F^_d
 //   k_update  : U* = a0 U^(0) + a1 U^(s) - c dt sum_d dF^_d/dx_d (eq. explicit)
 //               followed by the per-cell implicit source solve (Section 3.3)
 // All kernels read and write structure-of-arrays float64 planes in HBM; one
@@ -59,6 +59,9 @@ constexpr int kPicardSplit = RRMHD_PICARD_SPLIT;
 #endif
 #ifndef RRMHD_FACES_WAVES_HLL
 #define RRMHD_FACES_WAVES_HLL 3
+#endif
+#ifndef RRMHD_FACES_WAVES_JVP
+#define RRMHD_FACES_WAVES_JVP 2
 #endif
 #ifndef RRMHD_UPDATE_WAVES
 #define RRMHD_UPDATE_WAVES 2
@@ -331,7 +334,7 @@ struct FaceArgs {
 // then the PVM-int flux with beta from the two adjacent cells. REC >= 0 fixes
 // the limiter at compile time (the launch picks the MinMod copy when K.recon
 // is MinMod); REC < 0 reads K.recon.
-template <int d, int REC, bool HLL>
+template <int d, int REC, int SOLVER>
 __device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, long long f, const Phys& K,
                                           unsigned long long& fb, unsigned int& its) {
   int fn0 = G.n[0], fn1 = G.n[1];
@@ -369,7 +372,8 @@ __device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, l
   const double tauL = tp[1] * A.dx[d], tauR = tp[2] * A.dx[d];
   double Fq[NV];
   int fallback = 0, cit = 0;
-  if constexpr (HLL) rr::hll_face<d>(VL, VR, tauL, tauR, K, Fq);
+  if constexpr (SOLVER == RRMHD_SOLVER_HLL) rr::hll_face<d>(VL, VR, tauL, tauR, K, Fq);
+  else if constexpr (SOLVER == RRMHD_SOLVER_PVM_JVP) rr::pvm_face_jvp<d>(VL, VR, tauL, tauR, K, Fq, fallback, cit);
   else rr::pvm_face<d>(VL, VR, tauL, tauR, K, Fq, fallback, cit);
   double* out = A.Fh[d];
   const long long nf = A.nf[d];
@@ -431,7 +435,7 @@ __device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs
 // Face fluxes of all directions in one launch: blocks [0, nb0) take x faces,
 // the next nb1 blocks y faces, then z. The direction is uniform per block.
 // MIXED selects the mixed-precision stencil (FP32 fluxes out).
-template <bool MIXED, int REC, bool HLL = false>
+template <bool MIXED, int REC, int SOLVER = RRMHD_SOLVER_PVM>
 __device__ __forceinline__ void faces_block(long long lb, const GridDev& G, const FaceArgs& A, const Phys& K,
                                             DevReport* rep, unsigned int* blkmax) {
   long long b = lb;
@@ -446,9 +450,9 @@ __device__ __forceinline__ void faces_block(long long lb, const GridDev& G, cons
   unsigned int its = 0;
   if (f < A.nf[d]) {
     if constexpr (!MIXED) {
-      if (d == 0) face_body<0, REC, HLL>(G, A, f, K, fb, its);
-      else if (d == 1) face_body<1, REC, HLL>(G, A, f, K, fb, its);
-      else face_body<2, REC, HLL>(G, A, f, K, fb, its);
+      if (d == 0) face_body<0, REC, SOLVER>(G, A, f, K, fb, its);
+      else if (d == 1) face_body<1, REC, SOLVER>(G, A, f, K, fb, its);
+      else face_body<2, REC, SOLVER>(G, A, f, K, fb, its);
     } else {
       if (d == 0) face_body_mixed<0, REC>(G, A, f, K, fb, its);
       else if (d == 1) face_body_mixed<1, REC>(G, A, f, K, fb, its);
@@ -535,9 +539,11 @@ __device__ __forceinline__ void order_block(const BlockOrder& O) {
 // blocks do the step's time step (dt_block, with R.partial set) and the next
 // update pass's block order (order_block, with O.cost set); the rest take the
 // faces. The update pass, which reads both, runs after this launch.
-template <typename FT, int REC, bool HLL>
+template <typename FT, int REC, int SOLVER>
 __global__ void __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(HLL ? RRMHD_FACES_WAVES_HLL
+__attribute__((amdgpu_waves_per_eu(SOLVER == RRMHD_SOLVER_HLL ? RRMHD_FACES_WAVES_HLL
+                                   : SOLVER == RRMHD_SOLVER_PVM_JVP
+                                       ? RRMHD_FACES_WAVES_JVP
                                        : (sizeof(FT) == sizeof(double) ? RRMHD_FACES_WAVES : RRMHD_FACES_WAVES_MIXED))))
 k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, unsigned long long* wreset,
         DtReduce R, BlockOrder O) {
@@ -558,7 +564,7 @@ k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, uns
     }
     b -= 1;
   }
-  faces_block<sizeof(FT) == sizeof(float), REC, HLL>(b, G, A, K, rep, blkmax);
+  faces_block<sizeof(FT) == sizeof(float), REC, SOLVER>(b, G, A, K, rep, blkmax);
 }
 
 struct StageArgs {
@@ -1118,8 +1124,9 @@ bool params_valid(const rrmhd_params* p) {
   if (!(p->e_floor >= 0.0)) return false;
   if (p->precision != RRMHD_FP64 && p->precision != RRMHD_MIXED) return false;
   if (!(p->pvm_eps_mixed > 0.0 && p->pvm_eps_mixed < 0.5)) return false;
-  if (p->solver != RRMHD_SOLVER_PVM && p->solver != RRMHD_SOLVER_HLL) return false;
-  if (p->solver == RRMHD_SOLVER_HLL && p->precision != RRMHD_FP64) return false;
+  if (p->solver != RRMHD_SOLVER_PVM && p->solver != RRMHD_SOLVER_HLL && p->solver != RRMHD_SOLVER_PVM_JVP)
+    return false;
+  if (p->solver != RRMHD_SOLVER_PVM && p->precision != RRMHD_FP64) return false;
   return true;
 }
 
@@ -1346,14 +1353,17 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   const unsigned int nlaunch = (unsigned int)(nbt + (R.partial ? 1 : 0) + 1);
   pe = prof_begin(c, RRMHD_K_FACES, A.nf[0] + A.nf[1] + A.nf[2]);
   const bool mm = c->K.recon == RRMHD_RECON_MINMOD;
-  if (c->par.solver == RRMHD_SOLVER_HLL) {
-    k_faces<double, -1, true><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+  constexpr int PVM = RRMHD_SOLVER_PVM, HLL = RRMHD_SOLVER_HLL, JVP = RRMHD_SOLVER_PVM_JVP;
+  if (c->par.solver == HLL) {
+    k_faces<double, -1, HLL><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+  } else if (c->par.solver == JVP) {
+    k_faces<double, -1, JVP><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
   } else if (c->par.precision == RRMHD_MIXED) {
-    if (mm) k_faces<float, 1, false><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
-    else k_faces<float, -1, false><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    if (mm) k_faces<float, 1, PVM><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    else k_faces<float, -1, PVM><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
   } else {
-    if (mm) k_faces<double, 1, false><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
-    else k_faces<double, -1, false><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    if (mm) k_faces<double, 1, PVM><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    else k_faces<double, -1, PVM><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
   }
   prof_end(c, pe);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;

@@ -40,6 +40,33 @@ __device__ __forceinline__ double dabs(double a) { return (a < 0.0) ? -a : a; }
 __device__ __forceinline__ double dmax(double a, double b) { return (a > b) ? a : b; }
 __device__ __forceinline__ double dmin(double a, double b) { return (a < b) ? a : b; }
 
+// Dual number v + d e with e^2 = 0 (forward-mode derivative). Constants enter
+// with d = 0 and every operation is written on (v, d) pairs, so the templated
+// flux code below evaluates derivatives when instantiated with Dual.
+struct Dual {
+  double v, d;
+  __device__ __forceinline__ Dual() : v(0.0), d(0.0) {}
+  __device__ __forceinline__ Dual(double a) : v(a), d(0.0) {}
+  __device__ __forceinline__ Dual(double a, double b) : v(a), d(b) {}
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.v * b.d + a.d * b.v); }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+  const double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+// The global float and double overloads stay visible next to this one.
+using ::sqrt;
+__device__ __forceinline__ Dual sqrt(Dual a) {
+  const double r = ::sqrt(a.v);
+  return Dual(r, a.d / (2.0 * r));
+}
+__device__ __forceinline__ bool operator<(Dual a, Dual b) { return a.v < b.v; }
+__device__ __forceinline__ bool operator>(Dual a, Dual b) { return a.v > b.v; }
+__device__ __forceinline__ bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
+
 // ---------------------------------------------------------------------------
 // Quantities derived from primitives (definitions after eqs. eqU/eqF):
 // W, b^0 = W v.B, b^i = B^i/W + v^i b^0, |b|^2 = B^2/W^2 + (v.B)^2,
@@ -580,6 +607,181 @@ __device__ __forceinline__ void pvm_face(const double VL[NV], const double VR[NV
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) Fh[8 + q] = ok ? sh[(8 + q) * kParkLanes] : sh[(12 + q) * kParkLanes];
+}
+
+// ---------------------------------------------------------------------------
+// Exact-JVP variant of the PVM-int flux: the Horner scheme in A^2 of eq.
+// utilde with every product A w = (dF/dU)(U_m) w formed in forward mode (Dual)
+// instead of by the nested eps differences of eq. iterat. The recovery is
+// differentiated implicitly at its converged Z: with the residual
+// f(Z; U) = (Z + B^2) - p - B^2 (1 - v^2)/2 - (S.B/Z)^2/2 - (tau + D) of the
+// closed relations of eq. eqU (not scaled), dZ = -(df/dU . w)/(df/dZ), and V
+// follows from Z by v = (S + (S.B/Z) B)/(Z + B^2), 1/W = sqrt(1 - v^2),
+// rho = D/W, p = (gamma-1)/gamma (Z (1 - v^2) - rho). One recovery per face
+// (of U_m); none inside the chain. A failed recovery of U_m drops the face to
+// p_0 = 1, as in pvm_face.
+template <typename R>
+__device__ __forceinline__ void prim_aux_lw(const R V[NV], R l2, R iW, double g1, AuxT<R>& a) {
+  const R vx = V[1], vy = V[2], vz = V[3];
+  a.l2 = l2;
+  a.iW = iW;
+  a.W = R(1.0) / a.iW;
+  const R vB = (vx * V[5] + vy * V[6]) + vz * V[7];
+  a.b0 = a.W * vB;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) a.b[j] = V[5 + j] * a.iW + V[1 + j] * a.b0;
+  const R B2 = (V[5] * V[5] + V[6] * V[6]) + V[7] * V[7];
+  a.bb = B2 * a.l2 + vB * vB;
+  const R rhoh = V[0] + R(g1) * V[4];
+  a.wtot = (rhoh + a.bb) * (a.W * a.W);
+  a.ps = V[4] + R(0.5) * a.bb;
+  a.D = V[0] * a.W;
+}
+
+struct C2PInD {
+  Dual D, S[3], B[3], Et, B2, S2, SB;
+};
+
+__device__ __forceinline__ C2PInD c2p_in_dual(const double U[NV], const double w[NV]) {
+  C2PInD in;
+  in.D = Dual(U[0], w[0]);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    in.S[j] = Dual(U[1 + j], w[1 + j]);
+    in.B[j] = Dual(U[5 + j], w[5 + j]);
+  }
+  in.Et = Dual(U[4], w[4]) + in.D;
+  in.B2 = (in.B[0] * in.B[0] + in.B[1] * in.B[1]) + in.B[2] * in.B[2];
+  in.S2 = (in.S[0] * in.S[0] + in.S[1] * in.S[1]) + in.S[2] * in.S[2];
+  in.SB = (in.S[0] * in.B[0] + in.S[1] * in.B[1]) + in.S[2] * in.B[2];
+  return in;
+}
+
+// Fluid V (rows 0..7), 1 - v^2 and 1/W from Z; returns the residual f.
+__device__ __forceinline__ Dual c2p_closed(Dual Z, const C2PInD& in, const Phys& K, Dual V[8], Dual& l2, Dual& iW) {
+  const Dual vB = in.SB / Z;
+  const Dual iZb = Dual(1.0) / (Z + in.B2);
+  const Dual v2 = (in.S2 + (vB * vB) * (Z + (Z + in.B2))) * (iZb * iZb);
+  l2 = Dual(1.0) - v2;
+  iW = sqrt(l2);
+  const Dual rho = in.D * iW;
+  const Dual p = Dual(K.gm1g) * (Z * l2 - rho);
+  V[0] = rho;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) V[1 + j] = (in.S[j] + vB * in.B[j]) * iZb;
+  V[4] = p;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) V[5 + j] = in.B[j];
+  return (((Z + in.B2) - p) - Dual(0.5) * (in.B2 * l2)) - (Dual(0.5) * (vB * vB) + in.Et);
+}
+
+__device__ __forceinline__ double c2p_dfdZ(const double Um[NV], double Zm, const Phys& K) {
+  double zero[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) zero[q] = 0.0;
+  const C2PInD in = c2p_in_dual(Um, zero);
+  Dual V[8], l2, iW;
+  return c2p_closed(Dual(Zm, 1.0), in, K, V, l2, iW).d;
+}
+
+// A w at U_m, magnetofluid rows 0..7 (they depend on w[0..7] only).
+template <int d>
+__device__ __forceinline__ void jvp_flux_mhd(const double Um[8], double Zm, double fZ, const double w[8],
+                                             const Phys& K, double Aw[8]) {
+  double U12[NV], w12[NV];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) { U12[q] = Um[q]; w12[q] = w[q]; }
+#pragma unroll
+  for (int q = 8; q < NV; ++q) { U12[q] = 0.0; w12[q] = 0.0; }
+  const C2PInD in = c2p_in_dual(U12, w12);
+  Dual V[8], l2, iW;
+  const double fU = c2p_closed(Dual(Zm), in, K, V, l2, iW).d;
+  const double dZ = -(fU / fZ);
+  c2p_closed(Dual(Zm, dZ), in, K, V, l2, iW);
+  Dual V12[NV];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) V12[q] = V[q];
+  AuxT<Dual> a;
+  prim_aux_lw<Dual>(V12, l2, iW, K.g1, a);
+  Dual F[8];
+  flux_mhd<d, Dual>(V12, a, F);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) Aw[q] = F[q].d;
+}
+
+// A w at U_m, radiation rows 8..11 (Ur, w: E_r, F_r).
+template <int d>
+__device__ __forceinline__ void jvp_flux_rad(const double Ur[4], const double w[4], double Aw[4]) {
+  Dual X[4], F[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) X[q] = Dual(Ur[q], w[q]);
+  flux_rad<d, Dual>(X, F);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Aw[q] = F[q].d;
+}
+
+template <int d>
+__device__ __forceinline__ void pvm_face_jvp(const double VL[NV], const double VR[NV], double tauL,
+                                             double tauR, const Phys& K, double Fh[NV],
+                                             int& fallback, int& c2p_its) {
+  const double beta = 1.0 / dmax(dmax(tauL, tauR), 1.0);
+  double Fa[NV], U0[NV], Um[NV];
+  {
+    Aux aL, aR;
+    prim_aux(VL, K, aL);
+    prim_aux(VR, K, aR);
+    double UL[NV], UR[NV], FL[NV], FR[NV];
+    p2c(VL, aL, UL);
+    flux<d>(VL, aL, FL);
+    p2c(VR, aR, UR);
+    flux<d>(VR, aR, FR);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      U0[q] = UR[q] - UL[q];
+      Um[q] = 0.5 * (UL[q] + UR[q]);
+      Fa[q] = 0.5 * (FL[q] + FR[q]);
+    }
+  }
+  fallback = 0;
+  c2p_its = 0;
+  double w[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) w[q] = U0[q];
+  if (K.M > 0) {
+    double Vm[NV], Zm = 0.0;
+    int it = 0;
+    if (c2p<NV>(Um, K, 0.0, Vm, Zm, it) != 0) {
+      fallback = 1;
+    } else {
+      // radiation block
+      for (int l = 0; l < K.M; ++l) {
+        double t1[4], t2[4];
+        jvp_flux_rad<d>(&Um[8], &w[8], t1);
+        jvp_flux_rad<d>(&Um[8], t1, t2);
+        const double cnext = K.coef[K.M - 1 - l];
+        const double ctop = (l == 0) ? K.coef[K.M] : 1.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[8 + q] = (l == 0) ? ctop * t2[q] + cnext * U0[8 + q] : t2[q] + cnext * U0[8 + q];
+      }
+      // magnetofluid block
+      const double fZ = c2p_dfdZ(Um, Zm, K);
+      for (int l = 0; l < K.M; ++l) {
+        double t1[8], t2[8];
+        jvp_flux_mhd<d>(Um, Zm, fZ, w, K, t1);
+        jvp_flux_mhd<d>(Um, Zm, fZ, t1, K, t2);
+        const double cnext = K.coef[K.M - 1 - l];
+        const double ctop = (l == 0) ? K.coef[K.M] : 1.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w[q] = (l == 0) ? ctop * t2[q] + cnext * U0[q] : t2[q] + cnext * U0[q];
+      }
+    }
+    c2p_its = it;
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double bq = (K.beta_mode == 2 || (K.beta_mode == 1 && q < 8)) ? 1.0 : beta;
+    Fh[q] = Fa[q] - 0.5 * (bq * w[q]);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@ RRMHD_OK, RRMHD_E_INVALID, RRMHD_E_C2P, RRMHD_E_IMPLICIT = 0, -1, -2, -3
 RRMHD_E_NONFINITE, RRMHD_E_DEVICE, RRMHD_E_WORKSPACE = -4, -5, -6
 BC_PERIODIC, BC_OUTFLOW, BC_INFLOW = 0, 1, 2
 RECON_GODUNOV, RECON_MINMOD, RECON_MC, RECON_VANLEER = 0, 1, 2, 3
-SOLVER_PVM, SOLVER_HLL = 0, 1
+SOLVER_PVM, SOLVER_HLL, SOLVER_PVM_JVP = 0, 1, 2
 BETA_ALL, BETA_RAD_ONLY, BETA_OFF = 0, 1, 2
 IMP_PICARD_NEWTON, IMP_NEWTON, IMP_PICARD = 0, 1, 2
 FP64, MIXED = 0, 1

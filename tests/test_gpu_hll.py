@@ -123,7 +123,7 @@ def test_hll_refusals(R, torch_mod):
     P = I.blast_2d(0, 32, 32)
     g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
     assert R.rrmhd_workspace_bytes(g, R.rrmhd_default_params(solver=HLL, precision=R.MIXED)) == 0
-    assert R.rrmhd_workspace_bytes(g, R.rrmhd_default_params(solver=2)) == 0
+    assert R.rrmhd_workspace_bytes(g, R.rrmhd_default_params(solver=3)) == 0
     s = R.Solver(g, R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, solver=HLL))
     U = s.prim_to_cons(dev(torch_mod, P.V))
     B = R.Batch(2)

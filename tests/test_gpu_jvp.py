@@ -1,0 +1,86 @@
+"""GPU parity of the exact-JVP PVM-int flux (forward-mode Jacobian-vector
+products through the primitive recovery) against the CPU oracle: bit for bit
+per face and per step, at the benchmark's 512^2 size, and over a full Alfven
+period (Table 4)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2212_00370_amd import inputs as I
+from test_gpu_parity import R, torch_mod, dev, host, relerr, make_case, one_step_compare, advance_compare  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+JVP = 2
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_jvp_face_fluxes_1d(R, oracle, torch_mod, seed):
+    torch = torch_mod
+    P = I.riemann_1d(seed)
+    p, op, g, og, s, U, opac = make_case(R, oracle, torch, P, solver=JVP)
+    Fg = [host(f) for f in s.face_fluxes(dev(torch, U), opac)]
+    Fo, _ = oracle.face_fluxes(og, U, P.kappa, P.sigma, op)
+    assert np.array_equal(Fg[0], Fo[0]), relerr(Fg[0], Fo[0])
+    s.close()
+
+
+def test_jvp_face_fluxes_random_states(R, oracle, torch_mod):
+    """2e5 i.i.d. magnetised states with any radiation regime on a Godunov grid."""
+    torch = torch_mod
+    n = 200_000
+    rng = np.random.default_rng(22)
+    V = I.random_prims(122, n, er=(1e-6, 1e3))
+    V[9:12] *= rng.uniform(0, 1, n)
+    p = R.rrmhd_default_params(gamma=4 / 3, solver=JVP, recon=R.RECON_GODUNOV)
+    from test_gpu_parity import oracle_params
+    op = oracle_params(oracle, p)
+    g = R.make_grid((n,), (1.0 / n,))
+    s = R.Solver(g, p)
+    kap = 10 ** rng.uniform(-3, 4, n)
+    opac = R.make_opacities(dev(torch, kap), dev(torch, np.zeros(n)))
+    U = oracle.p2c(V, op)
+    Fg = host(s.face_fluxes(dev(torch, U), opac)[0])
+    Fo, _ = oracle.face_fluxes(oracle.make_grid((n,), (1.0 / n,)), U, kap, np.zeros(n), op)
+    assert np.array_equal(Fg, Fo[0]), relerr(Fg, Fo[0])
+    s.close()
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(recon=3), dict(rk_order=3), dict(pvm_k=4), dict(beta_mode=0)])
+def test_jvp_step_1d(R, oracle, torch_mod, kw):
+    for seed in (0, 4):
+        worst, bit = one_step_compare(R, oracle, torch_mod, I.riemann_1d(seed), steps=3, solver=JVP, **kw)
+        assert bit, (seed, worst)
+
+
+def test_jvp_step_2d_small(R, oracle, torch_mod):
+    worst, bit = one_step_compare(R, oracle, torch_mod, I.blast_2d(0, 64, 40), steps=3, solver=JVP)
+    assert bit
+
+
+def test_jvp_advance_2d_full_size(R, oracle, torch_mod):
+    oracle.threads(0)
+    assert advance_compare(R, oracle, torch_mod, I.blast_2d(0, 512), steps=2, solver=JVP)
+
+
+def test_jvp_alfven_wave_period_matches_oracle_and_table4(R, oracle, torch_mod):
+    torch = torch_mod
+    P = I.alfven_1d(64)
+    p, op, g, og, s, U, opac = make_case(R, oracle, torch, P, rk_order=3, recon=R.RECON_MINMOD, solver=JVP)
+    Ud = dev(torch, U)
+    Uo = U
+    t = 0.0
+    while t < P.t_end * (1 - 1e-14):
+        h = min(P.cfl * P.dx[0] / s.max_speed(Ud), P.t_end - t)
+        s.step(Ud, h, opac)
+        Uo, st, _ = oracle.step(og, Uo, h, P.kappa, P.sigma, op)
+        t += h
+    Ug = host(Ud)
+    s.close()
+    assert np.array_equal(Ug, Uo), relerr(Ug, Uo)
+    V, _, st, _ = oracle.c2p(Ug, op)
+    l1 = float(np.mean(np.abs(V[3] - P.V[3])))
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "alfven_pvm_int8_table4.txt")
+    printed = {int(r.split()[0]): float(r.split()[2]) for r in open(path) if r.strip() and not r.startswith("#")}
+    assert l1 == pytest.approx(printed[64], rel=3e-2), l1
