@@ -268,7 +268,7 @@ def main():
     hll = args.solver == "hll"
     solver_id = {"pvm": R.SOLVER_PVM, "hll": R.SOLVER_HLL, "jvp": R.SOLVER_PVM_JVP}[args.solver]
     solver_name = {"pvm": "PVM-int-8", "hll": "Rad-HLL", "jvp": "PVM-int-8 (exact JVP)"}[args.solver]
-    if args.solver != "pvm" and mixed:
+    if args.solver == "hll" and mixed:
         print(f"{solver_name} runs in FP64 only", file=sys.stderr)
         sys.exit(2)
     params = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=R.MIXED if mixed else R.FP64,

@@ -63,6 +63,9 @@ constexpr int kPicardSplit = RRMHD_PICARD_SPLIT;
 #ifndef RRMHD_FACES_WAVES_JVP
 #define RRMHD_FACES_WAVES_JVP 2
 #endif
+#ifndef RRMHD_FACES_WAVES_JVP_MIXED
+#define RRMHD_FACES_WAVES_JVP_MIXED 3
+#endif
 #ifndef RRMHD_UPDATE_WAVES
 #define RRMHD_UPDATE_WAVES 2
 #endif
@@ -385,7 +388,7 @@ __device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, l
 
 // Mixed precision: the same stencil in FP32 (FP64 recoveries inside), FP32
 // fluxes out.
-template <int d, int REC>
+template <int d, int REC, int SOLVER>
 __device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs& A, long long f, const Phys& K,
                                                 unsigned long long& fb, unsigned int& its) {
   int fn0 = G.n[0], fn1 = G.n[1];
@@ -423,7 +426,10 @@ __device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs
   const float dxd = (float)A.dx[d];
   float Fq[NV];
   int fallback = 0, cit = 0;
-  rr::pvm_face_mixed<d>(VL, VR, tp[1] * dxd, tp[2] * dxd, K, Fq, fallback, cit);
+  if constexpr (SOLVER == RRMHD_SOLVER_PVM_JVP)
+    rr::pvm_face_jvp_mixed<d>(VL, VR, tp[1] * dxd, tp[2] * dxd, K, Fq, fallback, cit);
+  else
+    rr::pvm_face_mixed<d>(VL, VR, tp[1] * dxd, tp[2] * dxd, K, Fq, fallback, cit);
   float* out = (float*)A.Fh[d];
   const long long nf = A.nf[d];
 #pragma unroll
@@ -454,9 +460,9 @@ __device__ __forceinline__ void faces_block(long long lb, const GridDev& G, cons
       else if (d == 1) face_body<1, REC, SOLVER>(G, A, f, K, fb, its);
       else face_body<2, REC, SOLVER>(G, A, f, K, fb, its);
     } else {
-      if (d == 0) face_body_mixed<0, REC>(G, A, f, K, fb, its);
-      else if (d == 1) face_body_mixed<1, REC>(G, A, f, K, fb, its);
-      else face_body_mixed<2, REC>(G, A, f, K, fb, its);
+      if (d == 0) face_body_mixed<0, REC, SOLVER>(G, A, f, K, fb, its);
+      else if (d == 1) face_body_mixed<1, REC, SOLVER>(G, A, f, K, fb, its);
+      else face_body_mixed<2, REC, SOLVER>(G, A, f, K, fb, its);
     }
   }
   report_add(rep, blkmax, lb, 0, fb, 0, 0, ULLONG_MAX, its, 0);
@@ -543,7 +549,8 @@ template <typename FT, int REC, int SOLVER>
 __global__ void __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(SOLVER == RRMHD_SOLVER_HLL ? RRMHD_FACES_WAVES_HLL
                                    : SOLVER == RRMHD_SOLVER_PVM_JVP
-                                       ? RRMHD_FACES_WAVES_JVP
+                                       ? (sizeof(FT) == sizeof(double) ? RRMHD_FACES_WAVES_JVP
+                                                                       : RRMHD_FACES_WAVES_JVP_MIXED)
                                        : (sizeof(FT) == sizeof(double) ? RRMHD_FACES_WAVES : RRMHD_FACES_WAVES_MIXED))))
 k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, unsigned long long* wreset,
         DtReduce R, BlockOrder O) {
@@ -1126,7 +1133,7 @@ bool params_valid(const rrmhd_params* p) {
   if (!(p->pvm_eps_mixed > 0.0 && p->pvm_eps_mixed < 0.5)) return false;
   if (p->solver != RRMHD_SOLVER_PVM && p->solver != RRMHD_SOLVER_HLL && p->solver != RRMHD_SOLVER_PVM_JVP)
     return false;
-  if (p->solver != RRMHD_SOLVER_PVM && p->precision != RRMHD_FP64) return false;
+  if (p->solver == RRMHD_SOLVER_HLL && p->precision != RRMHD_FP64) return false;
   return true;
 }
 
@@ -1357,7 +1364,10 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   if (c->par.solver == HLL) {
     k_faces<double, -1, HLL><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
   } else if (c->par.solver == JVP) {
-    k_faces<double, -1, JVP><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    if (c->par.precision == RRMHD_MIXED)
+      k_faces<float, -1, JVP><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    else
+      k_faces<double, -1, JVP><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
   } else if (c->par.precision == RRMHD_MIXED) {
     if (mm) k_faces<float, 1, PVM><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
     else k_faces<float, -1, PVM><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);

@@ -42,30 +42,54 @@ __device__ __forceinline__ double dmin(double a, double b) { return (a < b) ? a 
 
 // Dual number v + d e with e^2 = 0 (forward-mode derivative). Constants enter
 // with d = 0 and every operation is written on (v, d) pairs, so the templated
-// flux code below evaluates derivatives when instantiated with Dual.
-struct Dual {
-  double v, d;
-  __device__ __forceinline__ Dual() : v(0.0), d(0.0) {}
-  __device__ __forceinline__ Dual(double a) : v(a), d(0.0) {}
-  __device__ __forceinline__ Dual(double a, double b) : v(a), d(b) {}
+// flux code below evaluates derivatives when instantiated with Dual (binary64)
+// or DualF (binary32, the mixed-precision path).
+template <typename T>
+struct DualT {
+  T v, d;
+  __device__ __forceinline__ DualT() : v(T(0)), d(T(0)) {}
+  __device__ __forceinline__ DualT(T a) : v(a), d(T(0)) {}
+  __device__ __forceinline__ DualT(T a, T b) : v(a), d(b) {}
 };
-__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
-__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
-__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
-__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.v * b.d + a.d * b.v); }
-__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
-  const double q = a.v / b.v;
-  return Dual(q, (a.d - q * b.d) / b.v);
+using Dual = DualT<double>;
+using DualF = DualT<float>;
+template <typename T>
+__device__ __forceinline__ DualT<T> operator+(DualT<T> a, DualT<T> b) { return DualT<T>(a.v + b.v, a.d + b.d); }
+template <typename T>
+__device__ __forceinline__ DualT<T> operator-(DualT<T> a, DualT<T> b) { return DualT<T>(a.v - b.v, a.d - b.d); }
+template <typename T>
+__device__ __forceinline__ DualT<T> operator-(DualT<T> a) { return DualT<T>(-a.v, -a.d); }
+template <typename T>
+__device__ __forceinline__ DualT<T> operator*(DualT<T> a, DualT<T> b) {
+  return DualT<T>(a.v * b.v, a.v * b.d + a.d * b.v);
+}
+template <typename T>
+__device__ __forceinline__ DualT<T> operator/(DualT<T> a, DualT<T> b) {
+  const T q = a.v / b.v;
+  return DualT<T>(q, (a.d - q * b.d) / b.v);
 }
 // The global float and double overloads stay visible next to this one.
 using ::sqrt;
-__device__ __forceinline__ Dual sqrt(Dual a) {
-  const double r = ::sqrt(a.v);
-  return Dual(r, a.d / (2.0 * r));
+template <typename T>
+__device__ __forceinline__ DualT<T> sqrt(DualT<T> a) {
+  const T r = ::sqrt(a.v);
+  return DualT<T>(r, a.d / (T(2) * r));
 }
-__device__ __forceinline__ bool operator<(Dual a, Dual b) { return a.v < b.v; }
-__device__ __forceinline__ bool operator>(Dual a, Dual b) { return a.v > b.v; }
-__device__ __forceinline__ bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
+template <typename T>
+__device__ __forceinline__ bool operator<(DualT<T> a, DualT<T> b) { return a.v < b.v; }
+template <typename T>
+__device__ __forceinline__ bool operator>(DualT<T> a, DualT<T> b) { return a.v > b.v; }
+template <typename T>
+__device__ __forceinline__ bool operator>=(DualT<T> a, DualT<T> b) { return a.v >= b.v; }
+
+// Binary32 arithmetic types (float and its dual) take the reduced-flux form of
+// the M1 closure.
+template <typename R>
+struct LowP { static constexpr bool value = false; };
+template <>
+struct LowP<float> { static constexpr bool value = true; };
+template <>
+struct LowP<DualF> { static constexpr bool value = true; };
 
 // ---------------------------------------------------------------------------
 // Quantities derived from primitives (definitions after eqs. eqU/eqF):
@@ -152,7 +176,7 @@ constexpr double kMinNormal = 0x1p-1022;
 // products of raw F_r components underflow FP32 where E_r ~ 1e-11.
 template <int d, typename R>
 __device__ __forceinline__ void m1_row(R E, const R F[3], R P[3]) {
-  if constexpr (sizeof(R) == sizeof(float)) {
+  if constexpr (LowP<R>::value) {
     const R iE = R(1) / E;
     const R g[3] = {F[0] * iE, F[1] * iE, F[2] * iE};
     const R f2 = (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
@@ -974,6 +998,108 @@ __device__ __forceinline__ void pvm_face_mixed(const float VL[NV], const float V
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) Fh[8 + q] = ok ? sh[(8 + q) * kParkLanes] : sh[(12 + q) * kParkLanes];
+}
+
+// Mixed-precision form of the exact-JVP flux: reconstruction, fluxes and the
+// forward-mode products of eq. eqF in binary32 (DualF); the recovery of U_m,
+// its implicit derivative dZ and the derivative of V in binary64 (the parts
+// that need the digits), rounded to binary32 where the flux takes over.
+template <int d>
+__device__ __forceinline__ void jvp_flux_mhd_mixed(const double Umd[NV], double Zm, double fZ, const float w[8],
+                                                   const Phys& K, float Aw[8]) {
+  double w12[NV];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) w12[q] = (double)w[q];
+#pragma unroll
+  for (int q = 8; q < NV; ++q) w12[q] = 0.0;
+  const C2PInD in = c2p_in_dual(Umd, w12);
+  Dual V[8], l2, iW;
+  const double fU = c2p_closed(Dual(Zm), in, K, V, l2, iW).d;
+  const double dZ = -(fU / fZ);
+  c2p_closed(Dual(Zm, dZ), in, K, V, l2, iW);
+  DualF Vf[NV];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) Vf[q] = DualF((float)V[q].v, (float)V[q].d);
+  AuxT<DualF> a;
+  prim_aux_lw<DualF>(Vf, DualF((float)l2.v, (float)l2.d), DualF((float)iW.v, (float)iW.d), K.g1, a);
+  DualF F[8];
+  flux_mhd<d, DualF>(Vf, a, F);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) Aw[q] = F[q].d;
+}
+
+template <int d>
+__device__ __forceinline__ void jvp_flux_rad_f(const float Ur[4], const float w[4], float Aw[4]) {
+  DualF X[4], F[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) X[q] = DualF(Ur[q], w[q]);
+  flux_rad<d, DualF>(X, F);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Aw[q] = F[q].d;
+}
+
+template <int d>
+__device__ __forceinline__ void pvm_face_jvp_mixed(const float VL[NV], const float VR[NV], float tauL, float tauR,
+                                                   const Phys& K, float Fh[NV], int& fallback, int& c2p_its) {
+  const float g1 = (float)K.g1;
+  const float beta = 1.0f / fmaxf(fmaxf(tauL, tauR), 1.0f);
+  float Fa[NV], U0[NV], Um[NV];
+  {
+    AuxT<float> aL, aR;
+    prim_aux<float>(VL, g1, aL);
+    prim_aux<float>(VR, g1, aR);
+    float UL[NV], UR[NV], FL[NV], FR[NV];
+    p2c<float>(VL, aL, UL);
+    flux<d, float>(VL, aL, FL);
+    p2c<float>(VR, aR, UR);
+    flux<d, float>(VR, aR, FR);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      U0[q] = UR[q] - UL[q];
+      Um[q] = 0.5f * (UL[q] + UR[q]);
+      Fa[q] = 0.5f * (FL[q] + FR[q]);
+    }
+  }
+  fallback = 0;
+  c2p_its = 0;
+  float w[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) w[q] = U0[q];
+  if (K.M > 0) {
+    double Umd[NV], Vmd[NV], Zm = 0.0;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) Umd[q] = (double)Um[q];
+    int it = 0;
+    if (c2p<NV>(Umd, K, 0.0, Vmd, Zm, it) != 0) {
+      fallback = 1;
+    } else {
+      for (int l = 0; l < K.M; ++l) {
+        float t1[4], t2[4];
+        jvp_flux_rad_f<d>(&Um[8], &w[8], t1);
+        jvp_flux_rad_f<d>(&Um[8], t1, t2);
+        const float cnext = (float)K.coef[K.M - 1 - l];
+        const float ctop = (l == 0) ? (float)K.coef[K.M] : 1.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[8 + q] = ctop * t2[q] + cnext * U0[8 + q];
+      }
+      const double fZ = c2p_dfdZ(Umd, Zm, K);
+      for (int l = 0; l < K.M; ++l) {
+        float t1[8], t2[8];
+        jvp_flux_mhd_mixed<d>(Umd, Zm, fZ, w, K, t1);
+        jvp_flux_mhd_mixed<d>(Umd, Zm, fZ, t1, K, t2);
+        const float cnext = (float)K.coef[K.M - 1 - l];
+        const float ctop = (l == 0) ? (float)K.coef[K.M] : 1.0f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w[q] = ctop * t2[q] + cnext * U0[q];
+      }
+    }
+    c2p_its = it;
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const float bq = (K.beta_mode == 2 || (K.beta_mode == 1 && q < 8)) ? 1.0f : beta;
+    Fh[q] = Fa[q] - 0.5f * (bq * w[q]);
+  }
 }
 
 // ---------------------------------------------------------------------------
