@@ -84,3 +84,41 @@ def test_jvp_alfven_wave_period_matches_oracle_and_table4(R, oracle, torch_mod):
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "alfven_pvm_int8_table4.txt")
     printed = {int(r.split()[0]): float(r.split()[2]) for r in open(path) if r.strip() and not r.startswith("#")}
     assert l1 == pytest.approx(printed[64], rel=3e-2), l1
+
+
+def test_jvp_face_fluxes_2d_ragged(R, oracle, torch_mod):
+    torch = torch_mod
+    P = I.blast_2d(0, 72, 45)
+    p, op, g, og, s, U, opac = make_case(R, oracle, torch, P, solver=JVP)
+    Fg = [host(f) for f in s.face_fluxes(dev(torch, U), opac)]
+    Fo, _ = oracle.face_fluxes(og, U, P.kappa, P.sigma, op)
+    for d in range(2):
+        assert np.array_equal(Fg[d], Fo[d]), (d, relerr(Fg[d], Fo[d]))
+    s.close()
+
+
+def test_jvp_step_3d_periodic_rough(R, oracle, torch_mod):
+    """Periodic 3D grid of i.i.d. states: every face a strong jump, all three
+    directions of the forward-mode products."""
+    shape = (11, 7, 5)
+    n = int(np.prod(shape))
+    V = I.random_prims(77, n, vmax=0.6, rho=(0.5, 2.0), p=(0.5, 2.0), er=(0.1, 1.0))
+    rng = np.random.default_rng(3)
+    P = I.Problem(name="rough3d", shape=shape, dx=(0.1, 0.13, 0.17), x0=(0, 0, 0), V=V,
+                  kappa=rng.uniform(0.1, 10, n), sigma=rng.uniform(0.1, 10, n), gamma=5 / 3, a_rad=0.5,
+                  bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), cfl=0.3)
+    worst, bit = one_step_compare(R, oracle, torch_mod, P, steps=2, solver=JVP)
+    assert bit
+
+
+def test_jvp_rusanov_limit_equals_difference_flux(R, oracle, torch_mod):
+    """k = 0 (p_0 = 1): no Jacobian product at all, so the exact-JVP and the
+    difference flux are the same Rusanov flux, bit for bit."""
+    torch = torch_mod
+    P = I.riemann_1d(2)
+    outs = []
+    for solver in (0, JVP):
+        p, op, g, og, s, U, opac = make_case(R, oracle, torch, P, solver=solver, pvm_k=0)
+        outs.append(host(s.face_fluxes(dev(torch, U), opac)[0]))
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
