@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from paper_2212_00370_amd import inputs as I
-from test_oracle_integration import run
+from test_oracle_integration import diffusion_run, run
 
 GAMMA = 4.0 / 3.0
 
@@ -271,3 +271,16 @@ def test_optically_thin_radiation_riemann_pvm_sharper_than_hll(oracle):
         ratio[test] = [p / h for p, h in zip(err[oracle.SOLVER_PVM], err[oracle.SOLVER_HLL])]
     assert ratio[1][0] < 0.92 and ratio[1][1] < 0.85, ratio
     assert all(abs(r - 1) < 0.05 for r in ratio[2]), ratio
+
+
+@pytest.mark.parametrize("sigma", [100.0, 1000.0])
+def test_diffusion_pulse_pvm_more_accurate_than_limited_rad_hll(oracle, sigma):
+    """Section 4, optically thick radiation pulse (tau = 100, 1000 per cell):
+    with its speeds limited by eq. limits Rad-HLL follows the heat kernel
+    (L1 < 7 %), and PVM-int-8 with beta is more accurate still, as the paper
+    reports for the central, most diffusive region."""
+    oracle.threads(0)
+    e_pvm, _, _ = diffusion_run(oracle, sigma, 1, 1875.0)
+    e_hll, _, _ = diffusion_run(oracle, sigma, 1, 1875.0, solver=oracle.SOLVER_HLL)
+    assert e_hll < 0.07, e_hll
+    assert e_pvm < 0.6 * e_hll, (e_pvm, e_hll)

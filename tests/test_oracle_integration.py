@@ -99,7 +99,7 @@ def heat_kernel(x, t, A, w, D):
     return A * math.sqrt(w * w / s2) * np.exp(-x * x / s2)
 
 
-def diffusion_run(oracle, sigma, beta_mode, t_end):
+def diffusion_run(oracle, sigma, beta_mode, t_end, solver=0):
     """Optically thick pulse (Section 4, radiation pulse): static uniform gas,
     kappa = 0, scattering sigma, Gaussian E_r; [-50, 50] with 100 zones."""
     n = 100
@@ -109,7 +109,7 @@ def diffusion_run(oracle, sigma, beta_mode, t_end):
     V = np.zeros((12, n))
     V[0] = 1.0; V[4] = 1.0
     V[8] = Eb + A * np.exp(-(x / w) ** 2)
-    par = oracle.params(gamma=5 / 3, beta_mode=beta_mode)
+    par = oracle.params(gamma=5 / 3, beta_mode=beta_mode, solver=solver)
     g = oracle.make_grid((n,), (dx,))
     U0 = oracle.p2c(V, par)
     U, t, nst = run(oracle, g, U0, par, 0.0, sigma, 0.4, t_end=t_end, dx=(dx,))
