@@ -1,0 +1,70 @@
+"""The paper's convergence tables at the resolutions the CPU oracle is too slow
+for: the circularly polarised Alfven wave (Section 4.1) at N = 256 and 512 on
+the GPU, one period with RK3 and CFL 0.3, for PVM-int-8 (Table 4) and HLL
+(Table 1) with every reconstruction. The bit-for-bit agreement of these paths
+with the oracle is established at N = 64 (test_gpu_parity, test_gpu_hll)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2212_00370_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2212_00370_amd import rrmhd
+    return rrmhd
+
+
+def _table(name):
+    rows = {}
+    for ln in open(os.path.join(HERE, "golden", name)):
+        if ln.strip() and not ln.startswith("#"):
+            n, *errs = ln.split()
+            rows[int(n)] = [float(e) for e in errs]
+    return rows
+
+
+def _alfven_l1(R, oracle, n, recon, solver):
+    import torch
+    P = I.alfven_1d(n)
+    p = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, rk_order=3, recon=recon, solver=solver)
+    op = oracle.params(gamma=P.gamma, a_rad=P.a_rad)
+    s = R.Solver(R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi), p)
+    Ud = torch.from_numpy(oracle.p2c(P.V, op)).to("cuda:0")
+    opac = R.make_opacities(torch.from_numpy(P.kappa).to("cuda:0"), torch.from_numpy(P.sigma).to("cuda:0"))
+    t = 0.0
+    while t < P.t_end * (1 - 1e-14):
+        h = min(P.cfl * P.dx[0] / s.max_speed(Ud), P.t_end - t)
+        s.step(Ud, h, opac)
+        t += h
+    rep = s.report()
+    U = Ud.cpu().numpy()
+    s.close()
+    assert rep["c2p_fail"] == 0 and rep["imp_fail"] == 0
+    V, _, st, _ = oracle.c2p(U, op)
+    assert np.all(st == 0)
+    return float(np.mean(np.abs(V[3] - P.V[3])))
+
+
+# relative tolerance per reconstruction (Godunov, MinMod, MC, VanLeer); measured
+# deviations: PVM 2e-5, 1.4 %, 0.8 %, 1.1 %; HLL 2e-5, 0.2 %, 0.2 %, 0.02 %
+_REL = {0: (1e-4, 2e-2, 2e-2, 2e-2), 1: (1e-4, 5e-3, 5e-3, 2e-3)}
+
+
+@pytest.mark.parametrize("solver,table", [(0, "alfven_pvm_int8_table4.txt"), (1, "alfven_hll_table1.txt")])
+@pytest.mark.parametrize("recon", [0, 1, 2, 3])
+def test_alfven_tables_at_high_resolution(R, oracle, solver, table, recon):
+    rows = _table(table)
+    errs = {n: _alfven_l1(R, oracle, n, recon, solver) for n in (256, 512)}
+    print(table, recon, errs, {n: rows[n][recon] for n in errs})
+    for n, e in errs.items():
+        assert e == pytest.approx(rows[n][recon], rel=_REL[solver][recon]), (n, e, rows[n][recon])
