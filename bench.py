@@ -231,6 +231,8 @@ def main():
                     help="face flux: PVM-int-8 (the method), Rad-HLL (the paper's comparison solver) or "
                          "PVM-int-8 with exact Jacobian-vector products")
     ap.add_argument("--mode", choices=("step", "serving", "beam3d", "copycal"), default="step")
+    ap.add_argument("--no-variants", dest="variants", action="store_false",
+                    help="skip the Rad-HLL / exact-JVP / mixed-precision lines of the default run")
     ap.add_argument("--requests", type=int, default=120)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate / measured capacity")
     args = ap.parse_args()
@@ -372,9 +374,50 @@ def main():
         "kernels_ms_per_step_note": "separate run of min(steps, 20) steps with every launch timed",
         "failures": {k: rep[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")},
     }
+    if args.variants and args.solver == "pvm" and not mixed:
+        out["variants"] = variants_bench(R, P, grid, V, opac, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_steps, solver_id)
     print(json.dumps(out), flush=True)
+
+
+def variants_bench(R, P, grid, V, opac, steps, warmup):
+    """The same workload with the other face fluxes and precisions (each its own
+    context; same step count; timed like the main line), for the cost ratios:
+    Rad-HLL (the paper's comparison solver), the exact-JVP PVM-int-8 flux, and
+    mixed precision with the difference and the exact-JVP flux."""
+    import torch
+    res = {}
+    for name, solver, prec in (("rad_hll_fp64", R.SOLVER_HLL, R.FP64), ("pvm_jvp_fp64", R.SOLVER_PVM_JVP, R.FP64),
+                               ("pvm_mixed", R.SOLVER_PVM, R.MIXED), ("pvm_jvp_mixed", R.SOLVER_PVM_JVP, R.MIXED)):
+        params = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=prec, solver=solver)
+        sv = R.Solver(grid, params, device=V.device)
+        U0 = sv.prim_to_cons(V)
+        Uw = U0.clone()
+        sv.advance(Uw, P.cfl, warmup, opac)
+        torch.cuda.synchronize()
+        sv.report()
+        U = U0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sv.advance(U, P.cfl, steps, opac)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rep = sv.report()
+        Ub = U0.clone()
+        R.rrmhd_profile_enable(sv.ctx, 1 << R.K_FACES)
+        nb = min(steps, 20)
+        sv.advance(Ub, P.cfl, nb, opac)
+        torch.cuda.synchronize()
+        fms, fl, _ = R.rrmhd_profile_read(sv.ctx, R.K_FACES)
+        R.rrmhd_profile_enable(sv.ctx, False)
+        sv.report()
+        res[name] = {"value": P.ncell * steps / el, "ms_per_step": 1e3 * el / steps,
+                     "faces_ms_per_step": round(fms / nb, 4), "faces_mean_launch_ms": round(fms / max(fl, 1), 4),
+                     "failures": {k: rep[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")}}
+        sv.close()
+        del U, Ub, Uw, U0
+    return res
 
 
 if __name__ == "__main__":
