@@ -59,8 +59,8 @@ enum { RRMHD_IMP_PICARD_NEWTON = 0, RRMHD_IMP_NEWTON = 1, RRMHD_IMP_PICARD = 2 }
  * PVM-int polynomial with every Jacobian-vector product exact (forward-mode
  * derivative through the primitive recovery) instead of a difference; pvm_eps
  * and pvm_eps_mixed are unused (with RRMHD_MIXED the flux products are binary32
- * and the recovery of U_m and its derivative binary64). HLL is FP64 only
- * (precision RRMHD_MIXED with it is RRMHD_E_INVALID); neither is available to
+ * and the recovery of U_m and its derivative binary64). With RRMHD_MIXED,
+ * Rad-HLL runs entirely in binary32. Neither HLL nor PVM_JVP is available to
  * the batched entry points. */
 enum { RRMHD_SOLVER_PVM = 0, RRMHD_SOLVER_HLL = 1, RRMHD_SOLVER_PVM_JVP = 2 };
 /* Precision of the explicit step. RRMHD_FP64: everything in binary64.

@@ -428,6 +428,8 @@ __device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs
   int fallback = 0, cit = 0;
   if constexpr (SOLVER == RRMHD_SOLVER_PVM_JVP)
     rr::pvm_face_jvp_mixed<d>(VL, VR, tp[1] * dxd, tp[2] * dxd, K, Fq, fallback, cit);
+  else if constexpr (SOLVER == RRMHD_SOLVER_HLL)
+    rr::hll_face<d, float>(VL, VR, tp[1] * dxd, tp[2] * dxd, K, Fq);
   else
     rr::pvm_face_mixed<d>(VL, VR, tp[1] * dxd, tp[2] * dxd, K, Fq, fallback, cit);
   float* out = (float*)A.Fh[d];
@@ -1133,7 +1135,6 @@ bool params_valid(const rrmhd_params* p) {
   if (!(p->pvm_eps_mixed > 0.0 && p->pvm_eps_mixed < 0.5)) return false;
   if (p->solver != RRMHD_SOLVER_PVM && p->solver != RRMHD_SOLVER_HLL && p->solver != RRMHD_SOLVER_PVM_JVP)
     return false;
-  if (p->solver == RRMHD_SOLVER_HLL && p->precision != RRMHD_FP64) return false;
   return true;
 }
 
@@ -1362,7 +1363,10 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   const bool mm = c->K.recon == RRMHD_RECON_MINMOD;
   constexpr int PVM = RRMHD_SOLVER_PVM, HLL = RRMHD_SOLVER_HLL, JVP = RRMHD_SOLVER_PVM_JVP;
   if (c->par.solver == HLL) {
-    k_faces<double, -1, HLL><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    if (c->par.precision == RRMHD_MIXED)
+      k_faces<float, -1, HLL><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
+    else
+      k_faces<double, -1, HLL><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);
   } else if (c->par.solver == JVP) {
     if (c->par.precision == RRMHD_MIXED)
       k_faces<float, -1, JVP><<<nlaunch, kBlock, 0, c->stream>>>(G, A, c->K, c->rep, c->blkmax, wreset, R, O);

@@ -1522,22 +1522,23 @@ __device__ __forceinline__ int implicit_newton_quad(const double Us[NV], double 
 // ---------------------------------------------------------------------------
 // The outer M1 eigenvalues lambda_r1 <= lambda_r3 in direction d (eqs.
 // lam1-lam3): f = |F|/E capped at 1, cos(theta) = F_d/|F| (0 when F = 0).
-template <int d>
-__device__ __forceinline__ void rad_speeds(const double V[NV], double& l1, double& l3) {
-  const double E = V[8];
-  const double FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
-  double f = 0.0, cth = 0.0;
-  if (FF > 0.0) {
-    const double Fn = sqrt(FF);
-    f = dmin(Fn / E, 1.0);
+template <int d, typename R = double>
+__device__ __forceinline__ void rad_speeds(const R V[NV], R& l1, R& l3) {
+  const R E = V[8];
+  const R FF = (V[9] * V[9] + V[10] * V[10]) + V[11] * V[11];
+  R f = R(0), cth = R(0);
+  if (FF > R(0)) {
+    const R Fn = sqrt(FF);
+    const R fe = Fn / E;
+    f = (fe < R(1)) ? fe : R(1);
     cth = V[9 + d] / Fn;
   }
-  const double f2 = f * f;
-  const double r43 = 4.0 - 3.0 * f2;
-  const double sr = sqrt(r43);
-  double zz = (2.0 / 3.0) * (r43 - sr) + (2.0 * (cth * cth)) * ((2.0 - f2) - sr);
-  zz = (zz > 0.0) ? zz : 0.0;
-  const double zeta = sqrt(zz);
+  const R f2 = f * f;
+  const R r43 = R(4) - R(3) * f2;
+  const R sr = sqrt(r43);
+  R zz = (R(2) / R(3)) * (r43 - sr) + (R(2) * (cth * cth)) * ((R(2) - f2) - sr);
+  zz = (zz > R(0)) ? zz : R(0);
+  const R zeta = sqrt(zz);
   l1 = (f * cth - zeta) / sr;
   l3 = (f * cth + zeta) / sr;
 }
@@ -1592,32 +1593,34 @@ __device__ __forceinline__ double cell_speed(const double V[NV], const Aux& a, c
 // of F_L and F_R.
 constexpr int kQuartIt = 20;
 
+template <typename R>
 struct QuartIn {
-  double w1cs, wcsb, cs2, W2, vd, bd, b0;
+  R w1cs, wcsb, cs2, W2, vd, bd, b0;
 };
 
 // Q, Q', Q'' at l from the factored form (A = a^2, br = (w cs^2 + |b|^2) A -
 // cs^2 B~^2, om = 1 - l^2, Q = w (1 - cs^2) A^2 - om br).
-__device__ __forceinline__ void quartic(const QuartIn& q, double l, double& Q, double& dQ, double& d2Q) {
-  const double x = l - q.vd;
-  const double A = q.W2 * (x * x);
-  const double Bt = q.bd - l * q.b0;
-  const double om = 1.0 - l * l;
-  const double br = q.wcsb * A - q.cs2 * (Bt * Bt);
+template <typename R>
+__device__ __forceinline__ void quartic(const QuartIn<R>& q, R l, R& Q, R& dQ, R& d2Q) {
+  const R x = l - q.vd;
+  const R A = q.W2 * (x * x);
+  const R Bt = q.bd - l * q.b0;
+  const R om = R(1) - l * l;
+  const R br = q.wcsb * A - q.cs2 * (Bt * Bt);
   Q = q.w1cs * (A * A) - om * br;
-  const double dA = 2.0 * (q.W2 * x);
-  const double dbr = q.wcsb * dA + 2.0 * (q.cs2 * (q.b0 * Bt));
-  const double d2br = q.wcsb * (2.0 * q.W2) - 2.0 * (q.cs2 * (q.b0 * q.b0));
-  dQ = ((2.0 * q.w1cs) * (A * dA) + (2.0 * l) * br) - om * dbr;
-  d2Q = (((2.0 * q.w1cs) * (dA * dA + A * (2.0 * q.W2)) + 2.0 * br) + (4.0 * l) * dbr) - om * d2br;
+  const R dA = R(2) * (q.W2 * x);
+  const R dbr = q.wcsb * dA + R(2) * (q.cs2 * (q.b0 * Bt));
+  const R d2br = q.wcsb * (R(2) * q.W2) - R(2) * (q.cs2 * (q.b0 * q.b0));
+  dQ = ((R(2) * q.w1cs) * (A * dA) + (R(2) * l) * br) - om * dbr;
+  d2Q = (((R(2) * q.w1cs) * (dA * dA + A * (R(2) * q.W2)) + R(2) * br) + (R(4) * l) * dbr) - om * d2br;
 }
 
-template <int d>
-__device__ __forceinline__ QuartIn quartic_in(const double V[NV], const Aux& a, const Phys& K) {
-  QuartIn q;
-  const double w = V[0] + K.g1 * V[4];
-  q.cs2 = (K.gamma * V[4]) / w;
-  q.w1cs = w * (1.0 - q.cs2);
+template <int d, typename R>
+__device__ __forceinline__ QuartIn<R> quartic_in(const R V[NV], const AuxT<R>& a, R gamma, R g1) {
+  QuartIn<R> q;
+  const R w = V[0] + g1 * V[4];
+  q.cs2 = (gamma * V[4]) / w;
+  q.w1cs = w * (R(1) - q.cs2);
   q.wcsb = w * q.cs2 + a.bb;
   q.W2 = a.W * a.W;
   q.vd = V[1 + d];
@@ -1627,65 +1630,71 @@ __device__ __forceinline__ QuartIn quartic_in(const double V[NV], const Aux& a, 
 }
 
 // lam[0], lam[1]: min and max of state L; lam[2], lam[3]: of state R.
-__device__ __forceinline__ void fast_speeds2(const QuartIn& qL, const QuartIn& qR, double lam[4]) {
+template <typename R>
+__device__ __forceinline__ void fast_speeds2(const QuartIn<R>& qL, const QuartIn<R>& qR, R lam[4]) {
   bool run[4] = {true, true, true, true};
-  lam[0] = -1.0; lam[1] = 1.0; lam[2] = -1.0; lam[3] = 1.0;
+  lam[0] = R(-1); lam[1] = R(1); lam[2] = R(-1); lam[3] = R(1);
   for (int it = 0; it < kQuartIt; ++it) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const bool down = (r & 1) != 0;  // the largest root is approached from above
-      double Q, dQ, d2Q;
-      quartic((r < 2) ? qL : qR, lam[r], Q, dQ, d2Q);
-      const double iQ = 1.0 / Q;
-      const double G = dQ * iQ;
-      const double H = G * G - d2Q * iQ;
-      double t = 3.0 * (4.0 * H - G * G);
-      t = (t > 0.0) ? t : 0.0;
-      const double sq = sqrt(t);
-      const double ln = lam[r] - 4.0 / (down ? (G + sq) : (G - sq));
-      run[r] = run[r] && (Q > 0.0) && (down ? (ln < lam[r]) : (ln > lam[r]));
+      R Q, dQ, d2Q;
+      quartic<R>((r < 2) ? qL : qR, lam[r], Q, dQ, d2Q);
+      const R iQ = R(1) / Q;
+      const R G = dQ * iQ;
+      const R H = G * G - d2Q * iQ;
+      R t = R(3) * (R(4) * H - G * G);
+      t = (t > R(0)) ? t : R(0);
+      const R sq = sqrt(t);
+      const R ln = lam[r] - R(4) / (down ? (G + sq) : (G - sq));
+      run[r] = run[r] && (Q > R(0)) && (down ? (ln < lam[r]) : (ln > lam[r]));
       lam[r] = run[r] ? ln : lam[r];
     }
     if (!(run[0] || run[1] || run[2] || run[3])) break;
   }
 }
 
-__device__ __forceinline__ void hll_rows(const double* FL, const double* FR, const double* UL, const double* UR,
-                                         double lL, double lR, int n, double* Fh) {
+template <typename R>
+__device__ __forceinline__ void hll_rows(const R* FL, const R* FR, const R* UL, const R* UR, R lL, R lR, int n,
+                                         R* Fh) {
 #pragma unroll
   for (int q = 0; q < n; ++q) {
-    const double h = ((lR * FL[q] - lL * FR[q]) + (lR * lL) * (UR[q] - UL[q])) / (lR - lL);
-    const double m = 0.5 * (FL[q] + FR[q]);
-    Fh[q] = (lL > 0.0) ? FL[q] : ((lR < 0.0) ? FR[q] : ((lR > lL) ? h : m));
+    const R h = ((lR * FL[q] - lL * FR[q]) + (lR * lL) * (UR[q] - UL[q])) / (lR - lL);
+    const R m = R(0.5) * (FL[q] + FR[q]);
+    Fh[q] = (lL > R(0)) ? FL[q] : ((lR < R(0)) ? FR[q] : ((lR > lL) ? h : m));
   }
 }
 
-template <int d>
-__device__ __forceinline__ void hll_face(const double VL[NV], const double VR[NV], double tauL, double tauR,
-                                         const Phys& K, double Fh[NV]) {
+template <int d, typename R = double>
+__device__ __forceinline__ void hll_face(const R VL[NV], const R VR[NV], R tauL, R tauR, const Phys& K, R Fh[NV]) {
+  const R g1 = R(K.g1), gam = R(K.gamma);
   // radiation block: its variables are both primitive and conserved
   {
-    double r1L, r3L, r1R, r3R;
-    rad_speeds<d>(VL, r1L, r3L);
-    rad_speeds<d>(VR, r1R, r3R);
-    const double lim = 4.0 / (3.0 * dmax(tauL, tauR));
-    double FL[4], FR[4];
-    flux_rad<d>(VL + 8, FL);
-    flux_rad<d>(VR + 8, FR);
-    hll_rows(FL, FR, VL + 8, VR + 8, dmax(dmin(r1L, r1R), -lim), dmin(dmax(r3L, r3R), lim), 4, Fh + 8);
+    R r1L, r3L, r1R, r3R;
+    rad_speeds<d, R>(VL, r1L, r3L);
+    rad_speeds<d, R>(VR, r1R, r3R);
+    const R tm = (tauL > tauR) ? tauL : tauR;
+    const R lim = R(4) / (R(3) * tm);
+    R FL[4], FR[4];
+    flux_rad<d, R>(VL + 8, FL);
+    flux_rad<d, R>(VR + 8, FR);
+    const R mn = (r1L < r1R) ? r1L : r1R, mx = (r3L > r3R) ? r3L : r3R;
+    const R nlim = -lim;
+    hll_rows<R>(FL, FR, VL + 8, VR + 8, (mn > nlim) ? mn : nlim, (mx < lim) ? mx : lim, 4, Fh + 8);
   }
   // magnetofluid block
-  Aux aL, aR;
-  prim_aux(VL, K, aL);
-  prim_aux(VR, K, aR);
-  double lam[4];
-  fast_speeds2(quartic_in<d>(VL, aL, K), quartic_in<d>(VR, aR, K), lam);
-  double UL[8], UR[8], FL[8], FR[8];
-  p2c8(VL, aL, UL);
-  flux_mhd<d>(VL, aL, FL);
-  p2c8(VR, aR, UR);
-  flux_mhd<d>(VR, aR, FR);
-  hll_rows(FL, FR, UL, UR, dmin(lam[0], lam[2]), dmax(lam[1], lam[3]), 8, Fh);
+  AuxT<R> aL, aR;
+  prim_aux<R>(VL, g1, aL);
+  prim_aux<R>(VR, g1, aR);
+  R lam[4];
+  fast_speeds2<R>(quartic_in<d, R>(VL, aL, gam, g1), quartic_in<d, R>(VR, aR, gam, g1), lam);
+  R UL[8], UR[8], FL[8], FR[8];
+  p2c8<R>(VL, aL, UL);
+  flux_mhd<d, R>(VL, aL, FL);
+  p2c8<R>(VR, aR, UR);
+  flux_mhd<d, R>(VR, aR, FR);
+  const R lo = (lam[0] < lam[2]) ? lam[0] : lam[2], hi = (lam[1] > lam[3]) ? lam[1] : lam[3];
+  hll_rows<R>(FL, FR, UL, UR, lo, hi, 8, Fh);
 }
 
 }  // namespace rr

@@ -115,12 +115,12 @@ def test_workspace_bytes(R):
     R._lib.rrmhd_default_params(C.byref(q))
     q.gamma = 0.5
     assert R._lib.rrmhd_workspace_bytes(C.byref(_grid(R, (16, 16))), C.byref(q)) == 0
-    # Rad-HLL: FP64 only (the exact-JVP PVM flux has a mixed form); unknown solvers are refused
+    # every solver in both precisions; unknown solvers are refused
     R._lib.rrmhd_default_params(C.byref(q))
     q.solver = R.SOLVER_HLL
     assert R._lib.rrmhd_workspace_bytes(C.byref(_grid(R, (16, 16))), C.byref(q)) > 0
     q.precision = R.MIXED
-    assert R._lib.rrmhd_workspace_bytes(C.byref(_grid(R, (16, 16))), C.byref(q)) == 0
+    assert R._lib.rrmhd_workspace_bytes(C.byref(_grid(R, (16, 16))), C.byref(q)) > 0
     q.solver = R.SOLVER_PVM_JVP
     assert R._lib.rrmhd_workspace_bytes(C.byref(_grid(R, (16, 16))), C.byref(q)) > 0
     q.precision = R.FP64

@@ -1,8 +1,8 @@
 """GPU parity of the Rad-HLL face flux (Section 3.2, Radiative HLL) against
 the CPU oracle: bit for bit per face and per step, in 1D, 2D and 3D, at the
 benchmark's 512^2 size, over a full period of the Alfven wave (whose L1 error
-is the printed Table 1 value), plus the documented refusals (mixed precision,
-batched entry points).
+is the printed Table 1 value), plus the documented refusals (batched entry
+points).
 """
 import os
 
@@ -119,10 +119,10 @@ def test_hll_alfven_wave_period_matches_oracle_and_table1(R, oracle, torch_mod):
 
 
 def test_hll_refusals(R, torch_mod):
-    """Rad-HLL is FP64-only and not offered by the batched entry points."""
+    """Rad-HLL is not offered by the batched entry points; unknown solvers are
+    refused."""
     P = I.blast_2d(0, 32, 32)
     g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
-    assert R.rrmhd_workspace_bytes(g, R.rrmhd_default_params(solver=HLL, precision=R.MIXED)) == 0
     assert R.rrmhd_workspace_bytes(g, R.rrmhd_default_params(solver=3)) == 0
     s = R.Solver(g, R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, solver=HLL))
     U = s.prim_to_cons(dev(torch_mod, P.V))
