@@ -22,8 +22,8 @@ SOLVER_PVM, SOLVER_HLL, SOLVER_PVM_JVP = 0, 1, 2
 BETA_ALL, BETA_RAD_ONLY, BETA_OFF = 0, 1, 2
 IMP_PICARD_NEWTON, IMP_NEWTON, IMP_PICARD = 0, 1, 2
 FP64, MIXED = 0, 1
-K_PRIMS, K_FACES, K_UPDATE, K_SPEED, K_NEWTON = 0, 1, 2, 3, 4
-PROFILE_ALL = (1 << 5) - 1
+K_PRIMS, K_FACES, K_UPDATE, K_SPEED, K_NEWTON, K_COUNT = 0, 1, 2, 3, 4, 5
+PROFILE_ALL = (1 << K_COUNT) - 1
 
 
 class rrmhd_grid(C.Structure):

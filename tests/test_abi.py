@@ -155,3 +155,20 @@ def test_error_strings(R):
         s = R._lib.rrmhd_strerror(st)
         assert s and len(s.decode()) >= 2
     assert R._lib.rrmhd_strerror(-99)
+
+
+def test_header_enums_match_binding(R):
+    """Every enumerator of include/rrmhd.h has the same value in the binding
+    (RRMHD_X -> X or RRMHD_X in paper_2212_00370_amd/rrmhd.py)."""
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "rrmhd.h")).read()
+    seen = 0
+    for body in re.findall(r"enum\s*(?:\w+\s*)?\{([^}]*)\}", hdr):
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        for name, val in re.findall(r"(RRMHD_\w+)\s*=\s*(-?\d+)", body):
+            short = name[len("RRMHD_"):]
+            py = getattr(R, short, getattr(R, name, None))
+            assert py is not None, name
+            assert py == int(val), (name, py, val)
+            seen += 1
+    assert seen >= 20
