@@ -197,3 +197,13 @@ def test_optically_thick_pulse_full_run(R, oracle, torch_mod, solver):
     ex = Eb + A * math.sqrt(w * w / s2) * np.exp(-x * x / s2)
     err = np.sum(np.abs(Ug[8] - ex)) / np.sum(np.abs(ex - Eb))
     assert err < (0.03 if solver == 0 else 0.07), err
+
+
+@pytest.mark.parametrize("solver", [HLL, 2])
+def test_advance_3d_beam_inflow_other_fluxes(R, oracle, torch_mod, solver):
+    """The 3D beam through the inflow mask (rrmhd_advance, device time step)
+    with Rad-HLL and with the exact-JVP flux: bit for bit with the oracle."""
+    from test_gpu_parity import beam_case
+    oracle.threads(0)
+    P = I.beam_3d(0, 24, 20, 16, r_noz=0.2)
+    assert advance_compare(R, oracle, torch_mod, P, steps=6, case=beam_case, e_floor=1e-14, solver=solver)
