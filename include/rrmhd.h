@@ -60,8 +60,8 @@ enum { RRMHD_IMP_PICARD_NEWTON = 0, RRMHD_IMP_NEWTON = 1, RRMHD_IMP_PICARD = 2 }
  * derivative through the primitive recovery) instead of a difference; pvm_eps
  * and pvm_eps_mixed are unused (with RRMHD_MIXED the flux products are binary32
  * and the recovery of U_m and its derivative binary64). With RRMHD_MIXED,
- * Rad-HLL runs entirely in binary32. Neither HLL nor PVM_JVP is available to
- * the batched entry points. */
+ * Rad-HLL runs entirely in binary32. Every solver and precision can be mixed
+ * in one batch of rrmhd_step_batch. */
 enum { RRMHD_SOLVER_PVM = 0, RRMHD_SOLVER_HLL = 1, RRMHD_SOLVER_PVM_JVP = 2 };
 /* Precision of the explicit step. RRMHD_FP64: everything in binary64.
  * RRMHD_MIXED: reconstruction, fluxes and the PVM Horner / finite-difference

@@ -939,6 +939,7 @@ struct SimDesc {
   long long npartial;
   double dt;
   int mixed;
+  int solver;  // RRMHD_SOLVER_*: which face-kernel launch of a tick takes this simulation
 };
 
 enum { OFF_PRIMS = 0, OFF_FACES = 1, OFF_CELLS = 2, OFF_NEWTON = 3, OFF_KINDS = 4 };
@@ -996,15 +997,20 @@ __global__ void __launch_bounds__(kBlock) k_prims_b(const SimDesc* __restrict__ 
               D.wcount, D.Zc);
 }
 
+// One launch per face flux present in the batch (each its own kernel copy, so
+// the PVM copy keeps its register budget); a block of a simulation with
+// another flux returns at once.
+template <int SOLVER>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_faces_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, int nsim) {
   const long long* o = off + OFF_FACES * (nsim + 1);
   const int s = find_sim(o, nsim, blockIdx.x);
   const SimDesc& D = T[s];
+  if (D.solver != SOLVER) return;
   // the work-list counter of this simulation's update pass that follows
   if (blockIdx.x == o[s] && threadIdx.x == 0) *D.wcount = 0;
-  if (D.mixed) faces_block<true, -1>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
-  else faces_block<false, -1>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
+  if (D.mixed) faces_block<true, -1, SOLVER>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
+  else faces_block<false, -1, SOLVER>(blockIdx.x - o[s], D.G, D.FA, D.K, D.rep, D.blkmax);
 }
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
@@ -1428,6 +1434,7 @@ SimDesc make_desc(rrmhd_ctx* c, double* U, const rrmhd_opacities* opac, double d
   D.npartial = L.npartial;
   D.dt = dt;
   D.mixed = (c->par.precision == RRMHD_MIXED) ? 1 : 0;
+  D.solver = c->par.solver;
   return D;
 }
 
@@ -1487,7 +1494,6 @@ rrmhd_status batch_check(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, const 
   for (int s = 0; s < nsim; ++s) {
     if (!ctx[s] || !U[s]) return RRMHD_E_INVALID;
     if (ctx[s]->par.rk_order != ctx[0]->par.rk_order) return RRMHD_E_INVALID;
-    if (ctx[s]->par.solver != RRMHD_SOLVER_PVM) return RRMHD_E_INVALID;
     for (int t = 0; t < s; ++t)
       if (ctx[t] == ctx[s]) return RRMHD_E_INVALID;  // each context's workspace is used once per launch
   }
@@ -1912,7 +1918,15 @@ rrmhd_status rrmhd_step_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, d
       k_prims_b<<<(unsigned int)tot[OFF_PRIMS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s);
       if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
     }
-    k_faces_b<<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off, nsim);
+    bool has[3] = {false, false, false};
+    for (int t = 0; t < nsim; ++t) has[ctx[t]->par.solver] = true;
+    if (has[RRMHD_SOLVER_PVM])
+      k_faces_b<RRMHD_SOLVER_PVM><<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off, nsim);
+    if (has[RRMHD_SOLVER_HLL])
+      k_faces_b<RRMHD_SOLVER_HLL><<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off, nsim);
+    if (has[RRMHD_SOLVER_PVM_JVP])
+      k_faces_b<RRMHD_SOLVER_PVM_JVP><<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off,
+                                                                                         nsim);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
     k_update_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s, last, co[s][0],
                                                                        co[s][1], co[s][2]);

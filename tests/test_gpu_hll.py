@@ -1,8 +1,7 @@
 """GPU parity of the Rad-HLL face flux (Section 3.2, Radiative HLL) against
 the CPU oracle: bit for bit per face and per step, in 1D, 2D and 3D, at the
 benchmark's 512^2 size, over a full period of the Alfven wave (whose L1 error
-is the printed Table 1 value), plus the documented refusals (batched entry
-points).
+is the printed Table 1 value), and batches that mix every flux and precision.
 """
 import os
 
@@ -118,19 +117,43 @@ def test_hll_alfven_wave_period_matches_oracle_and_table1(R, oracle, torch_mod):
     assert l1 == pytest.approx(printed[64], rel=1e-2), l1
 
 
-def test_hll_refusals(R, torch_mod):
-    """Rad-HLL is not offered by the batched entry points; unknown solvers are
-    refused."""
+def test_unknown_solver_refused(R, torch_mod):
     P = I.blast_2d(0, 32, 32)
     g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
     assert R.rrmhd_workspace_bytes(g, R.rrmhd_default_params(solver=3)) == 0
-    s = R.Solver(g, R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, solver=HLL))
-    U = s.prim_to_cons(dev(torch_mod, P.V))
-    B = R.Batch(2)
-    with pytest.raises(R.RRMHDError):
-        B.max_speed([s], [U])
+
+
+def test_batch_of_every_solver_and_precision_equals_single(R, torch_mod):
+    """rrmhd_step_batch over simulations with different fluxes and precisions
+    (one face launch per flux present) equals each context stepped alone."""
+    torch = torch_mod
+    probs = [(I.blast_2d(0, 40, 32), 0, R.FP64), (I.blast_2d(1, 36, 28), HLL, R.FP64),
+             (I.riemann_1d(3), 2, R.FP64), (I.blast_2d(2, 32, 32), HLL, R.MIXED),
+             (I.riemann_1d(5), 2, R.MIXED), (I.blast_2d(3, 24, 40), 0, R.MIXED)]
+
+    def make(P, solver, prec):
+        s = R.Solver(R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi),
+                     R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, solver=solver, precision=prec))
+        U = s.prim_to_cons(dev(torch, P.V))
+        o = R.make_opacities(dev(torch, P.kappa), dev(torch, P.sigma))
+        return s, U, o
+    single = [make(*c) for c in probs]
+    batched = [make(*c) for c in probs]
+    B = R.Batch(8)
+    for k in range(3):
+        sm = B.max_speed([c[0] for c in batched], [c[1] for c in batched])
+        dts = []
+        for (P, _, _), (s, U, o), smb in zip(probs, single, sm):
+            assert s.max_speed(U) == smb
+            dt = P.cfl * min(P.dx) / smb
+            dts.append(dt)
+            s.step(U, dt, o)
+        B.step([c[0] for c in batched], [c[1] for c in batched], dts, [c[2] for c in batched])
+        for (s1, U1, _), (s2, U2, _) in zip(single, batched):
+            assert torch.equal(U1, U2), k
+    for c in single + batched:
+        c[0].close()
     B.close()
-    s.close()
 
 
 @pytest.mark.parametrize("solver", [0, HLL])
