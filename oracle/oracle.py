@@ -89,6 +89,8 @@ def _setup(lib):
     lib.or_p2c.argtypes = [ll, vp, ll, vp, vp, ll]; lib.or_p2c.restype = None
     lib.or_flux.argtypes = [ll, vp, ll, i, vp, vp, ll]; lib.or_flux.restype = None
     lib.or_c2p.argtypes = [ll, vp, ll, vp, vp, vp, ll, vp, vp, vp]; lib.or_c2p.restype = None
+    lib.or_c2p_lw.argtypes = [ll, vp, ll, vp, vp, ll, vp, vp]; lib.or_c2p_lw.restype = None
+    lib.or_c2p_eval.argtypes = [ll, vp, ll, vp, vp, vp]; lib.or_c2p_eval.restype = None
     lib.or_pvm_face.argtypes = [ll, vp, vp, ll, vp, vp, i, vp, vp, ll, vp, vp]; lib.or_pvm_face.restype = None
     lib.or_hll_face.argtypes = [ll, vp, vp, ll, vp, vp, i, vp, vp, ll, vp]; lib.or_hll_face.restype = None
     lib.or_fast_speeds.argtypes = [ll, vp, ll, i, vp, vp, vp, vp]; lib.or_fast_speeds.restype = None
@@ -157,6 +159,29 @@ def c2p(U, par=None, Z_in=None):
     zin = None if Z_in is None else np.ascontiguousarray(Z_in, dtype=np.float64)
     lib().or_c2p(n, _dp(U), n, C.byref(par), _dp(zin), _dp(V), n, _dp(Z), _dp(st), _dp(it))
     return V, Z, st, it
+
+
+def c2p_lw(U, par=None):
+    """Cold-start recovery; returns (V, [1 - v^2, 1/W] as the recovery formed
+    them, status)."""
+    U = _soa(U); n = U.shape[1]
+    V = np.empty_like(U); lw = np.zeros((2, n)); st = np.zeros(n, np.int32)
+    par = par or params()
+    lib().or_c2p_lw(n, _dp(U), n, C.byref(par), _dp(V), n, _dp(lw), _dp(st))
+    return V, lw, st
+
+
+def c2p_eval(U, Z, par=None):
+    """One evaluation of the recovery residual at Z per state: dict of arrays
+    ok, l2 (1 - v^2), iW (1/W), iZ, iZb (1/(Z + B^2)), fW (f/W), dfW (f'/W),
+    rho, p."""
+    U = _soa(U); n = U.shape[1]
+    Z = np.ascontiguousarray(np.broadcast_to(Z, (n,)), dtype=np.float64)
+    out = np.zeros((9, n))
+    par = par or params()
+    lib().or_c2p_eval(n, _dp(U), n, _dp(Z), C.byref(par), _dp(out))
+    keys = ["ok", "l2", "iW", "iZ", "iZb", "fW", "dfW", "rho", "p"]
+    return {k: out[i] for i, k in enumerate(keys)}
 
 
 def pvm_face(VL, VR, tauL, tauR, d, par=None):

@@ -269,7 +269,7 @@ struct C2PIn {
 
 struct C2PEval {
   bool ok;
-  real l2, iW, rho, p, vB, iZb, f, df;
+  real l2, iW, rho, p, vB, iZ, iZb, f, df;
 };
 
 static C2PEval c2p_eval(real Z, const C2PIn& in, const Consts& K, bool want_df) {
@@ -278,6 +278,7 @@ static C2PEval c2p_eval(real Z, const C2PIn& in, const Consts& K, bool want_df) 
   // 1/Z and 1/(Z + B^2) from one reciprocal of the product
   const real rZZb = 1.0 / (Z * Zb);
   const real iZ = Zb * rZZb;
+  e.iZ = iZ;
   e.iZb = Z * rZZb;
   e.vB = in.SB * iZ;
   const real vB2 = e.vB * e.vB;
@@ -1452,6 +1453,53 @@ void or_c2p(long long n, const double* U, long long su, const OPar* P, const dou
     if (Z_out) Z_out[c] = dv(Z);
     if (status) status[c] = st;
     if (iters) iters[c] = it;
+  }
+}
+
+// Recovery of each U (cold start) that also returns 1 - v^2 and 1/W as the
+// final evaluation at the converged Z forms them: lw[0][c] = 1 - v^2,
+// lw[1][c] = 1/W (0 where the recovery failed). For the tests that compare
+// this Lorentz factor with the one of the recovered velocity.
+void or_c2p_lw(long long n, const double* U, long long su, const OPar* P, double* V, long long sv,
+               double* lw, int* status) {
+  const Consts K = consts_of(*P);
+  for (long long c = 0; c < n; ++c) {
+    real Uc[NV], Vc[NV], Z = 0.0, l[2] = {0.0, 0.0};
+    for (int q = 0; q < NV; ++q) Uc[q] = U[q * su + c];
+    int it = 0;
+    const int st = c2p(Uc, *P, K, real(0.0), Vc, &Z, &it, l);
+    if (st != 0) c2p_fallback(Uc, *P, Vc);
+    for (int q = 0; q < NV; ++q) V[q * sv + c] = dv(Vc[q]);
+    lw[c] = dv(l[0]);
+    lw[n + c] = dv(l[1]);
+    if (status) status[c] = st;
+  }
+}
+
+// One evaluation of the recovery's residual at a given Z for each U:
+// out[k][c] for k = 0..8 is (ok, 1 - v^2, 1/W, 1/Z, 1/(Z + B^2), f/W, f'/W,
+// rho, p), the quantities the Newton iteration on Z uses (f and f' are
+// returned scaled by 1/W, as the iteration takes them). For the tests that
+// compare them with their plain forms.
+void or_c2p_eval(long long n, const double* U, long long su, const double* Z, const OPar* P,
+                 double* out) {
+  const Consts K = consts_of(*P);
+  for (long long c = 0; c < n; ++c) {
+    C2PIn in;
+    in.D = U[0 * su + c];
+    for (int j = 0; j < 3; ++j) { in.S[j] = U[(1 + j) * su + c]; in.B[j] = U[(5 + j) * su + c]; }
+    in.Et = real(U[4 * su + c]) + in.D;
+    in.B2 = (in.B[0] * in.B[0] + in.B[1] * in.B[1]) + in.B[2] * in.B[2];
+    in.S2 = (in.S[0] * in.S[0] + in.S[1] * in.S[1]) + in.S[2] * in.S[2];
+    in.SB = (in.S[0] * in.B[0] + in.S[1] * in.B[1]) + in.S[2] * in.B[2];
+    const C2PEval e = c2p_eval(real(Z[c]), in, K, true);
+    // 1/Z and 1/(Z + B^2) are formed before any admissibility test; the rest
+    // only for an admissible Z (v^2 < 1, p > 0).
+    double r[9] = {e.ok ? 1.0 : 0.0, 0.0, 0.0, dv(e.iZ), dv(e.iZb), 0.0, 0.0, 0.0, 0.0};
+    if (e.ok) {
+      r[1] = dv(e.l2); r[2] = dv(e.iW); r[5] = dv(e.f); r[6] = dv(e.df); r[7] = dv(e.rho); r[8] = dv(e.p);
+    }
+    for (int k = 0; k < 9; ++k) out[k * n + c] = r[k];
   }
 }
 

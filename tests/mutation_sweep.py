@@ -1,0 +1,108 @@
+"""Mutation sweep of the CPU oracle (test infrastructure; run by hand, not
+collected by pytest):
+
+    python tests/mutation_sweep.py [mutant ...]
+
+Each mutant plants one plausible mistake in a scratch copy of
+``oracle/rrmhd_oracle.cpp`` (a dropped term, a flipped sign, a wrong index or
+cell, a missing limit, a rearrangement that is no longer the same quantity),
+builds it, and runs the CPU pin tests (``tests/test_oracle_*.py``) against
+it. A mutant that passes every pin is a gap in the pins. The sweep works on a
+temporary copy only; the repository is not modified.
+"""
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+FALLBACK = ("    if (!(v2lo < real(1.0)) || !(v2hi < real(1.0)))\n"
+            "      for (int q = 0; q < NV; ++q) s[q] = 0.0;")
+RESCALE = ("  const real FF = (X[1] * X[1] + X[2] * X[2]) + X[3] * X[3];\n"
+           "  if (FF > X[0] * X[0]) {\n    const real r = X[0] / rsqrt_(FF);")
+
+# name: (text in the oracle, replacement)
+MUTANTS = {
+    # physics of eqs. eqU, eqF, xi
+    "flux_drops_total_pressure": ("F[1 + j] = (wv * V[1 + j] + a.ps) - a.b[d] * a.b[j];",
+                                  "F[1 + j] = (wv * V[1 + j]) - a.b[d] * a.b[j];"),
+    "p2c_drops_b0_b": ("U[1 + j] = a.wtot * V[1 + j] - a.b0 * a.b[j];", "U[1 + j] = a.wtot * V[1 + j];"),
+    "bb_drops_vB2": ("a.bb = B2 * a.l2 + vB * vB;", "a.bb = B2 * a.l2;"),
+    "closure_sign": ("const T cb = T(0.5) * (T(3.0) * xi - T(1.0));", "const T cb = T(0.5) * (T(1.0) - T(3.0) * xi);"),
+    # recovery (reading of the recovery algorithm)
+    "residual_drops_term": ("const real f = (((Z + in.B2) - e.p) - 0.5 * (in.B2 * e.l2)) - (0.5 * vB2 + in.Et);",
+                            "const real f = ((Z + in.B2) - e.p) - (0.5 * vB2 + in.Et);"),
+    "one_reciprocal_off": ("  const real iZ = Zb * rZZb;\n", "  const real iZ = Zb * rZZb * (1.0 + 1e-15);\n"),
+    "slope_drops_term": ("e.df = ((e.iW - dpw) + (0.5 * (in.B2 * dv2)) * e.iW) + (vB2 * iZ) * e.iW;",
+                         "e.df = ((e.iW - dpw) + (0.5 * (in.B2 * dv2)) * e.iW);"),
+    "residual_scaled_wrongly": ("  e.f = f * e.iW;", "  e.f = f * e.l2;"),
+    "recovered_W_wrong": ("  if (lw) { lw[0] = e.l2; lw[1] = e.iW; }", "  if (lw) { lw[0] = e.l2; lw[1] = e.l2; }"),
+    # PVM chain and beta (Section 3.2, eqs. iterat, utilde, beta, limits)
+    "horner_index": ("const real cnext = coef[M - 1 - l];\n      if (l == 0) {\n        const real ctop = coef[M];\n        for (int q = 0; q < NV; ++q) w[q] = ctop * ((Ft[q] - Fm[q]) * ieps) + cnext * U0[q];",
+                     "const real cnext = coef[l];\n      if (l == 0) {\n        const real ctop = coef[M];\n        for (int q = 0; q < NV; ++q) w[q] = ctop * ((Ft[q] - Fm[q]) * ieps) + cnext * U0[q];"),
+    "beta_from_smaller_depth": ("const real beta = 1.0 / rmax(rmax(tauL, tauR), real(1.0));\n  fo.fallback = 0;\n  fo.c2p_it = 0;\n  real Uk[NV];\n  bool ok",
+                                "const real beta = 1.0 / rmax(rmin(tauL, tauR), real(1.0));\n  fo.fallback = 0;\n  fo.c2p_it = 0;\n  real Uk[NV];\n  bool ok"),
+    "tauL_from_cell_i_minus_1": ("const real tauL = tp[1] * dxd, tauR = tp[2] * dxd;",
+                                 "const real tauL = tp[0] * dxd, tauR = tp[2] * dxd;"),
+    "tau_without_W": ("cp.taup[c] = dv(Uc[0] * (real(opac_at(kap, kap0, c)) + real(opac_at(sig, sig0, c))));",
+                      "cp.taup[c] = dv(Vc[0] * (real(opac_at(kap, kap0, c)) + real(opac_at(sig, sig0, c))));"),
+    # reconstruction (Section 3.2, reconstruction paragraph)
+    "minmod_takes_larger": ("if (same_sign(a, b)) return (rabs(a) < rabs(b)) ? a : b;",
+                            "if (same_sign(a, b)) return (rabs(a) > rabs(b)) ? a : b;"),
+    "no_superluminal_fallback": (FALLBACK, FALLBACK.replace("if (!(v2lo < real(1.0)) || !(v2hi < real(1.0)))",
+                                                            "if (false)")),
+    "fallback_upper_face_only": (FALLBACK, FALLBACK.replace("if (!(v2lo < real(1.0)) || !(v2hi < real(1.0)))",
+                                                            "if (!(v2hi < real(1.0)))")),
+    "fallback_lower_face_only": (FALLBACK, FALLBACK.replace("if (!(v2lo < real(1.0)) || !(v2hi < real(1.0)))",
+                                                            "if (!(v2lo < real(1.0)))")),
+    "fallback_velocity_only": (FALLBACK, FALLBACK.replace("int q = 0; q < NV", "int q = 1; q < 4")),
+    # time stepping (Section 3.1)
+    "rk2_weight": ("s[1] = {0.5, 0.5, 0.5};", "s[1] = {0.5, 0.5, 1.0};"),
+    "rk3_weight": ("s[1] = {0.75, 0.25, 0.25};", "s[1] = {0.75, 0.25, 0.5};"),
+    "outflow_ghost_off_by_one": ("    } else c[d] = 0;\n  } else if", "    } else c[d] = 1;\n  } else if"),
+    # signal speed
+    "cfl_sign": ("const real lp = (vd * (1.0 - a2) + sq) / den;", "const real lp = (vd * (1.0 - a2) - sq) / den;"),
+    # implicit solve (Section 3.3, eqs. g0, gi)
+    "implicit_Cij_sign": ("sy.C[1 + i][1 + j] = (i == j) ? 1.0 + hrW * (ks + g) : hrW * g;",
+                          "sy.C[1 + i][1 + j] = (i == j) ? 1.0 - hrW * (ks + g) : hrW * g;"),
+    "emission_with_scattering": ("const real em = (hr * kap) * aT4;", "const real em = (hr * (kap + sig)) * aT4;"),
+    "no_post_solve_flux_limit": (RESCALE, RESCALE.replace("if (FF > X[0]", "if (false && FF > X[0]")),
+    # Rad-HLL (Section 3.2, Radiative HLL)
+    "hll_limit_without_four_thirds": ("const real lim = 4.0 / (3.0 * rmax(tauL, tauR));",
+                                      "const real lim = 1.0 / rmax(tauL, tauR);"),
+    "hll_middle_sign": ("((lR * FL[q] - lL * FR[q]) + (lR * lL) * (UR[q] - UL[q]))",
+                        "((lR * FL[q] - lL * FR[q]) - (lR * lL) * (UR[q] - UL[q]))"),
+}
+
+
+def run(names):
+    survivors = []
+    for name in names:
+        old, new = MUTANTS[name]
+        with tempfile.TemporaryDirectory() as tmp:
+            for d in ("oracle", "tests", "paper_2212_00370_amd"):
+                shutil.copytree(os.path.join(ROOT, d), os.path.join(tmp, d),
+                                ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc"))
+            src = os.path.join(tmp, "oracle", "rrmhd_oracle.cpp")
+            text = open(src).read()
+            if text.count(old) != 1:
+                raise SystemExit(f"{name}: target text found {text.count(old)} times")
+            open(src, "w").write(text.replace(old, new))
+            subprocess.check_call([sys.executable, "-c", "from oracle import oracle as O; O.build()"], cwd=tmp)
+            tests = sorted("tests/" + t for t in os.listdir(os.path.join(tmp, "tests"))
+                           if t.startswith("test_oracle") and t.endswith(".py"))
+            r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-m", "not gpu",
+                                "-p", "no:cacheprovider", *tests], cwd=tmp, capture_output=True, text=True)
+            tail = r.stdout.strip().splitlines()[-1] if r.stdout.strip() else r.stderr.strip()[-200:]
+            verdict = "killed" if r.returncode != 0 else "SURVIVED"
+            if r.returncode == 0:
+                survivors.append(name)
+            print(f"{name:34s} {verdict:9s} {tail}", flush=True)
+    print(f"{len(names) - len(survivors)} of {len(names)} mutants killed; survivors: {survivors}")
+    return survivors
+
+
+if __name__ == "__main__":
+    sys.exit(1 if run(sys.argv[1:] or list(MUTANTS)) else 0)

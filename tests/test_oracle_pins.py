@@ -313,6 +313,28 @@ def test_fluid_speed_hydro_sound(oracle):
     assert oracle.cell_speed(V, 0, par)[0] == pytest.approx(cs, rel=1e-14)
 
 
+def test_fluid_speed_moving_gas_is_velocity_addition(oracle):
+    """B = 0, gas moving along d with speed v: the fast-speed bound is the
+    relativistic sum of v and the sound speed, (v + c_s)/(1 + v c_s) downstream
+    and (v - c_s)/(1 - v c_s) upstream. A hot gas (c_s = 0.5..0.7) moving at
+    v = 0.1..0.8 puts the larger of the two above the radiation's 1/sqrt(3)."""
+    g = 5.0 / 3.0
+    par = oracle.params(gamma=g)
+    for d in range(3):
+        for v in (0.1, 0.3, 0.5, 0.8):
+            for p in (0.8, 3.0, 100.0):
+                vel = [0.0, 0.0, 0.0]
+                vel[d] = v
+                V = rest_state(1, rho=1.0, p=p, E=1e-6, v=tuple(vel))
+                h = 1 + g / (g - 1) * p
+                cs = math.sqrt(g * p / h)
+                lp = (v + cs) / (1 + v * cs)
+                lm = (v - cs) / (1 - v * cs)
+                expect = max(abs(lp), abs(lm), 1 / math.sqrt(3))
+                assert max(abs(lp), abs(lm)) > 1 / math.sqrt(3) or p < 1.0
+                assert oracle.cell_speed(V, d, par)[0] == pytest.approx(expect, rel=1e-13), (d, v, p)
+
+
 # --------------------------------------------------------------- implicit ----
 def static_solution(Estar, tau_t, rho, B2, h, kap, a_rad, g):
     """Static medium, no flux: E = (E* + h rho kappa a T^4)/(1 + h rho kappa)
