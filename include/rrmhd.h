@@ -178,8 +178,8 @@ rrmhd_status rrmhd_max_speed(rrmhd_ctx* ctx, const double* U, const rrmhd_grid* 
  * s_max, s_max as rrmhd_max_speed computes it (CFL condition, Section 3.2;
  * signal speeds of eqs. lam1-lam3). The result is bitwise that of calling
  * rrmhd_max_speed and then rrmhd_step with that dt on the host, nsteps times,
- * but nothing waits on the host: the work is enqueued on the context's stream
- * (so a caller may also capture it in a HIP graph). The first stage's
+ * but nothing waits on the host: the work is enqueued on the context's stream.
+ * (Capturing it in a HIP graph is untested and not supported.) The first stage's
  * primitive recovery and the signal speeds share one pass, so a recovery
  * failure in the step's initial state is counted once in the report (the
  * separate calls count it in both). A step whose s_max is 0 or not a number
