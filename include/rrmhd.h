@@ -191,6 +191,33 @@ rrmhd_status rrmhd_max_speed(rrmhd_ctx* ctx, const double* U, const rrmhd_grid* 
 rrmhd_status rrmhd_advance(rrmhd_ctx* ctx, double* U, const rrmhd_grid* g, double cfl, int nsteps,
                            const rrmhd_opacities* opac, double* dt_out);
 
+/* Allocation-free variant of rrmhd_advance, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc): the
+ * same nsteps IMEX steps with dt formed on the device, bitwise equal to
+ * rrmhd_advance on a context with the same grid and parameters, but with no
+ * context, no caller workspace and no allocation of any kind (device or
+ * host). Its workspace is a per-device array inside the library of 64 MiB
+ * (67108864 bytes), loaded with the library's code object and held by each
+ * GPU until the process ends; a grid whose rrmhd_workspace_bytes exceeds it
+ * (above about 140 000 cells, e.g. 2D grids beyond 360^2) returns
+ * RRMHD_E_WORKSPACE with nothing enqueued.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents: the call clears what must start at zero (counters,
+ * iteration maxima) itself, but calls that overlap on one GPU (on different
+ * streams, or from host threads without ordering) race and give undefined
+ * results. Work runs on the current device, enqueued on hip_stream (NULL:
+ * the default stream), which must belong to that device.
+ * g, p: as for rrmhd_init; U, cfl, nsteps, opac, dt_out: as for
+ * rrmhd_advance. report_dev: optional caller-owned DEVICE pointer to one
+ * rrmhd_report, which receives this call's failure counters once its work
+ * has run (enqueued after it; NULL: not written).
+ * Errors: RRMHD_E_INVALID (bad grid, parameters, cfl or nsteps; nothing
+ * enqueued), RRMHD_E_WORKSPACE (grid too large for the scratch array),
+ * RRMHD_E_DEVICE (no current device, symbol lookup or launch failure). */
+rrmhd_status rrmhd_advance_noalloc(const rrmhd_grid* g, const rrmhd_params* p, double* U, double cfl, int nsteps,
+                                   const rrmhd_opacities* opac, double* dt_out, rrmhd_report* report_dev,
+                                   void* hip_stream);
+
 /* Diagnostic: the face fluxes of the first stage for state U (recovery,
  * reconstruction and PVM-int flux, Section 3.2). Fh: device, the directions
  * one after another, each [12][faces_d] with faces_d = prod(n) with n_d + 1

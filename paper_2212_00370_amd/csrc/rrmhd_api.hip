@@ -17,6 +17,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -68,6 +69,11 @@ constexpr int kPicardSplit = RRMHD_PICARD_SPLIT;
 #endif
 #ifndef RRMHD_UPDATE_WAVES
 #define RRMHD_UPDATE_WAVES 2
+#endif
+// Size of the per-device scratch array of rrmhd_advance_noalloc (64 MiB: the
+// workspace of grids up to about 140 000 cells, e.g. 360^2 or 1D runs).
+#ifndef RRMHD_NOALLOC_SCRATCH_BYTES
+#define RRMHD_NOALLOC_SCRATCH_BYTES (64ull << 20)
 #endif
 
 struct DevReport {
@@ -1057,12 +1063,12 @@ __global__ void __launch_bounds__(kBlock) k_report_reset(DevReport* rep, unsigne
     blkmax[i] = 0;
 }
 
-// Fold the per-block iteration maxima into the report (single block).
 __global__ void __launch_bounds__(kBlock) k_zero_u32(unsigned int* p, long long n) {
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += (long long)gridDim.x * kBlock) p[i] = 0u;
 }
 
-__global__ void __launch_bounds__(kRedBlock) k_report_fold(DevReport* rep, const unsigned int* blkmax, long long nblk) {
+// Fold the per-block iteration maxima into the report (single block).
+__device__ __forceinline__ void k_report_fold_body(DevReport* rep, const unsigned int* blkmax, long long nblk) {
   __shared__ unsigned int red[2][kRedBlock / kWave];
   unsigned int a = 0, b = 0;
   for (long long i = threadIdx.x; i < nblk; i += blockDim.x) {
@@ -1082,6 +1088,27 @@ __global__ void __launch_bounds__(kRedBlock) k_report_fold(DevReport* rep, const
     b = (red[1][0] > b) ? red[1][0] : b;
     rep->max_c2p_it = (a > rep->max_c2p_it) ? a : rep->max_c2p_it;
     rep->max_imp_it = (b > rep->max_imp_it) ? b : rep->max_imp_it;
+  }
+}
+
+__global__ void __launch_bounds__(kRedBlock) k_report_fold(DevReport* rep, const unsigned int* blkmax, long long nblk) {
+  k_report_fold_body(rep, blkmax, nblk);
+}
+
+// Fold the per-block iteration maxima and write the counters as the public
+// report struct to caller-owned device memory (single block).
+__global__ void __launch_bounds__(kRedBlock) k_report_out(DevReport* rep, const unsigned int* blkmax, long long nblk,
+                                                          rrmhd_report* out) {
+  k_report_fold_body(rep, blkmax, nblk);
+  if (threadIdx.x == 0) {
+    out->c2p_fail = (long long)rep->c2p_fail;
+    out->pvm_fallback = (long long)rep->pvm_fallback;
+    out->imp_fail = (long long)rep->imp_fail;
+    out->nonfinite = (long long)rep->nonfinite;
+    out->e_floor_hits = (long long)rep->e_floor_hits;
+    out->first_bad_cell = (rep->first_bad == ULLONG_MAX) ? -1 : (long long)rep->first_bad;
+    out->max_c2p_it = (int)rep->max_c2p_it;
+    out->max_imp_it = (int)rep->max_imp_it;
   }
 }
 
@@ -1500,6 +1527,51 @@ rrmhd_status batch_check(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, const 
   return RRMHD_OK;
 }
 
+// Point a context at its workspace (no allocation).
+void ctx_bind(rrmhd_ctx* c, const rrmhd_grid* g, const rrmhd_params* p, const Layout& L, char* ws,
+              void* hip_stream) {
+  c->grid = *g;
+  c->par = *p;
+  c->K = make_phys(p);
+  c->L = L;
+  c->ws = ws;
+  c->Vp = (double*)(c->ws + L.off_Vp);
+  c->taup = (double*)(c->ws + L.off_taup);
+  c->Us = (double*)(c->ws + L.off_Us);
+  for (int d = 0; d < 3; ++d) c->Fh[d] = (double*)(c->ws + L.off_Fh[d]);
+  c->partial = (double*)(c->ws + L.off_partial);
+  c->smax = (double*)(c->ws + L.off_smax);
+  c->rep = (DevReport*)(c->ws + L.off_rep);
+  c->blkmax = (unsigned int*)(c->ws + L.off_blkmax);
+  c->work = (long long*)(c->ws + L.off_work);
+  c->wcount = (unsigned long long*)(c->ws + L.off_wcount);
+  c->stage_ctr = 0;
+  c->Zc = (double*)(c->ws + L.off_Zc);
+  c->cost = (unsigned int*)(c->ws + L.off_cost);
+  c->perm = (unsigned int*)(c->ws + L.off_perm);
+  c->stream = (hipStream_t)hip_stream;
+  c->host = nullptr;
+  c->prof = 0;
+  c->prof_stride = 1;
+  for (int k = 0; k < RRMHD_K_COUNT; ++k) c->prof_seen[k] = 0;
+  c->ev_used = 0;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+    ncu = 256;
+  c->newton_blocks = (unsigned int)(4 * ncu * (256 / kBlock));  // kBlock/4 cells (4 lanes each) per block
+}
+
+// Clear what the kernels expect to start at zero: the failure counters, the
+// per-block iteration maxima and the update blocks' costs (enqueued kernels,
+// no memset, so a captured graph replays them as well).
+rrmhd_status ctx_clear(rrmhd_ctx* c) {
+  k_report_reset<<<64, kBlock, 0, c->stream>>>(c->rep, c->blkmax, 2 * c->L.nblkmax);
+  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  k_zero_u32<<<64, kBlock, 0, c->stream>>>(c->cost, c->L.npartial);
+  return launch_ok();
+}
+
 }  // namespace
 
 extern "C" {
@@ -1541,45 +1613,12 @@ rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params
   if (!workspace || ws_bytes < L.total || ((uintptr_t)workspace & 255u) != 0) return RRMHD_E_WORKSPACE;
   rrmhd_ctx* c = new (std::nothrow) rrmhd_ctx;
   if (!c) return RRMHD_E_DEVICE;
-  c->grid = *g;
-  c->par = *p;
-  c->K = make_phys(p);
-  c->L = L;
-  c->ws = (char*)workspace;
-  c->Vp = (double*)(c->ws + L.off_Vp);
-  c->taup = (double*)(c->ws + L.off_taup);
-  c->Us = (double*)(c->ws + L.off_Us);
-  for (int d = 0; d < 3; ++d) c->Fh[d] = (double*)(c->ws + L.off_Fh[d]);
-  c->partial = (double*)(c->ws + L.off_partial);
-  c->smax = (double*)(c->ws + L.off_smax);
-  c->rep = (DevReport*)(c->ws + L.off_rep);
-  c->blkmax = (unsigned int*)(c->ws + L.off_blkmax);
-  c->work = (long long*)(c->ws + L.off_work);
-  c->wcount = (unsigned long long*)(c->ws + L.off_wcount);
-  c->stage_ctr = 0;
-  c->Zc = (double*)(c->ws + L.off_Zc);
-  c->cost = (unsigned int*)(c->ws + L.off_cost);
-  c->perm = (unsigned int*)(c->ws + L.off_perm);
-  c->stream = (hipStream_t)hip_stream;
-  c->host = nullptr;
-  c->prof = 0;
-  c->prof_stride = 1;
-  for (int k = 0; k < RRMHD_K_COUNT; ++k) c->prof_seen[k] = 0;
-  c->ev_used = 0;
-  {
-    int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
-      ncu = 256;
-    c->newton_blocks = (unsigned int)(4 * ncu * (256 / kBlock));  // kBlock/4 cells (4 lanes each) per block
-  }
+  ctx_bind(c, g, p, L, (char*)workspace, hip_stream);
   if (hipHostMalloc(&c->host, sizeof(DevReport) + sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return RRMHD_E_DEVICE;
   }
-  k_report_reset<<<64, kBlock, 0, c->stream>>>(c->rep, c->blkmax, 2 * L.nblkmax);
-  if (launch_ok() == RRMHD_OK) k_zero_u32<<<64, kBlock, 0, c->stream>>>(c->cost, L.npartial);
-  if (launch_ok() != RRMHD_OK) {
+  if (ctx_clear(c) != RRMHD_OK) {
     (void)hipHostFree(c->host);
     delete c;
     return RRMHD_E_DEVICE;
@@ -1734,6 +1773,66 @@ rrmhd_status rrmhd_advance(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double 
     red.k = k;
     const rrmhd_status st = step_stages(c, U, g, 0.0, c->smax + 1, op, true, k + 1 < nsteps, &red);
     if (st != RRMHD_OK) return st;
+  }
+  return RRMHD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of rrmhd_advance. Its workspace is this array: one
+// copy per device, allocated when the code object is loaded and held until
+// the process ends. Host code never passes `scratch` itself to a kernel (on
+// the host it is only a stand-in for the symbol); it uses the device address
+// that hipGetSymbolAddress returns for the current device.
+static constexpr size_t kScratchBytes = (size_t)RRMHD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current and kept.
+rrmhd_status scratch_for_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RRMHD_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RRMHD_E_DEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RRMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rrmhd_status rrmhd_advance_noalloc(const rrmhd_grid* g, const rrmhd_params* p, double* U, double cfl, int nsteps,
+                                   const rrmhd_opacities* opac, double* dt_out, rrmhd_report* report_dev,
+                                   void* hip_stream) {
+  if (!U || !grid_valid(g) || !params_valid(p)) return RRMHD_E_INVALID;
+  if (!(cfl > 0.0) || !(cfl < 1e300) || nsteps < 0) return RRMHD_E_INVALID;
+  const Layout L = make_layout(g);
+  if (L.total > kScratchBytes) return RRMHD_E_WORKSPACE;
+  void* ws = nullptr;
+  const rrmhd_status sst = scratch_for_current_device(&ws);
+  if (sst != RRMHD_OK) return sst;
+  // A context on the stack (its profiling vectors stay empty: no host
+  // allocation), pointed at the device's scratch array.
+  rrmhd_ctx c;
+  ctx_bind(&c, g, p, L, (char*)ws, hip_stream);
+  if (ctx_clear(&c) != RRMHD_OK) return RRMHD_E_DEVICE;
+  const rrmhd_status st = rrmhd_advance(&c, U, g, cfl, nsteps, opac, dt_out);
+  if (st != RRMHD_OK) return st;
+  if (report_dev) {
+    k_report_out<<<1, kRedBlock, 0, c.stream>>>(c.rep, c.blkmax, L.nblkmax, report_dev);
+    return launch_ok();
   }
   return RRMHD_OK;
 }

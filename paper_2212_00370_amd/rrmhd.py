@@ -72,6 +72,7 @@ SIGNATURES = {
     "rrmhd_step": ([_vp, _vp, _vp, _d, _vp], C.c_int),
     "rrmhd_max_speed": ([_vp, _vp, _vp, _vp], C.c_int),
     "rrmhd_advance": ([_vp, _vp, _vp, _d, C.c_int, _vp, _vp], C.c_int),
+    "rrmhd_advance_noalloc": ([_vp, _vp, _vp, _d, C.c_int, _vp, _vp, _vp, _vp], C.c_int),
     "rrmhd_face_fluxes": ([_vp, _vp, _vp, _vp], C.c_int),
     "rrmhd_profile_enable": ([_vp, C.c_int], C.c_int),
     "rrmhd_profile_stride": ([_vp, C.c_int], C.c_int),
@@ -158,6 +159,28 @@ def rrmhd_advance(ctx, U, grid: rrmhd_grid, cfl: float, nsteps: int, opac: rrmhd
         assert dt_out.dtype == torch.float64 and dt_out.is_cuda and dt_out.numel() >= nsteps
     _check(_lib.rrmhd_advance(ctx, _ptr(U), C.byref(grid), float(cfl), int(nsteps), C.byref(opac),
                               None if dt_out is None else _ptr(dt_out)), "rrmhd_advance")
+
+
+def rrmhd_advance_noalloc(grid: rrmhd_grid, params: rrmhd_params, U, cfl: float, nsteps: int,
+                          opac: rrmhd_opacities, dt_out=None, report_dev=None, stream=None) -> None:
+    """rrmhd_advance without a context or workspace (the library's per-device
+    scratch array); enqueued. report_dev: optional device tensor of at least
+    sizeof(rrmhd_report) bytes receiving the call's failure counters."""
+    if dt_out is not None:
+        import torch
+        assert dt_out.dtype == torch.float64 and dt_out.is_cuda and dt_out.numel() >= nsteps
+    if report_dev is not None:
+        assert report_dev.is_cuda and report_dev.numel() * report_dev.element_size() >= C.sizeof(rrmhd_report)
+    _check(_lib.rrmhd_advance_noalloc(C.byref(grid), C.byref(params), _ptr(U), float(cfl), int(nsteps),
+                                      C.byref(opac), None if dt_out is None else _ptr(dt_out),
+                                      None if report_dev is None else _ptr(report_dev),
+                                      None if stream is None else C.c_void_p(stream.cuda_stream)),
+           "rrmhd_advance_noalloc")
+
+
+def report_from_bytes(raw: bytes) -> dict:
+    """The rrmhd_report written by rrmhd_advance_noalloc, from its bytes."""
+    return rrmhd_report.from_buffer_copy(raw[: C.sizeof(rrmhd_report)]).as_dict()
 
 
 def rrmhd_max_speed(ctx, U, grid: rrmhd_grid) -> float:

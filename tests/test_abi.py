@@ -148,6 +148,20 @@ def test_argument_errors_need_no_device(R):
     assert R._lib.rrmhd_advance(None, None, C.byref(g), 0.4, 1, C.byref(op), None) == R.RRMHD_E_INVALID
     out = C.c_double()
     assert R._lib.rrmhd_max_speed(None, None, C.byref(g), C.byref(out)) == R.RRMHD_E_INVALID
+    # the allocation-free advance validates before touching a device: a null
+    # state, a bad cfl or step count, and a grid whose workspace exceeds the
+    # 64 MiB scratch array are refused (the state pointer is never read)
+    fake = C.c_void_p(0x1000)
+    na = R._lib.rrmhd_advance_noalloc
+    assert na(C.byref(g), C.byref(p), None, 0.4, 1, C.byref(op), None, None, None) == R.RRMHD_E_INVALID
+    assert na(C.byref(g), C.byref(p), fake, 0.0, 1, C.byref(op), None, None, None) == R.RRMHD_E_INVALID
+    assert na(C.byref(g), C.byref(p), fake, 0.4, -1, C.byref(op), None, None, None) == R.RRMHD_E_INVALID
+    assert na(C.byref(g2), C.byref(p), fake, 0.4, 1, C.byref(op), None, None, None) == R.RRMHD_E_INVALID
+    big = _grid(R, (512, 512))
+    assert R._lib.rrmhd_workspace_bytes(C.byref(big), C.byref(p)) > (64 << 20)
+    assert na(C.byref(big), C.byref(p), fake, 0.4, 1, C.byref(op), None, None, None) == R.RRMHD_E_WORKSPACE
+    fits = _grid(R, (360, 360))
+    assert R._lib.rrmhd_workspace_bytes(C.byref(fits), C.byref(p)) <= (64 << 20)
 
 
 def test_error_strings(R):
