@@ -189,11 +189,13 @@ def radiation_rp_1d(test: int, n: int = 256) -> Problem:
 
 
 def blast_2d(seed: int = 0, nx: int = 512, ny: int | None = None, steps: int = 200,
-             e_bg: float = 0.0) -> Problem:
+             e_bg: float = 0.0, p_in: float = 10.0) -> Problem:
     """Magnetised cylindrical blast on [-1/2, 1/2]^2 (periodic).
 
     Radiation starts in equilibrium with the gas, E_r = a_R T^4, plus an
-    optional uniform isotropic background ``e_bg``; F_r = 0."""
+    optional uniform isotropic background ``e_bg``; F_r = 0. ``p_in``: the
+    pressure inside r < 0.1 (10: overpressure 1e3 over the ambient 0.01); the
+    radiation constant stays 1e-3."""
     ny = nx if ny is None else ny
     rng = np.random.default_rng(seed)
     dx, dy = 1.0 / nx, 1.0 / ny
@@ -209,7 +211,7 @@ def blast_2d(seed: int = 0, nx: int = 512, ny: int | None = None, steps: int = 2
     g /= np.max(np.abs(g))
     rho = 1.0 + 0.01 * g
     r = np.sqrt(X * X + Y * Y)
-    p = np.where(r < 0.1, 10.0, 0.01)
+    p = np.where(r < 0.1, p_in, 0.01)
     T = p / rho
     a_rad = 10.0 / 10.0 ** 4          # p_in / T_in^4: radiation ~ gas pressure inside
     V = np.zeros((NV, ny * nx))
