@@ -40,7 +40,7 @@ class OPar(C.Structure):
         ("rho_floor", C.c_double), ("p_floor", C.c_double),
         ("pvm_k", C.c_int), ("beta_mode", C.c_int), ("recon", C.c_int), ("rk_order", C.c_int),
         ("c2p_maxit", C.c_int), ("imp_maxit", C.c_int), ("imp_picard_it", C.c_int),
-        ("imp_method", C.c_int), ("e_floor", C.c_double), ("solver", C.c_int),
+        ("imp_method", C.c_int), ("e_floor", C.c_double), ("solver", C.c_int), ("ct", C.c_int),
     ]
 
 
@@ -63,7 +63,7 @@ class OReport(C.Structure):
 DEFAULTS = dict(
     gamma=5.0 / 3.0, a_rad=1.0, t_coeff=1.0, pvm_eps=1e-8, c2p_tol=1e-12, imp_tol=1e-13,
     rho_floor=1e-12, p_floor=1e-12, pvm_k=3, beta_mode=1, recon=1, rk_order=2,
-    c2p_maxit=100, imp_maxit=50, imp_picard_it=8, imp_method=0, e_floor=0.0, solver=0,
+    c2p_maxit=100, imp_maxit=50, imp_picard_it=8, imp_method=0, e_floor=0.0, solver=0, ct=0,
 )
 
 SOLVER_PVM, SOLVER_HLL, SOLVER_PVM_JVP = 0, 1, 2
@@ -132,6 +132,15 @@ def threads(n: int = 0) -> int:
 def _soa(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     assert a.ndim == 2 and a.shape[0] == 12
+    return a
+
+
+def _state(a):
+    """A grid state: the 12 conserved planes, plus with constrained transport
+    one staggered normal-field plane per grid dimension (the face on the lower
+    side of each cell)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    assert a.ndim == 2 and 12 <= a.shape[0] <= 15
     return a
 
 
@@ -310,8 +319,9 @@ def _opac(kap, sig, ncell):
 
 
 def step(grid, U, dt, kap, sig, par=None):
-    """One IMEX step; U is [12, ncell] (x fastest) and is not modified."""
-    U = np.array(_soa(U), copy=True)
+    """One IMEX step; U is [12, ncell] (x fastest; [12 + ndim, ncell] with
+    constrained transport) and is not modified."""
+    U = np.array(_state(U), copy=True)
     ncell = U.shape[1]
     assert ncell == grid.var_stride
     ka, sa, k0, s0 = _opac(kap, sig, ncell)
@@ -323,7 +333,7 @@ def step(grid, U, dt, kap, sig, par=None):
 
 
 def max_speed(grid, U, par=None):
-    U = _soa(U)
+    U = _state(U)
     nf = C.c_longlong(0)
     par = par or params()
     s = lib().or_max_speed(C.byref(grid), C.byref(par), _dp(U), C.byref(nf))
@@ -331,7 +341,7 @@ def max_speed(grid, U, par=None):
 
 
 def face_fluxes(grid, U, kap, sig, par=None):
-    U = _soa(U)
+    U = _state(U)
     ncell = U.shape[1]
     ka, sa, k0, s0 = _opac(kap, sig, ncell)
     n = [grid.n[e] for e in range(3)]

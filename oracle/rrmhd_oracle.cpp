@@ -123,6 +123,8 @@ struct OPar {
   double e_floor;    // > 0: a non-positive explicit E_r is raised to this (counted); 0: failure
   int solver;        // 0: PVM-int (Section 3.2); 1: Rad-HLL (Section 3.2, Radiative HLL);
                      // 2: PVM-int with exact Jacobian-vector products
+  int ct;            // 0: cell-centred B; 1: constrained transport (staggered normal B on
+                     //    the faces, CT-contact edge EMFs); periodic grids, ndim >= 2
 };
 
 struct OGrid {
@@ -1259,8 +1261,11 @@ static long long face_count(const Grid& G, int d) {
 // Face fluxes of one direction. Face index: along d the face i sits between
 // cells i-1 and i (i = 0..n_d); faces are numbered with x fastest over the
 // face-grid extents.
+// bface (constrained transport): the staggered normal field b_d, one value per
+// cell for the face on its lower side along d; both reconstructed states of a
+// face take the face's own b_d as their normal field component.
 static long long stage_faces(const Grid& G, const OPar& P, const Consts& K, const CellPrim& cp,
-                             int d, double* Fh, const double* coef, int M) {
+                             int d, double* Fh, const double* coef, int M, const double* bface = nullptr) {
   const long long nf = face_count(G, d);
   int fn[3] = {G.n[0], G.n[1], G.n[2]};
   fn[d] += 1;
@@ -1287,6 +1292,13 @@ static long long stage_faces(const Grid& G, const OPar& P, const Consts& K, cons
     for (int q = 0; q < NV; ++q) { VL[q] = Vs[1][q] + 0.5 * sa[q]; VR[q] = Vs[2][q] - 0.5 * sb[q]; }
     limit_rad_flux(VL);
     limit_rad_flux(VR);
+    if (bface) {
+      int cc[3] = {c[0], c[1], c[2]};
+      cc[d] = c[d] % G.n[d];  // face n_d is face 0 (periodic)
+      const real bn = bface[(long long)cc[0] + (long long)G.n[0] * ((long long)cc[1] + (long long)G.n[1] * cc[2])];
+      VL[5 + d] = bn;
+      VR[5 + d] = bn;
+    }
     const real tauL = tp[1] * dxd, tauR = tp[2] * dxd;
     real Fq[NV];
     FaceOut fo;
@@ -1297,6 +1309,135 @@ static long long stage_faces(const Grid& G, const OPar& P, const Consts& K, cons
     for (int q = 0; q < NV; ++q) Fh[q * nf + f] = dv(Fq[q]);
   }
   return nfb;
+}
+
+// ---------------------------------------------------------------------------
+// Constrained transport (Section 4, opening paragraph: div B = 0 is kept with
+// CT, the edge electromotive forces averaged by the CT-contact rule of
+// Gardiner & Stone 2005). Periodic grids with ndim >= 2.
+// Storage: the normal field b_a of the face on the lower side of cell c along
+// a; the edge EMF E_k (edge along k, (a, b, k) cyclic) of the edge at the
+// lower corner of cell c in the (a, b) plane. Only edges whose plane lies in
+// the grid exist (2D: E_z).
+// Face EMFs follow from the face fluxes of the induction equation,
+// F_a(B_b) = v_a B_b - B_a v_b = -E_k on a-faces and F_b(B_a) = +E_k on
+// b-faces; the cell-centre EMF from the cell's primitives,
+// E_k = -(v_a B_b - v_b B_a). The corner EMF is the mean of its four face
+// EMFs plus, along each plane direction, a quarter of the difference of the
+// EMF gradients on the two sides of the corner, each gradient taken from the
+// cell upwind of the contact (the sign of the mass flux through the face
+// that separates the two candidate cells; their mean when it is zero).
+
+// Periodic cell index of (i, j, k) + shifts.
+static long long pcell(const Grid& G, int i, int j, int k) {
+  i = ((i % G.n[0]) + G.n[0]) % G.n[0];
+  j = ((j % G.n[1]) + G.n[1]) % G.n[1];
+  k = ((k % G.n[2]) + G.n[2]) % G.n[2];
+  return (long long)i + (long long)G.n[0] * ((long long)j + (long long)G.n[1] * k);
+}
+
+// Index of the face on the lower side of cell (i, j, k) along d (face grid
+// with n_d + 1 faces along d, x fastest).
+static long long lower_face(const Grid& G, int d, int i, int j, int k) {
+  int fn[3] = {G.n[0], G.n[1], G.n[2]};
+  fn[d] += 1;
+  return (long long)i + (long long)fn[0] * ((long long)j + (long long)fn[1] * k);
+}
+
+// Upwind choice by the sign of a mass flux: lower-side value when it is
+// positive, upper-side when negative, their mean when zero.
+static real upwind(real mflux, real lower_side, real upper_side) {
+  if (mflux > real(0.0)) return lower_side;
+  if (mflux < real(0.0)) return upper_side;
+  return 0.5 * (lower_side + upper_side);
+}
+
+// Edge EMFs E_k (k = 0..2; empty where the edge's plane is not in the grid)
+// from the stage's face fluxes Fh[d] ([12][faces_d]) and cell primitives.
+static void ct_edge_emfs(const Grid& G, const CellPrim& cp, const std::vector<std::vector<double>>& Fh,
+                         std::vector<double> E[3]) {
+  const long long N = G.ncell;
+  const int nd = G.g.ndim;
+  for (int k = 0; k < 3; ++k) {
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    E[k].clear();
+    if (a >= nd || b >= nd) continue;
+    E[k].assign(N, 0.0);
+    const long long nfa = face_count(G, a), nfb = face_count(G, b);
+    const double* Fa = Fh[a].data();
+    const double* Fb = Fh[b].data();
+#pragma omp parallel for schedule(static)
+    for (long long c = 0; c < N; ++c) {
+      const int x[3] = {(int)(c % G.n[0]), (int)((c / G.n[0]) % G.n[1]), (int)(c / ((long long)G.n[0] * G.n[1]))};
+      // cells around the corner: c, c - e_a, c - e_b, c - e_a - e_b (periodic)
+      int ya[3] = {x[0], x[1], x[2]}, yb[3] = {x[0], x[1], x[2]}, yab[3] = {x[0], x[1], x[2]};
+      ya[a] -= 1; yb[b] -= 1; yab[a] -= 1; yab[b] -= 1;
+      const long long c_a = pcell(G, ya[0], ya[1], ya[2]);
+      const long long c_b = pcell(G, yb[0], yb[1], yb[2]);
+      const long long c_ab = pcell(G, yab[0], yab[1], yab[2]);
+      // lower faces (along a of c and c - e_b; along b of c and c - e_a)
+      const long long fa_c = lower_face(G, a, x[0], x[1], x[2]);
+      const int xb[3] = {(int)(c_b % G.n[0]), (int)((c_b / G.n[0]) % G.n[1]), (int)(c_b / ((long long)G.n[0] * G.n[1]))};
+      const long long fa_cb = lower_face(G, a, xb[0], xb[1], xb[2]);
+      const long long fb_c = lower_face(G, b, x[0], x[1], x[2]);
+      const int xa[3] = {(int)(c_a % G.n[0]), (int)((c_a / G.n[0]) % G.n[1]), (int)(c_a / ((long long)G.n[0] * G.n[1]))};
+      const long long fb_ca = lower_face(G, b, xa[0], xa[1], xa[2]);
+      // face EMFs
+      const real Ea_c = -real(Fa[(5 + b) * nfa + fa_c]);
+      const real Ea_cb = -real(Fa[(5 + b) * nfa + fa_cb]);
+      const real Eb_c = real(Fb[(5 + a) * nfb + fb_c]);
+      const real Eb_ca = real(Fb[(5 + a) * nfb + fb_ca]);
+      // cell-centre EMFs
+      auto ecell = [&](long long m) {
+        const real va = cp.V[(1 + a) * N + m], vb = cp.V[(1 + b) * N + m];
+        const real Ba = cp.V[(5 + a) * N + m], Bb = cp.V[(5 + b) * N + m];
+        return -(va * Bb - vb * Ba);
+      };
+      const real Ec_c = ecell(c), Ec_a = ecell(c_a), Ec_b = ecell(c_b), Ec_ab = ecell(c_ab);
+      // mass fluxes through the faces that separate the candidate cells
+      const real ma_c = Fa[0 * nfa + fa_c], ma_cb = Fa[0 * nfa + fa_cb];
+      const real mb_c = Fb[0 * nfb + fb_c], mb_ca = Fb[0 * nfb + fb_ca];
+      // gradients along b on the upper (b) and lower (b - 1) side of the
+      // corner, and along a on the upper (a) and lower (a - 1) side, as
+      // differences over half a cell
+      const real Dbhi = upwind(ma_c, Ec_a - Eb_ca, Ec_c - Eb_c);
+      const real Dblo = upwind(ma_cb, Eb_ca - Ec_ab, Eb_c - Ec_b);
+      const real Dahi = upwind(mb_c, Ec_b - Ea_cb, Ec_c - Ea_c);
+      const real Dalo = upwind(mb_ca, Ea_cb - Ec_ab, Ea_c - Ec_a);
+      const real s4 = (Ea_c + Ea_cb) + (Eb_c + Eb_ca);
+      const real corr = (Dblo - Dbhi) + (Dalo - Dahi);
+      E[k][c] = dv(0.25 * (s4 + corr));
+    }
+  }
+}
+
+// New face fields b_a = a0 b_a^(0) + a1 b_a^(s) - c dt (curl E)_a of a stage,
+// (curl E)_a = dE_k/dx_b - dE_b/dx_k for (a, b, k) cyclic (terms whose edges
+// exist only).
+static void ct_face_update(const Grid& G, const std::vector<double> E[3], const double idx[3], const double* b0,
+                           const double* bs, double a0, double a1, real cdt, double* bn) {
+  const long long N = G.ncell;
+  const int nd = G.g.ndim;
+  for (int a = 0; a < nd; ++a) {
+    const int b = (a + 1) % 3, k = (a + 2) % 3;
+#pragma omp parallel for schedule(static)
+    for (long long c = 0; c < N; ++c) {
+      const int x[3] = {(int)(c % G.n[0]), (int)((c / G.n[0]) % G.n[1]), (int)(c / ((long long)G.n[0] * G.n[1]))};
+      real t1 = 0.0, t2 = 0.0;
+      if (!E[k].empty()) {
+        int y[3] = {x[0], x[1], x[2]};
+        y[b] += 1;
+        t1 = (real(E[k][pcell(G, y[0], y[1], y[2])]) - real(E[k][c])) * idx[b];
+      }
+      if (!E[b].empty()) {
+        int y[3] = {x[0], x[1], x[2]};
+        y[k] += 1;
+        t2 = (real(E[b][pcell(G, y[0], y[1], y[2])]) - real(E[b][c])) * idx[k];
+      }
+      const real curl = t1 - t2;
+      bn[a * N + c] = dv((real(a0) * real(b0[a * N + c]) + real(a1) * real(bs[a * N + c])) - cdt * curl);
+    }
+  }
 }
 
 struct StageCoef { double a0, a1, c; };
@@ -1330,9 +1471,21 @@ static int step_impl(const OGrid& og, const OPar& P, double* U, const double* ka
   double coef[17];
   const int M = internal_poly(P.pvm_k, coef);
   OReport R = {0, 0, 0, 0, 0, -1, 0, 0};
-  std::vector<double> U0((size_t)NV * N), Us((size_t)NV * N);
-  for (int q = 0; q < NV; ++q)
+  if (P.ct) {
+    // constrained transport is defined here for periodic grids of 2 or 3 dimensions
+    bool ok = og.ndim >= 2;
+    for (int d = 0; d < og.ndim; ++d) ok = ok && og.bc_lo[d] == 0 && og.bc_hi[d] == 0;
+    if (!ok) { if (rep) *rep = R; return 5; }
+  }
+  // With constrained transport, planes NV .. NV + ndim - 1 hold the staggered
+  // normal fields, and the cell-centred B_a (a < ndim) is the mean of the two
+  // face values of its cell.
+  const int nb = P.ct ? og.ndim : 0;
+  const int NT = NV + nb;
+  std::vector<double> U0((size_t)NT * N), Us((size_t)NT * N);
+  for (int q = 0; q < NT; ++q)
     for (long long c = 0; c < N; ++c) { U0[q * N + c] = U[q * vs + c]; Us[q * N + c] = U[q * vs + c]; }
+  std::vector<double> Ek[3], bnew;
   StageCoef sc[3];
   const int ns = rk_stages(P.rk_order, sc);
   std::vector<std::vector<double>> Fh(og.ndim);
@@ -1345,10 +1498,17 @@ static int step_impl(const OGrid& og, const OPar& P, double* U, const double* ka
     R.c2p_fail += stage_prims(Gs, P, K, Us.data(), kap, sig, kap0, sig0, cp, &R.first_bad_cell, &R.max_c2p_it);
     for (int d = 0; d < og.ndim; ++d) {
       Fh[d].assign((size_t)NV * face_count(G, d), 0.0);
-      R.pvm_fallback += stage_faces(G, P, K, cp, d, Fh[d].data(), coef, M);
+      R.pvm_fallback += stage_faces(G, P, K, cp, d, Fh[d].data(), coef, M,
+                                    P.ct ? Us.data() + (size_t)(NV + d) * N : nullptr);
     }
     const real cdt = real(sc[s].c) * real(dt);
-    std::vector<double> Un((size_t)NV * N);
+    if (P.ct) {
+      ct_edge_emfs(G, cp, Fh, Ek);
+      bnew.assign((size_t)nb * N, 0.0);
+      ct_face_update(G, Ek, idx, U0.data() + (size_t)NV * N, Us.data() + (size_t)NV * N, sc[s].a0, sc[s].a1, cdt,
+                     bnew.data());
+    }
+    std::vector<double> Un((size_t)NT * N);
     long long nimp = 0, nnf = 0, nfl = 0, fb = -1;
     int mit = 0;
 #pragma omp parallel for schedule(static) reduction(+ : nimp, nnf, nfl) reduction(max : mit)
@@ -1356,6 +1516,14 @@ static int step_impl(const OGrid& og, const OPar& P, double* U, const double* ka
       const int ci[3] = {(int)(c % G.n[0]), (int)((c / G.n[0]) % G.n[1]), (int)(c / ((long long)G.n[0] * G.n[1]))};
       real Ust[NV];
       for (int q = 0; q < NV; ++q) {
+        if (q >= 5 && q < 5 + nb) {
+          // constrained transport: the mean of the cell's two new face values
+          int y[3] = {ci[0], ci[1], ci[2]};
+          y[q - 5] += 1;
+          const int a = q - 5;
+          Ust[q] = 0.5 * (real(bnew[a * N + c]) + real(bnew[a * N + pcell(G, y[0], y[1], y[2])]));
+          continue;
+        }
         real div = 0.0;
         for (int d = 0; d < og.ndim; ++d) {
           int fn[3] = {G.n[0], G.n[1], G.n[2]};
@@ -1380,6 +1548,7 @@ static int step_impl(const OGrid& og, const OPar& P, double* U, const double* ka
       mit = std::max(mit, iters);
       bool fin = true;
       for (int q = 0; q < NV; ++q) { Un[q * N + c] = dv(Unc[q]); if (!std::isfinite(dv(Unc[q]))) fin = false; }
+      for (int a = 0; a < nb; ++a) Un[(NV + a) * N + c] = bnew[a * N + c];
       if (!fin) nnf += 1;
       if (st != 0 || !fin) {
 #pragma omp critical
@@ -1393,7 +1562,7 @@ static int step_impl(const OGrid& og, const OPar& P, double* U, const double* ka
     if (mit > R.max_imp_it) R.max_imp_it = mit;
     Us.swap(Un);
   }
-  for (int q = 0; q < NV; ++q)
+  for (int q = 0; q < NT; ++q)
     for (long long c = 0; c < N; ++c) U[q * vs + c] = Us[q * N + c];
   if (rep) *rep = R;
   return (R.c2p_fail || R.imp_fail) ? 1 : ((R.nonfinite) ? 4 : 0);
@@ -1724,7 +1893,8 @@ long long or_face_fluxes(const OGrid* og, const OPar* P, const double* U, const 
   stage_prims(G, *P, K, U, kap, sig, kap0, sig0, cp, nullptr, nullptr);
   long long off = 0, nfb = 0;
   for (int d = 0; d < og->ndim; ++d) {
-    nfb += stage_faces(G, *P, K, cp, d, Fh + off, coef, M);
+    nfb += stage_faces(G, *P, K, cp, d, Fh + off, coef, M,
+                       P->ct ? U + (size_t)(NV + d) * og->var_stride : nullptr);
     off += NV * face_count(G, d);
   }
   return nfb;

@@ -21,6 +21,13 @@ Workloads (shapes and value ranges of the paper's test problems, Section 4):
     Section 4.1 (no radiation coupling), periodic on [0, 2 pi], gamma = 4/3.
   * ``serving_mix`` -- request mixes for the serving loop.
   * ``random_prims`` -- i.i.d. admissible states for unit-level checks.
+  * ``alfven_2d``, ``field_loop_2d`` -- periodic 2D problems for constrained
+    transport (staggered face fields in ``extra["bface"]``).
+
+For constrained transport a problem also carries the staggered normal field
+``extra["bface"]`` ``[ndim, ncell]``: row a holds b_a on the face on the lower
+side of each cell along a, with the cell-centred B_a of ``V`` the mean of its
+cell's two face values.
 """
 from __future__ import annotations
 
@@ -166,6 +173,72 @@ def alfven_1d(n: int) -> Problem:
     return Problem(name=f"alfven1d_n{n}", shape=(n,), dx=(dx,), x0=(0.0,), V=V, kappa=np.zeros(n),
                    sigma=np.zeros(n), gamma=gamma, a_rad=0.0, bc_lo=(PERIODIC,) * 3, bc_hi=(PERIODIC,) * 3,
                    cfl=0.3, t_end=length / va, extra={"v_a": va, "amplitude": amp})
+
+
+def uniform_face_fields(P: Problem) -> np.ndarray:
+    """Staggered normal fields of a problem whose in-plane field is uniform
+    (the blast): every face of direction a carries the cell value B_a."""
+    out = np.zeros((P.ndim, P.ncell))
+    for a in range(P.ndim):
+        assert np.all(P.V[5 + a] == P.V[5 + a][0]), "the in-plane field is not uniform"
+        out[a] = P.V[5 + a]
+    return out
+
+
+def alfven_2d(n: int, ny: int = 2) -> Problem:
+    """The Alfven wave of ``alfven_1d`` on an n x ny periodic grid, uniform in
+    y (dy = dx). Face fields: b_x = B_0 on every x-face; b_y of a y-face is
+    the B_y of the cells it separates (the field depends on x only)."""
+    P1 = alfven_1d(n)
+    dx = P1.dx[0]
+    V = np.tile(P1.V, (1, ny))
+    bface = np.zeros((2, n * ny))
+    bface[0] = V[5]
+    bface[1] = V[6]
+    return Problem(name=f"alfven2d_n{n}x{ny}", shape=(n, ny), dx=(dx, dx), x0=(0.0, 0.0), V=V,
+                   kappa=np.zeros(n * ny), sigma=np.zeros(n * ny), gamma=P1.gamma, a_rad=0.0,
+                   bc_lo=(PERIODIC,) * 3, bc_hi=(PERIODIC,) * 3, cfl=P1.cfl, t_end=P1.t_end,
+                   extra=dict(P1.extra, bface=bface))
+
+
+def field_loop_2d(nx: int, ny: int | None = None, v0: float = 0.5, b0: float = 1e-3, radius: float = 0.3,
+                  angle_deg: float | None = None) -> Problem:
+    """Advection of a weak magnetic field loop (the constrained-transport test
+    of Gardiner & Stone 2005) on [-1, 1] x [-1/2, 1/2], periodic: uniform
+    rho = 1, p = 1, velocity v0 along the diagonal of the box, field from the
+    vector potential A_z = b0 (R - r) for r < R (0 outside), gamma = 5/3;
+    radiation passive (E_r = 1e-8, no opacity). The face fields are the
+    differences of A_z at the cell corners (b_x = dA_z/dy, b_y = -dA_z/dx),
+    so their discrete divergence is zero; the cell-centred field is the mean
+    of each cell's two face values. One crossing of the box takes
+    t = 2 / (v0 cos theta)."""
+    ny = nx // 2 if ny is None else ny
+    lx, ly = 2.0, 1.0
+    dx, dy = lx / nx, ly / ny
+    theta = math.atan2(ly, lx) if angle_deg is None else math.radians(angle_deg)
+    xc = -1.0 + (np.arange(nx + 1)) * dx          # corners
+    yc = -0.5 + (np.arange(ny + 1)) * dy
+    Xc, Yc = np.meshgrid(xc, yc, indexing="xy")   # [ny + 1, nx + 1]
+    r = np.sqrt(Xc * Xc + Yc * Yc)
+    Az = np.where(r < radius, b0 * (radius - r), 0.0)
+    bx = (Az[1:, :-1] - Az[:-1, :-1]) / dy        # x-face (i - 1/2, j): corners j-1/2 .. j+1/2
+    by = -(Az[:-1, 1:] - Az[:-1, :-1]) / dx       # y-face (i, j - 1/2): corners i-1/2 .. i+1/2
+    Bx = 0.5 * (bx + np.roll(bx, -1, axis=1))
+    By = 0.5 * (by + np.roll(by, -1, axis=0))
+    N = nx * ny
+    V = np.zeros((NV, N))
+    V[0] = 1.0
+    V[1] = v0 * math.cos(theta)
+    V[2] = v0 * math.sin(theta)
+    V[4] = 1.0
+    V[5] = Bx.reshape(-1)
+    V[6] = By.reshape(-1)
+    V[8] = 1e-8
+    return Problem(name=f"fieldloop2d_{nx}x{ny}", shape=(nx, ny), dx=(dx, dy), x0=(-1.0, -0.5), V=V,
+                   kappa=np.zeros(N), sigma=np.zeros(N), gamma=5.0 / 3.0, a_rad=0.0,
+                   bc_lo=(PERIODIC,) * 3, bc_hi=(PERIODIC,) * 3, cfl=0.4,
+                   t_end=lx / (v0 * math.cos(theta)),
+                   extra={"bface": np.stack([bx.reshape(-1), by.reshape(-1)]), "b0": b0, "radius": radius})
 
 
 def radiation_rp_1d(test: int, n: int = 256) -> Problem:

@@ -69,6 +69,15 @@ MUTANTS = {
                           "sy.C[1 + i][1 + j] = (i == j) ? 1.0 - hrW * (ks + g) : hrW * g;"),
     "emission_with_scattering": ("const real em = (hr * kap) * aT4;", "const real em = (hr * (kap + sig)) * aT4;"),
     "no_post_solve_flux_limit": (RESCALE, RESCALE.replace("if (FF > X[0]", "if (false && FF > X[0]")),
+    # constrained transport (Section 4; CT-contact EMFs)
+    "ct_arithmetic_average": ("E[k][c] = dv(0.25 * (s4 + corr));", "E[k][c] = dv(0.25 * s4);"),
+    "ct_downwind": ("  if (mflux > real(0.0)) return lower_side;\n  if (mflux < real(0.0)) return upper_side;",
+                    "  if (mflux > real(0.0)) return upper_side;\n  if (mflux < real(0.0)) return lower_side;"),
+    "ct_face_emf_sign": ("const real Ea_c = -real(Fa[(5 + b) * nfa + fa_c]);", "const real Ea_c = real(Fa[(5 + b) * nfa + fa_c]);"),
+    "ct_curl_sign": ("      const real curl = t1 - t2;", "      const real curl = t1 + t2;"),
+    "ct_cell_field_lower_face": ("Ust[q] = 0.5 * (real(bnew[a * N + c]) + real(bnew[a * N + pcell(G, y[0], y[1], y[2])]));",
+                                 "Ust[q] = real(bnew[a * N + c]);"),
+    "ct_no_normal_field_override": ("      VL[5 + d] = bn;\n      VR[5 + d] = bn;", "      (void)bn;"),
     # Rad-HLL (Section 3.2, Radiative HLL)
     "hll_limit_without_four_thirds": ("const real lim = 4.0 / (3.0 * rmax(tauL, tauR));",
                                       "const real lim = 1.0 / rmax(tauL, tauR);"),
