@@ -57,45 +57,63 @@ def load_json(path):
         return None
 
 
-def cpu_baseline(P, steps: int, solver: int = 0):
+def cpu_baseline(P, steps: int, solver: int = 0, compare=None):
     """The CPU oracle (as it stands, OpenMP over cells) on the first `steps`
-    steps of the same workload from the same initial state."""
+    steps of the same workload from the same initial state. compare:
+    (k, U_gpu): the GPU state after k steps (k <= steps), checked against the
+    oracle's state after k steps (same time-step rule, so the same dt)."""
+    import numpy as np
     from oracle import oracle as O
     nthreads = O.threads(0)
     par = O.params(gamma=P.gamma, a_rad=P.a_rad, beta_mode=1, solver=solver)
     g = O.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
     U = O.p2c(P.V, par)
+    check = None
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         s, _ = O.max_speed(g, U, par)
         dt = P.cfl * min(P.dx) / s
         U, st, rep = O.step(g, U, dt, P.kappa, P.sigma, par)
+        if compare is not None and k + 1 == compare[0]:
+            c0 = time.perf_counter()
+            Ug = compare[1]
+            scale = np.maximum(np.abs(U), 1e-3 * np.abs(U).max(axis=1, keepdims=True))
+            scale[scale == 0] = 1.0
+            check = {"step": k + 1, "bitwise": bool(np.array_equal(Ug, U)),
+                     "max_rel_err": float(np.max(np.abs(Ug - U) / scale))}
+            t0 += time.perf_counter() - c0
     el = time.perf_counter() - t0
-    return dict(value=P.ncell * steps / el, unit="zone-updates/s", cores=nthreads, kind="oracle",
-                sample=f"first {steps} steps of the same {P.shape[0]}x{P.shape[1]} blast "
-                       f"(CFL signal speed + IMEX step), {el:.1f} s")
+    out = dict(value=P.ncell * steps / el, unit="zone-updates/s", cores=nthreads, kind="oracle",
+               sample=f"first {steps} steps of the same {P.shape[0]}x{P.shape[1]} blast "
+                      f"(CFL signal speed + IMEX step), {el:.1f} s")
+    return out, check
 
 
-def serving_bench(args):
-    """Continuous batching of a Poisson stream of independent problems (1D
-    Riemann N ~ logU[256, 8192] to t = 0.05; 2D blasts N^2, N ~ logU[64, 512],
-    10-50 steps; FP64 / mixed 50/50). Capacity is measured first with every
-    request present at t = 0; the timed run uses Poisson arrivals at
-    `load` x capacity. The comparison runs the same requests one at a time in
-    FP64 through rrmhd_step."""
+def log(msg):
+    """Progress of a long leg, on stderr (the JSON line is the only stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def serving_run(mix, loads, seed, seq_sample, budget_frac=0.5, label="serving"):
+    """Continuous batching of independent problems (serving.Server: one
+    batched launch per kernel class and tick, admission by HBM footprint).
+    Capacity is measured first with every request present at t = 0; each timed
+    run then draws Poisson arrivals at load x capacity. The comparison runs the
+    first `seq_sample` requests one at a time in FP64 through rrmhd_max_speed +
+    rrmhd_step (the single-simulation entry points)."""
     import numpy as np
     import torch
     from paper_2212_00370_amd import inputs as I
     from paper_2212_00370_amd import rrmhd as R
     from paper_2212_00370_amd import serving as S
 
-    mix = I.serving_mix(args.seed, args.requests)
-    def reqs(arrivals, force_fp64=False):
-        return [S.Request(rid=i, problem=m["problem"], precision=R.FP64 if (force_fp64 or not m["mixed"]) else R.MIXED,
-                          t_end=m["t_end"], steps=m["steps"], arrival=float(a)) for i, (m, a) in enumerate(zip(mix, arrivals))]
+    def reqs(arrivals, subset=None):
+        idx = range(len(mix)) if subset is None else subset
+        return [S.Request(rid=i, problem=mix[i]["problem"], precision=R.MIXED if mix[i]["mixed"] else R.FP64,
+                          t_end=mix[i]["t_end"], steps=mix[i]["steps"], arrival=float(a))
+                for i, a in zip(idx, arrivals)]
     free, total = torch.cuda.mem_get_info()
-    budget = int(0.5 * free)
-    # capacity: all requests present at once
+    budget = int(budget_frac * free)
     srv = S.Server(budget, max_sims=256)
     t0 = time.perf_counter()
     res0 = srv.run(reqs(np.zeros(len(mix))))
@@ -103,44 +121,144 @@ def serving_bench(args):
     srv.close()
     zu = sum(r.zone_updates for r in res0)
     mu = len(mix) / cap_s
-    rate = args.load * mu
-    arr = I.poisson_arrivals(args.seed + 1, len(mix), rate)
-    srv = S.Server(budget, max_sims=256)
+    fails = sum(1 for r in res0 if r.report.get("imp_fail", 0) or r.report.get("c2p_fail", 0))
+    log(f"{label}: capacity run, {len(mix)} requests in {cap_s:.1f} s")
+    runs = []
+    for li, load in enumerate(loads):
+        rate = load * mu
+        arr = I.poisson_arrivals(seed + 1 + li, len(mix), rate)
+        srv = S.Server(budget, max_sims=256)
+        t0 = time.perf_counter()
+        res = srv.run(reqs(arr))
+        wall = time.perf_counter() - t0
+        srv.close()
+        tts = [r.time_to_solution for r in res]
+        runs.append({"load": load, "arrival_rate_per_s": rate,
+                     "p50_time_to_solution_s": S.percentile(tts, 50),
+                     "p99_time_to_solution_s": S.percentile(tts, 99),
+                     "zone_updates_per_s": sum(r.zone_updates for r in res) / wall, "wall_s": wall,
+                     "ticks": srv.ticks, "mean_batch": float(np.mean(srv.batch_sizes)),
+                     "peak_resident_bytes": srv.peak_in_use})
+        log(f"{label}: load {load}, p50 {runs[-1]['p50_time_to_solution_s']:.3f} s, "
+            f"p99 {runs[-1]['p99_time_to_solution_s']:.3f} s, {wall:.1f} s")
+    # one at a time, FP64, single-simulation entry points, on a sample
+    ns = min(seq_sample, len(mix))
+    zs = 0
     t0 = time.perf_counter()
-    res = srv.run(reqs(arr))
-    wall = time.perf_counter() - t0
-    tts = [r.time_to_solution for r in res]
-    # one at a time, FP64, single-simulation entry points
-    t0 = time.perf_counter()
-    for m in mix:
+    for m in mix[:ns]:
         P = m["problem"]
         p = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad)
         g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
-        s = R.Solver(g, p)
-        U = s.prim_to_cons(torch.from_numpy(P.V).cuda())
+        sv = R.Solver(g, p)
+        U = sv.prim_to_cons(torch.from_numpy(P.V).cuda())
         o = R.make_opacities(torch.from_numpy(P.kappa).cuda(), torch.from_numpy(P.sigma).cuda())
         t, k = 0.0, 0
         while (m["steps"] is not None and k < m["steps"]) or (m["t_end"] is not None and t < m["t_end"] * (1 - 1e-14)):
-            dt = P.cfl * min(P.dx) / s.max_speed(U)
+            dt = P.cfl * min(P.dx) / sv.max_speed(U)
             if m["t_end"] is not None:
                 dt = min(dt, m["t_end"] - t)
-            s.step(U, dt, o)
-            t += dt; k += 1
+            sv.step(U, dt, o)
+            t += dt
+            k += 1
         torch.cuda.synchronize()
-        s.close()
+        sv.close()
+        zs += k * P.ncell
     seq_s = time.perf_counter() - t0
+    log(f"{label}: one-at-a-time FP64 on {ns} requests in {seq_s:.1f} s")
+    return {"requests": len(mix), "capacity_req_per_s": mu, "capacity_zone_updates_per_s": zu / cap_s,
+            "requests_with_counted_failures": fails, "runs": runs,
+            "one_at_a_time_fp64": {"requests": ns, "zone_updates_per_s": zs / seq_s, "wall_s": seq_s},
+            "batched_capacity_over_one_at_a_time_fp64": (zu / cap_s) / (zs / seq_s),
+            "hbm_budget_bytes": budget}
+
+
+def serving_bench(args):
+    """The serving workload as specified: >= 1000 requests, half 1D Riemann
+    problems (N ~ logU[256, 8192], to t = 0.4), half 2D blasts (N^2 cells,
+    N ~ logU[64, 512], 100 steps), FP64 / mixed 50/50, Poisson arrivals at
+    each load x capacity."""
+    from paper_2212_00370_amd import inputs as I
+    mix = I.serving_mix(args.seed, args.requests, t_end_1d=args.t_end_1d, steps_2d=(args.steps_2d, args.steps_2d))
+    loads = [float(x) for x in args.loads.split(",")]
+    r = serving_run(mix, loads, args.seed, args.seq_sample)
+    main = min(r["runs"], key=lambda x: abs(x["load"] - 0.8))
     return {
-        "metric": METRIC, "value": zu / wall, "unit": "zone-updates/s", "n_gpus": 1,
-        "mode": "serving", "requests": len(mix), "higher_is_better": True, "data": "synthetic",
+        "metric": METRIC, "value": main["zone_updates_per_s"], "unit": "zone-updates/s", "n_gpus": 1,
+        "mode": "serving", "higher_is_better": True, "data": "synthetic",
         "dtype": "f64 and f32+f64 requests (50/50)",
-        "p50_time_to_solution_s": S.percentile(tts, 50), "p99_time_to_solution_s": S.percentile(tts, 99),
-        "arrival_rate_per_s": rate, "capacity_req_per_s": mu, "load": args.load,
-        "capacity_zone_updates_per_s": zu / cap_s, "sequential_fp64_zone_updates_per_s": zu / seq_s,
-        "wall_s": wall, "ticks": srv.ticks, "mean_batch": float(np.mean(srv.batch_sizes)),
-        "hbm_budget_bytes": budget, "peak_resident_bytes": srv.peak_in_use,
-        "config": {"workload": "Poisson stream: 1D Riemann N~logU[256,8192] to t=0.05, 2D blast N^2 with "
-                               "N~logU[64,512] for 10-50 steps, FP64/mixed 50/50"},
+        "p50_time_to_solution_s": main["p50_time_to_solution_s"],
+        "p99_time_to_solution_s": main["p99_time_to_solution_s"], "load": main["load"],
+        "config": {"workload": f"Poisson stream of {args.requests} requests: 1D Riemann N~logU[256,8192] to "
+                               f"t={args.t_end_1d}, 2D blast N^2 with N~logU[64,512] for {args.steps_2d} steps, "
+                               f"FP64/mixed 50/50, loads {args.loads}"},
+        "serving": r,
     }
+
+
+def riemann1d_bench(args):
+    """A batch of seeded 1D Riemann problems (400 cells on [0, 1], PLM MinMod,
+    PVM-int-8, IMEX RK2, CFL 0.4) run to t = 0.4 together through
+    rrmhd_max_speed_batch + rrmhd_step_batch: one problem cannot fill the
+    GPU, so the throughput figure is for `--batch` seeds at once (each with its
+    own time step; finished problems leave the batch)."""
+    import numpy as np
+    import torch
+    from paper_2212_00370_amd import inputs as I
+    from paper_2212_00370_amd import rrmhd as R
+
+    nb = args.batch
+    prec = R.MIXED if args.precision == "mixed" else R.FP64
+    sims = []
+    for seed in range(nb):
+        P = I.riemann_1d(seed, 400)
+        p = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=prec)
+        g = R.make_grid(P.shape, P.dx, P.bc_lo, P.bc_hi)
+        sv = R.Solver(g, p)
+        U = sv.prim_to_cons(torch.from_numpy(P.V).cuda())
+        o = R.make_opacities(torch.from_numpy(P.kappa).cuda(), torch.from_numpy(P.sigma).cuda())
+        sims.append(dict(P=P, s=sv, U=U, U0=U.clone(), o=o, t=0.0, k=0))
+    batch = R.Batch(nb)
+    torch.cuda.synchronize()
+
+    def run_all(max_ticks=None):
+        for d in sims:
+            d["U"].copy_(d["U0"]); d["t"] = 0.0; d["k"] = 0
+            d["s"].report()
+        active = list(sims)
+        ticks = 0
+        while active and (max_ticks is None or ticks < max_ticks):
+            sm = batch.max_speed([d["s"] for d in active], [d["U"] for d in active])
+            dts = [min(d["P"].cfl * d["P"].dx[0] / v, d["P"].t_end - d["t"]) for d, v in zip(active, sm)]
+            batch.step([d["s"] for d in active], [d["U"] for d in active], dts, [d["o"] for d in active])
+            for d, dt in zip(active, dts):
+                d["t"] += dt
+                d["k"] += 1
+            active = [d for d in active if d["t"] < d["P"].t_end * (1 - 1e-14)]
+            ticks += 1
+        torch.cuda.synchronize()
+        return ticks
+
+    run_all(max_ticks=5)                      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ticks = run_all()
+    el = time.perf_counter() - t0
+    zu = sum(d["k"] * d["P"].ncell for d in sims)
+    reps = [d["s"].report() for d in sims]
+    failing = sorted(i for i, r in enumerate(reps) if r["imp_fail"] or r["c2p_fail"])
+    batch.close()
+    for d in sims:
+        d["s"].close()
+    return {"metric": METRIC, "value": zu / el, "unit": "zone-updates/s", "n_gpus": 1,
+            "steps": int(np.max([d["k"] for d in sims])), "warmup": 5, "ms_per_step": 1e3 * el / ticks,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64" if prec == R.MIXED else "f64", "data": "synthetic", "mode": "riemann1d",
+            "config": {"workload": f"{nb} seeded 1D RRMHD+M1 Riemann problems x 400 cells, PVM-int-8, PLM MinMod, "
+                                   f"IMEX RK2, CFL 0.4, to t=0.4, batched (rrmhd_step_batch)",
+                       "problems": nb, "cells_per_problem": 400},
+            "ticks": ticks, "zone_updates": zu, "wall_s": el,
+            "steps_per_problem": {"min": int(min(d["k"] for d in sims)), "max": int(max(d["k"] for d in sims))},
+            "problems_with_counted_failures": len(failing), "failing_seeds_below_32": [i for i in failing if i < 32]}
 
 
 def beam3d_bench(args):
@@ -233,11 +351,18 @@ def main():
     ap.add_argument("--solver", choices=("pvm", "hll", "jvp"), default="pvm",
                     help="face flux: PVM-int-8 (the method), Rad-HLL (the paper's comparison solver) or "
                          "PVM-int-8 with exact Jacobian-vector products")
-    ap.add_argument("--mode", choices=("step", "serving", "beam3d", "copycal"), default="step")
+    ap.add_argument("--mode", choices=("step", "serving", "riemann1d", "beam3d", "copycal"), default="step")
     ap.add_argument("--no-variants", dest="variants", action="store_false",
                     help="skip the Rad-HLL / exact-JVP / mixed-precision lines of the default run")
-    ap.add_argument("--requests", type=int, default=120)
-    ap.add_argument("--load", type=float, default=0.8, help="arrival rate / measured capacity")
+    ap.add_argument("--no-serving", dest="serving", action="store_false",
+                    help="skip the short serving leg of the default run")
+    ap.add_argument("--requests", type=int, default=1000, help="--mode serving: number of requests")
+    ap.add_argument("--loads", default="0.5,0.8,0.95", help="--mode serving: arrival rate / measured capacity")
+    ap.add_argument("--t-end-1d", type=float, default=0.4, help="--mode serving: end time of the 1D requests")
+    ap.add_argument("--steps-2d", type=int, default=100, help="--mode serving: steps of the 2D requests")
+    ap.add_argument("--seq-sample", type=int, default=100,
+                    help="--mode serving: requests run one at a time in FP64 for the comparison")
+    ap.add_argument("--batch", type=int, default=1024, help="--mode riemann1d: problems run together")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for {args.gpus}); "
@@ -254,6 +379,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.mode == "serving":
         print(json.dumps(serving_bench(args)), flush=True)
+        return
+    if args.mode == "riemann1d":
+        print(json.dumps(riemann1d_bench(args)), flush=True)
         return
     if args.mode == "beam3d":
         print(json.dumps(beam3d_bench(args)), flush=True)
@@ -284,9 +412,9 @@ def main():
     opac = R.make_opacities(kap, sig)
     dxmin = min(P.dx)
 
-    def run(U, nsteps):
+    def run(U, nsteps, dt_out=None):
         # each step: signal speed, dt = cfl dx_min / s_max on the device, IMEX step
-        solver.advance(U, P.cfl, nsteps, opac)
+        solver.advance(U, P.cfl, nsteps, opac, dt_out)
 
     # warm-up on a copy, then restart from the initial state
     Uw = U0.clone()
@@ -300,9 +428,10 @@ def main():
     # sampled; each event pair serializes the stream around its launch).
     R.rrmhd_profile_enable(solver.ctx, 1 << R.K_FACES)
     R.rrmhd_profile_stride(solver.ctx, 7)
+    dts = torch.zeros(args.steps, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run(U, args.steps)
+    run(U, args.steps, dts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -350,6 +479,17 @@ def main():
                 "ops_per_face": round(per_face, 1), "faces_per_launch": ffaces // flaunch,
                 "mean_launch_ms": round(1e3 * mean_s, 4)}
 
+    # the implicit pass (flux divergence + implicit solve + next-stage
+    # recovery: k_update and k_newton), per stage, from the breakdown run
+    imp = None
+    if ops and not mixed and "update" in breakdown and "newton" in breakdown:
+        per_cell = ops["divergence_ops_per_cell"] + ops["implicit_ops_per_cell"] + ops["prims_ops_per_cell"]
+        stage_s = (breakdown["update"] + breakdown["newton"]) / 2 / 1e3
+        a = per_cell * P.ncell / stage_s / 1e12
+        imp = {"bound": "alu", "kernels": "k_update + k_newton", "ops_per_cell": round(per_cell, 1),
+               "cells_per_stage": P.ncell, "us_per_stage": round(1e6 * stage_s, 1), "achieved": round(a, 3),
+               "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(a / FP64_PEAK_TFLOPS, 4)}
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -370,15 +510,90 @@ def main():
                    "cells": P.ncell, "precision": args.precision, "solver": args.solver,
                    "beta_mode": "radiation rows" if not hll else None},
         "roofline": roof,
+        "roofline_implicit_pass": imp,
         "kernels_ms_per_step": breakdown,
         "kernels_ms_per_step_note": "separate run of min(steps, 20) steps with every launch timed",
         "failures": {k: rep[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")},
     }
+    Ufinal = U.cpu().numpy()
+    dts_host = dts.cpu().numpy()
     if args.variants and args.solver == "pvm" and not mixed:
         out["variants"] = variants_bench(R, P, grid, V, opac, args.steps, args.warmup)
+        log("variants done")
+        out["mixed_vs_fp64"] = mixed_accuracy(R, P, grid, V, opac, dts_host, Ufinal)
+        log("mixed-precision accuracy done")
+    if args.serving and args.solver == "pvm" and not mixed:
+        out["serving"] = serving_leg(args.seed)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(P, args.cpu_steps, solver_id)
+        cmp = (args.steps, Ufinal) if (args.steps <= args.cpu_steps and not mixed) else None
+        out["cpu_baseline"], chk = cpu_baseline(P, args.cpu_steps, solver_id, cmp)
+        if chk is not None:
+            out["fp64_vs_oracle"] = dict(chk, note="GPU state after the timed steps against the CPU oracle's "
+                                                   "state after the same steps from the same initial state")
     print(json.dumps(out), flush=True)
+
+
+def serving_leg(seed):
+    """A short serving run inside the default benchmark: 48 requests of the
+    serving mix with shorter runs (1D to t = 0.05, 2D 10-50 steps), Poisson
+    arrivals at 0.8 x capacity, and the same requests one at a time in FP64."""
+    from paper_2212_00370_amd import inputs as I
+    mix = I.serving_mix(seed, 48, t_end_1d=0.05, steps_2d=(10, 50))
+    r = serving_run(mix, [0.8], seed, len(mix), label="serving leg")
+    run = r["runs"][0]
+    return {"workload": "48 Poisson requests at 0.8 x capacity: 1D Riemann N~logU[256,8192] to t=0.05, "
+                        "2D blast N^2, N~logU[64,512], 10-50 steps; FP64/mixed 50/50",
+            "p50_time_to_solution_s": run["p50_time_to_solution_s"],
+            "p99_time_to_solution_s": run["p99_time_to_solution_s"],
+            "zone_updates_per_s": run["zone_updates_per_s"],
+            "capacity_zone_updates_per_s": r["capacity_zone_updates_per_s"],
+            "one_at_a_time_fp64_zone_updates_per_s": r["one_at_a_time_fp64"]["zone_updates_per_s"],
+            "batched_capacity_over_one_at_a_time_fp64": r["batched_capacity_over_one_at_a_time_fp64"],
+            "mean_batch": run["mean_batch"], "requests_with_counted_failures": r["requests_with_counted_failures"]}
+
+
+def mixed_accuracy(R, P, grid, V, opac, dts, U64_final):
+    """L1 of each mixed-precision form against the FP64 path with the same
+    face flux, both advanced from the same initial state with the same time
+    steps (those of the timed FP64 run): L1_rel(q) = sum|q_mixed - q_fp64| /
+    sum|q_fp64| for q = rho and E_r, at steps 1, 10, 50, 200 (those within the
+    run). The FP64 PVM-int-8 state is first checked to equal the timed run's
+    (and so the oracle's, bit for bit)."""
+    import torch
+    marks = [k for k in (1, 10, 50, 200) if k <= len(dts)]
+    if len(dts) not in marks:
+        marks.append(len(dts))
+
+    def trajectory(solver, prec):
+        params = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=prec, solver=solver)
+        sv = R.Solver(grid, params, device=V.device)
+        U = sv.prim_to_cons(V)
+        snaps = {}
+        for k, dt in enumerate(dts, start=1):
+            sv.step(U, float(dt), opac)
+            if k in marks:
+                Vp = sv.cons_to_prim(U)
+                snaps[k] = (Vp[0].clone(), U[8].clone())
+        rep = sv.report()
+        Uf = U.cpu().numpy()
+        sv.close()
+        return snaps, Uf, rep
+
+    l1 = lambda a, b: float((a - b).abs().sum() / b.abs().sum())
+    res = {"steps": marks, "dt_sequence": "that of the timed FP64 PVM-int-8 run",
+           "accumulation": "face fluxes binary32; flux divergence, recoveries and implicit solve binary64"}
+    import numpy as np
+    for name, solver in (("pvm", R.SOLVER_PVM), ("pvm_jvp", R.SOLVER_PVM_JVP), ("rad_hll", R.SOLVER_HLL)):
+        ref, Uref, _ = trajectory(solver, R.FP64)
+        if solver == R.SOLVER_PVM:
+            res["fp64_host_dt_equals_timed_run"] = bool(np.array_equal(Uref, U64_final))
+        mix, _, rep = trajectory(solver, R.MIXED)
+        res[name] = {"L1_rho": [l1(mix[k][0], ref[k][0]) for k in marks],
+                     "L1_Er": [l1(mix[k][1], ref[k][1]) for k in marks],
+                     "mixed_failures": {k: rep[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")}}
+        del ref, mix
+        torch.cuda.empty_cache()
+    return res
 
 
 def variants_bench(R, P, grid, V, opac, steps, warmup):
