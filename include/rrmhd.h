@@ -111,6 +111,14 @@ typedef struct {
                        the cell; > 0: it is raised to e_floor keeping tau + E_r and
                        S + F_r (the gas pays), and counted in e_floor_hits           */
   int solver;       /* RRMHD_SOLVER_*: face flux of the explicit step                 */
+  int ct;           /* 0: cell-centred B; 1: constrained transport (Section 4: div B
+                       kept by CT with CT-contact averaged edge EMFs). With ct = 1
+                       the state carries, after its 12 planes, one plane per grid
+                       dimension: plane 12 + a holds the normal field b_a of the
+                       face on the lower side of each cell along a, and the
+                       cell-centred B_a (a < ndim) is kept equal to the mean of
+                       its cell's two face values. Periodic grids with ndim >= 2
+                       only; not available in rrmhd_step_batch                */
 } rrmhd_params;
 
 /* Gray comoving opacities per unit mass (eqs. g0, gi): device arrays [ncell]
@@ -149,7 +157,8 @@ rrmhd_status rrmhd_init(rrmhd_ctx** ctx, const rrmhd_grid* g, const rrmhd_params
                         void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* Primitive -> conserved map of eq. eqU on every cell of the context's grid.
- * V, U: device, [12][var_stride]. Enqueued. */
+ * V, U: device, [12][var_stride] (with ct = 1 only U's first 12 planes are
+ * written; the face planes are the caller's). Enqueued. */
 rrmhd_status rrmhd_prim_to_cons(rrmhd_ctx* ctx, const double* V, double* U);
 
 /* Conserved -> primitive recovery (the inversion used in the PVM algorithm and
@@ -160,7 +169,8 @@ rrmhd_status rrmhd_cons_to_prim(rrmhd_ctx* ctx, const double* U, double* V);
 /* One IMEX step of size dt (Section 3.1: explicit stage with the PVM-int
  * face fluxes of Section 3.2, eq. explicit, then the implicit solve of
  * Section 3.3, eq. impliciteq; stages of the SSP RK pattern). U: device
- * [12][var_stride], updated in place. g must describe the context's grid
+ * [12][var_stride] ([12 + ndim][var_stride] with ct = 1: the face fields
+ * advance by the curl of the CT-contact edge EMFs), updated in place. g must describe the context's grid
  * (same ndim and n; dx and boundaries are taken from g). Enqueued; on a
  * numerical failure the failing cells keep their explicit state and the
  * counters say which. */

@@ -337,7 +337,23 @@ struct FaceArgs {
   long long nf[3];
   long long nb[3];   // blocks per direction
   double dx[3];
+  // Constrained transport: plane d of bface (stride bs) holds the normal
+  // field of the face on the lower side of each cell along d; nullptr: none.
+  const double* bface;
+  long long bs;
 };
+
+// Constrained transport: both states of a d-face take the face's own normal
+// field (face n_d is face 0 of the periodic grid).
+template <int d, typename T>
+__device__ __forceinline__ void face_normal_field(const GridDev& G, const FaceArgs& A, const int c[3], T VL[NV],
+                                                  T VR[NV]) {
+  int cc[3] = {c[0], c[1], c[2]};
+  if (cc[d] == G.n[d]) cc[d] = 0;
+  const double bn = A.bface[d * A.bs + ((long long)cc[0] + (long long)G.n[0] * ((long long)cc[1] + (long long)G.n[1] * cc[2]))];
+  VL[5 + d] = (T)bn;
+  VR[5 + d] = (T)bn;
+}
 
 // One face of direction d: PLM on the 4-cell stencil, |F_r| <= E_r,
 // then the PVM-int flux with beta from the two adjacent cells. REC >= 0 fixes
@@ -378,6 +394,7 @@ __device__ __forceinline__ void face_body(const GridDev& G, const FaceArgs& A, l
   for (int q = 0; q < NV; ++q) { VL[q] = Vs[1][q] + 0.5 * sa[q]; VR[q] = Vs[2][q] - 0.5 * sb[q]; }
   rr::limit_rad_flux(VL);
   rr::limit_rad_flux(VR);
+  if (A.bface) face_normal_field<d>(G, A, c, VL, VR);
   const double tauL = tp[1] * A.dx[d], tauR = tp[2] * A.dx[d];
   double Fq[NV];
   int fallback = 0, cit = 0;
@@ -429,6 +446,7 @@ __device__ __forceinline__ void face_body_mixed(const GridDev& G, const FaceArgs
   for (int q = 0; q < NV; ++q) { VL[q] = Vs[1][q] + 0.5f * sa[q]; VR[q] = Vs[2][q] - 0.5f * sb[q]; }
   rr::limit_rad_flux<float>(VL);
   rr::limit_rad_flux<float>(VR);
+  if (A.bface) face_normal_field<d>(G, A, c, VL, VR);
   const float dxd = (float)A.dx[d];
   float Fq[NV];
   int fallback = 0, cit = 0;
@@ -582,6 +600,135 @@ k_faces(GridDev G, FaceArgs A, Phys K, DevReport* rep, unsigned int* blkmax, uns
   faces_block<sizeof(FT) == sizeof(float), REC, SOLVER>(b, G, A, K, rep, blkmax);
 }
 
+// Periodic cell index of cell (x) shifted by +1 along axis e.
+__device__ __forceinline__ long long cell_plus(const GridDev& G, const int x[3], int e) {
+  int y[3] = {x[0], x[1], x[2]};
+  y[e] += 1;
+  if (y[e] == G.n[e]) y[e] = 0;
+  return (long long)y[0] + (long long)G.n[0] * ((long long)y[1] + (long long)G.n[1] * y[2]);
+}
+
+__device__ __forceinline__ void cell_coords(const GridDev& G, long long c, int x[3]) {
+  // 32-bit index arithmetic: fewer than 2^31 cells (grid_valid)
+  const unsigned int cu = (unsigned int)c, u0 = (unsigned int)G.n[0], u1 = (unsigned int)G.n[1];
+  const unsigned int q0 = cu / u0;
+  x[0] = (int)(cu - q0 * u0);
+  const unsigned int q1 = q0 / u1;
+  x[1] = (int)(q0 - q1 * u1);
+  x[2] = (int)q1;
+}
+
+// ---------------------------------------------------------------------------
+// Constrained transport (Section 4: div B kept by CT with CT-contact averaged
+// EMFs, after Gardiner & Stone 2005). Periodic grids. The normal field b_a is
+// held per cell for the face on its lower side along a; the edge EMF E_k
+// (edge along k, (a, b, k) cyclic) per cell for the edge at its lower corner
+// in the (a, b) plane. Face EMFs come from the face fluxes of the induction
+// equation (F_a(B_b) = -E_k on a-faces, F_b(B_a) = +E_k on b-faces), the
+// cell-centre EMF from the stage primitives, E_k = -(v_a B_b - v_b B_a). The
+// edge value is the mean of its four face EMFs plus a quarter of the
+// difference of the half-cell EMF gradients on both sides of the edge along
+// each plane direction, each taken from the cell upwind of the contact (sign
+// of the mass flux through the face between the two candidate cells; their
+// mean for zero).
+struct CTArgs {
+  const void* Fh[3];    // stage face fluxes (double, or float in mixed precision)
+  long long nf[3];
+  const double* Vp;     // stage primitives, stride np
+  long long np;
+  double* E;            // edge EMFs [3][N] (planes of edges in the grid only)
+  double* bnew;         // new face fields [ndim][N]
+  const double* b0;     // face fields of U^(0) (stride s0) and U^(s) (stride ss)
+  long long s0;
+  const double* bs;
+  long long ss;
+  double idx[3];
+  double a0, a1, cdt, cc;
+  const double* dtp;    // device time step (rrmhd_advance), or nullptr
+};
+
+__device__ __forceinline__ double ct_upwind(double mflux, double lower_side, double upper_side) {
+  if (mflux > 0.0) return lower_side;
+  if (mflux < 0.0) return upper_side;
+  return 0.5 * (lower_side + upper_side);
+}
+
+// Index of the face on the lower side of cell x along d.
+__device__ __forceinline__ long long lower_face_index(const GridDev& G, int d, const int x[3]) {
+  int fn0 = G.n[0], fn1 = G.n[1];
+  if (d == 0) fn0 += 1;
+  if (d == 1) fn1 += 1;
+  return (long long)x[0] + (long long)fn0 * ((long long)x[1] + (long long)fn1 * x[2]);
+}
+
+template <typename FT>
+__global__ void __launch_bounds__(kBlock) k_ct_emf(GridDev G, CTArgs A) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= G.N) return;
+  int x[3];
+  cell_coords(G, c, x);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    if (a >= G.ndim || b >= G.ndim) continue;
+    const FT* Fa = (const FT*)A.Fh[a];
+    const FT* Fb = (const FT*)A.Fh[b];
+    const long long nfa = A.nf[a], nfb = A.nf[b];
+    // cells around the edge: x, x - e_a, x - e_b, x - e_a - e_b (periodic)
+    int xa[3] = {x[0], x[1], x[2]}, xb[3] = {x[0], x[1], x[2]}, xab[3] = {x[0], x[1], x[2]};
+    xa[a] = (x[a] == 0) ? G.n[a] - 1 : x[a] - 1;
+    xb[b] = (x[b] == 0) ? G.n[b] - 1 : x[b] - 1;
+    xab[a] = xa[a];
+    xab[b] = xb[b];
+    const long long c_a = (long long)xa[0] + (long long)G.n[0] * ((long long)xa[1] + (long long)G.n[1] * xa[2]);
+    const long long c_b = (long long)xb[0] + (long long)G.n[0] * ((long long)xb[1] + (long long)G.n[1] * xb[2]);
+    const long long c_ab = (long long)xab[0] + (long long)G.n[0] * ((long long)xab[1] + (long long)G.n[1] * xab[2]);
+    const long long fa_c = lower_face_index(G, a, x), fa_cb = lower_face_index(G, a, xb);
+    const long long fb_c = lower_face_index(G, b, x), fb_ca = lower_face_index(G, b, xa);
+    const double Ea_c = -(double)Fa[(5 + b) * nfa + fa_c];
+    const double Ea_cb = -(double)Fa[(5 + b) * nfa + fa_cb];
+    const double Eb_c = (double)Fb[(5 + a) * nfb + fb_c];
+    const double Eb_ca = (double)Fb[(5 + a) * nfb + fb_ca];
+    const double* V = A.Vp;
+    const long long np = A.np;
+    const double Ec_c = -(V[(1 + a) * np + c] * V[(5 + b) * np + c] - V[(1 + b) * np + c] * V[(5 + a) * np + c]);
+    const double Ec_a = -(V[(1 + a) * np + c_a] * V[(5 + b) * np + c_a] - V[(1 + b) * np + c_a] * V[(5 + a) * np + c_a]);
+    const double Ec_b = -(V[(1 + a) * np + c_b] * V[(5 + b) * np + c_b] - V[(1 + b) * np + c_b] * V[(5 + a) * np + c_b]);
+    const double Ec_ab =
+        -(V[(1 + a) * np + c_ab] * V[(5 + b) * np + c_ab] - V[(1 + b) * np + c_ab] * V[(5 + a) * np + c_ab]);
+    const double ma_c = (double)Fa[fa_c], ma_cb = (double)Fa[fa_cb];
+    const double mb_c = (double)Fb[fb_c], mb_ca = (double)Fb[fb_ca];
+    const double Dbhi = ct_upwind(ma_c, Ec_a - Eb_ca, Ec_c - Eb_c);
+    const double Dblo = ct_upwind(ma_cb, Eb_ca - Ec_ab, Eb_c - Ec_b);
+    const double Dahi = ct_upwind(mb_c, Ec_b - Ea_cb, Ec_c - Ea_c);
+    const double Dalo = ct_upwind(mb_ca, Ea_cb - Ec_ab, Ea_c - Ec_a);
+    const double s4 = (Ea_c + Ea_cb) + (Eb_c + Eb_ca);
+    const double corr = (Dblo - Dbhi) + (Dalo - Dahi);
+    A.E[k * G.N + c] = 0.25 * (s4 + corr);
+  }
+}
+
+// New face fields of a stage: b_a = a0 b_a^(0) + a1 b_a^(s) - c dt (curl E)_a
+// with (curl E)_a = dE_k/dx_b - dE_b/dx_k, (a, b, k) cyclic (edges in the
+// grid only).
+__global__ void __launch_bounds__(kBlock) k_ct_face(GridDev G, CTArgs A) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= G.N) return;
+  int x[3];
+  cell_coords(G, c, x);
+  const double cdt = A.dtp ? A.cc * A.dtp[0] : A.cdt;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a >= G.ndim) continue;
+    const int b = (a + 1) % 3, k = (a + 2) % 3;
+    double t1 = 0.0, t2 = 0.0;
+    if (b < G.ndim) t1 = (A.E[k * G.N + cell_plus(G, x, b)] - A.E[k * G.N + c]) * A.idx[b];
+    if (k < G.ndim) t2 = (A.E[b * G.N + cell_plus(G, x, k)] - A.E[b * G.N + c]) * A.idx[k];
+    const double curl = t1 - t2;
+    A.bnew[a * G.N + c] = (A.a0 * A.b0[a * A.s0 + c] + A.a1 * A.bs[a * A.ss + c]) - cdt * curl;
+  }
+}
+
 struct StageArgs {
   const double* U0;
   long long s0;
@@ -615,6 +762,10 @@ struct StageArgs {
   // identity) and each block's cost, written for the next ordering.
   const unsigned int* perm;
   unsigned int* cost;
+  // Constrained transport: the stage's new face fields ([ndim][N], from
+  // k_ct_face); the cell-centred B_a is their mean over the cell's two faces
+  // and they go to the output's planes 12 + a. nullptr: none.
+  const double* bnew;
 };
 
 __device__ __forceinline__ double stage_cdt(const StageArgs& A) { return A.dtp ? A.cc * A.dtp[0] : A.cdt; }
@@ -714,6 +865,19 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
     double Ust[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) Ust[q] = (A.a0 * u0[q] + A.a1 * us[q]) - cdt * div[q];
+    if (A.bnew) {
+      // constrained transport: B_a of the cell is the mean of its two new
+      // face values, which also become the output's face planes (unrolled:
+      // constant register indices)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (a < G.ndim) {
+          const double blo = A.bnew[a * G.N + c];
+          Ust[5 + a] = 0.5 * (blo + A.bnew[a * G.N + cell_plus(G, ci, a)]);
+          A.Uo[(NV + a) * A.so + c] = blo;
+        }
+      }
+    }
     double Un[NV];
     bool floored = false;
     rr::ImpIn in;
@@ -989,6 +1153,7 @@ __device__ __forceinline__ StageArgs stage_args(const SimDesc& D, int stage, int
   A.npart = 0;
   A.perm = nullptr;
   A.cost = nullptr;
+  A.bnew = nullptr;
   return A;
 }
 
@@ -1168,6 +1333,16 @@ bool params_valid(const rrmhd_params* p) {
   if (!(p->pvm_eps_mixed > 0.0 && p->pvm_eps_mixed < 0.5)) return false;
   if (p->solver != RRMHD_SOLVER_PVM && p->solver != RRMHD_SOLVER_HLL && p->solver != RRMHD_SOLVER_PVM_JVP)
     return false;
+  if (p->ct != 0 && p->ct != 1) return false;
+  return true;
+}
+
+// Constrained transport is defined for periodic grids of 2 or 3 dimensions.
+bool ct_grid_ok(const rrmhd_grid* g, const rrmhd_params* p) {
+  if (!p->ct) return true;
+  if (g->ndim < 2) return false;
+  for (int e = 0; e < g->ndim; ++e)
+    if (g->bc_lo[e] != RRMHD_BC_PERIODIC || g->bc_hi[e] != RRMHD_BC_PERIODIC) return false;
   return true;
 }
 
@@ -1225,11 +1400,12 @@ struct Layout {
   long long npartial;
   long long nb_faces[3];
   long long nblkmax;  // block slots for the iteration maxima
+  int nb;             // face-field planes of the state (constrained transport: ndim)
   size_t off_Vp, off_taup, off_Us, off_Fh[3], off_partial, off_smax, off_rep, off_blkmax, off_work, off_wcount, off_Zc,
-      off_cost, off_perm, total;
+      off_cost, off_perm, off_ctE, off_ctb, total;
 };
 
-Layout make_layout(const rrmhd_grid* g) {
+Layout make_layout(const rrmhd_grid* g, const rrmhd_params* p) {
   Layout L;
   std::memset(&L, 0, sizeof(L));
   L.N = grid_cells(g);
@@ -1249,9 +1425,10 @@ Layout make_layout(const rrmhd_grid* g) {
   const long long nbc = (L.N + L.nt + kBlock - 1) / kBlock;
   L.nblkmax = (nbf > nbc) ? nbf : nbc;
   size_t o = 0;
+  L.nb = (p && p->ct) ? g->ndim : 0;
   L.off_Vp = o; o = align256(o + sizeof(double) * NV * L.Np);
   L.off_taup = o; o = align256(o + sizeof(double) * L.Np);
-  L.off_Us = o; o = align256(o + sizeof(double) * NV * L.Ns);
+  L.off_Us = o; o = align256(o + sizeof(double) * (NV + L.nb) * L.Ns);
   for (int d = 0; d < 3; ++d) { L.off_Fh[d] = o; o = align256(o + sizeof(double) * NV * L.nf[d]); }
   // signal-speed block maxima: cell blocks, then work-list blocks (<= cell blocks)
   L.off_partial = o; o = align256(o + sizeof(double) * 2 * L.npartial);
@@ -1264,6 +1441,9 @@ Layout make_layout(const rrmhd_grid* g) {
   // update-pass block costs and dispatch order (cell blocks)
   L.off_cost = o; o = align256(o + sizeof(unsigned int) * L.npartial);
   L.off_perm = o; o = align256(o + sizeof(unsigned int) * L.npartial);
+  // constrained transport: edge EMFs [3][N] and the stage's new face fields [ndim][N]
+  L.off_ctE = o; o = align256(o + (L.nb ? sizeof(double) * 3 * L.N : 0));
+  L.off_ctb = o; o = align256(o + sizeof(double) * L.nb * L.N);
   L.total = o;
   return L;
 }
@@ -1302,6 +1482,8 @@ struct rrmhd_ctx {
   double* Zc;                   // recovery Z of the stage state per cell
   unsigned int* cost;           // per cell block: cost in the last update pass
   unsigned int* perm;           // dispatch order of the next update pass
+  double* ctE;                  // constrained transport: edge EMFs [3][N]
+  double* ctb;                  // ... and the stage's new face fields [ndim][N]
   hipStream_t stream;
   unsigned int newton_blocks;
   void* host;  // pinned: DevReport + one double
@@ -1376,6 +1558,8 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   A.Vp = c->Vp;
   A.taup = c->taup;
   A.np = L.Np;
+  A.bface = L.nb ? Us + NV * ss : nullptr;
+  A.bs = ss;
   long long nbt = 0;
   for (int d = 0; d < 3; ++d) {
     const bool on = d < g->ndim;
@@ -1521,6 +1705,7 @@ rrmhd_status batch_check(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, const 
   for (int s = 0; s < nsim; ++s) {
     if (!ctx[s] || !U[s]) return RRMHD_E_INVALID;
     if (ctx[s]->par.rk_order != ctx[0]->par.rk_order) return RRMHD_E_INVALID;
+    if (ctx[s]->par.ct) return RRMHD_E_INVALID;  // constrained transport: single-simulation entry points only
     for (int t = 0; t < s; ++t)
       if (ctx[t] == ctx[s]) return RRMHD_E_INVALID;  // each context's workspace is used once per launch
   }
@@ -1549,6 +1734,8 @@ void ctx_bind(rrmhd_ctx* c, const rrmhd_grid* g, const rrmhd_params* p, const La
   c->Zc = (double*)(c->ws + L.off_Zc);
   c->cost = (unsigned int*)(c->ws + L.off_cost);
   c->perm = (unsigned int*)(c->ws + L.off_perm);
+  c->ctE = L.nb ? (double*)(c->ws + L.off_ctE) : nullptr;
+  c->ctb = L.nb ? (double*)(c->ws + L.off_ctb) : nullptr;
   c->stream = (hipStream_t)hip_stream;
   c->host = nullptr;
   c->prof = 0;
@@ -1600,16 +1787,16 @@ void rrmhd_default_params(rrmhd_params* p) {
 }
 
 size_t rrmhd_workspace_bytes(const rrmhd_grid* g, const rrmhd_params* p) {
-  if (!grid_valid(g) || !params_valid(p)) return 0;
-  return make_layout(g).total;
+  if (!grid_valid(g) || !params_valid(p) || !ct_grid_ok(g, p)) return 0;
+  return make_layout(g, p).total;
 }
 
 rrmhd_status rrmhd_init(rrmhd_ctx** out, const rrmhd_grid* g, const rrmhd_params* p, void* workspace,
                         size_t ws_bytes, void* hip_stream) {
   if (!out) return RRMHD_E_INVALID;
   *out = nullptr;
-  if (!grid_valid(g) || !params_valid(p)) return RRMHD_E_INVALID;
-  const Layout L = make_layout(g);
+  if (!grid_valid(g) || !params_valid(p) || !ct_grid_ok(g, p)) return RRMHD_E_INVALID;
+  const Layout L = make_layout(g, p);
   if (!workspace || ws_bytes < L.total || ((uintptr_t)workspace & 255u) != 0) return RRMHD_E_WORKSPACE;
   rrmhd_ctx* c = new (std::nothrow) rrmhd_ctx;
   if (!c) return RRMHD_E_DEVICE;
@@ -1719,6 +1906,37 @@ rrmhd_status step_stages(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt
     A.npart = L.npartial;
     A.perm = c->perm;
     A.cost = c->cost;
+    A.bnew = nullptr;
+    if (L.nb) {
+      // constrained transport: edge EMFs, then the new face fields
+      CTArgs T;
+      for (int d = 0; d < 3; ++d) {
+        T.Fh[d] = (d < g->ndim) ? (const void*)c->Fh[d] : (const void*)c->Fh[0];
+        T.nf[d] = (d < g->ndim) ? L.nf[d] : 0;
+        T.idx[d] = A.idx[d];
+      }
+      T.Vp = c->Vp;
+      T.np = L.Np;
+      T.E = c->ctE;
+      T.bnew = c->ctb;
+      T.b0 = U + NV * vs;
+      T.s0 = vs;
+      T.bs = Us + NV * ss;
+      T.ss = ss;
+      T.a0 = A.a0;
+      T.a1 = A.a1;
+      T.cdt = A.cdt;
+      T.cc = A.cc;
+      T.dtp = A.dtp;
+      if (c->par.precision == RRMHD_MIXED)
+        k_ct_emf<float><<<nblocks(L.N), kBlock, 0, c->stream>>>(G, T);
+      else
+        k_ct_emf<double><<<nblocks(L.N), kBlock, 0, c->stream>>>(G, T);
+      if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+      k_ct_face<<<nblocks(L.N), kBlock, 0, c->stream>>>(G, T);
+      if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+      A.bnew = c->ctb;
+    }
     int pe = prof_begin(c, RRMHD_K_UPDATE, L.N);
     if (c->par.precision == RRMHD_MIXED)
       k_update<float><<<nblocks(L.N), kBlock, 0, c->stream>>>(G, A, op, c->K, c->rep, c->blkmax, c->work, wc);
@@ -1816,9 +2034,9 @@ extern "C" {
 rrmhd_status rrmhd_advance_noalloc(const rrmhd_grid* g, const rrmhd_params* p, double* U, double cfl, int nsteps,
                                    const rrmhd_opacities* opac, double* dt_out, rrmhd_report* report_dev,
                                    void* hip_stream) {
-  if (!U || !grid_valid(g) || !params_valid(p)) return RRMHD_E_INVALID;
+  if (!U || !grid_valid(g) || !params_valid(p) || !ct_grid_ok(g, p)) return RRMHD_E_INVALID;
   if (!(cfl > 0.0) || !(cfl < 1e300) || nsteps < 0) return RRMHD_E_INVALID;
-  const Layout L = make_layout(g);
+  const Layout L = make_layout(g, p);
   if (L.total > kScratchBytes) return RRMHD_E_WORKSPACE;
   void* ws = nullptr;
   const rrmhd_status sst = scratch_for_current_device(&ws);

@@ -42,7 +42,7 @@ class rrmhd_params(C.Structure):
         ("pvm_k", C.c_int), ("beta_mode", C.c_int), ("recon", C.c_int), ("rk_order", C.c_int),
         ("c2p_maxit", C.c_int), ("imp_maxit", C.c_int), ("imp_picard_it", C.c_int),
         ("imp_method", C.c_int), ("precision", C.c_int), ("pvm_eps_mixed", C.c_double),
-        ("e_floor", C.c_double), ("solver", C.c_int),
+        ("e_floor", C.c_double), ("solver", C.c_int), ("ct", C.c_int),
     ]
 
 
