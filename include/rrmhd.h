@@ -65,9 +65,10 @@ enum { RRMHD_IMP_PICARD_NEWTON = 0, RRMHD_IMP_NEWTON = 1, RRMHD_IMP_PICARD = 2 }
 enum { RRMHD_SOLVER_PVM = 0, RRMHD_SOLVER_HLL = 1, RRMHD_SOLVER_PVM_JVP = 2 };
 /* Precision of the explicit step. RRMHD_FP64: everything in binary64.
  * RRMHD_MIXED: reconstruction, fluxes and the PVM Horner / finite-difference
- * arithmetic in binary32 with a relative difference step pvm_eps_mixed; all
- * primitive recoveries, the flux divergence and the implicit solve in
- * binary64. */
+ * arithmetic in binary32, each difference taken with a step normalised to
+ * its direction (U_m + s w with s = pvm_eps_mixed max|U_m| / max|w| over the
+ * chain's rows, divided by s); all primitive recoveries, the flux divergence
+ * and the implicit solve in binary64. */
 enum { RRMHD_FP64 = 0, RRMHD_MIXED = 1 };
 
 /* Cartesian grid of interior cells (Section 3.1: finite volumes, cell
@@ -106,7 +107,8 @@ typedef struct {
   int imp_picard_it;/* Picard iterations before Newton (eq. C^(m) iteration)            */
   int imp_method;   /* RRMHD_IMP_*                                                      */
   int precision;    /* RRMHD_FP64 | RRMHD_MIXED                                         */
-  double pvm_eps_mixed; /* relative finite-difference step of the FP32 chain (2^-12)   */
+  double pvm_eps_mixed; /* size of the FP32 chain's difference step relative to max|U_m|
+                           (2^-12; see RRMHD_MIXED)                                  */
   double e_floor;   /* 0 (default): a non-positive E_r entering the implicit solve fails
                        the cell; > 0: it is raised to e_floor keeping tau + E_r and
                        S + F_r (the gas pays), and counted in e_floor_hits           */

@@ -315,9 +315,12 @@ __device__ __forceinline__ C2PEval c2p_eval(double Z, const C2PIn& in, const Phy
 // estimate gamma (E - B^2/2) - (gamma - 1) D is used.
 // NU = NV: full state; NU = 8: fluid and magnetic field only (the radiation
 // variables are not involved in the recovery).
+// tol > 0 replaces K.c2p_tol (the binary32 chain of mixed precision needs Z
+// only to its own rounding).
 template <int NU = NV>
 __device__ __forceinline__ int c2p(const double U[NU], const Phys& K, double Zguess, double V[NU],
-                                   double& Zout, int& nit, double* lw = nullptr) {
+                                   double& Zout, int& nit, double* lw = nullptr, double tol = -1.0) {
+  const double ztol = (tol > 0.0) ? tol : K.c2p_tol;
   C2PIn in;
   in.D = U[0];
 #pragma unroll
@@ -355,7 +358,7 @@ __device__ __forceinline__ int c2p(const double U[NU], const Phys& K, double Zgu
     const double Zn = take ? Zt : 0.5 * (lo + hi);
     const bool hit = e.ok && (e.f == 0.0);
     const double dZ = dabs(Zn - Z);
-    conv = hit || (dZ <= K.c2p_tol * Zn);
+    conv = hit || (dZ <= ztol * Zn);
     Z = hit ? Z : Zn;
     if (conv) break;
   }
@@ -817,6 +820,12 @@ __device__ __forceinline__ void pvm_face_jvp(const double VL[NV], const double V
 // unit roundoff, which balances truncation and rounding error.
 // recover_near for the FP32 chain's fluid block (8-wide): the recovery
 // itself in FP64.
+// Relative tolerance on Z of the recoveries inside the binary32 chain: below
+// binary32's half unit (2^-24), so the rounded primitives are those of the
+// converged root, and about one Newton step short of the binary64 tolerance
+// from the chain's 2^-12 perturbations.
+constexpr double kMixedC2PTol = 0x1p-26;
+
 __device__ __forceinline__ bool recover_near_mixed(const float U[8], const float Um[8], const float Vm[8],
                                                    double Zm, const Phys& K, float V[8], int& nit) {
   bool same = true;
@@ -833,7 +842,7 @@ __device__ __forceinline__ bool recover_near_mixed(const float U[8], const float
   double Ud[8], Vd[8], Z = 0.0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) Ud[q] = (double)U[q];
-  if (c2p<8>(Ud, K, Zm, Vd, Z, nit) != 0) return false;
+  if (c2p<8>(Ud, K, Zm, Vd, Z, nit, nullptr, kMixedC2PTol) != 0) return false;
 #pragma unroll
   for (int q = 0; q < 5; ++q) V[q] = (float)Vd[q];
 #pragma unroll
@@ -849,6 +858,27 @@ __device__ __forceinline__ float* park_lane_f() {
   return park + threadIdx.x;
 }
 
+// Difference step of the binary32 chain, normalised to the direction w: the
+// perturbation s w has max-norm h max|U_m| (h = 2^-12 ~ sqrt of the binary32
+// unit), so A w = (F(U_m + s w) - F(U_m)) / s keeps about half of the
+// binary32 digits however small w is against U_m (an absolute step h w
+// rounds away once |w| < 2^-12 |U_m|). Returns false when w is zero or too
+// small for any binary32 step (its image is then below the flux's rounding).
+template <int N>
+__device__ __forceinline__ bool dir_step(const float w[N], const float Um[N], float h, float& s, float& is) {
+  float wn = 0.0f, un = 0.0f;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    wn = fmaxf(wn, fabsf(w[q]));
+    un = fmaxf(un, fabsf(Um[q]));
+  }
+  if (!(wn > 0.0f)) return false;
+  s = (h * ((un > 0.0f) ? un : 1.0f)) / wn;
+  if (!(s < 1e30f)) return false;
+  is = 1.0f / s;
+  return true;
+}
+
 // The same block-diagonal split as pvm_face: radiation rows first, then the
 // fluid and magnetic rows with 8-wide states.
 template <int d>
@@ -857,7 +887,6 @@ __device__ __forceinline__ void pvm_face_mixed(const float VL[NV], const float V
   const float g1 = (float)K.g1;
   const float beta = 1.0f / fmaxf(fmaxf(tauL, tauR), 1.0f);
   const float h = (float)K.eps32;
-  const float ih = 1.0f / h;
   float* sh = park_lane_f();
   {
     float Fa[4], U0[4], Um[4], w[4];
@@ -878,14 +907,20 @@ __device__ __forceinline__ void pvm_face_mixed(const float VL[NV], const float V
       flux_rad<d, float>(Um, Fm);
       for (int l = 0; l < K.M; ++l) {
         float Ue[4], Fe[4], Y[4];
+        float s, is;
+        if (dir_step<4>(w, Um, h, s, is)) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Ue[q] = Um[q] + h * w[q];
-        flux_rad<d, float>(Ue, Fe);
+          for (int q = 0; q < 4; ++q) Ue[q] = Um[q] + s * w[q];
+          flux_rad<d, float>(Ue, Fe);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Ue[q] = Um[q] + (Fe[q] - Fm[q]);
-        flux_rad<d, float>(Ue, Fe);
+          for (int q = 0; q < 4; ++q) Ue[q] = Um[q] + (Fe[q] - Fm[q]);
+          flux_rad<d, float>(Ue, Fe);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Y[q] = (Fe[q] - Fm[q]) * ih;
+          for (int q = 0; q < 4; ++q) Y[q] = (Fe[q] - Fm[q]) * is;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Y[q] = 0.0f;
+        }
         const float cnext = (float)K.coef[K.M - 1 - l];
         if (l == 0) {
           const float ctop = (float)K.coef[K.M];
@@ -938,7 +973,7 @@ __device__ __forceinline__ void pvm_face_mixed(const float VL[NV], const float V
       double Ud[8], Vd[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) Ud[q] = (double)Um[q];
-      if (c2p<8>(Ud, K, 0.0, Vd, Zm, it) != 0) ok = false;
+      if (c2p<8>(Ud, K, 0.0, Vd, Zm, it, nullptr, kMixedC2PTol) != 0) ok = false;
 #pragma unroll
       for (int q = 0; q < 5; ++q) Vm[q] = (float)Vd[q];
 #pragma unroll
@@ -952,10 +987,14 @@ __device__ __forceinline__ void pvm_face_mixed(const float VL[NV], const float V
     }
     for (int l = 0; l < K.M && ok; ++l) {
       float Y[8];
-      {
+      float s, is;
+      if (!dir_step<8>(w, Um, h, s, is)) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Y[q] = 0.0f;
+      } else {
         float Ue[8], Ve[8], Fe[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) Ue[q] = Um[q] + h * w[q];
+        for (int q = 0; q < 8; ++q) Ue[q] = Um[q] + s * w[q];
         if (!recover_near_mixed(Ue, Um, Vm, Zm, K, Ve, it)) { ok = false; c2p_its += it; break; }
         c2p_its += it;
         {
@@ -973,7 +1012,7 @@ __device__ __forceinline__ void pvm_face_mixed(const float VL[NV], const float V
           flux_mhd<d, float>(Ve, at, Fe);
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) Y[q] = (Fe[q] - Fm[q]) * ih;
+        for (int q = 0; q < 8; ++q) Y[q] = (Fe[q] - Fm[q]) * is;
       }
       const float cnext = (float)K.coef[K.M - 1 - l];
       if (l == 0) {
