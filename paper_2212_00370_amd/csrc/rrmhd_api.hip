@@ -17,6 +17,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -1123,8 +1124,8 @@ __device__ __forceinline__ int find_sim(const long long* __restrict__ off, int n
   return lo;
 }
 
-__device__ __forceinline__ StageArgs stage_args(const SimDesc& D, int stage, int last, double a0, double a1,
-                                                double c) {
+__device__ __forceinline__ StageArgs stage_args(const SimDesc& D, double dt, int stage, int last, double a0,
+                                                double a1, double c) {
   StageArgs A;
   A.U0 = D.U; A.s0 = D.vs;
   A.Us = (stage == 0) ? D.U : D.Us;
@@ -1138,7 +1139,7 @@ __device__ __forceinline__ StageArgs stage_args(const SimDesc& D, int stage, int
   }
   A.a0 = a0;
   A.a1 = a1;
-  A.cdt = c * D.dt;
+  A.cdt = c * dt;
   A.dtp = nullptr;
   A.cc = c;
   A.Zc = D.Zc;
@@ -1185,22 +1186,23 @@ k_faces_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, int 
 }
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
-k_update_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, int nsim, int stage, int last,
-           double a0, double a1, double c) {
+k_update_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, const double* __restrict__ dts, int nsim,
+           int stage, int last, double a0, double a1, double c) {
   const long long* o = off + OFF_CELLS * (nsim + 1);
   const int s = find_sim(o, nsim, blockIdx.x);
   const SimDesc& D = T[s];
-  const StageArgs A = stage_args(D, stage, last, a0, a1, c);
+  const StageArgs A = stage_args(D, dts[s], stage, last, a0, a1, c);
   if (D.mixed) update_block<float>(blockIdx.x - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
   else update_block<double>(blockIdx.x - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
 }
 
 __global__ void __launch_bounds__(kBlock) k_newton_b(const SimDesc* __restrict__ T, const long long* __restrict__ off,
-                                                     int nsim, int stage, int last, double a0, double a1, double c) {
+                                                     const double* __restrict__ dts, int nsim, int stage, int last,
+                                                     double a0, double a1, double c) {
   const long long* o = off + OFF_NEWTON * (nsim + 1);
   const int s = find_sim(o, nsim, blockIdx.x);
   const SimDesc& D = T[s];
-  const StageArgs A = stage_args(D, stage, last, a0, a1, c);
+  const StageArgs A = stage_args(D, dts[s], stage, last, a0, a1, c);
   newton_blocks(blockIdx.x - o[s], o[s + 1] - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
 }
 
@@ -1495,6 +1497,7 @@ struct rrmhd_ctx {
   std::vector<int> ev_kind;
   std::vector<long long> ev_units;
   int ev_used;
+  unsigned long long serial;    // distinct per context created in this process (batch descriptor cache)
 };
 
 namespace {
@@ -1610,7 +1613,7 @@ long long newton_blocks_for(long long ncell_blocks, unsigned int cap) {
   return b;
 }
 
-SimDesc make_desc(rrmhd_ctx* c, double* U, const rrmhd_opacities* opac, double dt) {
+SimDesc make_desc(rrmhd_ctx* c, double* U, const rrmhd_opacities* opac) {
   SimDesc D;
   std::memset(&D, 0, sizeof(D));
   const Layout& L = c->L;
@@ -1643,7 +1646,6 @@ SimDesc make_desc(rrmhd_ctx* c, double* U, const rrmhd_opacities* opac, double d
   D.blkmax = c->blkmax;
   D.partial = c->partial;
   D.npartial = L.npartial;
-  D.dt = dt;
   D.mixed = (c->par.precision == RRMHD_MIXED) ? 1 : 0;
   D.solver = c->par.solver;
   return D;
@@ -1657,45 +1659,93 @@ struct rrmhd_batch {
   SimDesc* table;       // device
   long long* off;       // device [OFF_KINDS][max_sims + 1]
   double* smax;         // device [max_sims]
-  void* host[2];        // pinned staging: table + offsets
+  double* dts;          // device [max_sims]: each simulation's time step
+  void* host[2];        // pinned staging: table + offsets + time steps
   hipEvent_t ev[2];
   int cur;
   double* hsmax;        // pinned [max_sims]
   unsigned int newton_cap;
+  // The descriptor table on the device describes these simulations (same
+  // contexts, states and, when built by a step, opacities): a call with the
+  // same list reuses it and uploads only its time steps. A table built by a
+  // signal-speed pass (no opacities) serves only signal-speed passes.
+  int cached_n;
+  bool cached_with_opac;
+  std::vector<unsigned long long> cached_serial;
+  std::vector<const double*> cached_U;
+  std::vector<rrmhd_opacities> cached_op;
+  std::vector<char> cached_has_op;
+  long long cached_tot[4];
 };
 
 namespace {
 
 size_t batch_table_bytes(int m) { return align256(sizeof(SimDesc) * (size_t)m); }
 size_t batch_off_bytes(int m) { return align256(sizeof(long long) * OFF_KINDS * (size_t)(m + 1)); }
+size_t batch_dt_bytes(int m) { return align256(sizeof(double) * (size_t)m); }
+
+bool same_opac(const rrmhd_opacities* a, const rrmhd_opacities& b) {
+  return a->kappa == b.kappa && a->sigma == b.sigma && a->kappa0 == b.kappa0 && a->sigma0 == b.sigma0;
+}
 
 // Fill a staging buffer with the batch's descriptors and block offsets and
 // copy it to the device (enqueued). Returns total blocks per kind in tot[].
 rrmhd_status batch_upload(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, double* const* U,
                           const double* dt, const rrmhd_opacities* const* opac, long long tot[OFF_KINDS]) {
+  // Is the device table already that of this list?
+  bool same = b->cached_n == nsim && (opac == nullptr || b->cached_with_opac);
+  for (int s = 0; s < nsim && same; ++s) {
+    same = ctx[s]->serial == b->cached_serial[s] && U[s] == b->cached_U[s];
+    if (same && opac) {
+      const rrmhd_opacities* o = opac[s];
+      same = (o != nullptr) == (b->cached_has_op[s] != 0) && (o == nullptr || same_opac(o, b->cached_op[s]));
+    }
+  }
   const int k = b->cur;
   b->cur ^= 1;
   if (hipEventSynchronize(b->ev[k]) != hipSuccess) return RRMHD_E_DEVICE;
-  SimDesc* T = (SimDesc*)b->host[k];
-  long long* off = (long long*)((char*)b->host[k] + batch_table_bytes(b->max_sims));
-  for (int i = 0; i < OFF_KINDS; ++i) { off[i * (nsim + 1)] = 0; tot[i] = 0; }
-  for (int s = 0; s < nsim; ++s) {
-    rrmhd_ctx* c = ctx[s];
-    T[s] = make_desc(c, U[s], opac ? opac[s] : nullptr, dt ? dt[s] : 0.0);
-    const Layout& L = c->L;
-    const long long nbc = nblocks(L.N);
-    const long long nb[OFF_KINDS] = {(long long)nblocks(L.N + L.nt), L.nb_faces[0] + L.nb_faces[1] + L.nb_faces[2],
-                                     nbc, newton_blocks_for(nbc, b->newton_cap)};
-    for (int i = 0; i < OFF_KINDS; ++i) {
-      tot[i] += nb[i];
-      off[i * (nsim + 1) + s + 1] = tot[i];
+  char* hk = (char*)b->host[k];
+  if (!same) {
+    b->cached_n = 0;  // until the new table is complete
+    SimDesc* T = (SimDesc*)hk;
+    long long* off = (long long*)(hk + batch_table_bytes(b->max_sims));
+    for (int i = 0; i < OFF_KINDS; ++i) { off[i * (nsim + 1)] = 0; tot[i] = 0; }
+    for (int s = 0; s < nsim; ++s) {
+      rrmhd_ctx* c = ctx[s];
+      T[s] = make_desc(c, U[s], opac ? opac[s] : nullptr);
+      const Layout& L = c->L;
+      const long long nbc = nblocks(L.N);
+      const long long nb[OFF_KINDS] = {(long long)nblocks(L.N + L.nt), L.nb_faces[0] + L.nb_faces[1] + L.nb_faces[2],
+                                       nbc, newton_blocks_for(nbc, b->newton_cap)};
+      for (int i = 0; i < OFF_KINDS; ++i) {
+        tot[i] += nb[i];
+        off[i * (nsim + 1) + s + 1] = tot[i];
+      }
     }
+    if (hipMemcpyAsync(b->table, T, sizeof(SimDesc) * nsim, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+      return RRMHD_E_DEVICE;
+    if (hipMemcpyAsync(b->off, off, sizeof(long long) * OFF_KINDS * (nsim + 1), hipMemcpyHostToDevice, b->stream) !=
+        hipSuccess)
+      return RRMHD_E_DEVICE;
+    b->cached_n = nsim;
+    b->cached_with_opac = opac != nullptr;
+    for (int s = 0; s < nsim; ++s) {
+      b->cached_serial[s] = ctx[s]->serial;
+      b->cached_U[s] = U[s];
+      const rrmhd_opacities* o = opac ? opac[s] : nullptr;
+      b->cached_has_op[s] = o ? 1 : 0;
+      if (o) b->cached_op[s] = *o;
+    }
+    for (int i = 0; i < OFF_KINDS; ++i) b->cached_tot[i] = tot[i];
+  } else {
+    for (int i = 0; i < OFF_KINDS; ++i) tot[i] = b->cached_tot[i];
   }
-  if (hipMemcpyAsync(b->table, T, sizeof(SimDesc) * nsim, hipMemcpyHostToDevice, b->stream) != hipSuccess)
-    return RRMHD_E_DEVICE;
-  if (hipMemcpyAsync(b->off, off, sizeof(long long) * OFF_KINDS * (nsim + 1), hipMemcpyHostToDevice, b->stream) !=
-      hipSuccess)
-    return RRMHD_E_DEVICE;
+  if (dt) {
+    double* hd = (double*)(hk + batch_table_bytes(b->max_sims) + batch_off_bytes(b->max_sims));
+    std::memcpy(hd, dt, sizeof(double) * nsim);
+    if (hipMemcpyAsync(b->dts, hd, sizeof(double) * nsim, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+      return RRMHD_E_DEVICE;
+  }
   if (hipEventRecord(b->ev[k], b->stream) != hipSuccess) return RRMHD_E_DEVICE;
   return RRMHD_OK;
 }
@@ -1742,6 +1792,8 @@ void ctx_bind(rrmhd_ctx* c, const rrmhd_grid* g, const rrmhd_params* p, const La
   c->prof_stride = 1;
   for (int k = 0; k < RRMHD_K_COUNT; ++k) c->prof_seen[k] = 0;
   c->ev_used = 0;
+  static std::atomic<unsigned long long> next_serial{1};
+  c->serial = next_serial.fetch_add(1);
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
@@ -2150,7 +2202,7 @@ void rrmhd_destroy(rrmhd_ctx* c) {
 
 size_t rrmhd_batch_workspace_bytes(int max_sims) {
   if (max_sims < 1 || max_sims > 65536) return 0;
-  return batch_table_bytes(max_sims) + batch_off_bytes(max_sims) + align256(sizeof(double) * max_sims);
+  return batch_table_bytes(max_sims) + batch_off_bytes(max_sims) + 2 * batch_dt_bytes(max_sims);
 }
 
 rrmhd_status rrmhd_batch_init(rrmhd_batch** out, int max_sims, void* workspace, size_t ws_bytes, void* hip_stream) {
@@ -2159,17 +2211,25 @@ rrmhd_status rrmhd_batch_init(rrmhd_batch** out, int max_sims, void* workspace, 
   const size_t need = rrmhd_batch_workspace_bytes(max_sims);
   if (need == 0) return RRMHD_E_INVALID;
   if (!workspace || ws_bytes < need || ((uintptr_t)workspace & 255u) != 0) return RRMHD_E_WORKSPACE;
-  rrmhd_batch* b = new (std::nothrow) rrmhd_batch;
+  rrmhd_batch* b = new (std::nothrow) rrmhd_batch();
   if (!b) return RRMHD_E_DEVICE;
-  std::memset(b, 0, sizeof(*b));
   b->max_sims = max_sims;
   b->stream = (hipStream_t)hip_stream;
   char* w = (char*)workspace;
   b->table = (SimDesc*)w;
   b->off = (long long*)(w + batch_table_bytes(max_sims));
   b->smax = (double*)(w + batch_table_bytes(max_sims) + batch_off_bytes(max_sims));
-  const size_t hb = batch_table_bytes(max_sims) + batch_off_bytes(max_sims);
+  b->dts = (double*)(w + batch_table_bytes(max_sims) + batch_off_bytes(max_sims) + batch_dt_bytes(max_sims));
+  const size_t hb = batch_table_bytes(max_sims) + batch_off_bytes(max_sims) + batch_dt_bytes(max_sims);
   bool ok = true;
+  try {
+    b->cached_serial.assign(max_sims, 0);
+    b->cached_U.assign(max_sims, nullptr);
+    b->cached_op.assign(max_sims, rrmhd_opacities{});
+    b->cached_has_op.assign(max_sims, 0);
+  } catch (...) {
+    ok = false;
+  }
   for (int k = 0; k < 2 && ok; ++k) {
     ok = hipHostMalloc(&b->host[k], hb, hipHostMallocDefault) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming) == hipSuccess;
@@ -2245,11 +2305,11 @@ rrmhd_status rrmhd_step_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, d
       k_faces_b<RRMHD_SOLVER_PVM_JVP><<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off,
                                                                                          nsim);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-    k_update_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s, last, co[s][0],
-                                                                       co[s][1], co[s][2]);
+    k_update_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, b->dts, nsim, s, last,
+                                                                       co[s][0], co[s][1], co[s][2]);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-    k_newton_b<<<(unsigned int)tot[OFF_NEWTON], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s, last, co[s][0],
-                                                                        co[s][1], co[s][2]);
+    k_newton_b<<<(unsigned int)tot[OFF_NEWTON], kBlock, 0, b->stream>>>(b->table, b->off, b->dts, nsim, s, last,
+                                                                        co[s][0], co[s][1], co[s][2]);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   }
   return RRMHD_OK;

@@ -307,6 +307,33 @@ class Batch:
     def step(self, solvers, Us, dts, opacs):
         rrmhd_step_batch(self.handle, [s.ctx for s in solvers], Us, dts, opacs)
 
+    # A fixed active set: its pointer arrays are built once (set_active) and
+    # each tick marshals only the time steps. The library keeps the device
+    # descriptor table of an unchanged set and uploads only those.
+    def set_active(self, solvers, Us, opacs):
+        n = len(solvers)
+        self._n = n
+        self._cv = (C.c_void_p * n)(*[s.ctx.value for s in solvers])
+        self._uv = (C.c_void_p * n)(*[u.data_ptr() for u in Us])
+        self._ov = (C.c_void_p * n)(*[C.addressof(o) for o in opacs])
+        self._keep = (list(Us), list(opacs))
+        self._out = (C.c_double * n)()
+        self._dv = (C.c_double * n)()
+
+    def max_speed_active(self):
+        """Signal speeds of the active set, as a numpy view of the result
+        buffer (valid until the next call)."""
+        import numpy as np
+        _check(_lib.rrmhd_max_speed_batch(self.handle, self._n, self._cv, self._uv, self._out),
+               "rrmhd_max_speed_batch")
+        return np.ctypeslib.as_array(self._out)
+
+    def step_active(self, dts):
+        import numpy as np
+        np.ctypeslib.as_array(self._dv)[:] = dts
+        _check(_lib.rrmhd_step_batch(self.handle, self._n, self._cv, self._uv, self._dv, self._ov),
+               "rrmhd_step_batch")
+
     def close(self):
         if self.handle is not None:
             rrmhd_batch_destroy(self.handle)

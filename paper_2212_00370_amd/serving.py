@@ -108,6 +108,7 @@ class Server:
                 raise ValueError(f"request {r.rid} does not fit the HBM budget")
         active: list[_Sim] = []
         results: list[Result] = []
+        changed = True          # the active set differs from the batch's
         t0 = clock()
         qi = 0
         while qi < len(pending) or active:
@@ -124,6 +125,7 @@ class Server:
                 self.in_use += need
                 self.peak_in_use = max(self.peak_in_use, self.in_use)
                 active.append(sim)
+                changed = True
                 qi += 1
             if not active:
                 # idle until the next arrival
@@ -132,15 +134,17 @@ class Server:
                     if wait > 0:
                         time.sleep(min(wait, 0.01))
                 continue
-            Us = [s.U for s in active]
-            smax = self.batch.max_speed([s.solver for s in active], Us)
+            if changed:
+                self.batch.set_active([s.solver for s in active], [s.U for s in active], [s.opac for s in active])
+                changed = False
+            smax = self.batch.max_speed_active()
             dts = []
             for s, sm in zip(active, smax):
                 dt = s.req.problem.cfl * s.dxmin / sm
                 if s.req.t_end is not None:
                     dt = min(dt, s.req.t_end - s.t)
                 dts.append(dt)
-            self.batch.step([s.solver for s in active], Us, dts, [s.opac for s in active])
+            self.batch.step_active(dts)
             self.ticks += 1
             self.batch_sizes.append(len(active))
             for s, dt in zip(active, dts):
@@ -158,6 +162,7 @@ class Server:
                     self.in_use -= s.need
                     s.close()
                 active = [s for s in active if not s.done()]
+                changed = True
         return results
 
     def close(self):
