@@ -137,6 +137,13 @@ def serving_run(mix, loads, seed, seq_sample, budget_frac=0.5, label="serving"):
     zu = sum(r.zone_updates for r in res0)
     mu = len(mix) / cap_s
     fails = sum(1 for r in res0 if r.report.get("imp_fail", 0) or r.report.get("c2p_fail", 0))
+    by_kind = {}
+    for r in res0:
+        m = mix[r.rid]
+        kind = f"{m['problem'].ndim}d_{'mixed' if m['mixed'] else 'fp64'}"
+        e = by_kind.setdefault(kind, {"requests": 0, "with_counted_failures": 0})
+        e["requests"] += 1
+        e["with_counted_failures"] += int(bool(r.report.get("imp_fail", 0) or r.report.get("c2p_fail", 0)))
     log(f"{label}: capacity run, {len(mix)} requests in {cap_s:.1f} s")
     runs = []
     for li, load in enumerate(loads):
@@ -181,7 +188,7 @@ def serving_run(mix, loads, seed, seq_sample, budget_frac=0.5, label="serving"):
     seq_s = time.perf_counter() - t0
     log(f"{label}: one-at-a-time FP64 on {ns} requests in {seq_s:.1f} s")
     return {"requests": len(mix), "capacity_req_per_s": mu, "capacity_zone_updates_per_s": zu / cap_s,
-            "requests_with_counted_failures": fails, "runs": runs,
+            "requests_with_counted_failures": fails, "counted_failures_by_kind": by_kind, "runs": runs,
             "one_at_a_time_fp64": {"requests": ns, "zone_updates_per_s": zs / seq_s, "wall_s": seq_s},
             "batched_capacity_over_one_at_a_time_fp64": (zu / cap_s) / (zs / seq_s),
             "hbm_budget_bytes": budget}
@@ -628,16 +635,24 @@ def mixed_accuracy(R, P, grid, V, opac, dts, U64_final):
 def variants_bench(R, P, grid, V, opac, steps, warmup):
     """The same workload with the other face fluxes and precisions (each its own
     context; same step count; timed like the main line), for the cost ratios:
-    Rad-HLL (the paper's comparison solver), the exact-JVP PVM-int-8 flux, and
-    mixed precision with the difference, the exact-JVP and the Rad-HLL flux."""
+    Rad-HLL (the paper's comparison solver), the exact-JVP PVM-int-8 flux,
+    PVM-int-8 with constrained transport, and mixed precision with the
+    difference, the exact-JVP and the Rad-HLL flux."""
     import torch
+    from paper_2212_00370_amd import inputs as I
     res = {}
-    for name, solver, prec in (("rad_hll_fp64", R.SOLVER_HLL, R.FP64), ("pvm_jvp_fp64", R.SOLVER_PVM_JVP, R.FP64),
-                               ("pvm_mixed", R.SOLVER_PVM, R.MIXED), ("pvm_jvp_mixed", R.SOLVER_PVM_JVP, R.MIXED),
-                               ("rad_hll_mixed", R.SOLVER_HLL, R.MIXED)):
-        params = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=prec, solver=solver)
+    for name, solver, prec, ct in (("rad_hll_fp64", R.SOLVER_HLL, R.FP64, 0),
+                                   ("pvm_jvp_fp64", R.SOLVER_PVM_JVP, R.FP64, 0),
+                                   ("pvm_ct_fp64", R.SOLVER_PVM, R.FP64, 1),
+                                   ("pvm_mixed", R.SOLVER_PVM, R.MIXED, 0),
+                                   ("pvm_jvp_mixed", R.SOLVER_PVM_JVP, R.MIXED, 0),
+                                   ("rad_hll_mixed", R.SOLVER_HLL, R.MIXED, 0)):
+        params = R.rrmhd_default_params(gamma=P.gamma, a_rad=P.a_rad, precision=prec, solver=solver, ct=ct)
         sv = R.Solver(grid, params, device=V.device)
         U0 = sv.prim_to_cons(V)
+        if ct:
+            # constrained transport: the face-field planes of the uniform initial field
+            U0 = torch.cat([U0, torch.from_numpy(I.uniform_face_fields(P)).to(V.device)]).contiguous()
         Uw = U0.clone()
         sv.advance(Uw, P.cfl, warmup, opac)
         torch.cuda.synchronize()
@@ -660,6 +675,10 @@ def variants_bench(R, P, grid, V, opac, steps, warmup):
         res[name] = {"value": P.ncell * steps / el, "ms_per_step": 1e3 * el / steps,
                      "faces_ms_per_step": round(fms / nb, 4), "faces_mean_launch_ms": round(fms / max(fl, 1), 4),
                      "failures": {k: rep[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")}}
+        if prec == R.MIXED:
+            res[name]["accumulation"] = "binary32 face fluxes, binary64 flux divergence"
+        if ct:
+            res[name]["note"] = "constrained transport (staggered face fields, CT-contact edge EMFs)"
         sv.close()
         del U, Ub, Uw, U0
     return res

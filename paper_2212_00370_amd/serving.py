@@ -109,6 +109,15 @@ class Server:
         active: list[_Sim] = []
         results: list[Result] = []
         changed = True          # the active set differs from the batch's
+        t = nstep = None        # time and steps of the active set while it is unchanged
+
+        def sync():
+            """Write the active set's time and step count back to its sims."""
+            if t is not None and not changed:
+                for i, sim in enumerate(active):
+                    sim.t = float(t[i])
+                    sim.steps = int(nstep[i])
+
         t0 = clock()
         qi = 0
         while qi < len(pending) or active:
@@ -124,6 +133,7 @@ class Server:
                 sim.admitted = now
                 self.in_use += need
                 self.peak_in_use = max(self.peak_in_use, self.in_use)
+                sync()
                 active.append(sim)
                 changed = True
                 qi += 1
@@ -136,32 +146,34 @@ class Server:
                 continue
             if changed:
                 self.batch.set_active([s.solver for s in active], [s.U for s in active], [s.opac for s in active])
+                # per-simulation time-step data of the active set, as arrays
+                cfl_dx = np.array([s.req.problem.cfl * s.dxmin for s in active])
+                t_end = np.array([s.req.t_end if s.req.t_end is not None else np.inf for s in active])
+                t = np.array([s.t for s in active])
+                nstep = np.array([s.steps for s in active], dtype=np.int64)
+                max_steps = np.array([s.req.steps if s.req.steps is not None else -1 for s in active], dtype=np.int64)
                 changed = False
             smax = self.batch.max_speed_active()
-            dts = []
-            for s, sm in zip(active, smax):
-                dt = s.req.problem.cfl * s.dxmin / sm
-                if s.req.t_end is not None:
-                    dt = min(dt, s.req.t_end - s.t)
-                dts.append(dt)
+            dts = np.minimum(cfl_dx / smax, t_end - t)
             self.batch.step_active(dts)
             self.ticks += 1
             self.batch_sizes.append(len(active))
-            for s, dt in zip(active, dts):
-                s.t += dt
-                s.steps += 1
-            finished = [s for s in active if s.done()]
-            if finished:
+            t += dts
+            nstep += 1
+            done = np.where(max_steps >= 0, nstep >= max_steps, t >= t_end * (1.0 - 1e-14))
+            if done.any():
+                sync()
+                finished = [sim for sim, d in zip(active, done) if d]
                 torch.cuda.synchronize(self.device)
                 end = clock() - t0
-                for s in finished:
-                    results.append(Result(rid=s.req.rid, U=s.U.cpu().numpy(), steps=s.steps, t=s.t,
-                                          arrival=s.req.arrival, admitted=s.admitted, finished=end,
-                                          zone_updates=s.steps * s.req.problem.ncell,
-                                          report=s.solver.report()))
-                    self.in_use -= s.need
-                    s.close()
-                active = [s for s in active if not s.done()]
+                for sim in finished:
+                    results.append(Result(rid=sim.req.rid, U=sim.U.cpu().numpy(), steps=sim.steps, t=sim.t,
+                                          arrival=sim.req.arrival, admitted=sim.admitted, finished=end,
+                                          zone_updates=sim.steps * sim.req.problem.ncell,
+                                          report=sim.solver.report()))
+                    self.in_use -= sim.need
+                    sim.close()
+                active = [sim for sim, d in zip(active, done) if not d]
                 changed = True
         return results
 
