@@ -172,8 +172,9 @@ rrmhd_status rrmhd_cons_to_prim(rrmhd_ctx* ctx, const double* U, double* V);
  * face fluxes of Section 3.2, eq. explicit, then the implicit solve of
  * Section 3.3, eq. impliciteq; stages of the SSP RK pattern). U: device
  * [12][var_stride] ([12 + ndim][var_stride] with ct = 1: the face fields
- * advance by the curl of the CT-contact edge EMFs), updated in place. g must describe the context's grid
- * (same ndim and n; dx and boundaries are taken from g). Enqueued; on a
+ * advance by the curl of the CT-contact edge EMFs), updated in place. g must
+ * describe the context's grid (same ndim and n; dx and boundaries are taken
+ * from g). Enqueued; on a
  * numerical failure the failing cells keep their explicit state and the
  * counters say which. */
 rrmhd_status rrmhd_step(rrmhd_ctx* ctx, double* U, const rrmhd_grid* g, double dt,

@@ -7,9 +7,10 @@ per-step tests sample only briefly.
   the signal speed, the state and the failure counters must equal the
   oracle's bit for bit at every step, for all 32 seeds.
   Seeds 15 and 16 stop in their first step on the oracle as on the GPU (an
-  inadmissible explicit state at the contact; see the design doc for the
-  diagnosis); they are expected failures of the run to t = 0.4, and their
-  first step, failures included, is compared separately.
+  inadmissible explicit fluid state at the contact, and a negative E_r in an
+  optically thin cell next to a thick one); they are expected failures of the
+  run to t = 0.4, and their first step, failures included, is compared
+  separately.
 * The 2D blast with beta scaling all twelve rows of the viscosity (the
   literal eq. beta), on a weaker blast that this form survives.
 """
