@@ -73,9 +73,12 @@ def op_counts(path, steps):
             return sum(r[k] for r in snaps) / len(snaps)
         area = sum(0.5 * (a[k] + b[k]) * (b["step"] - a["step"]) for a, b in zip(snaps, snaps[1:]))
         return area / (snaps[-1]["step"] - snaps[0]["step"])
-    return {"faces_ops_per_face": mean("faces_ops_per_face"), "prims_ops_per_cell": mean("prims_ops_per_cell"),
-            "implicit_ops_per_cell": mean("implicit_ops_per_cell"),
-            "divergence_ops_per_cell": d["divergence_ops_per_cell"], "snapshot_steps": [r["step"] for r in snaps]}
+    res = {"faces_ops_per_face": mean("faces_ops_per_face"), "prims_ops_per_cell": mean("prims_ops_per_cell"),
+           "implicit_ops_per_cell": mean("implicit_ops_per_cell"),
+           "divergence_ops_per_cell": d["divergence_ops_per_cell"], "snapshot_steps": [r["step"] for r in snaps]}
+    if all("implicit_newton_ops_per_cell" in r for r in snaps):
+        res["implicit_newton_ops_per_cell"] = mean("implicit_newton_ops_per_cell")
+    return res
 
 
 def cpu_baseline(P, steps: int, solver: int = 0, compare=None):
@@ -532,6 +535,17 @@ def main():
                "ops_snapshots": ops["snapshot_steps"],
                "cells_per_stage": P.ncell, "us_per_stage": round(1e6 * stage_s, 1), "achieved": round(a, 3),
                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(a / FP64_PEAK_TFLOPS, 4)}
+        if "implicit_newton_ops_per_cell" in ops:
+            # per kernel: the update pass does the divergence, the Picard phase
+            # and the recoveries (those of its listed cells too, a small share);
+            # the work-list pass does the Newton phase
+            nw = ops["implicit_newton_ops_per_cell"]
+            for name, cell_ops, ms in (("k_update", per_cell - nw, breakdown["update"]),
+                                       ("k_newton", nw, breakdown["newton"])):
+                t = ms / 2 / 1e3
+                ak = cell_ops * P.ncell / t / 1e12
+                imp[name] = {"ops_per_cell_of_grid": round(cell_ops, 1), "us_per_stage": round(1e6 * t, 1),
+                             "achieved": round(ak, 3), "frac": round(ak / FP64_PEAK_TFLOPS, 4)}
 
     out = {
         "metric": METRIC,

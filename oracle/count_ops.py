@@ -7,7 +7,8 @@ each) of
   * the face-flux computation (PLM MinMod + Jacobian-free PVM-int-8 + beta),
     per face, both directions;
   * the cell primitive recovery of a stage, per cell;
-  * the implicit radiation-matter solve of the first stage, per cell.
+  * the implicit radiation-matter solve of the first stage, per cell, and
+    the part of it spent in the Newton phase (per cell of the grid).
 With --solver hll (jvp) the run and the face count use Rad-HLL (the exact-JVP
 PVM-int-8 flux) instead (``opcount_blast2d_512_hll.json``, ``..._jvp.json``).
 Writes ``opcount_blast2d_512.json`` next to this file. Test infrastructure:
@@ -34,13 +35,19 @@ from oracle import oracle as O  # noqa: E402
 from paper_2212_00370_amd import inputs as I  # noqa: E402
 
 
-def counted(fn):
+def counted(fn, newton=False):
+    """Operations of fn; with newton=True also those of the implicit solve's
+    Newton phase alone (a subset of the first)."""
     L = O.lib(count=True)
     L.or_opcount_reset()
     fn(L)
     out = (C.c_ulonglong * 4)()
     L.or_opcount_get(out)
-    return dict(add=out[0], mul=out[1], div=out[2], sqrt=out[3])
+    res = dict(add=out[0], mul=out[1], div=out[2], sqrt=out[3])
+    if not newton:
+        return res
+    L.or_opcount_get_newton(out)
+    return res, dict(add=out[0], mul=out[1], div=out[2], sqrt=out[3])
 
 
 def total(c):
@@ -92,12 +99,14 @@ def main():
         Ust, _ = O.explicit_stage(g, Uc, Uc, P.kappa, P.sigma, 1.0, 0.0, 1.0, dt, par)
         Us = np.ascontiguousarray(Ust)
         Un = np.empty_like(Us); h = np.full(N, dt); st2 = np.zeros(N, np.int32); it2 = np.zeros(N, np.int32)
-        c_imp = counted(lambda L: L.or_implicit(N, O._dp(Us), N, O._dp(h), O._dp(ka), O._dp(sa), C.byref(par),
-                                                O._dp(Un), N, O._dp(st2), O._dp(it2)))
+        c_imp, c_newton = counted(lambda L: L.or_implicit(N, O._dp(Us), N, O._dp(h), O._dp(ka), O._dp(sa),
+                                                          C.byref(par), O._dp(Un), N, O._dp(st2), O._dp(it2)),
+                                  newton=True)
         row = dict(step=step, faces_ops_per_face=total(faces) / sum(nf), faces_breakdown_per_face=
                    {k: v / sum(nf) for k, v in faces.items()}, prims_ops_per_cell=prims / N,
                    implicit_ops_per_cell=total(c_imp) / N,
                    implicit_breakdown_per_cell={k: v / N for k, v in c_imp.items()},
+                   implicit_newton_ops_per_cell=total(c_newton) / N,
                    elapsed_s=time.time() - t0)
         print(json.dumps(row), flush=True)
         rows.append(row)
@@ -109,6 +118,7 @@ def main():
         faces_ops_per_face=mean("faces_ops_per_face"),
         prims_ops_per_cell=mean("prims_ops_per_cell"),
         implicit_ops_per_cell=mean("implicit_ops_per_cell"),
+        implicit_newton_ops_per_cell=mean("implicit_newton_ops_per_cell"),
         divergence_ops_per_cell=12 * (2 * 2 + 3),
     )
     sfx = {"pvm": "", "hll": "_hll", "jvp": "_jvp"}[args.solver]

@@ -117,6 +117,7 @@ def lib(count: bool = False):
             _lib_count = _setup(C.CDLL(LIB_COUNT))
             _lib_count.or_opcount_reset.argtypes = []
             _lib_count.or_opcount_get.argtypes = [C.c_void_p]
+            _lib_count.or_opcount_get_newton.argtypes = [C.c_void_p]
         return _lib_count
     if _lib is None:
         if not os.path.exists(LIB):

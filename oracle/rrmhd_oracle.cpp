@@ -55,11 +55,26 @@ static inline bool operator!=(real a, real b) { return a.v != b.v; }
 static inline real rsqrt_(real a) { g_ops.sqrt++; return real(std::sqrt(a.v)); }
 static inline double dv(real a) { return a.v; }
 static inline bool rfinite(real a) { return std::isfinite(a.v); }
+// Operations spent in the Newton phase of the implicit solve (a subset of
+// g_ops), for the split of the implicit solve's work between its phases.
+static OpCounts g_ops_newton = {0, 0, 0, 0};
+struct NewtonPhaseOps {
+  OpCounts at_start;
+  NewtonPhaseOps() : at_start(g_ops) {}
+  ~NewtonPhaseOps() {
+    g_ops_newton.add += g_ops.add - at_start.add;
+    g_ops_newton.mul += g_ops.mul - at_start.mul;
+    g_ops_newton.div += g_ops.div - at_start.div;
+    g_ops_newton.sqrt += g_ops.sqrt - at_start.sqrt;
+  }
+};
+#define COUNT_NEWTON_PHASE NewtonPhaseOps newton_phase_ops_
 #else
 typedef double real;
 static inline real rsqrt_(real a) { return std::sqrt(a); }
 static inline double dv(real a) { return a; }
 static inline bool rfinite(real a) { return std::isfinite(a); }
+#define COUNT_NEWTON_PHASE
 #endif
 
 static inline real rabs(real a) { return (a < real(0.0)) ? -a : a; }
@@ -878,6 +893,7 @@ static int implicit_cell(const real Us[NV], real h, real kap, real sig, const OP
     if (dlast <= P.imp_tol * xscale(X)) { conv = true; break; }
   }
   if (!conv && have && P.imp_method != 2) {
+    COUNT_NEWTON_PHASE;
     // Newton phase (its system is rebuilt at the start point).
     const bool from_picard = built && capped && npic > 1 && dlast < dprev;
     if (!from_picard) {
@@ -1946,9 +1962,15 @@ long long or_explicit_stage(const OGrid* og, const OPar* P, const double* U0, co
 }
 
 #ifdef ORACLE_COUNT_OPS
-void or_opcount_reset(void) { g_ops = {0, 0, 0, 0}; }
+void or_opcount_reset(void) {
+  g_ops = {0, 0, 0, 0};
+  g_ops_newton = {0, 0, 0, 0};
+}
 void or_opcount_get(unsigned long long* out) {
   out[0] = g_ops.add; out[1] = g_ops.mul; out[2] = g_ops.div; out[3] = g_ops.sqrt;
+}
+void or_opcount_get_newton(unsigned long long* out) {
+  out[0] = g_ops_newton.add; out[1] = g_ops_newton.mul; out[2] = g_ops_newton.div; out[3] = g_ops_newton.sqrt;
 }
 #endif
 
