@@ -157,6 +157,18 @@ def test_ct_blast_512_full_size(R, oracle):
     assert bit
 
 
+@pytest.mark.parametrize("name", ["blast_41x29", "field_loop_37x23"])
+def test_ct_ragged_grid(R, oracle, name):
+    """Ragged periodic grids (41x29 and 37x23: no axis and no cell count a
+    multiple of the 64-thread blocks of the CT kernels): the magnetised blast
+    and the field loop, four device-dt steps bitwise, div b at round-off."""
+    oracle.threads(0)
+    P = I.blast_2d(0, 41, 29) if name.startswith("blast") else I.field_loop_2d(37, 23)
+    bit, Ug = advance_compare(R, oracle, P, 4)
+    assert bit
+    assert np.max(np.abs(div_face(P, Ug))) * P.dx[0] / np.max(np.abs(Ug[12:14])) < 1e-13
+
+
 def test_ct_field_loop_60_steps(R, oracle):
     """The field loop (64x32) for 60 host-dt steps, bitwise every step."""
     oracle.threads(0)

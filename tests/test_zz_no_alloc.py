@@ -29,6 +29,10 @@ def run_pair(R, P, nsteps, **kw):
     opac = R.make_opacities(dev(P.kappa), dev(P.sigma))
     s = R.Solver(g, p)
     U0 = s.prim_to_cons(dev(P.V))
+    if kw.get("ct"):
+        # constrained transport: the face-field planes follow the cell planes
+        bface = P.extra["bface"] if "bface" in P.extra else I.uniform_face_fields(P)
+        U0 = torch.cat([U0, dev(bface)]).contiguous()
     torch.cuda.synchronize()
     Ua = U0.clone()
     dta = torch.zeros(nsteps, dtype=torch.float64, device="cuda:0")
@@ -69,6 +73,18 @@ def test_noalloc_equals_advance_1d_then_smaller_1d(R):
     P = I.riemann_1d(5, 256)
     print("noalloc vs advance: riemann seed 5, 256 cells, mixed", flush=True)
     check(run_pair(R, P, 3, precision=R.MIXED))
+
+
+def test_noalloc_equals_advance_with_ct(R):
+    """Constrained transport (one face-field plane per dimension after the 12
+    cell planes): the 64x40 blast for 3 steps, then the smaller 48x24 field
+    loop for 2 steps."""
+    P = I.blast_2d(0, 64, 40)
+    print("noalloc vs advance: CT blast 64x40, 3 steps", flush=True)
+    check(run_pair(R, P, 3, ct=1))
+    P = I.field_loop_2d(48)
+    print("noalloc vs advance: CT field loop 48x24, 2 steps", flush=True)
+    check(run_pair(R, P, 2, ct=1))
 
 
 def test_noalloc_rejects_a_grid_beyond_the_scratch_array(R):
