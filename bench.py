@@ -502,6 +502,20 @@ def main():
     value = P.ncell * args.steps / elapsed
     ms_step = 1e3 * elapsed / args.steps
 
+    # the spread of the timed figure: four more runs of the same steps from
+    # the same initial state, timed the same way but without the first run's
+    # face-kernel event pairs (not part of `value`)
+    reps = [ms_step]
+    for _ in range(4):
+        Ur = U0.clone()
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        run(Ur, args.steps)
+        torch.cuda.synchronize()
+        reps.append(1e3 * (time.perf_counter() - r0) / args.steps)
+        del Ur
+    solver.report()
+
     # roofline of the dominant kernel (face fluxes)
     sfx = {"pvm": "", "hll": "_hll", "jvp": "_jvp"}[args.solver]
     ops = op_counts(os.path.join(ROOT, "oracle", f"opcount_blast2d_{args.n}{sfx}.json"), args.steps)
@@ -570,6 +584,8 @@ def main():
         "roofline_implicit_pass": imp,
         "kernels_ms_per_step": breakdown,
         "kernels_ms_per_step_note": "separate run of min(steps, 20) steps with every launch timed",
+        "ms_per_step_repeats": [round(x, 4) for x in reps],
+        "ms_per_step_median_of_5": round(sorted(reps)[2], 4),
         "failures": {k: rep[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")},
     }
     Ufinal = U.cpu().numpy()
