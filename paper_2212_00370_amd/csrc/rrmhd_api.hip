@@ -41,18 +41,16 @@ static_assert(kBlock == rr::kParkLanes, "the PVM chain's LDS slots assume one-wa
 // Workgroup size of the single-block reductions over per-block partials.
 constexpr int kRedBlock = 1024;
 constexpr int kWave = 64;
-// Picard iterations of the implicit solve done in the update pass; a cell
-// still iterating there continues, unchanged, in the work-list pass.
-#ifndef RRMHD_PICARD_SPLIT
-#define RRMHD_PICARD_SPLIT 9
-#endif
-constexpr int kPicardSplit = RRMHD_PICARD_SPLIT;
 // Minimum waves per SIMD the register allocation of the face and update
 // kernels targets (a hint to the compiler). Faces: three, with the PVM
 // chain's start-to-end values in LDS (FP64: 168 VGPRs and 12.5 KB LDS per
 // one-wave block; mixed precision: 136 VGPRs, 6.5 KB). Update pass: two (no
 // spills; its 4096 one-wave blocks at 512^2 cells fill two rounds of 2048
-// slots).
+// slots). Newton pass: two (256 VGPRs, 8 of them spilled; at one wave per
+// SIMD its work list needed two rounds of the 1024 slots late in a blast).
+#ifndef RRMHD_NEWTON_WAVES
+#define RRMHD_NEWTON_WAVES 2
+#endif
 #ifndef RRMHD_FACES_WAVES
 #define RRMHD_FACES_WAVES 3
 #endif
@@ -746,9 +744,6 @@ struct StageArgs {
   // cdt = cc * dtp[0] instead of cdt.
   const double* dtp;
   double cc;
-  // Picard iterations the update pass runs before it hands a cell to the
-  // work-list pass (which continues the same iteration).
-  int m_split;
   // Next stage's primitives: with nextp set, each cell's recovery from its
   // output state is done where the cell finishes (Vp, taup, Zc of the next
   // stage); with speed also set, the signal-speed block maxima go to
@@ -793,14 +788,14 @@ __device__ __forceinline__ double next_prims(const GridDev& G, const StageArgs& 
 }
 
 // Work-list entry of a cell handed to the second pass, planes of `xs`:
-// 0-3 X, 4 Zg, 5 dlast, 6 dprev, 7 Picard solves so far, 8 next Picard index m
-// (a Picard state to continue), or m = -1 with X, Zg the Newton start point.
-constexpr int kWorkPlanes = 9;
+// 0-3 the Newton start point X0, 4 its recovery warm start Z0, 5 the Picard
+// solves done.
+constexpr int kWorkPlanes = 6;
 
 // Flux divergence and stage combination, then phase 1 of the implicit solve
-// (Picard, up to A.m_split iterations). Cells that need more (the rest of
-// Picard, or Newton) get their explicit state U* written to the output and
-// are appended to `worklist` (one atomic per wave) with their Picard state.
+// (Picard). Cells that need phase 2 (Newton) get their explicit state U*
+// written to the output and are appended to `worklist` (one atomic per wave)
+// with their Newton start point.
 // FT: storage type of the face fluxes; the divergence is accumulated in FP64
 // either way (differences of stored values are exact in FP64 for FP32 data).
 template <typename FT>
@@ -816,8 +811,8 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
   unsigned int its = 0, cits = 0;
   double spd = 0.0;
   bool newton = false;
-  rr::PicardState S;
-  S.m = -1;
+  double X0[4] = {0.0, 0.0, 0.0, 0.0}, Z0 = 0.0;
+  int pits = 0;
   if (c < G.N) {
     int ci[3];
     {
@@ -884,26 +879,17 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
     rr::ImpIn in;
     int st;
     const double Zg0 = A.Zc[c];
-    S.it = 0;
     if (!rr::imp_prepare(Ust, K, in, floored)) {
 #pragma unroll
       for (int q = 0; q < NV; ++q) Un[q] = Ust[q];
       st = rr::IMP_FAILED;
     } else {
-      double X0[4], Z0;
-      rr::picard_start(in, Zg0, S);
-      st = rr::picard_run(Ust, in, cdt, opac_at(op.kappa, op.kappa0, c), opac_at(op.sigma, op.sigma0, c), K, S,
-                          A.m_split, Zg0, Un, X0, Z0);
-      if (st == rr::IMP_NEED_NEWTON) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) S.X[i] = X0[i];
-        S.Zg = Z0;
-        S.m = -1;
-      }
+      st = rr::picard_run(Ust, in, cdt, opac_at(op.kappa, op.kappa0, c), opac_at(op.sigma, op.sigma0, c), K, Zg0,
+                          Un, X0, Z0, pits);
     }
-    its = (unsigned int)S.it;
+    its = (unsigned int)pits;
     ffl = floored ? 1 : 0;
-    if (st == rr::IMP_NEED_NEWTON || st == rr::IMP_PENDING) {
+    if (st == rr::IMP_NEED_NEWTON) {
       newton = true;
 #pragma unroll
       for (int q = 0; q < NV; ++q) A.Uo[q * A.so + c] = Ust[q];
@@ -933,15 +919,12 @@ __device__ __forceinline__ void update_block(long long lb, const GridDev& G, con
       const unsigned long long slot = base + below;
       worklist[slot] = c;
       double* xs = (double*)(worklist + G.N);
-      xs[0 * G.N + slot] = S.X[0];
-      xs[1 * G.N + slot] = S.X[1];
-      xs[2 * G.N + slot] = S.X[2];
-      xs[3 * G.N + slot] = S.X[3];
-      xs[4 * G.N + slot] = S.Zg;
-      xs[5 * G.N + slot] = S.dlast;
-      xs[6 * G.N + slot] = S.dprev;
-      xs[7 * G.N + slot] = (double)S.it;
-      xs[8 * G.N + slot] = (double)S.m;
+      xs[0 * G.N + slot] = X0[0];
+      xs[1 * G.N + slot] = X0[1];
+      xs[2 * G.N + slot] = X0[2];
+      xs[3 * G.N + slot] = X0[3];
+      xs[4 * G.N + slot] = Z0;
+      xs[5 * G.N + slot] = (double)pits;
     }
   }
   report_add(rep, blkmax, lb, fc2p, 0, fimp, fnf, bad, cits, its, ffl);
@@ -961,11 +944,11 @@ k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* 
   update_block<FT>(lb, G, A, op, K, rep, blkmax, worklist, wcount);
 }
 
-// Second pass of the implicit solve for the cells in `worklist` (the rest of
-// the Picard phase, then Newton where needed); the explicit state U* was left
-// in the output by the update pass. Each cell is handled by a quad of 4
-// lanes (see implicit_newton_quad); grid-stride over the list with blocks
-// bi = 0..nb-1 (64 cells per block).
+// Second pass of the implicit solve for the cells in `worklist`: Newton from
+// the start point the update pass left; the explicit state U* is in the
+// output. Each cell is handled by a quad of 4 lanes (see
+// implicit_newton_quad); grid-stride over the list with blocks bi = 0..nb-1
+// (16 cells per block).
 __device__ __forceinline__ void newton_blocks(long long bi, long long nb, const GridDev& G, const StageArgs& A,
                                               const Opac& op, const Phys& K, DevReport* rep, unsigned int* blkmax,
                                               const long long* __restrict__ worklist,
@@ -984,30 +967,37 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, const 
   for (unsigned long long i = (unsigned long long)bi * kCellsPerBlock + quad; i < n;
        i += (unsigned long long)nb * kCellsPerBlock) {
     const long long c = worklist[i];
-    double Ust[NV], Un[NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) Ust[q] = A.Uo[q * A.so + c];
-    const double kap = opac_at(op.kappa, op.kappa0, c), sig = opac_at(op.sigma, op.sigma0, c);
-    rr::PicardState S;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) S.X[k] = xs[k * ncell + i];
-    S.Zg = xs[4 * ncell + i];
-    S.dlast = xs[5 * ncell + i];
-    S.dprev = xs[6 * ncell + i];
-    S.it = (int)xs[7 * ncell + i];
-    S.m = (int)xs[8 * ncell + i];
-    double X0[4] = {S.X[0], S.X[1], S.X[2], S.X[3]}, Z0 = S.Zg;
-    int st = rr::IMP_NEED_NEWTON;
-    if (S.m >= 0) {
-      // continue the Picard phase (the 4 lanes of the quad alike)
-      rr::ImpIn in;
-      bool floored = false;
-      rr::imp_prepare(Ust, K, in, floored);  // succeeded in the update pass
-      st = rr::picard_run(Ust, in, cdt, kap, sig, K, S, 0x7fffffff, A.Zc[c], Un, X0, Z0);
-    }
+    double Un[NV];
+    bool conv = false;
     int it = 0;
-    if (st == rr::IMP_NEED_NEWTON) st = rr::implicit_newton_quad(Ust, cdt, kap, sig, K, X0, Z0, Un, it);
-    it += S.it;
+    {
+      rr::ImpIn in;
+      {
+        double Ust[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Ust[q] = A.Uo[q * A.so + c];
+        bool floored = false;
+        rr::imp_prepare(Ust, K, in, floored);  // succeeded in the update pass
+      }
+      const double kap = opac_at(op.kappa, op.kappa0, c), sig = opac_at(op.sigma, op.sigma0, c);
+      double X[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) X[k] = xs[k * ncell + i];
+      const double Z0 = xs[4 * ncell + i];
+      it = (int)xs[5 * ncell + i];
+      int nit = 0;
+      conv = rr::implicit_newton_quad(in, cdt, kap, sig, K, X, Z0, nit);
+      it += nit;
+      if (conv) {
+        // D and B of the prepared state are those of U*
+        rr::imp_finish(X, in.Ul, in, Un);
+      } else {
+        // U* again, from the output (not kept in registers through the solve)
+        const volatile double* uo = A.Uo;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Un[q] = uo[q * A.so + c];
+      }
+    }
     if (lead) {
       bool fin = true;
 #pragma unroll
@@ -1015,9 +1005,9 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, const 
         A.Uo[q * A.so + c] = Un[q];
         fin = fin && isfinite(Un[q]);
       }
-      if (st != rr::IMP_DONE) fimp += 1;
+      if (!conv) fimp += 1;
       if (!fin) fnf += 1;
-      if ((st != rr::IMP_DONE || !fin) && (unsigned long long)c < bad) bad = (unsigned long long)c;
+      if ((!conv || !fin) && (unsigned long long)c < bad) bad = (unsigned long long)c;
       its = ((unsigned int)it > its) ? (unsigned int)it : its;
       if (A.nextp) spd = rr::dmax(spd, next_prims(G, A, op, K, c, Un, fc2p, bad, cits));
     }
@@ -1026,7 +1016,7 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, const 
   if (A.speed) block_max_to(spd, A.partial, A.npart + bi);
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_NEWTON_WAVES)))
 k_newton(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
          const long long* __restrict__ worklist, const unsigned long long* wcount) {
   newton_blocks(blockIdx.x, gridDim.x, G, A, op, K, rep, blkmax, worklist, wcount);
@@ -1143,7 +1133,6 @@ __device__ __forceinline__ StageArgs stage_args(const SimDesc& D, double dt, int
   A.dtp = nullptr;
   A.cc = c;
   A.Zc = D.Zc;
-  A.m_split = 0x7fffffff;
   // the next stage's primitives where each cell finishes (not after the last)
   A.nextp = last ? 0 : 1;
   A.speed = 0;
@@ -1196,7 +1185,8 @@ k_update_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, con
   else update_block<double>(blockIdx.x - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
 }
 
-__global__ void __launch_bounds__(kBlock) k_newton_b(const SimDesc* __restrict__ T, const long long* __restrict__ off,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_NEWTON_WAVES)))
+k_newton_b(const SimDesc* __restrict__ T, const long long* __restrict__ off,
                                                      const double* __restrict__ dts, int nsim, int stage, int last,
                                                      double a0, double a1, double c) {
   const long long* o = off + OFF_NEWTON * (nsim + 1);
@@ -1948,7 +1938,6 @@ rrmhd_status step_stages(rrmhd_ctx* c, double* U, const rrmhd_grid* g, double dt
     A.dtp = dt_dev;
     A.cc = co[s][2];
     A.Zc = c->Zc;
-    A.m_split = kPicardSplit;
     A.nextp = (!last || prims_after) ? 1 : 0;
     A.speed = (last && prims_after) ? 1 : 0;
     A.Vp = c->Vp;

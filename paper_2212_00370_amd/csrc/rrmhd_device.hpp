@@ -1341,52 +1341,30 @@ __device__ __forceinline__ void imp_finish(double X[4], const double Us[NV], con
   for (int j = 0; j < 3; ++j) Un[9 + j] = X[1 + j];
 }
 
-enum { IMP_DONE = 0, IMP_FAILED = 1, IMP_NEED_NEWTON = 2, IMP_PENDING = 3 };
+enum { IMP_DONE = 0, IMP_FAILED = 1, IMP_NEED_NEWTON = 2 };
 
-// State of the Picard phase between iterations: iterate X, warm start Zg of
-// the next recovery, the last two update norms, solves done, next index m.
-struct PicardState {
-  double X[4];
-  double Zg, dlast, dprev;
-  int it, m;
-};
-
-__device__ __forceinline__ void picard_start(const ImpIn& in, double Zg0, PicardState& S) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i) S.X[i] = in.Ul[8 + i];
-  S.Zg = Zg0;
-  S.dlast = 0.0;
-  S.dprev = 0.0;
-  S.it = 0;
-  S.m = 0;
-}
-
-// Picard iterations m = S.m, S.m + 1, ... of phase 1. Stopping before
-// iteration m_lim leaves S exactly as an uninterrupted run has it there
-// (IMP_PENDING), so a later call continues the same sequence. Otherwise:
-// IMP_DONE: Un holds the result; IMP_FAILED: Un = Us; IMP_NEED_NEWTON: phase 2
-// must finish the cell from X0 (warm start Z0): the last Picard iterate if
-// Picard was still contracting at its cap, else X* (with Zg0, the recovery Z
-// of the stage's cell state).
+// Phase 1, the paper's Picard iteration from X* (recovery warm start Zg0,
+// the stage cell's Z). IMP_DONE: Un holds the result; IMP_FAILED: Un = Us;
+// IMP_NEED_NEWTON: phase 2 must finish the cell from X0 (recovery warm start
+// Z0): the last Picard iterate if Picard was still contracting at its cap,
+// else X* with Zg0. its: Picard solves done.
 __device__ __forceinline__ int picard_run(const double Us[NV], const ImpIn& in, double h, double kap, double sig,
-                                          const Phys& K, PicardState& S, int m_lim, double Zg0, double Un[NV],
-                                          double X0[4], double& Z0) {
+                                          const Phys& K, double Zg0, double Un[NV], double X0[4], double& Z0,
+                                          int& its) {
   ImpSys sy;
   int c2p_it = 0;
-  bool conv = false, built = false, capped = false;
-  bool have = S.m > 0;  // the build at m = 0 succeeded
+  double X[4] = {in.Ul[8], in.Ul[9], in.Ul[10], in.Ul[11]};
+  double Zg = Zg0, dlast = 0.0, dprev = 0.0;
+  bool conv = false, built = false, capped = false, have = false;
+  its = 0;
   const int npic = (K.imp_method == 1) ? 0 : ((K.imp_method == 2) ? K.imp_maxit : K.imp_picard_it);
-  for (int m = S.m; m <= npic; ++m) {
-    if (m >= m_lim) {
-      S.m = m;
-      return IMP_PENDING;
-    }
-    built = imp_build(S.X, in.Ul, in.Et, in.St, h, kap, sig, K, S.Zg, sy, c2p_it);
+  for (int m = 0; m <= npic; ++m) {
+    built = imp_build(X, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sy, c2p_it);
     if (!built) break;
-    S.Zg = sy.Z;
+    Zg = sy.Z;
     if (m == 0) have = true;
     if (m == npic) { capped = true; break; }
-    if (m > 1 && K.imp_method == 0 && S.dlast > S.dprev) break;
+    if (m > 1 && K.imp_method == 0 && dlast > dprev) break;
     double A[4][4], bb[4], Xn[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -1395,32 +1373,26 @@ __device__ __forceinline__ int picard_run(const double Us[NV], const ImpIn& in, 
       for (int j = 0; j < 4; ++j) A[i][j] = sy.C[i][j];
     }
     if (!solve4(A, bb, Xn)) break;
-    ++S.it;
+    ++its;
     if (!(Xn[0] > 0.0) || !isfinite(Xn[0]) || !isfinite(Xn[1]) || !isfinite(Xn[2]) || !isfinite(Xn[3])) break;
     double dd[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { dd[i] = Xn[i] - S.X[i]; S.X[i] = Xn[i]; }
-    S.dprev = S.dlast;
-    S.dlast = vmaxabs4(dd);
+    for (int i = 0; i < 4; ++i) { dd[i] = Xn[i] - X[i]; X[i] = Xn[i]; }
+    dprev = dlast;
+    dlast = vmaxabs4(dd);
     // converged once the update is below tolerance; the system is not built
     // again at the accepted iterate
-    if (S.dlast <= K.imp_tol * vmaxabs4(S.X)) { conv = true; break; }
+    if (dlast <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
   }
   if (conv) {
-    imp_finish(S.X, Us, in, Un);
+    imp_finish(X, Us, in, Un);
     return IMP_DONE;
   }
   if (have && K.imp_method != 2) {
-    const bool from_picard = built && capped && npic > 1 && S.dlast < S.dprev;
-    if (from_picard) {
+    const bool from_picard = built && capped && npic > 1 && dlast < dprev;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) X0[i] = S.X[i];
-      Z0 = S.Zg;
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) X0[i] = in.Ul[8 + i];
-      Z0 = Zg0;
-    }
+    for (int i = 0; i < 4; ++i) X0[i] = from_picard ? X[i] : in.Ul[8 + i];
+    Z0 = from_picard ? Zg : Zg0;
     return IMP_NEED_NEWTON;
   }
 #pragma unroll
@@ -1430,132 +1402,130 @@ __device__ __forceinline__ int picard_run(const double Us[NV], const ImpIn& in, 
 
 // Phase 2, Newton on C(X) X - b(X) from X0 (warm start Z0), on a quad of 4
 // lanes (lanes 4k..4k+3 of a wave, all on the same cell and all active
-// together): lane j builds Jacobian column j (forward difference, step
-// 1e-8 max(|X|, |b_i/C_ii|)) and tries line-search step 2^-(j + 4r) in round
-// r; the quad then shares the results. The selections are those of one lane
-// doing it all in order (columns 0..3, stopping at the first that fails;
-// the first acceptable step of 1, 1/2, 1/4, ...), so the result is the same
-// bit for bit. Returns IMP_DONE or IMP_FAILED (then Un = Us).
+// together). Each Newton iteration is a column round, where lane j evaluates
+// the system at X + del e_j for Jacobian column j (forward difference, step
+// 1e-8 max(|X|, |b_i/C_ii|)), followed by line-search rounds, where lane j
+// evaluates it at X + 2^-(j + 4r) dX in round r; the quad then shares the
+// results. The selections are those of one lane doing it all in order
+// (columns 0..3, stopping at the first that fails; the first acceptable step
+// of 1, 1/2, 1/4, ...), so the result is the same bit for bit. Every round
+// evaluates one point per lane through the same code (one recovery and
+// system build), which keeps the register footprint of a single evaluation.
+// Returns true on convergence with the root in X (before imp_finish).
 __device__ __forceinline__ double quad_get(double v, int base, int k) { return __shfl(v, base + k, 64); }
 
-__device__ __forceinline__ int implicit_newton_quad(const double Us[NV], double h, double kap, double sig,
-                                                    const Phys& K, const double X0[4], double Z0, double Un[NV],
-                                                    int& iters) {
+__device__ __forceinline__ bool implicit_newton_quad(const ImpIn& in, double h, double kap, double sig,
+                                                     const Phys& K, double X[4], double Z0, int& iters) {
   const int lane = threadIdx.x & 63;
   const int j = lane & 3;
   const int base = lane & ~3;
-  ImpIn in;
-  iters = 0;
+  enum { kInit = 0, kColumns = 1, kSearch = 2 };
+  int phase = kInit, round = 0, n = 0, it = 0;
+  double R[4] = {0.0, 0.0, 0.0, 0.0}, bd[4] = {0.0, 0.0, 0.0, 0.0}, dX[4] = {0.0, 0.0, 0.0, 0.0};
+  double Zg = Z0, sc = 0.0, del = 0.0, lam0 = 1.0, rn = 0.0, dn = 0.0, sprev = 0.0;
   bool conv = false;
-  double X[4];
-  bool floored = false;
-  if (imp_prepare(Us, K, in, floored)) {
-    X[0] = X0[0]; X[1] = X0[1]; X[2] = X0[2]; X[3] = X0[3];
-    ImpSys sy;
-    double Zg = Z0, R[4];
-    int it = 0, c2p_it = 0;
-    if (imp_build(X, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sy, c2p_it)) {
-      Zg = sy.Z;
-      imp_residual(sy, X, R);
-      double sprev = 0.0;
-      for (int n = 0; n < K.imp_maxit; ++n) {
-        ++it;
-        double bd[4];
+  // every round advances `round` (at most 3 per iteration) or `n` (at most
+  // imp_maxit), so the loop ends
+  while (true) {
+    // this lane's evaluation point
+    double Xe[4] = {X[0], X[1], X[2], X[3]};
+    double lam = lam0;
+    bool valid = true;
+    if (phase == kColumns) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bd[i] = sy.b[i] / sy.C[i][i];
-        const double sc = dmax(vmaxabs4(X), vmaxabs4(bd));
-        const double del = 1e-8 * sc;
-        // column j on lane j
-        double col[4] = {0.0, 0.0, 0.0, 0.0};
-        double okc;
-        {
-          double Xp[4] = {X[0], X[1], X[2], X[3]};
-          Xp[j] = Xp[j] + del;
-          ImpSys sp;
-          okc = imp_build(Xp, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sp, c2p_it) ? 1.0 : 0.0;
-          if (okc != 0.0) {
-            double Rp[4];
-            imp_residual(sp, Xp, Rp);
+      for (int k = 0; k < 4; ++k) Xe[k] = (k == j) ? X[k] + del : X[k];
+    } else if (phase == kSearch) {
+      for (int k = 0; k < j; ++k) lam = 0.5 * lam;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) col[i] = (Rp[i] - R[i]) / del;
-          }
+      for (int i = 0; i < 4; ++i) Xe[i] = X[i] + lam * dX[i];
+      valid = Xe[0] > 0.0;
+    }
+    double Re[4] = {0.0, 0.0, 0.0, 0.0}, be[4] = {0.0, 0.0, 0.0, 0.0}, Ze = 0.0;
+    bool ok = false;
+    if (valid) {
+      ImpSys sy;
+      int c2p_it = 0;
+      ok = imp_build(Xe, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, sy, c2p_it);
+      if (ok) {
+        imp_residual(sy, Xe, Re);
+        if (phase != kColumns) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) be[i] = sy.b[i] / sy.C[i][i];
+          Ze = sy.Z;
         }
-        // the sequential rule stops at the first failing column: any failure breaks
-        const double okall = quad_get(okc, base, 0) * quad_get(okc, base, 1) * quad_get(okc, base, 2) *
-                             quad_get(okc, base, 3);
-        if (okall == 0.0) break;
-        double J[4][4];
+      }
+    }
+    bool start = false;
+    if (phase == kInit) {
+      // all four lanes evaluated X0
+      if (!ok) break;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+      for (int i = 0; i < 4; ++i) { R[i] = Re[i]; bd[i] = be[i]; }
+      Zg = Ze;
+      start = true;
+    } else if (phase == kColumns) {
+      double col[4] = {0.0, 0.0, 0.0, 0.0};
+      if (ok) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) J[i][k] = quad_get(col[i], base, k);
-        double nR[4] = {-R[0], -R[1], -R[2], -R[3]}, dX[4];
-        if (!solve4(J, nR, dX)) break;
-        const double rn = vmaxabs4(R);
-        const double dn = vmaxabs4(dX);
-        bool acc = false;
-        double Xt[4], Rt[4], Zt = 0.0, bt[4], Ct[4];
-        double lam0 = 1.0;
-        for (int round = 0; round < 3 && !acc; ++round) {
-          double lam = lam0;
-          for (int k = 0; k < j; ++k) lam = 0.5 * lam;
-          double mx[4], mr[4], mb[4], mc[4], mz = 0.0, good = 0.0;
+        for (int i = 0; i < 4; ++i) col[i] = (Re[i] - R[i]) / del;
+      }
+      const double okc = ok ? 1.0 : 0.0;
+      // the sequential rule stops at the first failing column: any failure breaks
+      const double okall = quad_get(okc, base, 0) * quad_get(okc, base, 1) * quad_get(okc, base, 2) *
+                           quad_get(okc, base, 3);
+      if (okall == 0.0) break;
+      double J[4][4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) { mx[i] = X[i] + lam * dX[i]; mr[i] = 0.0; mb[i] = 0.0; mc[i] = 1.0; }
-          ImpSys st;
-          if (mx[0] > 0.0 && imp_build(mx, in.Ul, in.Et, in.St, h, kap, sig, K, Zg, st, c2p_it)) {
-            imp_residual(st, mx, mr);
-            if (vmaxabs4(mr) < rn || lam * dn <= 1e-10 * sc) {
-              good = 1.0;
-              mz = st.Z;
+      for (int k = 0; k < 4; ++k)
 #pragma unroll
-              for (int i = 0; i < 4; ++i) { mb[i] = st.b[i]; mc[i] = st.C[i][i]; }
-            }
-          }
-          // first acceptable lane in order 0..3
-          int pick = -1;
+        for (int i = 0; i < 4; ++i) J[i][k] = quad_get(col[i], base, k);
+      double nR[4] = {-R[0], -R[1], -R[2], -R[3]};
+      if (!solve4(J, nR, dX)) break;
+      rn = vmaxabs4(R);
+      dn = vmaxabs4(dX);
+      lam0 = 1.0;
+      round = 0;
+      phase = kSearch;
+    } else {
+      const double good = (ok && (vmaxabs4(Re) < rn || lam * dn <= 1e-10 * sc)) ? 1.0 : 0.0;
+      // first acceptable lane in order 0..3
+      int pick = -1;
 #pragma unroll
-          for (int k = 3; k >= 0; --k)
-            if (quad_get(good, base, k) != 0.0) pick = k;
-          if (pick >= 0) {
-            acc = true;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              Xt[i] = quad_get(mx[i], base, pick);
-              Rt[i] = quad_get(mr[i], base, pick);
-              bt[i] = quad_get(mb[i], base, pick);
-              Ct[i] = quad_get(mc[i], base, pick);
-            }
-            Zt = quad_get(mz, base, pick);
-          }
-          lam0 = 0.5 * (0.5 * (0.5 * (0.5 * lam0)));
-        }
-        if (!acc) break;
+      for (int k = 3; k >= 0; --k)
+        if (quad_get(good, base, k) != 0.0) pick = k;
+      if (pick < 0) {
+        if (++round == 3) break;
+        lam0 = 0.5 * (0.5 * (0.5 * (0.5 * lam0)));
+      } else {
         double stp[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          stp[i] = Xt[i] - X[i];
-          X[i] = Xt[i];
-          R[i] = Rt[i];
-          sy.b[i] = bt[i];
-          sy.C[i][i] = Ct[i];
+          const double xt = quad_get(Xe[i], base, pick);
+          stp[i] = xt - X[i];
+          X[i] = xt;
+          R[i] = quad_get(Re[i], base, pick);
+          bd[i] = quad_get(be[i], base, pick);
         }
-        Zg = Zt;
+        Zg = quad_get(Ze, base, pick);
         const double sn = vmaxabs4(stp);
         if (sn <= K.imp_tol * vmaxabs4(X)) { conv = true; break; }
         if (n > 0 && sn <= 1e-9 * sc && sn >= sprev) { conv = true; break; }
         sprev = sn;
+        ++n;
+        start = true;
       }
     }
-    iters = it;
+    if (start) {
+      // next Newton iteration: its difference step
+      if (n >= K.imp_maxit) break;
+      ++it;
+      sc = dmax(vmaxabs4(X), vmaxabs4(bd));
+      del = 1e-8 * sc;
+      phase = kColumns;
+    }
   }
-  if (!conv) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) Un[q] = Us[q];
-    return IMP_FAILED;
-  }
-  imp_finish(X, Us, in, Un);
-  return IMP_DONE;
+  iters = it;
+  return conv;
 }
 
 // ---------------------------------------------------------------------------
