@@ -119,8 +119,9 @@ def log(msg):
 
 
 def serving_run(mix, loads, seed, seq_sample, budget_frac=0.5, label="serving"):
-    """Continuous batching of independent problems (serving.Server: one
-    batched launch per kernel class and tick, admission by HBM footprint).
+    """Continuous batching of independent problems (serving.Server: light
+    and heavy size classes on their own streams, batched launches, time steps
+    formed on the device, admission by HBM footprint).
     Capacity is measured first with every request present at t = 0; each timed
     run then draws Poisson arrivals at load x capacity. The comparison runs the
     first `seq_sample` requests one at a time in FP64 through rrmhd_max_speed +
@@ -168,7 +169,7 @@ def serving_run(mix, loads, seed, seq_sample, budget_frac=0.5, label="serving"):
                      "p50_time_to_solution_s": S.percentile(tts, 50),
                      "p99_time_to_solution_s": S.percentile(tts, 99),
                      "zone_updates_per_s": sum(r.zone_updates for r in res) / wall, "wall_s": wall,
-                     "ticks": srv.ticks, "mean_batch": float(np.mean(srv.batch_sizes)),
+                     "rounds": srv.ticks, "mean_resident": float(np.mean(srv.batch_sizes)),
                      "peak_resident_bytes": srv.peak_in_use})
         log(f"{label}: load {load}, p50 {runs[-1]['p50_time_to_solution_s']:.3f} s, "
             f"p99 {runs[-1]['p99_time_to_solution_s']:.3f} s, {wall:.1f} s")
@@ -229,9 +230,10 @@ def serving_bench(args):
 def riemann1d_bench(args):
     """A batch of seeded 1D Riemann problems (400 cells on [0, 1], PLM MinMod,
     PVM-int-8, IMEX RK2, CFL 0.4) run to t = 0.4 together through
-    rrmhd_max_speed_batch + rrmhd_step_batch: one problem cannot fill the
-    GPU, so the throughput figure is for `--batch` seeds at once (each with its
-    own time step; finished problems leave the batch)."""
+    rrmhd_advance_batch: one problem cannot fill the GPU, so the throughput
+    figure is for `--batch` seeds at once, each with its own CFL time step
+    formed on the device (`--chunk` steps per call and synchronization;
+    finished problems are skipped)."""
     import numpy as np
     import torch
     from paper_2212_00370_amd import inputs as I
@@ -254,38 +256,33 @@ def riemann1d_bench(args):
     cfl_dx = np.array([d["P"].cfl * d["P"].dx[0] for d in sims])
     t_end = np.array([d["P"].t_end for d in sims])
 
-    def run_all(max_ticks=None):
+    no_count = np.full(nb, -1, dtype=np.int64)
+    batch.set_active([d["s"] for d in sims], [d["U"] for d in sims], [d["o"] for d in sims])
+
+    def run_all(max_steps=None):
+        # each problem's CFL loop on the device, `chunk` steps per call; a
+        # problem at t_end is skipped by the launches that follow
         for d in sims:
             d["U"].copy_(d["U0"])
             d["s"].report()
+        torch.cuda.synchronize()
         t = np.zeros(nb)
         k = np.zeros(nb, dtype=np.int64)
-        idx = np.arange(nb)
-        ticks = 0
-        changed = True
-        while idx.size and (max_ticks is None or ticks < max_ticks):
-            if changed:
-                batch.set_active([sims[i]["s"] for i in idx], [sims[i]["U"] for i in idx], [sims[i]["o"] for i in idx])
-                changed = False
-            sm = batch.max_speed_active()
-            dts = np.minimum(cfl_dx[idx] / sm, t_end[idx] - t[idx])
-            batch.step_active(dts)
-            t[idx] += dts
-            k[idx] += 1
-            keep = t[idx] < t_end[idx] * (1 - 1e-14)
-            if not keep.all():
-                idx = idx[keep]
-                changed = True
-            ticks += 1
+        calls = 0
+        while not (t >= t_end * (1 - 1e-14)).all() and (max_steps is None or k.max() < max_steps):
+            chunk = args.chunk if max_steps is None else min(args.chunk, max_steps - int(k.max()))
+            batch.advance_active(cfl_dx, t_end, no_count, t, k, chunk)
+            t, k = batch.clock_active()
+            calls += 1
         torch.cuda.synchronize()
         for i, d in enumerate(sims):
             d["k"] = int(k[i])
-        return ticks
+        return int(k.max()), calls
 
-    run_all(max_ticks=5)                      # warm-up
+    run_all(max_steps=5)                      # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ticks = run_all()
+    ticks, calls = run_all()
     el = time.perf_counter() - t0
     zu = sum(d["k"] * d["P"].ncell for d in sims)
     reps = [d["s"].report() for d in sims]
@@ -298,9 +295,10 @@ def riemann1d_bench(args):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32+f64" if prec == R.MIXED else "f64", "data": "synthetic", "mode": "riemann1d",
             "config": {"workload": f"{nb} seeded 1D RRMHD+M1 Riemann problems x 400 cells, PVM-int-8, PLM MinMod, "
-                                   f"IMEX RK2, CFL 0.4, to t=0.4, batched (rrmhd_step_batch)",
+                                   f"IMEX RK2, CFL 0.4, to t=0.4, batched (rrmhd_advance_batch, {args.chunk} "
+                                   f"device-side CFL steps per call)",
                        "problems": nb, "cells_per_problem": 400},
-            "ticks": ticks, "zone_updates": zu, "wall_s": el,
+            "ticks": ticks, "calls": calls, "zone_updates": zu, "wall_s": el,
             "steps_per_problem": {"min": int(min(d["k"] for d in sims)), "max": int(max(d["k"] for d in sims))},
             "problems_with_counted_failures": len(failing), "failing_seeds_below_32": [i for i in failing if i < 32]}
 
@@ -407,6 +405,8 @@ def main():
     ap.add_argument("--seq-sample", type=int, default=100,
                     help="--mode serving: requests run one at a time in FP64 for the comparison")
     ap.add_argument("--batch", type=int, default=1024, help="--mode riemann1d: problems run together")
+    ap.add_argument("--chunk", type=int, default=64,
+                    help="--mode riemann1d: device-side steps per rrmhd_advance_batch call")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for {args.gpus}); "
@@ -635,7 +635,7 @@ def serving_leg(seed):
             "capacity_zone_updates_per_s": r["capacity_zone_updates_per_s"],
             "one_at_a_time_fp64_zone_updates_per_s": r["one_at_a_time_fp64"]["zone_updates_per_s"],
             "batched_capacity_over_one_at_a_time_fp64": r["batched_capacity_over_one_at_a_time_fp64"],
-            "mean_batch": run["mean_batch"], "requests_with_counted_failures": r["requests_with_counted_failures"]}
+            "mean_resident": run["mean_resident"], "requests_with_counted_failures": r["requests_with_counted_failures"]}
 
 
 def mixed_accuracy(R, P, grid, V, opac, dts, U64_final):

@@ -299,6 +299,34 @@ rrmhd_status rrmhd_max_speed_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* c
 rrmhd_status rrmhd_step_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, double* const* U,
                               const double* dt_host, const rrmhd_opacities* const* opac);
 
+/* Up to nsteps steps of each simulation's own CFL loop, run on the device
+ * with no host synchronization (Sec. 3.1 time stepping with the CFL rule of
+ * rrmhd_max_speed): per step, the signal speeds; then, for each simulation s
+ * not at its end, dt = min(cfl_dx[s] / s_max, t_end[s] - t), t += dt, n += 1,
+ * and the IMEX step with that dt. Simulation s is at its end once
+ * n >= max_steps[s] when max_steps[s] >= 0, else once
+ * t >= t_end[s] (1 - 1e-14); from then on it is not stepped (its blocks of
+ * every launch return at once). Each simulation's time steps and states are
+ * those of the host loop rrmhd_max_speed_batch + rrmhd_step_batch with the
+ * same rule, bit for bit, whatever else is in the batch.
+ *   cfl_dx:    [nsim] host, CFL number times the smallest cell width, > 0.
+ *   t_end:     [nsim] host, end time (>= 0; may be +inf for a step-count
+ *              request).
+ *   max_steps: [nsim] host, steps to take, or < 0 for an end-time request.
+ *   t, n:      [nsim] host, the time and steps reached so far (uploaded).
+ * A time step that is not finite and >= 0 is counted as non-finite in that
+ * simulation's report and its time set to +inf (it takes no further step).
+ * Enqueued on the batch's stream; rrmhd_batch_clock returns the clock after
+ * it. RRMHD_E_INVALID for bad sizes or values (nothing enqueued). */
+rrmhd_status rrmhd_advance_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, double* const* U,
+                                 const rrmhd_opacities* const* opac, const double* cfl_dx, const double* t_end,
+                                 const long long* max_steps, const double* t, const long long* n, int nsteps);
+
+/* Wait for the last rrmhd_advance_batch of this batch and copy its
+ * simulations' clock to t[nsim], n[nsim] (host). nsim must be that call's.
+ * Synchronizes with that call only (an event), not with later work. */
+rrmhd_status rrmhd_batch_clock(rrmhd_batch* b, int nsim, double* t, long long* n);
+
 void rrmhd_batch_destroy(rrmhd_batch* b);
 
 /* Release the context (not the workspace, which the caller owns). */

@@ -137,7 +137,7 @@ __device__ __forceinline__ void report_add(DevReport* rep, unsigned int* blkmax,
                                            unsigned long long f_pvm, unsigned long long f_imp,
                                            unsigned long long f_nf, unsigned long long bad_cell,
                                            unsigned int c2p_it, unsigned int imp_it,
-                                           unsigned long long f_floor = 0) {
+                                           unsigned long long f_floor = 0, bool shared_slot = false) {
   __shared__ unsigned int red_it[2][kBlock / kWave];
   const unsigned long long s_c2p = wave_sum_u64(f_c2p);
   const unsigned long long s_pvm = wave_sum_u64(f_pvm);
@@ -168,8 +168,14 @@ __device__ __forceinline__ void report_add(DevReport* rep, unsigned int* blkmax,
       b = (red_it[1][w] > b) ? red_it[1][w] : b;
     }
     unsigned int* slot = blkmax + 2 * (size_t)slot_block;
-    if (a > slot[0]) slot[0] = a;
-    if (b > slot[1]) slot[1] = b;
+    if (shared_slot) {
+      // a slot that another block may update at the same time
+      if (a) atomicMax(&slot[0], a);
+      if (b) atomicMax(&slot[1], b);
+    } else {
+      if (a > slot[0]) slot[0] = a;
+      if (b > slot[1]) slot[1] = b;
+    }
   }
 }
 
@@ -952,7 +958,8 @@ k_update(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* 
 __device__ __forceinline__ void newton_blocks(long long bi, long long nb, const GridDev& G, const StageArgs& A,
                                               const Opac& op, const Phys& K, DevReport* rep, unsigned int* blkmax,
                                               const long long* __restrict__ worklist,
-                                              const unsigned long long* wcount) {
+                                              const unsigned long long* wcount, long long slot,
+                                              bool shared_slot = false) {
   const long long ncell = G.N;
   const double* xs = (const double*)(worklist + ncell);
   const unsigned long long n = *wcount;
@@ -1012,14 +1019,14 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, const 
       if (A.nextp) spd = rr::dmax(spd, next_prims(G, A, op, K, c, Un, fc2p, bad, cits));
     }
   }
-  report_add(rep, blkmax, bi, fc2p, 0, fimp, fnf, bad, cits, its);
+  report_add(rep, blkmax, slot, fc2p, 0, fimp, fnf, bad, cits, its, 0, shared_slot);
   if (A.speed) block_max_to(spd, A.partial, A.npart + bi);
 }
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_NEWTON_WAVES)))
 k_newton(GridDev G, StageArgs A, Opac op, Phys K, DevReport* rep, unsigned int* blkmax,
          const long long* __restrict__ worklist, const unsigned long long* wcount) {
-  newton_blocks(blockIdx.x, gridDim.x, G, A, op, K, rep, blkmax, worklist, wcount);
+  newton_blocks(blockIdx.x, gridDim.x, G, A, op, K, rep, blkmax, worklist, wcount, blockIdx.x);
 }
 
 // Per-block maximum of the cell signal speeds -> partial[lb].
@@ -1098,6 +1105,7 @@ struct SimDesc {
   unsigned int* blkmax;
   double* partial;
   long long npartial;
+  long long nblkmax;  // report slots of the simulation's per-block maxima
   double dt;
   int mixed;
   int solver;  // RRMHD_SOLVER_*: which face-kernel launch of a tick takes this simulation
@@ -1113,6 +1121,26 @@ __device__ __forceinline__ int find_sim(const long long* __restrict__ off, int n
   }
   return lo;
 }
+
+// Per-simulation clock of the batched advance (rrmhd_advance_batch), [nsim]
+// arrays on the device. t == nullptr: no clock (the per-call entry points).
+struct BatchClock {
+  double* t;              // time reached
+  long long* n;           // steps taken
+  const double* tend;     // end time (+inf for a step-count request)
+  const long long* nmax;  // steps to take (< 0: an end-time request)
+  const double* cfl_dx;   // CFL number times the smallest cell width
+};
+
+// Simulation s has reached its end: n >= nmax for a step-count request,
+// t >= t_end (1 - 1e-14) otherwise (the same test as the serving loop's).
+__device__ __forceinline__ bool clock_at_end(const BatchClock& C, int s) {
+  return (C.nmax[s] >= 0) ? (C.n[s] >= C.nmax[s]) : (C.t[s] >= C.tend[s] * (1.0 - 1e-14));
+}
+
+// Blocks of a step launch skip a simulation whose time step in `gate` is 0
+// (one at its end in rrmhd_advance_batch); gate == nullptr: none skipped.
+__device__ __forceinline__ bool step_gated(const double* gate, int s) { return gate && !(gate[s] > 0.0); }
 
 __device__ __forceinline__ StageArgs stage_args(const SimDesc& D, double dt, int stage, int last, double a0,
                                                 double a1, double c) {
@@ -1148,9 +1176,10 @@ __device__ __forceinline__ StageArgs stage_args(const SimDesc& D, double dt, int
 }
 
 __global__ void __launch_bounds__(kBlock) k_prims_b(const SimDesc* __restrict__ T, const long long* __restrict__ off,
-                                                    int nsim, int stage) {
+                                                    int nsim, int stage, const double* gate) {
   const long long* o = off + OFF_PRIMS * (nsim + 1);
   const int s = find_sim(o, nsim, blockIdx.x);
+  if (step_gated(gate, s)) return;
   const SimDesc& D = T[s];
   const double* Us = (stage == 0) ? D.U : D.Us;
   const long long ss = (stage == 0) ? D.vs : D.ns;
@@ -1163,9 +1192,10 @@ __global__ void __launch_bounds__(kBlock) k_prims_b(const SimDesc* __restrict__ 
 // another flux returns at once.
 template <int SOLVER>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
-k_faces_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, int nsim) {
+k_faces_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, int nsim, const double* gate) {
   const long long* o = off + OFF_FACES * (nsim + 1);
   const int s = find_sim(o, nsim, blockIdx.x);
+  if (step_gated(gate, s)) return;
   const SimDesc& D = T[s];
   if (D.solver != SOLVER) return;
   // the work-list counter of this simulation's update pass that follows
@@ -1176,37 +1206,114 @@ k_faces_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, int 
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_update_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, const double* __restrict__ dts, int nsim,
-           int stage, int last, double a0, double a1, double c) {
+           int stage, int last, double a0, double a1, double c, const double* gate) {
   const long long* o = off + OFF_CELLS * (nsim + 1);
   const int s = find_sim(o, nsim, blockIdx.x);
+  if (step_gated(gate, s)) return;
   const SimDesc& D = T[s];
   const StageArgs A = stage_args(D, dts[s], stage, last, a0, a1, c);
   if (D.mixed) update_block<float>(blockIdx.x - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
   else update_block<double>(blockIdx.x - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
 }
 
+// Work-list blocks of a batch's Newton pass: simulation s has
+// ceil(wcount_s / (kBlock/4)) of them (none when gated); vprefix[s] is the
+// number before s, vprefix[nsim] the total. One block.
+__global__ void __launch_bounds__(kRedBlock) k_wprefix_b(const SimDesc* __restrict__ T, int nsim,
+                                                      long long* __restrict__ vprefix, const double* gate) {
+  __shared__ long long wsum[kRedBlock / kWave];
+  __shared__ long long carry;
+  constexpr long long kq = kBlock / 4;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nsim; base += kRedBlock) {
+    const int s = base + (int)threadIdx.x;
+    long long v = 0;
+    if (s < nsim && !step_gated(gate, s)) v = ((long long)*T[s].wcount + kq - 1) / kq;
+    // inclusive scan within the wave, then across the waves
+    long long x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const long long y = __shfl_up(x, o, kWave);
+      if ((int)(threadIdx.x & (kWave - 1)) >= o) x += y;
+    }
+    if ((threadIdx.x & (kWave - 1)) == kWave - 1) wsum[threadIdx.x / kWave] = x;
+    __syncthreads();
+    long long before = carry;
+    for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) before += wsum[w];
+    if (s < nsim) vprefix[s] = before + x - v;
+    __syncthreads();
+    if (threadIdx.x == kRedBlock - 1) carry = before + x;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) vprefix[nsim] = carry;
+}
+
+// The batch's Newton pass, balanced over the batch: the grid walks the
+// work-list blocks of all simulations (vprefix), each taking kBlock/4 entries
+// of one simulation, so a simulation with a long list gets as many blocks as
+// it needs whatever its size. Report maxima go to slot vb mod nblkmax of the
+// simulation (atomic: several blocks may share a slot).
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_NEWTON_WAVES)))
-k_newton_b(const SimDesc* __restrict__ T, const long long* __restrict__ off,
-                                                     const double* __restrict__ dts, int nsim, int stage, int last,
-                                                     double a0, double a1, double c) {
-  const long long* o = off + OFF_NEWTON * (nsim + 1);
-  const int s = find_sim(o, nsim, blockIdx.x);
-  const SimDesc& D = T[s];
-  const StageArgs A = stage_args(D, dts[s], stage, last, a0, a1, c);
-  newton_blocks(blockIdx.x - o[s], o[s + 1] - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
+k_newton_b(const SimDesc* __restrict__ T, const long long* __restrict__ vprefix, const double* __restrict__ dts,
+           int nsim, int stage, int last, double a0, double a1, double c) {
+  const long long total = vprefix[nsim];
+  for (long long v = blockIdx.x; v < total; v += gridDim.x) {
+    int lo = 0, hi = nsim;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (vprefix[mid] <= v) lo = mid; else hi = mid;
+    }
+    const SimDesc& D = T[lo];
+    const StageArgs A = stage_args(D, dts[lo], stage, last, a0, a1, c);
+    const long long vb = v - vprefix[lo];
+    newton_blocks(vb, vprefix[lo + 1] - vprefix[lo], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount,
+                  vb % D.nblkmax, true);
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_speed_b(const SimDesc* __restrict__ T, const long long* __restrict__ off,
-                                                    int nsim) {
+                                                    int nsim, BatchClock C) {
   const long long* o = off + OFF_CELLS * (nsim + 1);
   const int s = find_sim(o, nsim, blockIdx.x);
+  if (C.t && clock_at_end(C, s)) return;
   const SimDesc& D = T[s];
   speed_block(blockIdx.x - o[s], D.G, D.U, D.vs, D.K, D.partial, D.rep, D.blkmax);
 }
 
-__global__ void __launch_bounds__(kRedBlock) k_reduce_max_b(const SimDesc* __restrict__ T, double* __restrict__ smax) {
+__global__ void __launch_bounds__(kRedBlock) k_reduce_max_b(const SimDesc* __restrict__ T, double* __restrict__ smax,
+                                                         BatchClock C) {
+  if (C.t && clock_at_end(C, (int)blockIdx.x)) return;
   const SimDesc& D = T[blockIdx.x];
   reduce_max_block(D.partial, D.npartial, smax + blockIdx.x);
+}
+
+// Each simulation's time step of a batched advance: for one not at its end,
+// dt = min(cfl_dx / s_max, t_end - t) (the serving loop's rule), then t += dt,
+// n += 1; dts[s] = 0 for one at its end, which the step launches then skip.
+// A time step that is not finite and >= 0 is counted as non-finite and sets
+// t = +inf (an end-time request then ends; a step-count request stops
+// advancing).
+__global__ void __launch_bounds__(kRedBlock) k_dt_b(const SimDesc* __restrict__ T, const double* __restrict__ smax,
+                                                 double* __restrict__ dts, int nsim, BatchClock C) {
+  for (int s = threadIdx.x; s < nsim; s += kRedBlock) {
+    if (clock_at_end(C, s)) {
+      dts[s] = 0.0;
+      continue;
+    }
+    const double a = C.cfl_dx[s] / smax[s];
+    const double b = C.tend[s] - C.t[s];
+    const double dt = (b < a) ? b : a;
+    if (!(dt >= 0.0) || !(dt < 1e300)) {
+      dts[s] = 0.0;
+      C.t[s] = HUGE_VAL;
+      atomicAdd(&T[s].rep->nonfinite, 1ull);
+      continue;
+    }
+    dts[s] = dt;
+    C.t[s] = C.t[s] + dt;
+    C.n[s] = C.n[s] + 1;
+  }
 }
 
 // Clear the counters and the per-block iteration maxima.
@@ -1594,15 +1701,6 @@ rrmhd_status stage_fluxes(rrmhd_ctx* c, const rrmhd_grid* g, const double* Us, l
   return RRMHD_OK;
 }
 
-// Blocks of the Newton pass per simulation (kBlock/4 cells per block): about one per
-// 4 cell blocks.
-long long newton_blocks_for(long long ncell_blocks, unsigned int cap) {
-  long long b = ncell_blocks / 4;
-  if (b < 1) b = 1;
-  if (b > (long long)cap) b = cap;
-  return b;
-}
-
 SimDesc make_desc(rrmhd_ctx* c, double* U, const rrmhd_opacities* opac) {
   SimDesc D;
   std::memset(&D, 0, sizeof(D));
@@ -1636,6 +1734,7 @@ SimDesc make_desc(rrmhd_ctx* c, double* U, const rrmhd_opacities* opac) {
   D.blkmax = c->blkmax;
   D.partial = c->partial;
   D.npartial = L.npartial;
+  D.nblkmax = L.nblkmax;
   D.mixed = (c->par.precision == RRMHD_MIXED) ? 1 : 0;
   D.solver = c->par.solver;
   return D;
@@ -1650,10 +1749,21 @@ struct rrmhd_batch {
   long long* off;       // device [OFF_KINDS][max_sims + 1]
   double* smax;         // device [max_sims]
   double* dts;          // device [max_sims]: each simulation's time step
-  void* host[2];        // pinned staging: table + offsets + time steps
+  long long* vprefix;   // device [max_sims + 1]: work-list blocks before each simulation
+  // device [max_sims] each: the clock of rrmhd_advance_batch (t, n, t_end,
+  // step count, cfl * dx_min)
+  double* ct;
+  long long* cn;
+  double* ctend;
+  long long* cnmax;
+  double* ccfl;
+  void* host[2];        // pinned staging: table + offsets + time steps + clock
   hipEvent_t ev[2];
   int cur;
   double* hsmax;        // pinned [max_sims]
+  double* hclock;       // pinned [2][max_sims]: (t, n) after the last advance
+  hipEvent_t ev_clock;  // recorded after the last advance's clock copy
+  int clock_n;          // simulations of the last advance (0: none yet)
   unsigned int newton_cap;
   // The descriptor table on the device describes these simulations (same
   // contexts, states and, when built by a step, opacities): a call with the
@@ -1673,6 +1783,20 @@ namespace {
 size_t batch_table_bytes(int m) { return align256(sizeof(SimDesc) * (size_t)m); }
 size_t batch_off_bytes(int m) { return align256(sizeof(long long) * OFF_KINDS * (size_t)(m + 1)); }
 size_t batch_dt_bytes(int m) { return align256(sizeof(double) * (size_t)m); }
+// clock planes: t, n, t_end, step count, cfl * dx_min
+constexpr int kClockPlanes = 5;
+size_t batch_staging_bytes(int m) {
+  return batch_table_bytes(m) + batch_off_bytes(m) + (1 + kClockPlanes) * batch_dt_bytes(m);
+}
+
+// Host values of a batched advance's clock, uploaded with the table.
+struct ClockIn {
+  const double* t;
+  const long long* n;
+  const double* tend;
+  const long long* nmax;
+  const double* cfl_dx;
+};
 
 bool same_opac(const rrmhd_opacities* a, const rrmhd_opacities& b) {
   return a->kappa == b.kappa && a->sigma == b.sigma && a->kappa0 == b.kappa0 && a->sigma0 == b.sigma0;
@@ -1681,7 +1805,8 @@ bool same_opac(const rrmhd_opacities* a, const rrmhd_opacities& b) {
 // Fill a staging buffer with the batch's descriptors and block offsets and
 // copy it to the device (enqueued). Returns total blocks per kind in tot[].
 rrmhd_status batch_upload(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, double* const* U,
-                          const double* dt, const rrmhd_opacities* const* opac, long long tot[OFF_KINDS]) {
+                          const double* dt, const rrmhd_opacities* const* opac, long long tot[OFF_KINDS],
+                          const ClockIn* clock = nullptr) {
   // Is the device table already that of this list?
   bool same = b->cached_n == nsim && (opac == nullptr || b->cached_with_opac);
   for (int s = 0; s < nsim && same; ++s) {
@@ -1706,7 +1831,7 @@ rrmhd_status batch_upload(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, doubl
       const Layout& L = c->L;
       const long long nbc = nblocks(L.N);
       const long long nb[OFF_KINDS] = {(long long)nblocks(L.N + L.nt), L.nb_faces[0] + L.nb_faces[1] + L.nb_faces[2],
-                                       nbc, newton_blocks_for(nbc, b->newton_cap)};
+                                       nbc, (L.N + kBlock / 4 - 1) / (kBlock / 4)};
       for (int i = 0; i < OFF_KINDS; ++i) {
         tot[i] += nb[i];
         off[i * (nsim + 1) + s + 1] = tot[i];
@@ -1726,6 +1851,8 @@ rrmhd_status batch_upload(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, doubl
       b->cached_has_op[s] = o ? 1 : 0;
       if (o) b->cached_op[s] = *o;
     }
+    // the Newton launch: a grid walking every simulation's work-list blocks
+    if (tot[OFF_NEWTON] > (long long)b->newton_cap) tot[OFF_NEWTON] = b->newton_cap;
     for (int i = 0; i < OFF_KINDS; ++i) b->cached_tot[i] = tot[i];
   } else {
     for (int i = 0; i < OFF_KINDS; ++i) tot[i] = b->cached_tot[i];
@@ -1735,6 +1862,17 @@ rrmhd_status batch_upload(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, doubl
     std::memcpy(hd, dt, sizeof(double) * nsim);
     if (hipMemcpyAsync(b->dts, hd, sizeof(double) * nsim, hipMemcpyHostToDevice, b->stream) != hipSuccess)
       return RRMHD_E_DEVICE;
+  }
+  if (clock) {
+    char* hc = hk + batch_table_bytes(b->max_sims) + batch_off_bytes(b->max_sims) + batch_dt_bytes(b->max_sims);
+    const size_t pb = batch_dt_bytes(b->max_sims);
+    const void* src[kClockPlanes] = {clock->t, clock->n, clock->tend, clock->nmax, clock->cfl_dx};
+    void* dst[kClockPlanes] = {b->ct, b->cn, b->ctend, b->cnmax, b->ccfl};
+    for (int i = 0; i < kClockPlanes; ++i) {
+      std::memcpy(hc + i * pb, src[i], 8 * (size_t)nsim);
+      if (hipMemcpyAsync(dst[i], hc + i * pb, 8 * (size_t)nsim, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return RRMHD_E_DEVICE;
+    }
   }
   if (hipEventRecord(b->ev[k], b->stream) != hipSuccess) return RRMHD_E_DEVICE;
   return RRMHD_OK;
@@ -1748,6 +1886,62 @@ rrmhd_status batch_check(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, const 
     if (ctx[s]->par.ct) return RRMHD_E_INVALID;  // constrained transport: single-simulation entry points only
     for (int t = 0; t < s; ++t)
       if (ctx[t] == ctx[s]) return RRMHD_E_INVALID;  // each context's workspace is used once per launch
+  }
+  return RRMHD_OK;
+}
+
+
+// Signal-speed passes of a batch into b->smax (simulations at the end of
+// their clock skipped when C.t is set).
+rrmhd_status batch_speed_launches(rrmhd_batch* b, int nsim, const long long tot[OFF_KINDS], const BatchClock& C) {
+  k_speed_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, C);
+  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  k_reduce_max_b<<<(unsigned int)nsim, kRedBlock, 0, b->stream>>>(b->table, b->smax, C);
+  return launch_ok();
+}
+
+// The stages of one IMEX step of a batch with the time steps in b->dts
+// (simulations whose gate entry is 0 skipped when gate is set).
+rrmhd_status batch_step_launches(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, const long long tot[OFF_KINDS],
+                                 const double* gate) {
+  double co[3][3];
+  int ns;
+  if (ctx[0]->par.rk_order == 3) {
+    const double t[3][3] = {{1.0, 0.0, 1.0}, {0.75, 0.25, 0.25}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
+    std::memcpy(co, t, sizeof(t));
+    ns = 3;
+  } else {
+    const double t[3][3] = {{1.0, 0.0, 1.0}, {0.5, 0.5, 0.5}, {0.0, 0.0, 0.0}};
+    std::memcpy(co, t, sizeof(t));
+    ns = 2;
+  }
+  for (int s = 0; s < ns; ++s) {
+    const int last = (s == ns - 1) ? 1 : 0;
+    // later stages get their primitives from the passes that finish each cell
+    if (s == 0) {
+      k_prims_b<<<(unsigned int)tot[OFF_PRIMS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s, gate);
+      if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    }
+    bool has[3] = {false, false, false};
+    for (int t = 0; t < nsim; ++t) has[ctx[t]->par.solver] = true;
+    if (has[RRMHD_SOLVER_PVM])
+      k_faces_b<RRMHD_SOLVER_PVM><<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off, nsim,
+                                                                                     gate);
+    if (has[RRMHD_SOLVER_HLL])
+      k_faces_b<RRMHD_SOLVER_HLL><<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off, nsim,
+                                                                                     gate);
+    if (has[RRMHD_SOLVER_PVM_JVP])
+      k_faces_b<RRMHD_SOLVER_PVM_JVP><<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off,
+                                                                                         nsim, gate);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    k_update_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, b->dts, nsim, s, last,
+                                                                       co[s][0], co[s][1], co[s][2], gate);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    k_wprefix_b<<<1, kRedBlock, 0, b->stream>>>(b->table, nsim, b->vprefix, gate);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    k_newton_b<<<(unsigned int)tot[OFF_NEWTON], kBlock, 0, b->stream>>>(b->table, b->vprefix, b->dts, nsim, s, last,
+                                                                        co[s][0], co[s][1], co[s][2]);
+    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   }
   return RRMHD_OK;
 }
@@ -2191,7 +2385,8 @@ void rrmhd_destroy(rrmhd_ctx* c) {
 
 size_t rrmhd_batch_workspace_bytes(int max_sims) {
   if (max_sims < 1 || max_sims > 65536) return 0;
-  return batch_table_bytes(max_sims) + batch_off_bytes(max_sims) + 2 * batch_dt_bytes(max_sims);
+  return batch_table_bytes(max_sims) + batch_off_bytes(max_sims) + (2 + kClockPlanes) * batch_dt_bytes(max_sims) +
+         batch_dt_bytes(max_sims + 1);
 }
 
 rrmhd_status rrmhd_batch_init(rrmhd_batch** out, int max_sims, void* workspace, size_t ws_bytes, void* hip_stream) {
@@ -2209,7 +2404,18 @@ rrmhd_status rrmhd_batch_init(rrmhd_batch** out, int max_sims, void* workspace, 
   b->off = (long long*)(w + batch_table_bytes(max_sims));
   b->smax = (double*)(w + batch_table_bytes(max_sims) + batch_off_bytes(max_sims));
   b->dts = (double*)(w + batch_table_bytes(max_sims) + batch_off_bytes(max_sims) + batch_dt_bytes(max_sims));
-  const size_t hb = batch_table_bytes(max_sims) + batch_off_bytes(max_sims) + batch_dt_bytes(max_sims);
+  {
+    char* cw = w + batch_table_bytes(max_sims) + batch_off_bytes(max_sims) + 2 * batch_dt_bytes(max_sims);
+    const size_t pb = batch_dt_bytes(max_sims);
+    b->ct = (double*)cw;
+    b->cn = (long long*)(cw + pb);
+    b->ctend = (double*)(cw + 2 * pb);
+    b->cnmax = (long long*)(cw + 3 * pb);
+    b->ccfl = (double*)(cw + 4 * pb);
+    b->vprefix = (long long*)(cw + 5 * pb);
+  }
+  b->clock_n = 0;
+  const size_t hb = batch_staging_bytes(max_sims);
   bool ok = true;
   try {
     b->cached_serial.assign(max_sims, 0);
@@ -2224,6 +2430,8 @@ rrmhd_status rrmhd_batch_init(rrmhd_batch** out, int max_sims, void* workspace, 
     ok = ok && hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming) == hipSuccess;
   }
   ok = ok && hipHostMalloc((void**)&b->hsmax, sizeof(double) * max_sims, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&b->hclock, 2 * sizeof(double) * max_sims, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&b->ev_clock, hipEventDisableTiming) == hipSuccess;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
@@ -2245,10 +2453,8 @@ rrmhd_status rrmhd_max_speed_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* c
   long long tot[OFF_KINDS];
   st = batch_upload(b, nsim, ctx, (double* const*)U, nullptr, nullptr, tot);
   if (st != RRMHD_OK) return st;
-  k_speed_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, nsim);
-  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-  k_reduce_max_b<<<(unsigned int)nsim, kRedBlock, 0, b->stream>>>(b->table, b->smax);
-  if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+  st = batch_speed_launches(b, nsim, tot, BatchClock{});
+  if (st != RRMHD_OK) return st;
   if (hipMemcpyAsync(b->hsmax, b->smax, sizeof(double) * nsim, hipMemcpyDeviceToHost, b->stream) != hipSuccess)
     return RRMHD_E_DEVICE;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return RRMHD_E_DEVICE;
@@ -2266,41 +2472,47 @@ rrmhd_status rrmhd_step_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, d
   long long tot[OFF_KINDS];
   st = batch_upload(b, nsim, ctx, U, dt_host, opac, tot);
   if (st != RRMHD_OK) return st;
-  double co[3][3];
-  int ns;
-  if (ctx[0]->par.rk_order == 3) {
-    const double t[3][3] = {{1.0, 0.0, 1.0}, {0.75, 0.25, 0.25}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
-    std::memcpy(co, t, sizeof(t));
-    ns = 3;
-  } else {
-    const double t[3][3] = {{1.0, 0.0, 1.0}, {0.5, 0.5, 0.5}, {0.0, 0.0, 0.0}};
-    std::memcpy(co, t, sizeof(t));
-    ns = 2;
+  return batch_step_launches(b, nsim, ctx, tot, nullptr);
+}
+
+rrmhd_status rrmhd_advance_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, double* const* U,
+                                 const rrmhd_opacities* const* opac, const double* cfl_dx, const double* t_end,
+                                 const long long* max_steps, const double* t, const long long* n, int nsteps) {
+  rrmhd_status st = batch_check(b, nsim, ctx, (const void* const*)U);
+  if (st != RRMHD_OK) return st;
+  if (!cfl_dx || !t_end || !max_steps || !t || !n || nsteps < 0) return RRMHD_E_INVALID;
+  for (int s = 0; s < nsim; ++s) {
+    if (!(cfl_dx[s] > 0.0) || !(cfl_dx[s] < 1e300)) return RRMHD_E_INVALID;
+    if (!(t_end[s] >= 0.0) || !(t[s] >= 0.0) || !(t[s] < 1e300) || n[s] < 0) return RRMHD_E_INVALID;
+    if (max_steps[s] < 0 && !(t_end[s] < 1e300)) return RRMHD_E_INVALID;  // neither end given
   }
-  for (int s = 0; s < ns; ++s) {
-    const int last = (s == ns - 1) ? 1 : 0;
-    // later stages get their primitives from the passes that finish each cell
-    if (s == 0) {
-      k_prims_b<<<(unsigned int)tot[OFF_PRIMS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s);
-      if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-    }
-    bool has[3] = {false, false, false};
-    for (int t = 0; t < nsim; ++t) has[ctx[t]->par.solver] = true;
-    if (has[RRMHD_SOLVER_PVM])
-      k_faces_b<RRMHD_SOLVER_PVM><<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off, nsim);
-    if (has[RRMHD_SOLVER_HLL])
-      k_faces_b<RRMHD_SOLVER_HLL><<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off, nsim);
-    if (has[RRMHD_SOLVER_PVM_JVP])
-      k_faces_b<RRMHD_SOLVER_PVM_JVP><<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off,
-                                                                                         nsim);
+  long long tot[OFF_KINDS];
+  const ClockIn ci = {t, n, t_end, max_steps, cfl_dx};
+  st = batch_upload(b, nsim, ctx, U, nullptr, opac, tot, &ci);
+  if (st != RRMHD_OK) return st;
+  const BatchClock C = {b->ct, b->cn, b->ctend, b->cnmax, b->ccfl};
+  for (int k = 0; k < nsteps; ++k) {
+    st = batch_speed_launches(b, nsim, tot, C);
+    if (st != RRMHD_OK) return st;
+    k_dt_b<<<1, kRedBlock, 0, b->stream>>>(b->table, b->smax, b->dts, nsim, C);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-    k_update_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, b->dts, nsim, s, last,
-                                                                       co[s][0], co[s][1], co[s][2]);
-    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-    k_newton_b<<<(unsigned int)tot[OFF_NEWTON], kBlock, 0, b->stream>>>(b->table, b->off, b->dts, nsim, s, last,
-                                                                        co[s][0], co[s][1], co[s][2]);
-    if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    st = batch_step_launches(b, nsim, ctx, tot, b->dts);
+    if (st != RRMHD_OK) return st;
   }
+  if (hipMemcpyAsync(b->hclock, b->ct, sizeof(double) * nsim, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+      hipMemcpyAsync(b->hclock + b->max_sims, b->cn, sizeof(long long) * nsim, hipMemcpyDeviceToHost, b->stream) !=
+          hipSuccess ||
+      hipEventRecord(b->ev_clock, b->stream) != hipSuccess)
+    return RRMHD_E_DEVICE;
+  b->clock_n = nsim;
+  return RRMHD_OK;
+}
+
+rrmhd_status rrmhd_batch_clock(rrmhd_batch* b, int nsim, double* t, long long* n) {
+  if (!b || !t || !n || nsim < 1 || nsim != b->clock_n) return RRMHD_E_INVALID;
+  if (hipEventSynchronize(b->ev_clock) != hipSuccess) return RRMHD_E_DEVICE;
+  std::memcpy(t, b->hclock, sizeof(double) * nsim);
+  std::memcpy(n, b->hclock + b->max_sims, sizeof(long long) * nsim);
   return RRMHD_OK;
 }
 
@@ -2313,6 +2525,8 @@ void rrmhd_batch_destroy(rrmhd_batch* b) {
     if (b->ev[k]) (void)hipEventDestroy(b->ev[k]);
   }
   if (b->hsmax) (void)hipHostFree(b->hsmax);
+  if (b->hclock) (void)hipHostFree(b->hclock);
+  if (b->ev_clock) (void)hipEventDestroy(b->ev_clock);
   delete b;
 }
 

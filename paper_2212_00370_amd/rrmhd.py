@@ -82,6 +82,8 @@ SIGNATURES = {
     "rrmhd_batch_init": ([_vp, C.c_int, _vp, C.c_size_t, _vp], C.c_int),
     "rrmhd_max_speed_batch": ([_vp, C.c_int, _vp, _vp, _vp], C.c_int),
     "rrmhd_step_batch": ([_vp, C.c_int, _vp, _vp, _vp, _vp], C.c_int),
+    "rrmhd_advance_batch": ([_vp, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int], C.c_int),
+    "rrmhd_batch_clock": ([_vp, C.c_int, _vp, _vp], C.c_int),
     "rrmhd_batch_destroy": ([_vp], None),
     "rrmhd_destroy": ([_vp], None),
     "rrmhd_strerror": ([C.c_int], C.c_char_p),
@@ -333,6 +335,30 @@ class Batch:
         np.ctypeslib.as_array(self._dv)[:] = dts
         _check(_lib.rrmhd_step_batch(self.handle, self._n, self._cv, self._uv, self._dv, self._ov),
                "rrmhd_step_batch")
+
+    def advance_active(self, cfl_dx, t_end, max_steps, t, n, nsteps: int) -> None:
+        """Enqueue up to `nsteps` steps of each simulation of the active set
+        with its own CFL time step on the device (rrmhd_advance_batch).
+        cfl_dx, t_end, t: float64 arrays; max_steps, n: int64 arrays (< 0
+        max_steps: run to t_end). Read the clock with clock_active()."""
+        import numpy as np
+        arrs = [np.ascontiguousarray(a, dtype=dt) for a, dt in
+                ((cfl_dx, np.float64), (t_end, np.float64), (max_steps, np.int64), (t, np.float64), (n, np.int64))]
+        for a in arrs:
+            if a.shape != (self._n,):
+                raise RRMHDError("advance_active: one value per simulation of the active set")
+        self._clock_keep = arrs
+        _check(_lib.rrmhd_advance_batch(self.handle, self._n, self._cv, self._uv, self._ov,
+                                        *[a.ctypes.data for a in arrs], int(nsteps)), "rrmhd_advance_batch")
+
+    def clock_active(self):
+        """(t, n) of the active set after the last advance_active (waits for
+        it)."""
+        import numpy as np
+        t = np.empty(self._n, np.float64)
+        n = np.empty(self._n, np.int64)
+        _check(_lib.rrmhd_batch_clock(self.handle, self._n, t.ctypes.data, n.ctypes.data), "rrmhd_batch_clock")
+        return t, n
 
     def close(self):
         if self.handle is not None:

@@ -63,7 +63,7 @@ def test_server_alone_vs_mix_and_budget(mods):
     torch, R, S = mods
     mix = I.serving_mix(11, 10, n1d=(64, 400), n2d=(16, 48), t_end_1d=0.02, steps_2d=(3, 8))
     reqs = [S.Request(rid=i, problem=m["problem"], precision=R.MIXED if m["mixed"] else R.FP64,
-                      t_end=m["t_end"], steps=m["steps"], arrival=0.002 * i) for i, m in enumerate(mix)]
+                      t_end=m["t_end"], steps=m["steps"], arrival=0.0002 * i) for i, m in enumerate(mix)]
     fps = [S.footprint_bytes(r.problem, r.precision) for r in reqs]
     budget = int(2.5 * max(fps))          # forces queueing: at most a few resident at once
     srv = S.Server(budget, max_sims=8)
@@ -98,3 +98,68 @@ def test_failing_request_is_isolated(mods):
         ra = alone.run([reqs[rid]])[0]
         alone.close()
         assert np.array_equal(ra.U, res[rid].U)
+
+
+def test_advance_batch_equals_host_loop(mods):
+    """rrmhd_advance_batch (time steps formed on the device, simulations at
+    their end skipped) gives each simulation the states and clock of the host
+    loop rrmhd_max_speed_batch + rrmhd_step_batch with the same rule, bit for
+    bit, whatever the chunking of the device steps."""
+    torch, R, S = mods
+    cases = problems()
+    # end-time requests end after different numbers of steps; two step-count ones
+    t_end = np.array([0.01, 0.004, np.inf, 0.02, 0.003])
+    max_steps = np.array([-1, -1, 6, -1, -1], dtype=np.int64)
+    host = [make(torch, R, P, prec) for P, prec in cases]
+    dev = [make(torch, R, P, prec) for P, prec in cases]
+    cfl_dx = np.array([P.cfl * min(P.dx) for P, _ in cases])
+
+    def at_end(t, n):
+        return np.where(max_steps >= 0, n >= max_steps, t >= t_end * (1.0 - 1e-14))
+
+    B1 = R.Batch(8)
+    t = np.zeros(len(cases))
+    n = np.zeros(len(cases), dtype=np.int64)
+    while not at_end(t, n).all():
+        idx = np.where(~at_end(t, n))[0]
+        sm = np.array(B1.max_speed([host[i][0] for i in idx], [host[i][1] for i in idx]))
+        dts = np.minimum(cfl_dx[idx] / sm, t_end[idx] - t[idx])
+        B1.step([host[i][0] for i in idx], [host[i][1] for i in idx], list(dts), [host[i][2] for i in idx])
+        t[idx] += dts
+        n[idx] += 1
+    torch.cuda.synchronize()
+    assert n.max() > n.min() + 2          # the simulations end at different steps
+    B2 = R.Batch(8)
+    B2.set_active([c[0] for c in dev], [c[1] for c in dev], [c[2] for c in dev])
+    td = np.zeros(len(cases))
+    nd = np.zeros(len(cases), dtype=np.int64)
+    for chunk in (3, 1, 5, 2, 1000):
+        B2.advance_active(cfl_dx, t_end, max_steps, td, nd, chunk)
+        td, nd = B2.clock_active()
+    assert np.array_equal(nd, n)
+    assert np.array_equal(td, t)
+    for (s1, U1, _), (s2, U2, _) in zip(host, dev):
+        assert torch.equal(U1, U2)
+    for c in host + dev:
+        rep = c[0].report()
+        assert rep["c2p_fail"] == 0 and rep["imp_fail"] == 0 and rep["nonfinite"] == 0
+        c[0].close()
+    B1.close()
+    B2.close()
+
+
+def test_advance_batch_rejects_bad_clock(mods):
+    torch, R, S = mods
+    P, prec = problems()[0]
+    s, U, o = make(torch, R, P, prec)
+    B = R.Batch(2)
+    B.set_active([s], [U], [o])
+    one = np.ones(1)
+    with pytest.raises(R.RRMHDError):       # neither an end time nor a step count
+        B.advance_active(one, np.array([np.inf]), np.array([-1]), np.zeros(1), np.zeros(1, np.int64), 1)
+    with pytest.raises(R.RRMHDError):       # cfl * dx must be positive
+        B.advance_active(-one, one, np.array([-1]), np.zeros(1), np.zeros(1, np.int64), 1)
+    with pytest.raises(R.RRMHDError):       # negative step count
+        B.advance_active(one, one, np.array([-1]), np.zeros(1), np.zeros(1, np.int64), -1)
+    B.close()
+    s.close()
