@@ -670,13 +670,14 @@ def mixed_accuracy(R, P, grid, V, opac, dts, U64_final):
            "accumulation": "face fluxes binary32; flux divergence, recoveries and implicit solve binary64"}
     import numpy as np
     for name, solver in (("pvm", R.SOLVER_PVM), ("pvm_jvp", R.SOLVER_PVM_JVP), ("rad_hll", R.SOLVER_HLL)):
-        ref, Uref, _ = trajectory(solver, R.FP64)
+        ref, Uref, rep64 = trajectory(solver, R.FP64)
         if solver == R.SOLVER_PVM:
             res["fp64_host_dt_equals_timed_run"] = bool(np.array_equal(Uref, U64_final))
         mix, _, rep = trajectory(solver, R.MIXED)
         res[name] = {"L1_rho": [l1(mix[k][0], ref[k][0]) for k in marks],
                      "L1_Er": [l1(mix[k][1], ref[k][1]) for k in marks],
-                     "mixed_failures": {k: rep[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")}}
+                     "mixed_failures": {k: rep[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")},
+                     "fp64_failures": {k: rep64[k] for k in ("c2p_fail", "pvm_fallback", "imp_fail", "nonfinite")}}
         del ref, mix
         torch.cuda.empty_cache()
     return res

@@ -308,7 +308,9 @@ rrmhd_status rrmhd_step_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, d
  * t >= t_end[s] (1 - 1e-14); from then on it is not stepped (its blocks of
  * every launch return at once). Each simulation's time steps and states are
  * those of the host loop rrmhd_max_speed_batch + rrmhd_step_batch with the
- * same rule, bit for bit, whatever else is in the batch.
+ * same rule, bit for bit, whatever else is in the batch. After the first
+ * step of a call, the last stage of each step also recovers the next step's
+ * primitives and signal speeds (no separate passes for them).
  *   cfl_dx:    [nsim] host, CFL number times the smallest cell width, > 0.
  *   t_end:     [nsim] host, end time (>= 0; may be +inf for a step-count
  *              request).

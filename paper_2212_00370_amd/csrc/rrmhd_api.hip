@@ -256,6 +256,19 @@ __device__ __forceinline__ void block_max_to(double s, double* __restrict__ part
   }
 }
 
+// The block's maximum of s >= 0 (or NaN) folded into *slot by an atomic
+// maximum of the bit patterns (their order is that of the values for
+// non-negative doubles); *slot starts at +0.
+__device__ __forceinline__ void block_max_atomic(double s, double* slot) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) s = rr::dmax(s, __shfl_xor(s, o, kWave));
+  static_assert(kBlock == kWave, "one wave per block");
+  if (threadIdx.x == 0) {
+    const double w = (s == 0.0) ? 0.0 : s;  // -0 as +0
+    atomicMax((unsigned long long*)slot, (unsigned long long)__double_as_longlong(w));
+  }
+}
+
 // Largest signal speed of one cell with primitives v over the active directions.
 __device__ __forceinline__ double cell_signal_speed(const GridDev& G, const double v[NV], const Phys& K) {
   rr::Aux a;
@@ -1020,7 +1033,10 @@ __device__ __forceinline__ void newton_blocks(long long bi, long long nb, const 
     }
   }
   report_add(rep, blkmax, slot, fc2p, 0, fimp, fnf, bad, cits, its, 0, shared_slot);
-  if (A.speed) block_max_to(spd, A.partial, A.npart + bi);
+  if (A.speed) {
+    if (shared_slot) block_max_atomic(spd, A.partial + A.npart + bi % A.npart);
+    else block_max_to(spd, A.partial, A.npart + bi);
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_NEWTON_WAVES)))
@@ -1142,8 +1158,12 @@ __device__ __forceinline__ bool clock_at_end(const BatchClock& C, int s) {
 // (one at its end in rrmhd_advance_batch); gate == nullptr: none skipped.
 __device__ __forceinline__ bool step_gated(const double* gate, int s) { return gate && !(gate[s] > 0.0); }
 
+// after: the last stage also recovers the primitives of its result (the next
+// step's first stage) and the signal-speed maxima of the next step's time
+// step: update blocks into partial[0, npartial), Newton blocks into
+// partial[npartial, 2 npartial) (atomic maxima, cleared by the update pass).
 __device__ __forceinline__ StageArgs stage_args(const SimDesc& D, double dt, int stage, int last, double a0,
-                                                double a1, double c) {
+                                                double a1, double c, int after = 0) {
   StageArgs A;
   A.U0 = D.U; A.s0 = D.vs;
   A.Us = (stage == 0) ? D.U : D.Us;
@@ -1161,14 +1181,15 @@ __device__ __forceinline__ StageArgs stage_args(const SimDesc& D, double dt, int
   A.dtp = nullptr;
   A.cc = c;
   A.Zc = D.Zc;
-  // the next stage's primitives where each cell finishes (not after the last)
-  A.nextp = last ? 0 : 1;
-  A.speed = 0;
+  // the next stage's primitives where each cell finishes (after the last
+  // stage only when the step is followed by another in the same launch run)
+  A.nextp = (last && !after) ? 0 : 1;
+  A.speed = (last && after) ? 1 : 0;
   A.Vp = D.Vp;
   A.taup = D.taup;
   A.np = D.FA.np;
-  A.partial = nullptr;
-  A.npart = 0;
+  A.partial = A.speed ? D.partial : nullptr;
+  A.npart = A.speed ? D.npartial : 0;
   A.perm = nullptr;
   A.cost = nullptr;
   A.bnew = nullptr;
@@ -1206,12 +1227,14 @@ k_faces_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, int 
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_update_b(const SimDesc* __restrict__ T, const long long* __restrict__ off, const double* __restrict__ dts, int nsim,
-           int stage, int last, double a0, double a1, double c, const double* gate) {
+           int stage, int last, double a0, double a1, double c, const double* gate, int after) {
   const long long* o = off + OFF_CELLS * (nsim + 1);
   const int s = find_sim(o, nsim, blockIdx.x);
   if (step_gated(gate, s)) return;
   const SimDesc& D = T[s];
-  const StageArgs A = stage_args(D, dts[s], stage, last, a0, a1, c);
+  const StageArgs A = stage_args(D, dts[s], stage, last, a0, a1, c, after);
+  // the Newton pass's speed slot of this block, folded into atomically
+  if (A.speed && threadIdx.x == 0) A.partial[A.npart + (blockIdx.x - o[s])] = 0.0;
   if (D.mixed) update_block<float>(blockIdx.x - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
   else update_block<double>(blockIdx.x - o[s], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount);
 }
@@ -1256,7 +1279,7 @@ __global__ void __launch_bounds__(kRedBlock) k_wprefix_b(const SimDesc* __restri
 // simulation (atomic: several blocks may share a slot).
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RRMHD_NEWTON_WAVES)))
 k_newton_b(const SimDesc* __restrict__ T, const long long* __restrict__ vprefix, const double* __restrict__ dts,
-           int nsim, int stage, int last, double a0, double a1, double c) {
+           int nsim, int stage, int last, double a0, double a1, double c, int after) {
   const long long total = vprefix[nsim];
   for (long long v = blockIdx.x; v < total; v += gridDim.x) {
     int lo = 0, hi = nsim;
@@ -1265,7 +1288,7 @@ k_newton_b(const SimDesc* __restrict__ T, const long long* __restrict__ vprefix,
       if (vprefix[mid] <= v) lo = mid; else hi = mid;
     }
     const SimDesc& D = T[lo];
-    const StageArgs A = stage_args(D, dts[lo], stage, last, a0, a1, c);
+    const StageArgs A = stage_args(D, dts[lo], stage, last, a0, a1, c, after);
     const long long vb = v - vprefix[lo];
     newton_blocks(vb, vprefix[lo + 1] - vprefix[lo], D.G, A, D.op, D.K, D.rep, D.blkmax, D.work, D.wcount,
                   vb % D.nblkmax, true);
@@ -1281,11 +1304,13 @@ __global__ void __launch_bounds__(kBlock) k_speed_b(const SimDesc* __restrict__ 
   speed_block(blockIdx.x - o[s], D.G, D.U, D.vs, D.K, D.partial, D.rep, D.blkmax);
 }
 
+// slots: 1 after k_speed_b (cell blocks), 2 after a last stage with `after`
+// set (cell blocks, then the Newton pass's slots).
 __global__ void __launch_bounds__(kRedBlock) k_reduce_max_b(const SimDesc* __restrict__ T, double* __restrict__ smax,
-                                                         BatchClock C) {
+                                                         BatchClock C, int slots) {
   if (C.t && clock_at_end(C, (int)blockIdx.x)) return;
   const SimDesc& D = T[blockIdx.x];
-  reduce_max_block(D.partial, D.npartial, smax + blockIdx.x);
+  reduce_max_block(D.partial, slots * D.npartial, smax + blockIdx.x);
 }
 
 // Each simulation's time step of a batched advance: for one not at its end,
@@ -1896,14 +1921,17 @@ rrmhd_status batch_check(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, const 
 rrmhd_status batch_speed_launches(rrmhd_batch* b, int nsim, const long long tot[OFF_KINDS], const BatchClock& C) {
   k_speed_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, C);
   if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-  k_reduce_max_b<<<(unsigned int)nsim, kRedBlock, 0, b->stream>>>(b->table, b->smax, C);
+  k_reduce_max_b<<<(unsigned int)nsim, kRedBlock, 0, b->stream>>>(b->table, b->smax, C, 1);
   return launch_ok();
 }
 
 // The stages of one IMEX step of a batch with the time steps in b->dts
-// (simulations whose gate entry is 0 skipped when gate is set).
+// (simulations whose gate entry is 0 skipped when gate is set). prims0: the
+// first stage's primitives are in the workspaces (left by the previous step
+// with `after`). after: the last stage also leaves the next step's
+// primitives and signal-speed maxima (stage_args).
 rrmhd_status batch_step_launches(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx, const long long tot[OFF_KINDS],
-                                 const double* gate) {
+                                 const double* gate, bool prims0 = false, bool after = false) {
   double co[3][3];
   int ns;
   if (ctx[0]->par.rk_order == 3) {
@@ -1918,7 +1946,7 @@ rrmhd_status batch_step_launches(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx
   for (int s = 0; s < ns; ++s) {
     const int last = (s == ns - 1) ? 1 : 0;
     // later stages get their primitives from the passes that finish each cell
-    if (s == 0) {
+    if (s == 0 && !prims0) {
       k_prims_b<<<(unsigned int)tot[OFF_PRIMS], kBlock, 0, b->stream>>>(b->table, b->off, nsim, s, gate);
       if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
     }
@@ -1934,13 +1962,14 @@ rrmhd_status batch_step_launches(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx
       k_faces_b<RRMHD_SOLVER_PVM_JVP><<<(unsigned int)tot[OFF_FACES], kBlock, 0, b->stream>>>(b->table, b->off,
                                                                                          nsim, gate);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    const int aft = (last && after) ? 1 : 0;
     k_update_b<<<(unsigned int)tot[OFF_CELLS], kBlock, 0, b->stream>>>(b->table, b->off, b->dts, nsim, s, last,
-                                                                       co[s][0], co[s][1], co[s][2], gate);
+                                                                       co[s][0], co[s][1], co[s][2], gate, aft);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
     k_wprefix_b<<<1, kRedBlock, 0, b->stream>>>(b->table, nsim, b->vprefix, gate);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
     k_newton_b<<<(unsigned int)tot[OFF_NEWTON], kBlock, 0, b->stream>>>(b->table, b->vprefix, b->dts, nsim, s, last,
-                                                                        co[s][0], co[s][1], co[s][2]);
+                                                                        co[s][0], co[s][1], co[s][2], aft);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
   }
   return RRMHD_OK;
@@ -2492,11 +2521,18 @@ rrmhd_status rrmhd_advance_batch(rrmhd_batch* b, int nsim, rrmhd_ctx* const* ctx
   if (st != RRMHD_OK) return st;
   const BatchClock C = {b->ct, b->cn, b->ctend, b->cnmax, b->ccfl};
   for (int k = 0; k < nsteps; ++k) {
-    st = batch_speed_launches(b, nsim, tot, C);
-    if (st != RRMHD_OK) return st;
+    // later steps take their primitives and speed maxima from the last stage
+    // of the step before
+    if (k == 0) {
+      st = batch_speed_launches(b, nsim, tot, C);
+      if (st != RRMHD_OK) return st;
+    } else {
+      k_reduce_max_b<<<(unsigned int)nsim, kRedBlock, 0, b->stream>>>(b->table, b->smax, C, 2);
+      if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
+    }
     k_dt_b<<<1, kRedBlock, 0, b->stream>>>(b->table, b->smax, b->dts, nsim, C);
     if (launch_ok() != RRMHD_OK) return RRMHD_E_DEVICE;
-    st = batch_step_launches(b, nsim, ctx, tot, b->dts);
+    st = batch_step_launches(b, nsim, ctx, tot, b->dts, k > 0, k + 1 < nsteps);
     if (st != RRMHD_OK) return st;
   }
   if (hipMemcpyAsync(b->hclock, b->ct, sizeof(double) * nsim, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
