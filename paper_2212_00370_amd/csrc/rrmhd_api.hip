@@ -1301,6 +1301,9 @@ __global__ void __launch_bounds__(kBlock) k_speed_b(const SimDesc* __restrict__ 
   const int s = find_sim(o, nsim, blockIdx.x);
   if (C.t && clock_at_end(C, s)) return;
   const SimDesc& D = T[s];
+  // the Newton pass's slot of this block (read with the cell blocks' after a
+  // step that leaves the next step's speeds, and until then 0)
+  if (threadIdx.x == 0) D.partial[D.npartial + (blockIdx.x - o[s])] = 0.0;
   speed_block(blockIdx.x - o[s], D.G, D.U, D.vs, D.K, D.partial, D.rep, D.blkmax);
 }
 
