@@ -163,3 +163,46 @@ def test_advance_batch_rejects_bad_clock(mods):
         B.advance_active(one, one, np.array([-1]), np.zeros(1), np.zeros(1, np.int64), -1)
     B.close()
     s.close()
+
+
+def test_advance_batch_riemann_workload_equals_host_loop(mods):
+    """The 1D Riemann workload (400 cells to t = 0.4, stiff opacities, many
+    cells finished by the Newton pass) through rrmhd_advance_batch, whose
+    steps after the first of a call take their primitives and signal speeds
+    from the passes that finish each cell, equals the host loop of
+    rrmhd_max_speed_batch + rrmhd_step_batch bit for bit."""
+    torch, R, S = mods
+    cases = [(I.riemann_1d(seed), R.FP64 if seed % 3 else R.MIXED) for seed in range(12)]
+    t_end = np.full(len(cases), 0.4)
+    max_steps = np.full(len(cases), -1, dtype=np.int64)
+    host = [make(torch, R, P, prec) for P, prec in cases]
+    dev = [make(torch, R, P, prec) for P, prec in cases]
+    cfl_dx = np.array([P.cfl * min(P.dx) for P, _ in cases])
+    B1 = R.Batch(16)
+    t = np.zeros(len(cases))
+    n = np.zeros(len(cases), dtype=np.int64)
+    while not (t >= t_end * (1.0 - 1e-14)).all():
+        idx = np.where(~(t >= t_end * (1.0 - 1e-14)))[0]
+        sm = np.array(B1.max_speed([host[i][0] for i in idx], [host[i][1] for i in idx]))
+        dts = np.minimum(cfl_dx[idx] / sm, t_end[idx] - t[idx])
+        B1.step([host[i][0] for i in idx], [host[i][1] for i in idx], list(dts), [host[i][2] for i in idx])
+        t[idx] += dts
+        n[idx] += 1
+    torch.cuda.synchronize()
+    B2 = R.Batch(16)
+    B2.set_active([c[0] for c in dev], [c[1] for c in dev], [c[2] for c in dev])
+    td = np.zeros(len(cases))
+    nd = np.zeros(len(cases), dtype=np.int64)
+    for chunk in (50, 7, 1, 1000):
+        B2.advance_active(cfl_dx, t_end, max_steps, td, nd, chunk)
+        td, nd = B2.clock_active()
+    assert np.array_equal(nd, n)
+    assert np.array_equal(td, t)
+    for (s1, U1, _), (s2, U2, _) in zip(host, dev):
+        assert torch.equal(U1, U2)
+    its = max(c[0].report()["max_imp_it"] for c in dev)
+    assert its > 8        # some cells went on from the Picard cap to the Newton pass
+    for c in host + dev:
+        c[0].close()
+    B1.close()
+    B2.close()
