@@ -78,6 +78,11 @@ MUTANTS = {
     "ct_cell_field_lower_face": ("Ust[q] = 0.5 * (real(bnew[a * N + c]) + real(bnew[a * N + pcell(G, y[0], y[1], y[2])]));",
                                  "Ust[q] = real(bnew[a * N + c]);"),
     "ct_no_normal_field_override": ("      VL[5 + d] = bn;\n      VR[5 + d] = bn;", "      (void)bn;"),
+    # exact-JVP PVM-int (forward-mode dual numbers, the recovery differentiated implicitly)
+    "dual_product_drops_term": ("return Dual(a.v * b.v, a.v * b.d + a.d * b.v); }",
+                                "return Dual(a.v * b.v, a.v * b.d); }"),
+    "dual_quotient_sign": ("return Dual(q, (a.d - q * b.d) / b.v);", "return Dual(q, (a.d + q * b.d) / b.v);"),
+    "jvp_implicit_dZ_sign": ("const real dZ = -(fU / fZ);", "const real dZ = fU / fZ;"),
     # Rad-HLL (Section 3.2, Radiative HLL)
     "hll_limit_without_four_thirds": ("const real lim = 4.0 / (3.0 * rmax(tauL, tauR));",
                                       "const real lim = 1.0 / rmax(tauL, tauR);"),
