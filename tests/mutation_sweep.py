@@ -67,6 +67,10 @@ MUTANTS = {
     # implicit solve (Section 3.3, eqs. g0, gi)
     "implicit_Cij_sign": ("sy.C[1 + i][1 + j] = (i == j) ? 1.0 + hrW * (ks + g) : hrW * g;",
                           "sy.C[1 + i][1 + j] = (i == j) ? 1.0 - hrW * (ks + g) : hrW * g;"),
+    "implicit_C1j_factor": ("const real c1 = kap - sig * (2.0 * W2 - 1.0);", "const real c1 = kap - sig * (W2 - 1.0);"),
+    "implicit_Ci1_drops_flow_term": ("sy.C[1 + i][0] = -(hr * (ks * Du[i] + c2 * u[i]));",
+                                     "sy.C[1 + i][0] = -(hr * (ks * Du[i]));"),
+    "emission_energy_without_W": ("sy.b[0] = Us[8] + W * em;", "sy.b[0] = Us[8] + em;"),
     "emission_with_scattering": ("const real em = (hr * kap) * aT4;", "const real em = (hr * (kap + sig)) * aT4;"),
     "no_post_solve_flux_limit": (RESCALE, RESCALE.replace("if (FF > X[0]", "if (false && FF > X[0]")),
     # constrained transport (Section 4; CT-contact EMFs)
