@@ -88,6 +88,10 @@ MUTANTS = {
     "dual_quotient_sign": ("return Dual(q, (a.d - q * b.d) / b.v);", "return Dual(q, (a.d + q * b.d) / b.v);"),
     "jvp_implicit_dZ_sign": ("const real dZ = -(fU / fZ);", "const real dZ = fU / fZ;"),
     # Rad-HLL (Section 3.2, Radiative HLL)
+    "m1_speed_zeta_drops_angle_term": ("real zz = (2.0 / 3.0) * (r43 - sr) + (2.0 * (cth * cth)) * ((2.0 - f2) - sr);",
+                                       "real zz = (2.0 / 3.0) * (r43 - sr);"),
+    "laguerre_factor_three": ("real t = 3.0 * (4.0 * H - G * G);", "real t = 4.0 * H - G * G;"),
+    "induction_sign": ("F[5 + j] = vd * V[5 + j] - V[5 + d] * V[1 + j];", "F[5 + j] = vd * V[5 + j] + V[5 + d] * V[1 + j];"),
     "hll_limit_without_four_thirds": ("const real lim = 4.0 / (3.0 * rmax(tauL, tauR));",
                                       "const real lim = 1.0 / rmax(tauL, tauR);"),
     "hll_middle_sign": ("((lR * FL[q] - lL * FR[q]) + (lR * lL) * (UR[q] - UL[q]))",
