@@ -40,6 +40,16 @@ MUTANTS = {
     "residual_scaled_wrongly": ("  e.f = f * e.iW;", "  e.f = f * e.l2;"),
     "recovered_W_wrong": ("  if (lw) { lw[0] = e.l2; lw[1] = e.iW; }", "  if (lw) { lw[0] = e.l2; lw[1] = e.l2; }"),
     # PVM chain and beta (Section 3.2, eqs. iterat, utilde, beta, limits)
+    "beta_rows_include_field": ("      for (int q = 0; q < NV; ++q) Uk[q] = U0[q];\n    }\n  }\n  for (int q = 0; q < NV; ++q) {\n    const real bq = (P.beta_mode == 2 || (P.beta_mode == 1 && q < 8)) ? real(1.0) : beta;",
+                                "      for (int q = 0; q < NV; ++q) Uk[q] = U0[q];\n    }\n  }\n  for (int q = 0; q < NV; ++q) {\n    const real bq = (P.beta_mode == 2 || (P.beta_mode == 1 && q < 5)) ? real(1.0) : beta;"),
+    "jvp_beta_rows_include_field": ("    fo.c2p_it = it;\n  }\n  for (int q = 0; q < NV; ++q) {\n    const real bq = (P.beta_mode == 2 || (P.beta_mode == 1 && q < 8)) ? real(1.0) : beta;",
+                                    "    fo.c2p_it = it;\n  }\n  for (int q = 0; q < NV; ++q) {\n    const real bq = (P.beta_mode == 2 || (P.beta_mode == 1 && q < 5)) ? real(1.0) : beta;"),
+    "fallback_keeps_partial_chain": ("    } else {\n      fo.fallback = 1;\n      for (int q = 0; q < NV; ++q) Uk[q] = U0[q];",
+                                     "    } else {\n      fo.fallback = 1;\n      for (int q = 0; q < NV; ++q) Uk[q] = w[q];"),
+    "jvp_horner_index": ("        jvp_flux(Um, Zm, fZ, t1, d, K, t2);\n        const real cnext = coef[M - 1 - l];",
+                         "        jvp_flux(Um, Zm, fZ, t1, d, K, t2);\n        const real cnext = coef[l];"),
+    "jvp_drops_top_coefficient": ("for (int q = 0; q < NV; ++q) w[q] = ctop * t2[q] + cnext * U0[q];",
+                                  "for (int q = 0; q < NV; ++q) w[q] = t2[q] + cnext * U0[q];"),
     "horner_index": ("const real cnext = coef[M - 1 - l];\n      if (l == 0) {\n        const real ctop = coef[M];\n        for (int q = 0; q < NV; ++q) w[q] = ctop * ((Ft[q] - Fm[q]) * ieps) + cnext * U0[q];",
                      "const real cnext = coef[l];\n      if (l == 0) {\n        const real ctop = coef[M];\n        for (int q = 0; q < NV; ++q) w[q] = ctop * ((Ft[q] - Fm[q]) * ieps) + cnext * U0[q];"),
     "beta_from_smaller_depth": ("const real beta = 1.0 / rmax(rmax(tauL, tauR), real(1.0));\n  fo.fallback = 0;\n  fo.c2p_it = 0;\n  real Uk[NV];\n  bool ok",

@@ -255,3 +255,22 @@ def test_implicit_result_respects_the_flux_limit(oracle):
         m0 = U[1:4] + U[9:12]; m1 = Un[1:4] + Un[9:12]
         assert np.max(np.abs(m1 - m0)[:, ok] / np.maximum(np.abs(m0[:, ok]).max(axis=0), 1e-300)) < 4e-16
     assert on_limit >= 5
+
+
+def test_pvm_fallback_is_rusanov_whichever_step_fails(oracle):
+    """A failed intermediate recovery drops the face to p_0 = 1 (Rusanov with
+    lambda = 1) whichever Horner step it occurs in (Sec. 3.2, PVM algorithm;
+    the chain's partial result is discarded). With a large difference step
+    (pvm_eps = 0.5) some chains leave the admissible states in a later step:
+    every face counted as a fallback equals the k = 0 flux bit for bit, and
+    the others do not."""
+    par = oracle.params(pvm_eps=0.5, beta_mode=0)
+    par0 = oracle.params(pvm_k=0, beta_mode=0)
+    VL = I.random_prims(31, 4000, vmax=0.9)
+    VR = I.random_prims(32, 4000, vmax=0.9)
+    Fh, fb, _ = oracle.pvm_face(VL, VR, 0.5, 0.5, 0, par)
+    F0, _, _ = oracle.pvm_face(VL, VR, 0.5, 0.5, 0, par0)
+    m = fb == 1
+    assert 50 <= m.sum() <= 3950, m.sum()
+    assert np.array_equal(Fh[:, m], F0[:, m])
+    assert not np.any(np.all(Fh[:, ~m] == F0[:, ~m], axis=0))

@@ -125,6 +125,28 @@ def test_jvp_flux_matches_the_difference_flux_and_is_consistent(oracle):
     assert np.array_equal(Fe, oracle.flux(VL, 1, par))
 
 
+@pytest.mark.parametrize("beta_mode", [0, 1, 2])
+def test_jvp_flux_scales_the_same_rows_as_the_difference_flux(oracle, beta_mode):
+    """eq. beta at tau = 10 on both sides (beta = 0.1): the exact-JVP flux
+    applies beta to the same rows as the difference flux (all rows, the
+    radiation rows, none), so the two still agree to the difference flux's
+    O(eps) accuracy, and the rows beta leaves alone equal those of beta = 1."""
+    par = oracle.params(gamma=GAMMA, beta_mode=beta_mode)
+    parj = oracle.params(gamma=GAMMA, solver=JVP, beta_mode=beta_mode)
+    rng = np.random.default_rng(3)
+    VL = I.random_prims(6, 2000, vmax=0.9)
+    VR = VL * (1 + 0.05 * rng.normal(size=VL.shape))
+    VR[1:4] = 0.97 * VL[1:4]
+    F1, fb1, _ = oracle.pvm_face(VL, VR, 10.0, 10.0, 0, par)
+    F2, fb2, _ = oracle.pvm_face(VL, VR, 10.0, 10.0, 0, parj)
+    assert np.all(fb1 == 0) and np.all(fb2 == 0)
+    err = np.abs(F1 - F2).max(axis=0) / np.abs(F1).max(axis=0)
+    assert err.max() < 2e-6, err.max()
+    F3, _, _ = oracle.pvm_face(VL, VR, 10.0, 10.0, 0, oracle.params(gamma=GAMMA, solver=JVP, beta_mode=2))
+    rows = {0: [], 1: list(range(8)), 2: list(range(12))}[beta_mode]
+    assert np.array_equal(F2[rows], F3[rows])
+
+
 @pytest.mark.parametrize("recon", [0, 1, 2, 3])
 def test_alfven_wave_with_jvp_reproduces_table4(oracle, recon):
     """Section 4.1, Table 4 with the exact-JVP flux: the same printed rows
