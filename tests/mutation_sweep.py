@@ -97,6 +97,11 @@ MUTANTS = {
                                 "return Dual(a.v * b.v, a.v * b.d); }"),
     "dual_quotient_sign": ("return Dual(q, (a.d - q * b.d) / b.v);", "return Dual(q, (a.d + q * b.d) / b.v);"),
     "jvp_implicit_dZ_sign": ("const real dZ = -(fU / fZ);", "const real dZ = fU / fZ;"),
+    "ct_face_rk_weights_swapped": ("bn[a * N + c] = dv((real(a0) * real(b0[a * N + c]) + real(a1) * real(bs[a * N + c])) - cdt * curl);",
+                                   "bn[a * N + c] = dv((real(a1) * real(b0[a * N + c]) + real(a0) * real(bs[a * N + c])) - cdt * curl);"),
+    "inflow_mask_ignored": ("      if (G.g.inflow_mask && G.g.inflow_mask[t]) return -(t + 1);",
+                            "      if (G.g.inflow_mask) return -(t + 1);"),
+    "inflow_ghost_opacity_of_cell_0": ("      long long c = (dl == 0) ? 0 : t;", "      long long c = 0;"),
     # Rad-HLL (Section 3.2, Radiative HLL)
     "m1_speed_zeta_drops_angle_term": ("real zz = (2.0 / 3.0) * (r43 - sr) + (2.0 * (cth * cth)) * ((2.0 - f2) - sr);",
                                        "real zz = (2.0 / 3.0) * (r43 - sr);"),
