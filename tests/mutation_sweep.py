@@ -102,6 +102,8 @@ MUTANTS = {
     "inflow_mask_ignored": ("      if (G.g.inflow_mask && G.g.inflow_mask[t]) return -(t + 1);",
                             "      if (G.g.inflow_mask) return -(t + 1);"),
     "inflow_ghost_opacity_of_cell_0": ("      long long c = (dl == 0) ? 0 : t;", "      long long c = 0;"),
+    "cfl_alfven_term_dropped": ("  const real a2 = (cs2 + ca2) - cs2 * ca2;", "  const real a2 = cs2;"),
+    "cfl_radiation_speeds_ignored": ("  s = rmax(s, rmax(rabs(l1), rabs(l3)));\n  return s;", "  return s;"),
     # Rad-HLL (Section 3.2, Radiative HLL)
     "m1_speed_zeta_drops_angle_term": ("real zz = (2.0 / 3.0) * (r43 - sr) + (2.0 * (cth * cth)) * ((2.0 - f2) - sr);",
                                        "real zz = (2.0 / 3.0) * (r43 - sr);"),

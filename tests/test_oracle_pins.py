@@ -313,6 +313,26 @@ def test_fluid_speed_hydro_sound(oracle):
     assert oracle.cell_speed(V, 0, par)[0] == pytest.approx(cs, rel=1e-14)
 
 
+def test_fluid_speed_across_the_field_is_the_fast_speed(oracle):
+    """Magnetised gas at rest with B perpendicular to d: the fluid part of the
+    CFL speed (reading R19, the bound a^2 = c_s^2 + c_a^2 - c_s^2 c_a^2 with
+    c_a^2 = b^2 / (rho h + b^2)) is the RMHD fast speed across the field, the
+    extreme root of the quartic. A hot, strongly magnetised gas puts it above
+    the radiation's 1/sqrt(3) and well above c_s alone."""
+    g = 5.0 / 3.0
+    par = oracle.params(gamma=g)
+    rho, p, B = 1.0, 2.0, 3.0
+    V = rest_state(1, rho=rho, p=p, B=(0.0, B, 0.0), E=1e-6)
+    rhoh = rho + g / (g - 1) * p
+    cs2 = g * p / rhoh
+    ca2 = B * B / (rhoh + B * B)
+    cf = math.sqrt(cs2 + ca2 - cs2 * ca2)
+    assert cf > 1 / math.sqrt(3) and cf > 1.2 * math.sqrt(cs2)
+    assert oracle.cell_speed(V, 0, par)[0] == pytest.approx(cf, rel=1e-14)
+    lo, hi, _ = oracle.fast_speeds(V, 0, par)
+    assert hi[0] == pytest.approx(cf, rel=1e-10) and lo[0] == pytest.approx(-cf, rel=1e-10)
+
+
 def test_fluid_speed_moving_gas_is_velocity_addition(oracle):
     """B = 0, gas moving along d with speed v: the fast-speed bound is the
     relativistic sum of v and the sound speed, (v + c_s)/(1 + v c_s) downstream
