@@ -81,6 +81,7 @@ MUTANTS = {
     "implicit_Ci1_drops_flow_term": ("sy.C[1 + i][0] = -(hr * (ks * Du[i] + c2 * u[i]));",
                                      "sy.C[1 + i][0] = -(hr * (ks * Du[i]));"),
     "emission_energy_without_W": ("sy.b[0] = Us[8] + W * em;", "sy.b[0] = Us[8] + em;"),
+    "energy_floor_doubled": ("      Ul[8] = P.e_floor;\n", "      Ul[8] = 2.0 * P.e_floor;\n"),
     "emission_with_scattering": ("const real em = (hr * kap) * aT4;", "const real em = (hr * (kap + sig)) * aT4;"),
     "no_post_solve_flux_limit": (RESCALE, RESCALE.replace("if (FF > X[0]", "if (false && FF > X[0]")),
     # constrained transport (Section 4; CT-contact EMFs)

@@ -396,6 +396,30 @@ def test_implicit_static_closed_form(oracle, method):
         assert Vn[4, 0] == pytest.approx(pex, rel=1e-10)
 
 
+def test_implicit_energy_floor(oracle):
+    """A non-positive explicit E_r fails the cell (status 1, state kept) unless
+    e_floor > 0; then E* is raised to e_floor with tau + E_r kept, so the gas
+    pays (counted): in the static limit the result is the scalar root of
+    eqs. g0/gi with E* = e_floor and the original total tau_t."""
+    g = 5.0 / 3.0
+    rho, p, E, B = 1.0, 0.5, -0.01, (0.2, -0.1, 0.3)
+    a, kap, h, floor = 0.3, 2.0, 1e-2, 0.05
+    V = rest_state(1, rho=rho, p=p, B=B, E=E)
+    par0 = oracle.params(gamma=g, a_rad=a)
+    U = oracle.p2c(V, par0)
+    Un, st, _ = oracle.implicit(U, h, kap, 0.0, par0)
+    assert st[0] == 1 and np.array_equal(Un, U)
+    par = oracle.params(gamma=g, a_rad=a, e_floor=floor)
+    Un, st, _ = oracle.implicit(U, h, kap, 0.0, par)
+    assert st[0] == 0
+    tau_t = U[4, 0] + U[8, 0]
+    assert Un[4, 0] + Un[8, 0] == pytest.approx(tau_t, rel=1e-14)
+    Eex, pex = static_solution(floor, tau_t, rho, float(np.dot(B, B)), h, kap, a, g)
+    assert Un[8, 0] == pytest.approx(Eex, rel=1e-12)
+    Vn, _, _, _ = oracle.c2p(Un, par)
+    assert Vn[4, 0] == pytest.approx(pex, rel=1e-10)
+
+
 def test_implicit_stiff_limit(oracle):
     """h rho kappa -> infinity: radiation reaches equilibrium E = a_R T^4."""
     g = 5.0 / 3.0
