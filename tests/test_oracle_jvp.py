@@ -164,3 +164,4 @@ def test_alfven_wave_with_jvp_reproduces_table4(oracle, recon):
         V, _, st, _ = oracle.c2p(U, par)
         err = float(np.mean(np.abs(V[3] - P.V[3])))
         assert err == pytest.approx(table[n][recon], rel=rel), (n, err)
+
