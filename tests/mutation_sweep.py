@@ -107,6 +107,9 @@ MUTANTS = {
     "inflow_ghost_opacity_of_cell_0": ("      long long c = (dl == 0) ? 0 : t;", "      long long c = 0;"),
     "cfl_alfven_term_dropped": ("  const real a2 = (cs2 + ca2) - cs2 * ca2;", "  const real a2 = cs2;"),
     "cfl_radiation_speeds_ignored": ("  s = rmax(s, rmax(rabs(l1), rabs(l3)));\n  return s;", "  return s;"),
+    "z_divergence_stride": ("          if (d == 2) stride = (long long)fn[0] * fn[1];\n          const long long nf = face_count(G, d);\n          const real dF = real(Fh[d][q * nf + fm + stride]) - real(Fh[d][q * nf + fm]);\n          if (d == 0) div = dF * idx[0];",
+                            "          if (d == 2) stride = (long long)fn[0];\n          const long long nf = face_count(G, d);\n          const real dF = real(Fh[d][q * nf + fm + stride]) - real(Fh[d][q * nf + fm]);\n          if (d == 0) div = dF * idx[0];"),
+    "radiation_energy_flux_component": ("  F[8] = V[9 + d];\n", "  F[8] = V[9];\n"),
     # Rad-HLL (Section 3.2, Radiative HLL)
     "m1_speed_zeta_drops_angle_term": ("real zz = (2.0 / 3.0) * (r43 - sr) + (2.0 * (cth * cth)) * ((2.0 - f2) - sr);",
                                        "real zz = (2.0 / 3.0) * (r43 - sr);"),
