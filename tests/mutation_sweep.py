@@ -84,6 +84,9 @@ MUTANTS = {
                                      "sy.C[1 + i][0] = -(hr * (ks * Du[i]));"),
     "emission_energy_without_W": ("sy.b[0] = Us[8] + W * em;", "sy.b[0] = Us[8] + em;"),
     "energy_floor_doubled": ("      Ul[8] = P.e_floor;\n", "      Ul[8] = 2.0 * P.e_floor;\n"),
+    "no_pre_solve_flux_limit": ("  {\n    const real FF = (Ul[9] * Ul[9] + Ul[10] * Ul[10]) + Ul[11] * Ul[11];\n    if (FF > Ul[8] * Ul[8]) {",
+                                "  {\n    const real FF = (Ul[9] * Ul[9] + Ul[10] * Ul[10]) + Ul[11] * Ul[11];\n    if (false && FF > Ul[8] * Ul[8]) {"),
+    "recovery_bracket_without_gamma": ("  real hi = P.gamma * in.Et;", "  real hi = in.Et;"),
     "emission_with_scattering": ("const real em = (hr * kap) * aT4;", "const real em = (hr * (kap + sig)) * aT4;"),
     "no_post_solve_flux_limit": (RESCALE, RESCALE.replace("if (FF > X[0]", "if (false && FF > X[0]")),
     # constrained transport (Section 4; CT-contact EMFs)
@@ -115,6 +118,10 @@ MUTANTS = {
                                        "real zz = (2.0 / 3.0) * (r43 - sr);"),
     "laguerre_factor_three": ("real t = 3.0 * (4.0 * H - G * G);", "real t = 4.0 * H - G * G;"),
     "induction_sign": ("F[5 + j] = vd * V[5 + j] - V[5 + d] * V[1 + j];", "F[5 + j] = vd * V[5 + j] + V[5 + d] * V[1 + j];"),
+    "hll_fluid_speeds_from_left_only": ("  hll_rows(FL, FR, UL, UR, rmin(mnL, mnR), rmax(mxL, mxR), 0, 8, Fh);",
+                                        "  hll_rows(FL, FR, UL, UR, mnL, mxL, 0, 8, Fh);"),
+    "hll_radiation_limit_one_sided": ("  hll_rows(FL, FR, UL, UR, rmax(rmin(r1L, r1R), -lim), rmin(rmax(r3L, r3R), lim), 8, NV, Fh);",
+                                      "  hll_rows(FL, FR, UL, UR, rmin(r1L, r1R), rmin(rmax(r3L, r3R), lim), 8, NV, Fh);"),
     "hll_limit_without_four_thirds": ("const real lim = 4.0 / (3.0 * rmax(tauL, tauR));",
                                       "const real lim = 1.0 / rmax(tauL, tauR);"),
     "hll_middle_sign": ("((lR * FL[q] - lL * FR[q]) + (lR * lL) * (UR[q] - UL[q]))",

@@ -196,6 +196,32 @@ def test_hll_of_equal_states_is_the_physical_flux(oracle):
     assert np.array_equal(Fh, oracle.flux(S, 0, par))
 
 
+def test_hll_fluid_rows_take_the_extreme_speeds_of_both_states(oracle):
+    """Rad-HLL's magnetofluid rows (Sec. 3.2, Radiative HLL; reading R28):
+    lambda_L = min of the two states' slowest speeds, lambda_R = max of their
+    fastest, each the extreme root of the RMHD quartic. Independent random
+    states in every direction: rows 0..7 equal the HLL formula with those
+    speeds (up to the rounding of the quotient), so speeds from one state
+    alone, or a swapped min and max, fail."""
+    rng = np.random.default_rng(9)
+    n = 400
+    VL, VR = _states(rng, n), _states(rng, n)
+    par = oracle.params(gamma=GAMMA, solver=oracle.SOLVER_HLL)
+    for d in range(3):
+        Fh, _ = oracle.hll_face(VL, VR, 0.5, 0.5, d, par)
+        loL, hiL, _ = oracle.fast_speeds(VL, d, par)
+        loR, hiR, _ = oracle.fast_speeds(VR, d, par)
+        lL, lR = np.minimum(loL, loR), np.maximum(hiL, hiR)
+        UL, UR = oracle.p2c(VL, par), oracle.p2c(VR, par)
+        FL, FR = oracle.flux(VL, d, par), oracle.flux(VR, d, par)
+        mid = ((lR * FL - lL * FR) + (lR * lL) * (UR - UL)) / (lR - lL)
+        want = np.where(lL > 0, FL, np.where(lR < 0, FR, mid))[:8]
+        scale = np.abs(want).max(axis=0) + 1e-300
+        assert np.max(np.abs(Fh[:8] - want) / scale) < 1e-12, d
+        # the cases differ: one state's speeds alone would not do
+        assert np.mean((loL != lL) | (hiL != lR)) > 0.3
+
+
 @pytest.mark.parametrize("tau", [0.1, 1.0, 10.0, 1e3])
 def test_rad_hll_radiation_rows_in_the_diffusion_limit(oracle, tau):
     """Fluid at rest and unmagnetised, F_r = 0, a jump in E_r only: the
