@@ -63,6 +63,7 @@ MUTANTS = {
                             "if (same_sign(a, b)) return (rabs(a) > rabs(b)) ? a : b;"),
     "mc_without_central_slope": ("  return (rabs(c) < rabs(m)) ? c : m;", "  return m;"),
     "vanleer_without_factor_two": ("  return (real(2.0) * (a * b)) / (a + b);", "  return (a * b) / (a + b);"),
+    "no_face_flux_limit": ("    limit_rad_flux(VL);\n    limit_rad_flux(VR);", "    (void)VL;"),
     "no_superluminal_fallback": (FALLBACK, FALLBACK.replace("if (!(v2lo < real(1.0)) || !(v2hi < real(1.0)))",
                                                             "if (false)")),
     "fallback_upper_face_only": (FALLBACK, FALLBACK.replace("if (!(v2lo < real(1.0)) || !(v2hi < real(1.0)))",
