@@ -127,6 +127,17 @@ MUTANTS = {
                                       "const real lim = 1.0 / rmax(tauL, tauR);"),
     "hll_middle_sign": ("((lR * FL[q] - lL * FR[q]) + (lR * lL) * (UR[q] - UL[q]))",
                         "((lR * FL[q] - lL * FR[q]) - (lR * lL) * (UR[q] - UL[q]))"),
+    # failed recovery (reading of the state a failed cell takes), boundaries, linear solve
+    "failed_recovery_keeps_velocity": ("  V[1] = 0.0; V[2] = 0.0; V[3] = 0.0;\n  V[4] = P.p_floor;",
+                                       "  V[1] = U[1] / U[0]; V[2] = 0.0; V[3] = 0.0;\n  V[4] = P.p_floor;"),
+    "failed_recovery_without_density_floor": ("V[0] = (U[0] > real(0.0)) ? U[0] : real(P.rho_floor);",
+                                              "V[0] = U[0];"),
+    "failed_recovery_pressure_of_density_floor": ("  V[4] = P.p_floor;\n  for (int q = 5;",
+                                                  "  V[4] = P.rho_floor;\n  for (int q = 5;"),
+    "periodic_upper_wrap_off_by_one": ("if (G.g.bc_hi[d] == 0) c[d] = c[d] % nd;",
+                                       "if (G.g.bc_hi[d] == 0) c[d] = (c[d] + 1) % nd;"),
+    "solve4_transposed_back_substitution": ("for (int j = i + 1; j < 4; ++j) s = s - A[i][j] * x[j];",
+                                            "for (int j = i + 1; j < 4; ++j) s = s - A[j][i] * x[j];"),
 }
 
 

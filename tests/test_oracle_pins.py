@@ -136,6 +136,30 @@ def test_prim_cons_round_trip(oracle):
     assert it.max() <= 20
 
 
+def test_failed_recovery_takes_a_floored_state_at_rest(oracle):
+    """A conserved state with no admissible primitives (total energy below the
+    rest mass, or a non-positive D) fails its recovery and takes the finite
+    state the failure reading fixes: rho = D (the density floor when D <= 0),
+    v = 0, p = the pressure floor, with B, E_r and F_r passed through. The two
+    floors are set to distinct values so that neither stands in for the
+    other."""
+    par = oracle.params(rho_floor=3e-11, p_floor=7e-10)
+    U = np.zeros((12, 2))
+    U[0] = [1.0, -1e-3]                      # D
+    U[1:4, 0] = [0.3, -0.1, 0.05]            # S
+    U[4] = [-0.5, 1.0]                       # tau: tau + D = 0.5 < D in the first
+    U[5:8] = np.array([0.2, -0.1, 0.05])[:, None]
+    U[8] = 0.4
+    U[9:12] = np.array([0.1, 0.0, -0.05])[:, None]
+    V, _, st, _ = oracle.c2p(U, par)
+    assert np.all(st != 0)
+    want = np.zeros((12, 2))
+    want[0] = [1.0, 3e-11]
+    want[4] = 7e-10
+    want[5:] = U[5:]
+    assert np.array_equal(V, want), V
+
+
 def test_prim_cons_closed_forms(oracle):
     """Rest frame: D = rho, S = 0, tau = p/(gamma-1) + B^2/2; hydro (B = 0):
     S = rho h W^2 v, tau = rho h W^2 - p - rho W (eq. eqU)."""
