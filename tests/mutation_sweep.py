@@ -136,6 +136,10 @@ MUTANTS = {
                                                   "  V[4] = P.rho_floor;\n  for (int q = 5;"),
     "periodic_upper_wrap_off_by_one": ("if (G.g.bc_hi[d] == 0) c[d] = c[d] % nd;",
                                        "if (G.g.bc_hi[d] == 0) c[d] = (c[d] + 1) % nd;"),
+    "quartic_field_projection_sign": ("  const real Bt = q.bd - l * q.b0;", "  const real Bt = q.bd + l * q.b0;"),
+    "reuse_checks_density_only": ("  for (int q = 0; q < 8; ++q) same = same && (U[q] == Um[q]);",
+                                  "  for (int q = 0; q < 1; ++q) same = same && (U[q] == Um[q]);"),
+    "radiation_speed_cosine_along_x": ("    cth = V[9 + d] / Fn;", "    cth = V[9] / Fn;"),
     "solve4_transposed_back_substitution": ("for (int j = i + 1; j < 4; ++j) s = s - A[i][j] * x[j];",
                                             "for (int j = i + 1; j < 4; ++j) s = s - A[j][i] * x[j];"),
 }
