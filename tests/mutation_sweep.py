@@ -140,6 +140,13 @@ MUTANTS = {
     "reuse_checks_density_only": ("  for (int q = 0; q < 8; ++q) same = same && (U[q] == Um[q]);",
                                   "  for (int q = 0; q < 1; ++q) same = same && (U[q] == Um[q]);"),
     "radiation_speed_cosine_along_x": ("    cth = V[9 + d] / Fn;", "    cth = V[9] / Fn;"),
+    "emission_momentum_dropped": ("  for (int i = 0; i < 3; ++i) sy.b[1 + i] = Us[9 + i] + u[i] * em;",
+                                  "  for (int i = 0; i < 3; ++i) sy.b[1 + i] = Us[9 + i];"),
+    "implicit_Cij_offdiagonal_dropped": ("      sy.C[1 + i][1 + j] = (i == j) ? 1.0 + hrW * (ks + g) : hrW * g;",
+                                         "      sy.C[1 + i][1 + j] = (i == j) ? 1.0 + hrW * (ks + g) : real(0.0);"),
+    "implicit_tensor_isotropic": ("        Dm[i][j] = (i == j) ? ca + cb * nn : cb * nn;",
+                                  "        Dm[i][j] = (i == j) ? real(1.0 / 3.0) : real(0.0);"),
+    "implicit_temperature_without_rho": ("  const real T = (P.t_coeff * p) / rho;", "  const real T = P.t_coeff * p;"),
     "solve4_transposed_back_substitution": ("for (int j = i + 1; j < 4; ++j) s = s - A[i][j] * x[j];",
                                             "for (int j = i + 1; j < 4; ++j) s = s - A[j][i] * x[j];"),
 }
