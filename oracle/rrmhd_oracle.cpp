@@ -7,6 +7,7 @@
 // reference that the GPU library is checked against. Only the test suite, the
 // smoke check and the CPU-baseline leg of the benchmark may load it; the
 // product path never calls it. It shares no source with the GPU library.
+// Parity unpinned: the zero-mass-flux branch of the CT upwind rule (upwind).
 //
 // Every function follows the paper's definitions directly (section or
 // equation named in its comment). Where the paper leaves a choice open (the
@@ -1362,6 +1363,8 @@ static long long lower_face(const Grid& G, int d, int i, int j, int k) {
 
 // Upwind choice by the sign of a mass flux: lower-side value when it is
 // positive, upper-side when negative, their mean when zero.
+// Parity unpinned: the branch for an exactly zero face mass flux (the mean
+// of the two sides) has no CPU pin of its own.
 static real upwind(real mflux, real lower_side, real upper_side) {
   if (mflux > real(0.0)) return lower_side;
   if (mflux < real(0.0)) return upper_side;

@@ -147,6 +147,9 @@ MUTANTS = {
     "implicit_tensor_isotropic": ("        Dm[i][j] = (i == j) ? ca + cb * nn : cb * nn;",
                                   "        Dm[i][j] = (i == j) ? real(1.0 / 3.0) : real(0.0);"),
     "implicit_temperature_without_rho": ("  const real T = (P.t_coeff * p) / rho;", "  const real T = P.t_coeff * p;"),
+    "max_speed_first_direction_only": ("    for (int d = 0; d < og->ndim; ++d) smax = std::max(smax, dv(cell_speed(Vc, d, *P, K)));",
+                                       "    for (int d = 0; d < 1; ++d) smax = std::max(smax, dv(cell_speed(Vc, d, *P, K)));"),
+    "ct_upwind_tie_takes_lower": ("  return 0.5 * (lower_side + upper_side);\n}", "  return lower_side;\n}"),
     "solve4_transposed_back_substitution": ("for (int j = i + 1; j < 4; ++j) s = s - A[i][j] * x[j];",
                                             "for (int j = i + 1; j < 4; ++j) s = s - A[j][i] * x[j];"),
 }

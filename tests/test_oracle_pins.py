@@ -357,6 +357,27 @@ def test_fluid_speed_across_the_field_is_the_fast_speed(oracle):
     assert hi[0] == pytest.approx(cf, rel=1e-10) and lo[0] == pytest.approx(-cf, rel=1e-10)
 
 
+def test_cfl_speed_takes_every_direction_of_the_grid(oracle):
+    """The CFL rule's signal speed is the maximum over the cells and over all
+    directions of the grid: a uniform hot gas (B = 0) moving along the last
+    axis of a 2D or 3D grid has (v + c_s)/(1 + v c_s) there, above its speed
+    along x, and no other value."""
+    g = 5.0 / 3.0
+    par = oracle.params(gamma=g)
+    rho, p, v = 1.0, 3.0, 0.8
+    rhoh = rho + g / (g - 1) * p
+    cs = math.sqrt(g * p / rhoh)
+    want = (v + cs) / (1 + v * cs)
+    for shape in ((4, 3), (3, 2, 2)):
+        n = int(np.prod(shape))
+        vel = [0.0, 0.0, 0.0]
+        vel[len(shape) - 1] = v
+        U = oracle.p2c(rest_state(n, rho=rho, p=p, E=1e-6, v=vel), par)
+        s, nf = oracle.max_speed(oracle.make_grid(shape, (0.1,) * len(shape)), U, par)
+        assert nf == 0
+        assert s == pytest.approx(want, rel=1e-12), (shape, s, want)
+
+
 def test_fluid_speed_moving_gas_is_velocity_addition(oracle):
     """B = 0, gas moving along d with speed v: the fast-speed bound is the
     relativistic sum of v and the sound speed, (v + c_s)/(1 + v c_s) downstream
